@@ -1,0 +1,208 @@
+/*
+ * gcp.h -- C ABI of the MI355X (gfx950) GCP-CROWN bound-propagation library.
+ *
+ * GCP-CROWN (arXiv 2208.05740) lower-bounds  min_{x in C} c^T f(x)  for a
+ * ReLU network f over the L-inf box C = {x : |x - x0|_inf <= eps}
+ * (Sec. 2, eq. verification_definition), given root pre-activation bounds
+ * l <= x^(i) <= u (Sec. 2, neuron classes), BaB split constraints
+ * (Sec. 3.1, "Connection to CROWN-like methods"; Appendix B) and general
+ * cutting planes  sum_i H^(i) x^(i) + G^(i) x_hat^(i) + Q^(i) z^(i) <= d
+ * (Sec. 3.1, eq. cuts).  The bound is the closed-form dual objective of
+ * Theorem 3.1 (proof in Appendix A, Lemma A.1), with optimisable
+ *   alpha  in [0,1]  -- lower-relaxation slope of each root-unstable neuron,
+ *   beta   >= 0      -- multiplier of each split constraint,
+ *   gamma  >= 0      -- multiplier of each cut row
+ * (the paper names both multipliers beta).  Every (domain, spec row) pair is
+ * an independent scalar problem; the library evaluates M = B*S of them in
+ * one call, their gradients by a hand-written adjoint, and a projected Adam
+ * ascent (Appendix C.1: 20 iterations, lr 0.1 for alpha, 0.02 for the
+ * multipliers, decay 0.9 per iteration).
+ *
+ * Conventions for every entry point
+ *  - Return 0 (GCP_OK) or a negative GCP_E* code; gcp_last_error() returns a
+ *    thread-local message for the last failure.  No C++ exception crosses
+ *    the ABI.  Inputs are not modified on error.
+ *  - "host" pointers are read during the call only; "device" pointers are
+ *    caller-owned HIP device memory on the device current at the call and
+ *    must stay valid until the stream work completes.  Handles own their
+ *    device copies and are released by the matching *_destroy.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
+ *    default stream); results are ready when the stream is synchronised.
+ *  - Calls that share a gcp_net use its workspace: do not run two calls on
+ *    the same net concurrently on different streams.
+ *  - Row r of every per-row array is domain b = r / S, spec row s = r % S.
+ */
+#ifndef GCP_H
+#define GCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define GCP_OK            0
+#define GCP_EINVAL      (-1)   /* null pointer, bad shape or index           */
+#define GCP_ERANGE      (-2)   /* alpha outside [0,1], multiplier < 0, eps<0 */
+#define GCP_ENONFINITE  (-3)   /* NaN or Inf in an input                     */
+#define GCP_ENOMEM      (-4)   /* device allocation failed                   */
+#define GCP_EDEVICE     (-5)   /* HIP runtime error                          */
+#define GCP_EUNSUPPORTED (-6)  /* valid input the library does not handle    */
+
+/* ------------------------------------------------------------ network */
+#define GCP_EDGE_DENSE    0    /* W host fp32 [out][in], row-major           */
+#define GCP_EDGE_CONV     1    /* W host fp32 [c_out][c_in][kh][kw]          */
+#define GCP_EDGE_IDENTITY 2    /* W unused; source and node shapes equal     */
+
+/* One linear input of a node:  x_node += op(x_hat_src)  (Sec. 2, eq.
+ * mip_layer; residual sums for DAG networks).  src = -1 is the input x. */
+typedef struct {
+  int32_t src;
+  int32_t kind;
+  const float* W;
+  int32_t kh, kw, stride, pad;   /* conv only: square stride, symmetric pad */
+} gcp_edge_desc;
+
+/* A node  x = sum_e op_e(x_hat_src(e)) + bias,  shape (c, h, w) flattened in
+ * C order (dense nodes: c = size, h = w = 1).  Every node but the last is
+ * followed by a ReLU; the last node is the network output f(x).  lower/upper
+ * are the root pre-activation bounds l, u of a ReLU node (host fp64, l <= u;
+ * ignored for the output).  Neuron classes follow l, u: active if l >= 0,
+ * else inactive if u <= 0, else unstable (l < 0 < u). */
+typedef struct {
+  int32_t c, h, w;
+  const float* bias;
+  const double* lower;
+  const double* upper;
+  int32_t n_edges;
+  const gcp_edge_desc* edges;
+} gcp_node_desc;
+
+typedef struct {
+  int32_t in_c, in_h, in_w;
+  int32_t n_nodes;               /* >= 2: at least one ReLU node + output   */
+  const gcp_node_desc* nodes;    /* topological order: edges point backward */
+} gcp_net_desc;
+
+typedef struct gcp_net gcp_net;
+
+/* Copies weights, biases and root bounds to the current device (fp32 and
+ * bf16 copies of every weight).  Errors: EINVAL (shapes, edge sources not
+ * earlier, conv geometry), ENONFINITE (weights/bounds), ENOMEM, EDEVICE. */
+int gcp_net_create(const gcp_net_desc* desc, gcp_net** out);
+int gcp_net_destroy(gcp_net* net);
+
+typedef struct {
+  int32_t n_nodes;
+  int32_t in_size;               /* d_0                                     */
+  int32_t out_size;              /* d_L                                     */
+  int64_t n_relu;                /* sum of ReLU node sizes                  */
+  int64_t n_unstable;            /* n_I: length of an alpha row             */
+} gcp_net_info;
+
+/* Sizes of the network.  alpha rows list the root-unstable neurons node by
+ * node (topological order), ascending neuron index within a node. */
+int gcp_net_get_info(const gcp_net* net, gcp_net_info* info);
+
+/* ------------------------------------------------------------ cuts */
+#define GCP_CUT_H 0   /* coefficient on the pre-activation x_j   */
+#define GCP_CUT_G 1   /* coefficient on the post-activation x_hat_j (node -1: input x_j) */
+#define GCP_CUT_Q 2   /* coefficient on the ReLU indicator z_j    */
+
+typedef struct gcp_cuts gcp_cuts;
+
+/* N cut rows in coordinate form (host arrays of length nnz): entry e adds
+ * coef[e] * var(kind[e]) of neuron `neuron[e]` of node `node[e]` to the
+ * left side of cut `cut[e]`; d (host fp64 [N]) are the right sides
+ * (eq. cuts).  node = -1 (input) allows only GCP_CUT_G.  Repeated
+ * (cut, node, neuron, kind) entries are summed.  A Q term on a neuron that
+ * is active in a domain uses z = 1 there, on an inactive one z = 0.
+ * Coefficients are stored in fp32, d in fp64.  n_cuts = 0 is allowed
+ * (gamma rows then have length 0 and the bound is beta-CROWN's).
+ * Errors: EINVAL (index out of range, bad kind), ENONFINITE. */
+int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz,
+                    const int32_t* cut, const int32_t* node, const int32_t* neuron,
+                    const int8_t* kind, const double* coef, const double* d,
+                    gcp_cuts** out);
+int gcp_cuts_destroy(gcp_cuts* cuts);
+
+/* ------------------------------------------------------------ splits */
+typedef struct gcp_splits gcp_splits;
+
+/* B BaB domains with up to K split slots each (host [B][K] arrays):
+ * node[b][k] = -1 marks an unused slot; otherwise neuron `neuron[b][k]` of
+ * ReLU node `node[b][k]` is split with sign[b][k] = +1 (x >= 0: the neuron
+ * is treated as active and its multiplier enters as -beta) or -1 (x <= 0:
+ * inactive, +beta).  Split neurons must be root-unstable and distinct
+ * within a domain.  K = 0 (no splits) is allowed with B >= 1.
+ * Errors: EINVAL (index, sign, stable or repeated neuron). */
+int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K,
+                      const int32_t* node, const int32_t* neuron, const int8_t* sign,
+                      gcp_splits** out);
+int gcp_splits_destroy(gcp_splits* splits);
+
+/* ------------------------------------------------------------ bounding */
+#define GCP_MODE_FP32   0   /* GEMMs fp32 x fp32 -> fp32 on MFMA             */
+#define GCP_MODE_BF16   1   /* GEMM operands bf16, fp32 accumulation          */
+#define GCP_FLAG_VALIDATE 0x100  /* check alpha/beta/gamma ranges on device
+                                    (synchronises the stream)               */
+/* In every mode the row reductions (concretisation v.x0 - eps*|v|_1, bias,
+ * h and cut-offset sums, gamma.d) accumulate in fp64; the bound is fp64. */
+
+/* gcp_bound: the Theorem 3.1 bound for all M = B*S rows.
+ *   x0     device fp64 [d_0]       centre of the box; eps >= 0
+ *   C      device fp64 [S][d_L]    spec rows c_s (folded in as last layer)
+ *   alpha  device fp32 [M][n_I]    in [0,1]
+ *   beta   device fp32 [M][K]      >= 0 (K of `splits`)
+ *   gamma  device fp32 [M][N]      >= 0 (N of `cuts`; NULL if N = 0)
+ *   bound  device fp64 [M]         output
+ *   verified device uint8 [M]      optional output: 1 where bound >= 0,
+ *          i.e. the property is proven for that row (Sec. 2)
+ *   d_alpha/d_beta/d_gamma device fp32, shapes as the inputs: optional
+ *          outputs d bound_r / d param (row r's own parameters); pass all
+ *          three or none.
+ * The input term is v.x0 - eps*||v||_1 with v = Lambda^(1) W^(1). */
+int gcp_bound(const gcp_net* net, const double* x0, double eps,
+              const double* C, int32_t S,
+              const gcp_splits* splits, const gcp_cuts* cuts,
+              const float* alpha, const float* beta, const float* gamma,
+              int32_t mode, double* bound, uint8_t* verified,
+              float* d_alpha, float* d_beta, float* d_gamma, void* stream);
+
+/* Optimiser settings (Appendix C.1 defaults: iters 20, lr_alpha 0.1,
+ * lr_mult 0.02, decay 0.9, Adam 0.9/0.999/1e-8). */
+typedef struct {
+  int32_t iters;
+  float lr_alpha, lr_mult, decay;
+  float adam_b1, adam_b2, adam_eps;
+  int32_t use_graph;        /* capture one iteration in a hipGraph, replay */
+} gcp_opt;
+
+/* gcp_optimize: `iters` projected Adam ascent steps on sum_r bound_r, all on
+ * the device: each iteration runs the bound pass (GEMMs in `mode`), the
+ * adjoint, and the Adam update of alpha (clamped to [0,1]), beta and gamma
+ * (clamped >= 0) with lr_t = lr * decay^t.  alpha, beta, gamma are updated
+ * in place.  adam_state: device fp32 [2][M][n_I + K + N] (first and second
+ * moments, caller-owned so optimisation can resume); must be zero for a
+ * fresh start.  Finally the bound at the final parameters is recomputed
+ * with fp32 GEMMs and fp64 reductions (the certifying pass) into
+ * bound/verified. */
+int gcp_optimize(const gcp_net* net, const double* x0, double eps,
+                 const double* C, int32_t S,
+                 const gcp_splits* splits, const gcp_cuts* cuts,
+                 float* alpha, float* beta, float* gamma, float* adam_state,
+                 const gcp_opt* opt, int32_t mode,
+                 double* bound, uint8_t* verified, void* stream);
+
+/* Last error message of this thread ("" if none). */
+const char* gcp_last_error(void);
+
+/* Library version string. */
+const char* gcp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCP_H */

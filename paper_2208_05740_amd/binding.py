@@ -1,0 +1,296 @@
+"""ctypes binding of libgcp.so (C ABI in include/gcp.h).
+
+Argument marshalling only: every step of the bound pass, its adjoint and
+the optimiser runs in the HIP library.  torch supplies device memory and the
+current stream.  The library must be built (``python -m
+paper_2208_05740_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgcp.so")
+
+GCP_MODE_FP32 = 0
+GCP_MODE_BF16 = 1
+GCP_FLAG_VALIDATE = 0x100
+EDGE_KIND = {"dense": 0, "conv": 1, "identity": 2}
+ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE", -6: "EUNSUPPORTED"}
+
+
+class GcpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class EdgeDesc(C.Structure):
+    _fields_ = [("src", C.c_int32), ("kind", C.c_int32), ("W", C.POINTER(C.c_float)),
+                ("kh", C.c_int32), ("kw", C.c_int32), ("stride", C.c_int32), ("pad", C.c_int32)]
+
+
+class NodeDesc(C.Structure):
+    _fields_ = [("c", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
+                ("bias", C.POINTER(C.c_float)), ("lower", C.POINTER(C.c_double)),
+                ("upper", C.POINTER(C.c_double)), ("n_edges", C.c_int32),
+                ("edges", C.POINTER(EdgeDesc))]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("in_c", C.c_int32), ("in_h", C.c_int32), ("in_w", C.c_int32),
+                ("n_nodes", C.c_int32), ("nodes", C.POINTER(NodeDesc))]
+
+
+class NetInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("in_size", C.c_int32), ("out_size", C.c_int32),
+                ("n_relu", C.c_int64), ("n_unstable", C.c_int64)]
+
+
+class OptDesc(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("lr_alpha", C.c_float), ("lr_mult", C.c_float),
+                ("decay", C.c_float), ("adam_b1", C.c_float), ("adam_b2", C.c_float),
+                ("adam_eps", C.c_float), ("use_graph", C.c_int32)]
+
+
+_LIB = None
+EXPORTS = ["gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
+           "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_last_error",
+           "gcp_version"]
+
+
+def lib():
+    """Load libgcp.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2208_05740_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.gcp_net_create.argtypes = [C.POINTER(NetDesc), C.POINTER(vp)]
+    L.gcp_net_destroy.argtypes = [vp]
+    L.gcp_net_get_info.argtypes = [vp, C.POINTER(NetInfo)]
+    L.gcp_cuts_create.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
+    L.gcp_cuts_destroy.argtypes = [vp]
+    L.gcp_splits_create.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(vp)]
+    L.gcp_splits_destroy.argtypes = [vp]
+    L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
+    L.gcp_last_error.restype = C.c_char_p
+    L.gcp_version.restype = C.c_char_p
+    for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
+              "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize"):
+        getattr(L, f).restype = C.c_int
+    _LIB = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise GcpError(rc, lib().gcp_last_error().decode())
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Net:
+    """Device copy of a workloads.Net with its root bounds."""
+
+    def __init__(self, net, lu):
+        keep = []
+
+        def f32(a):
+            a = np.ascontiguousarray(a, np.float32)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_float))
+
+        def f64(a):
+            a = np.ascontiguousarray(a, np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        nodes = (NodeDesc * len(net.nodes))()
+        relu_pos = 0
+        edge_arrays = []
+        for i, n in enumerate(net.nodes):
+            shape = tuple(n.shape) if len(n.shape) == 3 else (n.size, 1, 1)
+            edges = (EdgeDesc * len(n.edges))()
+            for k, e in enumerate(n.edges):
+                edges[k].src = e.src
+                edges[k].kind = EDGE_KIND[e.kind]
+                if e.W is not None:
+                    edges[k].W = f32(e.W)
+                if e.kind == "conv":
+                    edges[k].kh, edges[k].kw = e.W.shape[2], e.W.shape[3]
+                edges[k].stride, edges[k].pad = e.stride, e.pad
+            edge_arrays.append(edges)
+            nodes[i].c, nodes[i].h, nodes[i].w = shape
+            nodes[i].bias = f32(n.bias)
+            if n.relu:
+                nodes[i].lower = f64(lu[relu_pos][0])
+                nodes[i].upper = f64(lu[relu_pos][1])
+                relu_pos += 1
+            nodes[i].n_edges = len(n.edges)
+            nodes[i].edges = edges
+        ins = tuple(net.in_shape) if len(net.in_shape) == 3 else (net.in_size, 1, 1)
+        desc = NetDesc(ins[0], ins[1], ins[2], len(net.nodes), nodes)
+        h = C.c_void_p()
+        _check(lib().gcp_net_create(C.byref(desc), C.byref(h)))
+        self.h = h
+        info = NetInfo()
+        _check(lib().gcp_net_get_info(h, C.byref(info)))
+        self.info = info
+        self.n_I = int(info.n_unstable)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.gcp_net_destroy(self.h)
+            self.h = None
+
+
+class Cuts:
+    def __init__(self, net: Net, cuts):
+        self.N = int(cuts.n)
+        a = [np.ascontiguousarray(x) for x in (cuts.cut.astype(np.int32), cuts.node.astype(np.int32),
+                                               cuts.neuron.astype(np.int32), cuts.kind.astype(np.int8),
+                                               cuts.coef.astype(np.float64), cuts.d.astype(np.float64))]
+        h = C.c_void_p()
+        _check(lib().gcp_cuts_create(net.h, self.N, a[0].size, *[x.ctypes.data for x in a], C.byref(h)))
+        self.h = h
+        self.net = net
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.gcp_cuts_destroy(self.h)
+            self.h = None
+
+
+class Splits:
+    def __init__(self, net: Net, splits):
+        self.B, self.K = splits.node.shape
+        a = [np.ascontiguousarray(x) for x in (splits.node.astype(np.int32), splits.neuron.astype(np.int32),
+                                               splits.sign.astype(np.int8))]
+        h = C.c_void_p()
+        _check(lib().gcp_splits_create(net.h, self.B, self.K, *[x.ctypes.data for x in a], C.byref(h)))
+        self.h = h
+        self.net = net
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.gcp_splits_destroy(self.h)
+            self.h = None
+
+
+def bound(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma,
+          mode: int = GCP_MODE_FP32, grads: bool = False, verified: bool = False, validate: bool = False):
+    """gcp_bound on torch device tensors; returns (bound[M] fp64, verified or
+    None, (d_alpha, d_beta, d_gamma) or None)."""
+    import torch
+    dev = x0.device
+    S = Cspec.shape[0]
+    M = splits.B * S
+    out = torch.empty(M, dtype=torch.float64, device=dev)
+    ver = torch.empty(M, dtype=torch.uint8, device=dev) if verified else None
+    g = None
+    if grads:
+        g = (torch.empty_like(alpha), torch.empty_like(beta), torch.empty_like(gamma))
+    md = mode | (GCP_FLAG_VALIDATE if validate else 0)
+    _check(lib().gcp_bound(net.h, _ptr(x0), float(eps), _ptr(Cspec), S, splits.h, cuts.h if cuts else None,
+                           _ptr(alpha) if alpha.numel() else None, _ptr(beta) if beta.numel() else None,
+                           _ptr(gamma) if gamma.numel() else None, md, _ptr(out), _ptr(ver),
+                           *((_ptr(t) if t.numel() else None) for t in g) if g else (None, None, None),
+                           _stream()))
+    return out, ver, g
+
+
+def optimize(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma,
+             adam_state, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.9, b2=0.999, adam_eps=1e-8,
+             mode: int = GCP_MODE_FP32, use_graph: bool = False, bound_out=None, verified_out=None):
+    """gcp_optimize (alpha, beta, gamma, adam_state updated in place);
+    returns (bound[M] fp64 of the certifying pass, verified[M] uint8)."""
+    import torch
+    dev = x0.device
+    S = Cspec.shape[0]
+    M = splits.B * S
+    out = bound_out if bound_out is not None else torch.empty(M, dtype=torch.float64, device=dev)
+    ver = verified_out if verified_out is not None else torch.empty(M, dtype=torch.uint8, device=dev)
+    o = OptDesc(iters, lr_alpha, lr_mult, decay, b1, b2, adam_eps, int(use_graph))
+    _check(lib().gcp_optimize(net.h, _ptr(x0), float(eps), _ptr(Cspec), S, splits.h, cuts.h if cuts else None,
+                              _ptr(alpha) if alpha.numel() else None, _ptr(beta) if beta.numel() else None,
+                              _ptr(gamma) if gamma.numel() else None, _ptr(adam_state), C.byref(o), mode,
+                              _ptr(out), _ptr(ver), _stream()))
+    return out, ver
+
+
+def adam_state_size(M, n_I, K, N):
+    return 2 * M * (n_I + K + N)
+
+
+class Problem:
+    """A workloads.Problem uploaded to the current device."""
+
+    def __init__(self, prob, device="cuda"):
+        import torch
+        self.prob = prob
+        self.net = Net(prob.net, prob.lu)
+        self.cuts = Cuts(self.net, prob.cuts) if prob.cuts.n > 0 else None
+        self.splits = Splits(self.net, prob.splits)
+        self.x0 = torch.tensor(prob.x0, dtype=torch.float64, device=device)
+        self.C = torch.tensor(prob.C, dtype=torch.float64, device=device)
+        self.eps = prob.eps
+        self.S = prob.S
+        self.B = prob.B
+        self.M = prob.B * prob.S
+        self.n_I = self.net.n_I
+        self.K = prob.splits.K
+        self.N = prob.cuts.n
+
+
+def _bound_autograd():
+    import torch
+
+    class GCPBound(torch.autograd.Function):
+        """bound = GCPBound.apply(problem, alpha, beta, gamma, mode): the
+        forward runs gcp_bound with gradients requested; the backward scales
+        the adjoint's per-row gradients by grad_output."""
+
+        @staticmethod
+        def forward(ctx, P, alpha, beta, gamma, mode=GCP_MODE_FP32):
+            out, _, g = bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha.detach(), beta.detach(),
+                              gamma.detach(), mode=mode, grads=True)
+            ctx.save_for_backward(*g)
+            return out
+
+        @staticmethod
+        def backward(ctx, go):
+            ga, gb, gc = ctx.saved_tensors
+            w = go.to(torch.float32)[:, None]
+            return None, ga * w, gb * w, gc * w, None
+
+    return GCPBound
+
+
+_GCPBound = None
+
+
+def gcp_bound_autograd(P, alpha, beta, gamma, mode=GCP_MODE_FP32):
+    global _GCPBound
+    if _GCPBound is None:
+        _GCPBound = _bound_autograd()
+    return _GCPBound.apply(P, alpha, beta, gamma, mode)

@@ -1,0 +1,931 @@
+// Host runtime of the GCP-CROWN library: argument validation, packing of
+// networks / cuts / splits into device layouts, workspace management, and
+// the launch schedules of the bound pass (Theorem 3.1), its adjoint and the
+// projected Adam loop (Appendix C.1).  Everything below the C ABI runs on
+// the caller's stream; no host synchronisation inside gcp_bound/gcp_optimize
+// unless GCP_FLAG_VALIDATE is set.
+#include "../../include/gcp.h"
+#include "gcp_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace gcp;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Err {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& m) { throw Err{code, m}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? GCP_ENOMEM : GCP_EDEVICE,
+                            std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Owned device allocation (zero-filled at allocation).
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    hip_check(hipMalloc(&p, n), "hipMalloc");
+    bytes = n;
+    hip_check(hipMemset(p, 0, n), "hipMemset");
+  }
+  void ensure(size_t n) {
+    if (n > bytes) alloc(n);
+  }
+  template <class T> void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+struct EdgeH {
+  int src, dst, kind;
+  int kh = 0, kw = 0, stride = 1, pad = 0;
+  int d_src = 0, d_dst = 0;
+  ConvGeom cg{};
+  DBuf W32;      // adjoint Bt: dense [d_dst][ld_src]; conv: [co][ci][kh][kw]
+  DBuf W16;
+  DBuf WT32;     // bound Bt: dense [d_src][ld_dst]
+  DBuf WT16;
+  DBuf Wraw;     // dense [d_dst][d_src] unpadded fp32 (for c-hat and W x0)
+};
+
+struct NodeH {
+  int c, h, w, size, ld;
+  bool relu;
+  std::vector<int> in_edges;      // edges whose dst is this node
+  std::vector<int> consumers;     // edges whose src is this node
+  DBuf bias, l, u, inv_ul, cls, rank;
+  int n_unst = 0, rank0 = 0;
+  NodeDev dev() const {
+    return NodeDev{size, ld, bias.as<float>(), l.as<float>(), u.as<float>(), inv_ul.as<float>(),
+                   cls.as<int8_t>(), rank.as<int32_t>()};
+  }
+};
+
+}  // namespace
+
+struct gcp_net {
+  int device = 0;
+  int in_c, in_h, in_w, in_size, in_ld;
+  std::vector<NodeH> nodes;
+  std::vector<std::unique_ptr<EdgeH>> edges;
+  int64_t n_relu = 0;
+  int n_I = 0;
+  int out = 0;
+  // input consumers (edges with src = -1)
+  std::vector<int> in_consumers;
+  // ---- workspace (grown on demand)
+  struct WS {
+    int M = 0, S = 0, nnz = 0;
+    std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
+    DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in;
+    std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
+    int n_slots = 0;
+  } ws;
+  std::map<std::tuple<int, int, int, int>, int> tile_cache;   // (bf16, M, N, K) -> cfg
+};
+
+struct gcp_cuts {
+  int N = 0;
+  int nnz_e = 0;
+  DBuf row_ptr;     // [N + 1] over merged entries in cut-major order
+  DBuf d;           // fp64 [N]
+  struct Col {
+    DBuf col_ptr, cut, pos, cH, cG, cQ;
+    bool any = false;
+    CutCol dev() const {
+      if (!any) return CutCol{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+      return CutCol{col_ptr.as<int32_t>(), cut.as<int32_t>(), pos.as<int32_t>(), cH.as<float>(), cG.as<float>(),
+                    cQ.as<float>()};
+    }
+  };
+  std::vector<Col> cols;   // per node; index n_nodes is the network input
+  const gcp_net* net = nullptr;
+};
+
+struct gcp_splits {
+  int B = 0, K = 0;
+  DBuf mask;        // int8 [B][n_I]
+  const gcp_net* net = nullptr;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+float round_down_f(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+float round_up_f(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+void check_finite(const float* p, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) fail(GCP_ENONFINITE, std::string(what) + " has a non-finite value");
+}
+
+std::vector<uint16_t> to_bf16(const std::vector<float>& v) {
+  // round to nearest even
+  std::vector<uint16_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    uint32_t b;
+    std::memcpy(&b, &v[i], 4);
+    uint32_t lsb = (b >> 16) & 1u;
+    b += 0x7fffu + lsb;
+    o[i] = (uint16_t)(b >> 16);
+  }
+  return o;
+}
+
+int node_size_of(const gcp_net* net, int src) { return src < 0 ? net->in_size : net->nodes[src].size; }
+int node_ld_of(const gcp_net* net, int src) { return src < 0 ? net->in_ld : net->nodes[src].ld; }
+
+// ------------------------------------------------------------------ net create
+
+void build_net(const gcp_net_desc* d, gcp_net* net) {
+  if (!d || !d->nodes) fail(GCP_EINVAL, "null network description");
+  if (d->n_nodes < 2) fail(GCP_EINVAL, "a network needs at least one ReLU node and an output node");
+  if (d->in_c <= 0 || d->in_h <= 0 || d->in_w <= 0) fail(GCP_EINVAL, "bad input shape");
+  hip_check(hipGetDevice(&net->device), "hipGetDevice");
+  net->in_c = d->in_c; net->in_h = d->in_h; net->in_w = d->in_w;
+  net->in_size = d->in_c * d->in_h * d->in_w;
+  net->in_ld = round_up(net->in_size, 16);
+  net->nodes.resize(d->n_nodes);
+  net->out = d->n_nodes - 1;
+  int rank0 = 0;
+  for (int i = 0; i < d->n_nodes; ++i) {
+    const gcp_node_desc& nd = d->nodes[i];
+    NodeH& n = net->nodes[i];
+    if (nd.c <= 0 || nd.h <= 0 || nd.w <= 0) fail(GCP_EINVAL, "bad node shape at node " + std::to_string(i));
+    n.c = nd.c; n.h = nd.h; n.w = nd.w;
+    n.size = nd.c * nd.h * nd.w;
+    n.ld = round_up(n.size, 16);
+    n.relu = (i != net->out);
+    if (!nd.bias) fail(GCP_EINVAL, "null bias at node " + std::to_string(i));
+    check_finite(nd.bias, n.size, "bias");
+    std::vector<float> b(nd.bias, nd.bias + n.size);
+    n.bias.upload(b);
+    if (nd.n_edges <= 0 || !nd.edges) fail(GCP_EINVAL, "node " + std::to_string(i) + " has no input edge");
+    if (n.relu) {
+      if (!nd.lower || !nd.upper) fail(GCP_EINVAL, "missing root bounds at node " + std::to_string(i));
+      std::vector<float> l(n.size), u(n.size), iul(n.size, 0.f);
+      std::vector<int8_t> cls(n.size);
+      std::vector<int32_t> rank(n.size, -1);
+      n.rank0 = rank0;
+      for (int j = 0; j < n.size; ++j) {
+        double lo = nd.lower[j], hi = nd.upper[j];
+        if (!std::isfinite(lo) || !std::isfinite(hi)) fail(GCP_ENONFINITE, "non-finite root bound");
+        if (lo > hi) fail(GCP_EINVAL, "root bound l > u at node " + std::to_string(i));
+        l[j] = round_down_f(lo);
+        u[j] = round_up_f(hi);
+        if (lo >= 0) cls[j] = ACTIVE;
+        else if (hi <= 0) cls[j] = INACTIVE;
+        else {
+          cls[j] = UNSTABLE;
+          rank[j] = rank0++;
+          iul[j] = (float)(1.0 / ((double)u[j] - (double)l[j]));
+        }
+      }
+      n.n_unst = rank0 - n.rank0;
+      n.l.upload(l); n.u.upload(u); n.inv_ul.upload(iul); n.cls.upload(cls); n.rank.upload(rank);
+      net->n_relu += n.size;
+    }
+    for (int e = 0; e < nd.n_edges; ++e) {
+      const gcp_edge_desc& ed = nd.edges[e];
+      if (ed.src < -1 || ed.src >= i) fail(GCP_EINVAL, "edge source must be an earlier node or the input");
+      if (ed.src >= 0 && !net->nodes[ed.src].relu) fail(GCP_EINVAL, "edge from the output node");
+      auto E = std::make_unique<EdgeH>();
+      E->src = ed.src; E->dst = i; E->kind = ed.kind;
+      E->d_src = node_size_of(net, ed.src);
+      E->d_dst = n.size;
+      int ld_src = node_ld_of(net, ed.src);
+      if (ed.kind == GCP_EDGE_DENSE) {
+        if (!ed.W) fail(GCP_EINVAL, "null dense weight");
+        size_t cnt = (size_t)E->d_dst * E->d_src;
+        check_finite(ed.W, cnt, "weight");
+        std::vector<float> raw(ed.W, ed.W + cnt);
+        std::vector<float> fw((size_t)E->d_dst * ld_src, 0.f), ft((size_t)E->d_src * n.ld, 0.f);
+        for (int o = 0; o < E->d_dst; ++o)
+          for (int k = 0; k < E->d_src; ++k) {
+            float w = raw[(size_t)o * E->d_src + k];
+            fw[(size_t)o * ld_src + k] = w;
+            ft[(size_t)k * n.ld + o] = w;
+          }
+        E->Wraw.upload(raw);
+        E->W32.upload(fw); E->W16.upload(to_bf16(fw));
+        E->WT32.upload(ft); E->WT16.upload(to_bf16(ft));
+      } else if (ed.kind == GCP_EDGE_CONV) {
+        if (!ed.W) fail(GCP_EINVAL, "null conv weight");
+        int ci, hi, wi;
+        if (ed.src < 0) { ci = net->in_c; hi = net->in_h; wi = net->in_w; }
+        else { ci = net->nodes[ed.src].c; hi = net->nodes[ed.src].h; wi = net->nodes[ed.src].w; }
+        if (ed.kh <= 0 || ed.kw <= 0 || ed.stride <= 0 || ed.pad < 0) fail(GCP_EINVAL, "bad conv geometry");
+        int ho = (hi + 2 * ed.pad - ed.kh) / ed.stride + 1;
+        int wo = (wi + 2 * ed.pad - ed.kw) / ed.stride + 1;
+        if (ho != n.h || wo != n.w) fail(GCP_EINVAL, "conv output shape does not match node " + std::to_string(i));
+        E->kh = ed.kh; E->kw = ed.kw; E->stride = ed.stride; E->pad = ed.pad;
+        E->cg = ConvGeom{ci, hi, wi, n.c, ho, wo, ed.kh, ed.kw, ed.stride, ed.pad};
+        size_t cnt = (size_t)n.c * ci * ed.kh * ed.kw;
+        check_finite(ed.W, cnt, "conv weight");
+        std::vector<float> raw(ed.W, ed.W + cnt);
+        E->W32.upload(raw);
+        E->Wraw.upload(raw);
+      } else if (ed.kind == GCP_EDGE_IDENTITY) {
+        if (E->d_src != E->d_dst) fail(GCP_EINVAL, "identity edge between different sizes");
+      } else {
+        fail(GCP_EINVAL, "unknown edge kind");
+      }
+      int eid = (int)net->edges.size();
+      n.in_edges.push_back(eid);
+      if (ed.src >= 0) net->nodes[ed.src].consumers.push_back(eid);
+      else net->in_consumers.push_back(eid);
+      net->edges.push_back(std::move(E));
+    }
+  }
+  net->n_I = rank0;
+  for (int i = 0; i < net->out; ++i)
+    if (net->nodes[i].consumers.empty()) fail(GCP_EUNSUPPORTED, "ReLU node without consumers");
+  if (net->in_consumers.empty()) fail(GCP_EINVAL, "network input is unused");
+  for (int eid : net->nodes[net->out].in_edges) {
+    const EdgeH& E = *net->edges[eid];
+    if (E.kind == GCP_EDGE_CONV) fail(GCP_EUNSUPPORTED, "conv edge into the output node");
+    if (E.src < 0) fail(GCP_EUNSUPPORTED, "output node fed directly by the input");
+  }
+  for (int i = 0; i < net->out; ++i) {
+    const NodeH& n = net->nodes[i];
+    int outs = 0;
+    for (int eid : n.consumers) outs += (net->edges[eid]->dst == net->out);
+    if (outs && n.consumers.size() > 1) fail(GCP_EUNSUPPORTED, "node feeding the output has other consumers");
+  }
+}
+
+// ------------------------------------------------------------------ tile choice
+
+int pick_cfg(gcp_net* net, int bf16, int M, int N, int K) {
+  auto key = std::make_tuple(bf16, M, N, K);
+  auto it = net->tile_cache.find(key);
+  if (it != net->tile_cache.end()) return it->second;
+  // Heuristic default: the largest tile that still yields >= 2 workgroups per CU.
+  static const int order[] = {3, 1, 2, 0, 4};
+  int best = 4;
+  for (int c : order) {
+    int bm, bn;
+    gemm_config_tile(c, &bm, &bn);
+    long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    if (tiles >= 512) { best = c; break; }
+  }
+  net->tile_cache[key] = best;
+  return best;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+#define GCP_TRY try {
+#define GCP_CATCH                                          \
+  }                                                        \
+  catch (const Err& e) {                                   \
+    g_err = e.msg;                                         \
+    return e.code;                                         \
+  }                                                        \
+  catch (const std::bad_alloc&) {                          \
+    g_err = "host allocation failed";                      \
+    return GCP_ENOMEM;                                     \
+  }                                                        \
+  catch (...) {                                            \
+    g_err = "unexpected internal error";                   \
+    return GCP_EDEVICE;                                    \
+  }
+
+extern "C" const char* gcp_last_error(void) { return g_err.c_str(); }
+extern "C" const char* gcp_version(void) { return "gcp-mi355x 0.1 (gfx950)"; }
+
+extern "C" int gcp_net_create(const gcp_net_desc* desc, gcp_net** out) {
+  GCP_TRY
+  if (!out) fail(GCP_EINVAL, "null output handle");
+  auto net = std::make_unique<gcp_net>();
+  build_net(desc, net.get());
+  *out = net.release();
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_net_destroy(gcp_net* net) {
+  delete net;
+  return GCP_OK;
+}
+
+extern "C" int gcp_net_get_info(const gcp_net* net, gcp_net_info* info) {
+  if (!net || !info) { g_err = "null argument"; return GCP_EINVAL; }
+  info->n_nodes = (int32_t)net->nodes.size();
+  info->in_size = net->in_size;
+  info->out_size = net->nodes[net->out].size;
+  info->n_relu = net->n_relu;
+  info->n_unstable = net->n_I;
+  return GCP_OK;
+}
+
+extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, const int32_t* cut,
+                               const int32_t* node, const int32_t* neuron, const int8_t* kind,
+                               const double* coef, const double* d, gcp_cuts** out) {
+  GCP_TRY
+  if (!net || !out) fail(GCP_EINVAL, "null argument");
+  if (n_cuts < 0 || nnz < 0) fail(GCP_EINVAL, "negative size");
+  if (nnz > 0 && (!cut || !node || !neuron || !kind || !coef)) fail(GCP_EINVAL, "null cut entry array");
+  if (n_cuts > 0 && !d) fail(GCP_EINVAL, "null cut offsets");
+  const int n_nodes = (int)net->nodes.size();
+  // merge (cut, node, neuron) -> (H, G, Q)
+  std::map<std::tuple<int, int, int>, std::array<double, 3>> m;
+  for (int64_t e = 0; e < nnz; ++e) {
+    int k = cut[e], nd = node[e], j = neuron[e], kd = kind[e];
+    if (k < 0 || k >= n_cuts) fail(GCP_EINVAL, "cut index out of range");
+    if (nd < -1 || nd >= n_nodes || (nd >= 0 && !net->nodes[nd].relu))
+      fail(GCP_EINVAL, "cut entry on a node that is not a ReLU node or the input");
+    if (kd < 0 || kd > 2) fail(GCP_EINVAL, "bad cut coefficient kind");
+    if (nd < 0 && kd != GCP_CUT_G) fail(GCP_EINVAL, "input-variable cut entries must be of kind G");
+    int sz = nd < 0 ? net->in_size : net->nodes[nd].size;
+    if (j < 0 || j >= sz) fail(GCP_EINVAL, "cut neuron index out of range");
+    if (!std::isfinite(coef[e])) fail(GCP_ENONFINITE, "non-finite cut coefficient");
+    auto& a = m[std::make_tuple(k, nd, j)];
+    a[kd] += coef[e];
+  }
+  for (int k = 0; k < n_cuts; ++k)
+    if (!std::isfinite(d[k])) fail(GCP_ENONFINITE, "non-finite cut offset");
+  auto C = std::make_unique<gcp_cuts>();
+  C->N = n_cuts;
+  C->net = net;
+  C->nnz_e = (int)m.size();
+  std::vector<int32_t> row_ptr(n_cuts + 1, 0);
+  struct Ent { int k, nd, j, pos; float h, g, q; };
+  std::vector<Ent> ents;
+  ents.reserve(m.size());
+  int pos = 0;
+  for (auto& kv : m) {   // std::map order = (cut, node, neuron): cut-major
+    int k = std::get<0>(kv.first);
+    row_ptr[k + 1]++;
+    ents.push_back(Ent{k, std::get<1>(kv.first), std::get<2>(kv.first), pos++, (float)kv.second[0],
+                       (float)kv.second[1], (float)kv.second[2]});
+  }
+  for (int k = 0; k < n_cuts; ++k) row_ptr[k + 1] += row_ptr[k];
+  C->row_ptr.upload(row_ptr);
+  std::vector<double> dv(d ? d : (const double*)nullptr, d ? d + n_cuts : (const double*)nullptr);
+  C->d.upload(dv);
+  C->cols.resize(n_nodes + 1);
+  for (int nd = -1; nd < n_nodes; ++nd) {
+    if (nd >= 0 && !net->nodes[nd].relu) continue;
+    int sz = nd < 0 ? net->in_size : net->nodes[nd].size;
+    std::vector<Ent> mine;
+    for (auto& e : ents)
+      if (e.nd == nd) mine.push_back(e);
+    auto& col = C->cols[nd < 0 ? n_nodes : nd];
+    if (mine.empty()) continue;
+    std::stable_sort(mine.begin(), mine.end(), [](const Ent& a, const Ent& b) { return a.j < b.j; });
+    std::vector<int32_t> cp(sz + 1, 0), ck, cpos;
+    std::vector<float> ch, cg, cq;
+    for (auto& e : mine) {
+      cp[e.j + 1]++;
+      ck.push_back(e.k); cpos.push_back(e.pos);
+      ch.push_back(e.h); cg.push_back(e.g); cq.push_back(e.q);
+    }
+    for (int j = 0; j < sz; ++j) cp[j + 1] += cp[j];
+    col.col_ptr.upload(cp); col.cut.upload(ck); col.pos.upload(cpos);
+    col.cH.upload(ch); col.cG.upload(cg); col.cQ.upload(cq);
+    col.any = true;
+  }
+  *out = C.release();
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_cuts_destroy(gcp_cuts* c) {
+  delete c;
+  return GCP_OK;
+}
+
+extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const int32_t* node,
+                                 const int32_t* neuron, const int8_t* sign, gcp_splits** out) {
+  GCP_TRY
+  if (!net || !out) fail(GCP_EINVAL, "null argument");
+  if (B <= 0 || K < 0 || K > 127) fail(GCP_EINVAL, "need B >= 1 and 0 <= K <= 127");
+  if (K > 0 && (!node || !neuron || !sign)) fail(GCP_EINVAL, "null split array");
+  std::vector<int8_t> mask((size_t)B * net->n_I, 0);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < K; ++k) {
+      size_t i = (size_t)b * K + k;
+      int nd = node[i];
+      if (nd < 0) continue;
+      if (nd >= (int)net->nodes.size() || !net->nodes[nd].relu) fail(GCP_EINVAL, "split on a non-ReLU node");
+      const NodeH& n = net->nodes[nd];
+      int j = neuron[i];
+      if (j < 0 || j >= n.size) fail(GCP_EINVAL, "split neuron out of range");
+      if (sign[i] != 1 && sign[i] != -1) fail(GCP_EINVAL, "split sign must be +1 or -1");
+      // rank lookup on the host copy of the class vector
+      std::vector<int32_t> rk(n.size);
+      hip_check(hipMemcpy(rk.data(), n.rank.p, n.size * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+      if (rk[j] < 0) fail(GCP_EINVAL, "split neuron is not root-unstable");
+      int8_t& mm = mask[(size_t)b * net->n_I + rk[j]];
+      if (mm != 0) fail(GCP_EINVAL, "neuron split twice in one domain");
+      mm = (int8_t)(sign[i] > 0 ? (k + 1) : -(k + 1));
+    }
+  auto S = std::make_unique<gcp_splits>();
+  S->B = B; S->K = K; S->net = net;
+  S->mask.upload(mask);
+  *out = S.release();
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_splits_destroy(gcp_splits* s) {
+  delete s;
+  return GCP_OK;
+}
+
+// ====================================================================== passes
+
+namespace {
+
+struct Call {
+  gcp_net* net;
+  const gcp_cuts* cuts;
+  const gcp_splits* splits;
+  const double* x0;
+  double eps;
+  const double* C;
+  int S, M, B;
+  RowParams rp;
+  hipStream_t st;
+  int nnz;
+};
+
+void ensure_ws(Call& c) {
+  gcp_net* net = c.net;
+  auto& ws = net->ws;
+  const int nn = (int)net->nodes.size();
+  bool grow = c.M > ws.M || c.nnz > ws.nnz || c.S > ws.S || ws.lam.empty();
+  if (!grow) return;
+  int M = std::max(c.M, ws.M), S = std::max(c.S, ws.S), nnz = std::max(c.nnz, ws.nnz);
+  ws.lam.clear(); ws.ahat.clear(); ws.dahat.clear(); ws.acc.clear(); ws.addv.clear();
+  for (int i = 0; i < nn; ++i) {
+    const NodeH& n = net->nodes[i];
+    size_t elems = n.relu ? (size_t)M * n.ld : 0;
+    auto mk = [&](size_t bytes) { auto b = std::make_unique<DBuf>(); b->alloc(bytes); return b; };
+    ws.lam.push_back(mk(elems * 4));
+    ws.ahat.push_back(mk(elems * 4));
+    ws.dahat.push_back(mk(elems * 4));
+    bool multi = n.relu && (n.consumers.size() > 1 || n.in_edges.size() > 1);
+    ws.acc.push_back(mk(multi ? elems * 4 : 0));
+    ws.addv.push_back(mk(n.relu ? (size_t)n.ld * 4 : 0));
+  }
+  ws.sign.alloc((size_t)M * net->in_ld);
+  ws.contrib.alloc((size_t)M * std::max(nnz, 1) * 4);
+  ws.chat_off.assign(nn, -1);
+  size_t chat_floats = 0;
+  for (int eid : net->nodes[net->out].in_edges) {
+    int p = net->edges[eid]->src;
+    ws.chat_off[p] = (int)chat_floats;
+    chat_floats += (size_t)S * net->nodes[p].ld;
+  }
+  ws.chat.alloc(std::max<size_t>(chat_floats, 1) * 4);
+  ws.cb.alloc((size_t)S * 8);
+  ws.consts.alloc(16);
+  ws.step.alloc(16);
+  ws.flags.alloc(16);
+  ws.acc_in.alloc((size_t)M * net->in_ld * 4);
+  ws.M = M; ws.S = S; ws.nnz = nnz;
+  ws.n_slots = 0;
+  ws.partial.release();
+}
+
+CutCol cut_col(const Call& c, int node) {
+  if (!c.cuts) return CutCol{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int idx = node < 0 ? (int)c.net->nodes.size() : node;
+  return c.cuts->cols[idx].dev();
+}
+
+const void* wt_bound(const EdgeH& E, int bf16) { return bf16 ? E.WT16.p : E.WT32.p; }
+const void* w_adj(const EdgeH& E, int bf16) { return bf16 ? E.W16.p : E.W32.p; }
+
+// ---------------------------------------------------------------- bound pass
+// Processes nodes from the output backwards.  For each target p the pushes
+// from its consumers are accumulated into acc[p] except the last one, which
+// runs fused with p's relaxation (or the concretisation for the input).
+struct BoundPass {
+  Call& c;
+  int bf16;
+  bool keep_ahat;     // adjoint will follow
+  bool want_contrib;  // gradient pieces for input cuts
+  bool dry;           // count partial slots only
+  int slot = 0;
+  std::vector<int> pushes_left;   // per node (index n_nodes: input)
+
+  BoundPass(Call& cc, int b, bool k, bool wc, bool d) : c(cc), bf16(b), keep_ahat(k), want_contrib(wc), dry(d) {}
+
+  int esz() const { return bf16 ? 2 : 4; }
+
+  BoundEpiArgs bound_args(int p, bool has_acc) {
+    auto& ws = c.net->ws;
+    BoundEpiArgs a{};
+    a.nd = c.net->nodes[p].dev();
+    a.cc = cut_col(c, p);
+    a.rp = c.rp;
+    a.acc_in = has_acc ? ws.acc[p]->as<float>() : nullptr;
+    a.lam_out = ws.lam[p]->p;
+    a.ahat_out = keep_ahat ? ws.ahat[p]->as<float>() : nullptr;
+    return a;
+  }
+
+  void check(hipError_t e) { hip_check(e, "kernel launch (bound pass)"); }
+
+  void run() {
+    gcp_net* net = c.net;
+    const int nn = (int)net->nodes.size();
+    auto& ws = net->ws;
+    pushes_left.assign(nn + 1, 0);
+    for (int i = 0; i < nn; ++i) pushes_left[i] = (int)net->nodes[i].consumers.size();
+    pushes_left[nn] = (int)net->in_consumers.size();
+    // output node: c-hat = C W (per spec row), constant C b_out
+    const NodeH& on = net->nodes[net->out];
+    if (!dry) {
+      check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
+      for (int eid : on.in_edges) {
+        const EdgeH& E = *net->edges[eid];
+        float* ch = ws.chat.as<float>() + ws.chat_off[E.src];
+        check(launch_chat(c.C, c.S, on.size, E.Wraw.as<float>(), E.d_src,
+                          E.kind == GCP_EDGE_IDENTITY ? 2 : 0, ch, net->nodes[E.src].ld, c.st));
+      }
+    }
+    for (int eid : on.in_edges) {
+      const EdgeH& E = *net->edges[eid];
+      int p = E.src;
+      // the output is p's only consumer (checked at creation): fused relaxation
+      pushes_left[p]--;
+      BoundEpiArgs a = bound_args(p, false);
+      int nslot = (net->nodes[p].size + 255) / 256;
+      if (!dry)
+        check(launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], a, ws.partial.as<double>(),
+                                       ws.n_slots, slot, c.st));
+      slot += nslot;
+    }
+    for (int i = net->out - 1; i >= 0; --i) {
+      const NodeH& n = net->nodes[i];
+      // edges ordered: identity first (they can only store), then the rest
+      std::vector<int> order;
+      for (int eid : n.in_edges)
+        if (net->edges[eid]->kind == GCP_EDGE_IDENTITY) order.push_back(eid);
+      for (int eid : n.in_edges)
+        if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
+      for (int eid : order) push(eid);
+    }
+  }
+
+  // Lambda^(dst) pushed through edge E into target src.
+  void push(int eid) {
+    gcp_net* net = c.net;
+    auto& ws = net->ws;
+    const EdgeH& E = *net->edges[eid];
+    const int nn = (int)net->nodes.size();
+    const int p = E.src;
+    const int pidx = p < 0 ? nn : p;
+    const bool last = (--pushes_left[pidx] == 0);
+    const int total = p < 0 ? (int)net->in_consumers.size() : (int)net->nodes[p].consumers.size();
+    const bool has_acc = total > 1;        // earlier pushes went to acc[p]
+    const bool first = !has_acc || (pushes_left[pidx] == total - 1);
+    const NodeH& dn = net->nodes[E.dst];
+    const int d_src = E.d_src;
+    const int ld_src = node_ld_of(net, p);
+    float* accbuf = p < 0 ? ws.acc_in.as<float>() : ws.acc[p]->as<float>();
+
+    if (E.kind == GCP_EDGE_DENSE) {
+      GemmArgs g{};
+      g.M = c.M; g.N = d_src; g.K = dn.size;
+      g.A = ws.lam[E.dst]->p; g.lda = dn.ld;
+      g.Bt = wt_bound(E, bf16); g.ldb = dn.ld;
+      g.a_is_sign = 0;
+      int cfg = pick_cfg(net, bf16, g.M, g.N, g.K);
+      int bm, bn;
+      gemm_config_tile(cfg, &bm, &bn);
+      if (!last) {
+        StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
+        g.partial = nullptr;
+        if (!dry) check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+        return;
+      }
+      int nslot = (d_src + bn - 1) / bn;
+      g.partial = ws.partial.as<double>(); g.n_slots = ws.n_slots; g.slot0 = slot;
+      if (p >= 0) {
+        BoundEpiArgs a = bound_args(p, has_acc);
+        if (!dry) check(launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st));
+      } else {
+        if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
+        ConcEpiArgs a{};
+        a.size = net->in_size; a.ld = net->in_ld; a.x0 = c.x0; a.eps = c.eps;
+        a.cc = cut_col(c, -1); a.rp = c.rp;
+        a.sign_out = keep_ahat ? ws.sign.as<int8_t>() : nullptr;
+        a.contrib = want_contrib ? ws.contrib.as<float>() : nullptr;
+        a.nnz_e = c.nnz;
+        if (!dry) check(launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st));
+      }
+      slot += nslot;
+      return;
+    }
+    fail(GCP_EUNSUPPORTED, "edge kind not supported yet in the bound pass");
+  }
+};
+
+// ---------------------------------------------------------------- adjoint
+struct AdjPass {
+  Call& c;
+  int bf16;
+  AdamArgs adam;
+  float* d_alpha; float* d_beta;
+  float* alpha_rw; float* beta_rw;
+  float *ma, *va, *mb, *vb;
+
+  void check(hipError_t e) { hip_check(e, "kernel launch (adjoint)"); }
+
+  void run() {
+    gcp_net* net = c.net;
+    auto& ws = net->ws;
+    // add vectors: bias (+ A x0 for edges from the input)
+    for (int i = 0; i < net->out; ++i) {
+      const NodeH& n = net->nodes[i];
+      bool seeded = false;
+      for (int eid : n.in_edges) {
+        const EdgeH& E = *net->edges[eid];
+        if (E.src >= 0) continue;
+        int kind = E.kind == GCP_EDGE_DENSE ? 0 : (E.kind == GCP_EDGE_CONV ? 1 : 2);
+        check(launch_wx0(&E.cg, kind, E.Wraw.as<float>(), n.size, net->in_size, c.x0,
+                         seeded ? nullptr : n.bias.as<float>(), ws.addv[i]->as<float>(), c.st));
+        seeded = true;
+      }
+      if (!seeded)
+        hip_check(hipMemcpyAsync(ws.addv[i]->p, n.bias.p, n.size * 4, hipMemcpyDeviceToDevice, c.st),
+                  "hipMemcpyAsync");
+    }
+    for (int i = 0; i < net->out; ++i) node(i);
+  }
+
+  void node(int i) {
+    gcp_net* net = c.net;
+    auto& ws = net->ws;
+    const NodeH& n = net->nodes[i];
+    std::vector<int> order;
+    for (int eid : n.in_edges)
+      if (net->edges[eid]->kind == GCP_EDGE_IDENTITY) order.push_back(eid);
+    for (int eid : n.in_edges)
+      if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
+    const bool has_acc = order.size() > 1;
+    float* accbuf = has_acc ? ws.acc[i]->as<float>() : nullptr;
+    for (size_t q = 0; q < order.size(); ++q) {
+      const EdgeH& E = *net->edges[order[q]];
+      const bool last = q + 1 == order.size();
+      const bool first = q == 0;
+      const int p = E.src;
+      const bool sign = p < 0;
+      const float scale = sign ? (float)(-c.eps) : 1.f;
+      const void* A = sign ? ws.sign.p : ws.dahat[p]->p;
+      const int lda = sign ? net->in_ld : net->nodes[p].ld;
+      if (E.kind == GCP_EDGE_DENSE) {
+        GemmArgs g{};
+        g.M = c.M; g.N = n.size; g.K = E.d_src;
+        g.A = A; g.lda = lda;
+        g.Bt = w_adj(E, bf16); g.ldb = lda;
+        g.a_is_sign = sign;
+        int cfg = pick_cfg(net, bf16, g.M, g.N, g.K);
+        if (!last) {
+          StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
+          check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+        } else {
+          AdjEpiArgs a = epi(i, has_acc ? accbuf : nullptr, scale);
+          check(launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st));
+        }
+      } else {
+        fail(GCP_EUNSUPPORTED, "edge kind not supported yet in the adjoint");
+      }
+    }
+  }
+
+  AdjEpiArgs epi(int i, float* acc_in, float scale) {
+    gcp_net* net = c.net;
+    auto& ws = net->ws;
+    const NodeH& n = net->nodes[i];
+    AdjEpiArgs a{};
+    a.nd = n.dev();
+    a.cc = cut_col(c, i);
+    a.rp = c.rp;
+    a.acc_in = acc_in;
+    a.gemm_scale = scale;
+    a.add_vec = ws.addv[i]->as<float>();
+    a.ahat = ws.ahat[i]->as<float>();
+    a.dahat_out = ws.dahat[i]->p;
+    a.contrib = c.nnz ? ws.contrib.as<float>() : nullptr;
+    a.nnz_e = c.nnz;
+    a.d_alpha = d_alpha; a.d_beta = d_beta;
+    a.m_alpha = ma; a.v_alpha = va; a.m_beta = mb; a.v_beta = vb;
+    a.alpha_rw = alpha_rw; a.beta_rw = beta_rw;
+    a.adam = adam;
+    return a;
+  }
+};
+
+void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                  const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                  const float* gamma, void* stream) {
+  if (!net) fail(GCP_EINVAL, "null net");
+  if (!splits) fail(GCP_EINVAL, "null splits (use a handle with K = 0 for no splits)");
+  if (splits->net != net) fail(GCP_EINVAL, "splits were created for another net");
+  if (cuts && cuts->net != net) fail(GCP_EINVAL, "cuts were created for another net");
+  if (!x0 || !C) fail(GCP_EINVAL, "null x0 or C");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) fail(GCP_ERANGE, "eps must be finite and >= 0");
+  if (S <= 0) fail(GCP_EINVAL, "S must be >= 1");
+  int N = cuts ? cuts->N : 0;
+  if (net->n_I > 0 && !alpha) fail(GCP_EINVAL, "null alpha");
+  if (splits->K > 0 && !beta) fail(GCP_EINVAL, "null beta");
+  if (N > 0 && !gamma) fail(GCP_EINVAL, "null gamma");
+  int dev;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != net->device) fail(GCP_EINVAL, "current device differs from the net's device");
+  c.net = net; c.cuts = (cuts && cuts->N > 0) ? cuts : nullptr; c.splits = splits;
+  c.x0 = x0; c.eps = eps; c.C = C; c.S = S; c.B = splits->B;
+  long long M = (long long)splits->B * S;
+  if (M > (1LL << 30)) fail(GCP_EINVAL, "too many rows");
+  c.M = (int)M;
+  c.nnz = c.cuts ? c.cuts->nnz_e : 0;
+  c.rp = RowParams{c.M, S, alpha, net->n_I, beta, splits->K, gamma, N,
+                   splits->K > 0 ? splits->mask.as<int8_t>() : nullptr};
+  c.st = (hipStream_t)stream;
+  ensure_ws(c);
+}
+
+void size_partials(Call& c, int bf16, bool keep, bool contrib) {
+  BoundPass dry(c, bf16, keep, contrib, true);
+  dry.run();
+  auto& ws = c.net->ws;
+  if (dry.slot > ws.n_slots || !ws.partial.p) {
+    ws.partial.alloc((size_t)ws.M * std::max(dry.slot, 1) * 8);
+    ws.n_slots = dry.slot;
+  }
+  // slot count must match exactly for the row reduction
+  if (dry.slot != ws.n_slots) {
+    ws.partial.alloc((size_t)ws.M * std::max(dry.slot, 1) * 8);
+    ws.n_slots = dry.slot;
+  }
+}
+
+void validate_params(Call& c, const float* alpha, const float* beta, const float* gamma) {
+  auto& ws = c.net->ws;
+  hip_check(hipMemsetAsync(ws.flags.p, 0, 16, c.st), "hipMemsetAsync");
+  int* f = ws.flags.as<int>();
+  hip_check(launch_validate(alpha, (int64_t)c.M * c.rp.n_I, 0.f, 1.f, f, c.st), "validate");
+  hip_check(launch_validate(beta, (int64_t)c.M * c.rp.K, 0.f, INFINITY, f, c.st), "validate");
+  hip_check(launch_validate(gamma, (int64_t)c.M * c.rp.N, 0.f, INFINITY, f, c.st), "validate");
+  int h = 0;
+  hip_check(hipMemcpyAsync(&h, f, 4, hipMemcpyDeviceToHost, c.st), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(c.st), "hipStreamSynchronize");
+  if (h & 1) fail(GCP_ENONFINITE, "non-finite alpha, beta or gamma");
+  if (h & 2) fail(GCP_ERANGE, "alpha outside [0,1] or a negative multiplier");
+}
+
+void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, uint8_t* verified) {
+  size_partials(c, bf16, keep_ahat, contrib);
+  BoundPass bp(c, bf16, keep_ahat, contrib, false);
+  bp.run();
+  auto& ws = c.net->ws;
+  hip_check(launch_reduce_rows(c.M, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(), c.rp.gamma,
+                               c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound, verified, c.st),
+            "reduce");
+}
+
+}  // namespace
+
+extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
+                         const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                         const float* gamma, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
+                         float* d_beta, float* d_gamma, void* stream) {
+  GCP_TRY
+  gcp_net* net = const_cast<gcp_net*>(net_c);
+  Call c{};
+  prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
+  const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
+  if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
+  if (!bound) fail(GCP_EINVAL, "null bound output");
+  const bool grads = d_alpha || d_beta || d_gamma;
+  if (grads) {
+    if ((net->n_I > 0 && !d_alpha) || (splits->K > 0 && !d_beta) || (c.rp.N > 0 && !d_gamma))
+      fail(GCP_EINVAL, "pass all gradient outputs or none");
+  }
+  if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
+  bound_pass(c, bf16, grads, grads && c.nnz > 0, bound, verified);
+  if (grads) {
+    if (splits->K > 0) hip_check(launch_fill_f32(d_beta, (int64_t)c.M * splits->K, 0.f, c.st), "fill");
+    AdjPass ap{c, bf16, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, d_alpha, d_beta, nullptr, nullptr,
+               nullptr, nullptr, nullptr, nullptr};
+    ap.run();
+    if (c.rp.N > 0)
+      hip_check(launch_gamma_update(c.M, c.rp.N, c.cuts->row_ptr.as<int32_t>(), net->ws.contrib.as<float>(), c.nnz,
+                                    c.cuts->d.as<double>(), nullptr, d_gamma, nullptr, nullptr,
+                                    AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st),
+                "gamma gradient");
+  }
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
+                            const gcp_splits* splits, const gcp_cuts* cuts, float* alpha, float* beta,
+                            float* gamma, float* adam_state, const gcp_opt* opt, int32_t mode, double* bound,
+                            uint8_t* verified, void* stream) {
+  GCP_TRY
+  gcp_net* net = const_cast<gcp_net*>(net_c);
+  Call c{};
+  prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
+  const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
+  if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
+  if (!opt || opt->iters < 0) fail(GCP_EINVAL, "bad optimiser settings");
+  if (!adam_state) fail(GCP_EINVAL, "null adam_state");
+  if (!bound) fail(GCP_EINVAL, "null bound output");
+  if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
+  auto& ws = net->ws;
+  const size_t M = c.M, nI = c.rp.n_I, K = c.rp.K, N = c.rp.N;
+  float* ma = adam_state;
+  float* va = ma + M * nI;
+  float* mb = va + M * nI;
+  float* vb = mb + M * K;
+  float* mg = vb + M * K;
+  float* vg = mg + M * N;
+  AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.consts.as<float>()};
+  hip_check(launch_adam_prepare(ws.step.as<int>(), 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam reset");
+  size_partials(c, bf16, true, c.nnz > 0);
+  for (int it = 0; it < opt->iters; ++it) {
+    hip_check(launch_adam_prepare(ws.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
+                                  opt->adam_b2, ws.consts.as<float>(), c.st),
+              "adam prepare");
+    BoundPass bp(c, bf16, true, c.nnz > 0, false);
+    bp.run();
+    AdjPass ap{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+    ap.run();
+    if (N > 0)
+      hip_check(launch_gamma_update(c.M, (int)N, c.cuts->row_ptr.as<int32_t>(), ws.contrib.as<float>(), c.nnz,
+                                    c.cuts->d.as<double>(), gamma, nullptr, mg, vg, adam, c.st),
+                "gamma update");
+  }
+  // certifying pass: fp32 GEMMs, fp64 reductions, margin check
+  bound_pass(c, 0, false, false, bound, verified);
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}

@@ -1,0 +1,145 @@
+// Internal declarations shared by the host runtime (gcp_api.cpp) and the
+// gfx950 kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcp {
+
+typedef __bf16 bf16;
+
+enum Cls : int8_t { INACTIVE = 0, ACTIVE = 1, UNSTABLE = 2 };
+
+// Per-node constant data on the device.
+struct NodeDev {
+  int size;          // neurons
+  int ld;            // row pitch of per-row activation buffers (multiple of 16)
+  const float* bias;     // [size]
+  const float* l;        // root lower bound (fp32, outward rounded)
+  const float* u;        // root upper bound
+  const float* inv_ul;   // 1 / (u - l) for unstable neurons, else 0
+  const int8_t* cls;     // root class
+  const int32_t* rank;   // column in an alpha row, or -1
+};
+
+// Cut entries of one node in column (neuron) order: entries
+// col_ptr[j] .. col_ptr[j+1]-1 touch neuron j.  Each merged entry carries the
+// three coefficients of one (cut, node, neuron) and its position in the
+// cut-major order used by the gamma gradient.
+struct CutCol {
+  const int32_t* col_ptr;  // [size + 1], null if the node has no entries
+  const int32_t* cut;      // cut index
+  const int32_t* pos;      // position in cut-major order
+  const float* cH;
+  const float* cG;
+  const float* cQ;
+};
+
+// Per-row parameters of one call.
+struct RowParams {
+  int M, S;
+  const float* alpha; int n_I;      // [M][n_I]
+  const float* beta;  int K;        // [M][K]
+  const float* gamma; int N;        // [M][N]
+  const int8_t* mask;               // [B][n_I]: 0, +(slot+1) x>=0, -(slot+1) x<=0
+};
+
+struct AdamArgs {
+  int enabled;           // 0: write raw gradients instead of updating
+  float b1, b2, eps;
+  const float* consts;   // device: {lr_alpha decay^t, lr_mult decay^t, 1-b1^(t+1), 1-b2^(t+1)}
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+
+// Epilogue selection for the tile GEMM.
+enum EpiKind { EPI_STORE = 0, EPI_BOUND = 1, EPI_CONC = 2, EPI_ADJ = 3 };
+
+struct BoundEpiArgs {       // Theorem 3.1 relaxation of one ReLU node
+  NodeDev nd; CutCol cc; RowParams rp;
+  const float* acc_in;      // optional extra pre-activation [M][ld] (fp32)
+  void* lam_out;            // [M][ld] in the GEMM operand type
+  float* ahat_out;          // optional [M][ld] fp32 (kept for the adjoint)
+};
+struct ConcEpiArgs {        // concretisation over the input box
+  int size, ld;
+  const double* x0; double eps;
+  CutCol cc; RowParams rp;  // input-variable cuts (G on x)
+  int8_t* sign_out;         // optional [M][ld] sign of v
+  float* contrib;           // optional [M][nnz_e] gamma-gradient pieces
+  int nnz_e;
+};
+struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
+  NodeDev nd; CutCol cc; RowParams rp;
+  const float* acc_in;      // optional extra dLambda [M][ld]
+  float gemm_scale;         // multiplies the GEMM result (-eps for the input edge)
+  const float* add_vec;     // [size] added to dLambda (bias, or W x0 + b)
+  const float* ahat;        // [M][ld] stored pre-activation coefficients
+  void* dahat_out;          // [M][ld] operand type, null if no consumer needs it
+  float* contrib; int nnz_e;
+  float* d_alpha; float* d_beta;      // raw gradient outputs (adam disabled)
+  float* m_alpha; float* v_alpha;     // Adam moments (adam enabled)
+  float* m_beta;  float* v_beta;
+  float* alpha_rw; float* beta_rw;    // parameters updated in place
+  AdamArgs adam;
+};
+struct StoreEpiArgs {       // raw accumulate into an fp32 buffer
+  int size, ld;
+  float scale;
+  const float* acc_in;
+  float* out;
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const void* A; int lda;   // [M][lda] (operand type, or int8 sign if a_is_sign)
+  const void* Bt; int ldb;  // [N][ldb] operand type
+  int a_is_sign;
+  double* partial; int n_slots; int slot0;   // row partial sums (may be null)
+};
+
+hipError_t launch_gemm(int bf16, int cfg, EpiKind kind, const GemmArgs& g, const void* epi,
+                       hipStream_t st);
+int gemm_num_configs();
+void gemm_config_tile(int cfg, int* bm, int* bn);
+
+// Elementwise epilogues (no GEMM): the pre-activation comes from a per-spec
+// broadcast [S][ld] (fp32) plus the optional acc_in of the epilogue args.
+hipError_t launch_bound_elementwise(int bf16, const float* bcast, const BoundEpiArgs& a, double* partial,
+                                    int n_slots, int slot0, hipStream_t st);
+hipError_t launch_adj_elementwise(int bf16, const AdjEpiArgs& a, hipStream_t st);
+
+// Direct (non-GEMM) convolution kernels for conv edges.
+struct ConvGeom { int ci, hi, wi, co, ho, wo, kh, kw, stride, pad; };
+// Bound direction: dst rows [M][co*ho*wo] -> src rows [M][ci*hi*wi]  (transposed conv)
+hipError_t launch_conv_t(int bf16, EpiKind kind, const ConvGeom& cg, int M,
+                         const void* lam, int ld_in, const float* W,
+                         const void* epi, double* partial, int n_slots, int slot0,
+                         hipStream_t st);
+// Adjoint direction: src rows [M][ci*hi*wi] -> dst rows [M][co*ho*wo]  (conv)
+hipError_t launch_conv_f(int bf16, int a_is_sign, const ConvGeom& cg, int M,
+                         const void* x, int ld_in, const float* W,
+                         const void* epi, hipStream_t st);
+// Identity edge: rows copied (bound direction uses BoundEpi/StoreEpi).
+
+hipError_t launch_chat(const double* C, int S, int d_out, const float* W, int d_in,
+                       int kind, float* chat, int ld, hipStream_t st);
+hipError_t launch_out_const(const double* C, int S, int d_out, const float* bias,
+                            double* cb, hipStream_t st);
+hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, int d_in,
+                      const double* x0, const float* bias, float* out, hipStream_t st);
+hipError_t launch_reduce_rows(int M, int S, const double* partial, int n_slots,
+                              const double* cb, const float* gamma, int N, const double* d,
+                              double* bound, uint8_t* verified, hipStream_t st);
+hipError_t launch_gamma_update(int M, int N, const int32_t* row_ptr, const float* contrib,
+                               int nnz_e, const double* d, float* gamma, float* d_gamma,
+                               float* m, float* v, AdamArgs adam, hipStream_t st);
+hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
+                               float b2, float* consts, hipStream_t st);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* flags,
+                           hipStream_t st);
+hipError_t launch_fill_bf16_from_f32(const float* src, bf16* dst, int64_t n, hipStream_t st);
+
+}  // namespace gcp

@@ -1,0 +1,151 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * FP32 path: |g_gpu - g_oracle| <= 1e-5 * max(|g|, T), T = the sum of the
+    magnitudes of every term added into the bound (the oracle's
+    error_scale); the fp32 GEMMs round each product with unit 6e-8 and the
+    sums are fp64, so the error is a small multiple of that scale.
+  * gradients: |d_gpu - d_oracle| <= 1e-4 * (max_row |d_oracle| + 1).
+  * BF16 path: bf16 operands carry 8 mantissa bits (unit 4e-3); the bound
+    error is checked at 2e-2 of T.
+"""
+import numpy as np
+import pytest
+
+from oracle import gcp_oracle as O
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def upload(prob):
+    from paper_2208_05740_amd import binding as B
+    return B.Problem(prob, device=_dev())
+
+
+def params(prob, P, alpha=None, beta=None, gamma=None):
+    import torch
+    a = O.full_alpha(prob) if alpha is None else alpha
+    b = prob.beta if beta is None else beta
+    c = prob.gamma if gamma is None else gamma
+    t = lambda x: torch.tensor(np.asarray(x, np.float32).reshape(P.M, -1), device=_dev())  # noqa: E731
+    return t(a), t(b), t(c), a, b, c
+
+
+def rel_err(g_gpu, g_ref, scale):
+    return np.abs(g_gpu - g_ref) / np.maximum(np.abs(g_ref), scale)
+
+
+def check_bound(prob, mode=0, tol=1e-5, alpha=None, beta=None, gamma=None, grads=True, gtol=1e-4):
+    from paper_2208_05740_amd import binding as B
+    P = upload(prob)
+    a, b, c, a64, b64, c64 = params(prob, P, alpha, beta, gamma)
+    out, ver, g = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, mode=mode, grads=grads,
+                          verified=True)
+    import torch
+    torch.cuda.synchronize()
+    gb = out.cpu().numpy()
+    a32 = a.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    b32 = b.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    c32 = c.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    ref, ga, gbb, gc = O.bound_and_grad(prob, a32, b32, c32)
+    ref = ref.reshape(-1)
+    T = O.error_scale(prob, a32, b32, c32).reshape(-1)
+    err = rel_err(gb, ref, T)
+    assert err.max() <= tol, (err.max(), gb[:4], ref[:4])
+    assert np.array_equal(ver.cpu().numpy(), (gb >= 0).astype(np.uint8))
+    if grads:
+        for got, want in zip(g, (ga, gbb, gc)):
+            got = got.cpu().numpy().reshape(prob.B * prob.S, -1)
+            want = want.reshape(prob.B * prob.S, -1)
+            if want.size == 0:
+                continue
+            scale = np.abs(want).max(1, keepdims=True) + 1.0
+            d = np.abs(got - want) / scale
+            assert d.max() <= gtol, (d.max(), np.unravel_index(d.argmax(), d.shape))
+    return gb, ref, T
+
+
+def test_config1_fp32_bound_and_gradients_match_oracle():
+    check_bound(gen.make_config(1, 0))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_mlp_with_splits_and_cuts(seed):
+    p = gen.make_tiny("mlp", seed, B=5, splits=(1, 3), n_cuts=6, input_terms=1)
+    check_bound(p)
+
+
+def test_config2_small_batch_fp32():
+    # 784-256x6-10 with 200 cuts, 1-8 splits per domain: several column tiles
+    # per layer and a ragged last row tile (M = 5 * 9 = 45).
+    p = gen.make_config(2, 0, B=5)
+    rng = np.random.default_rng(0)
+    prep = O.Prepared(p)
+    alpha = rng.random((p.B, p.S, prep.n_I)).astype(np.float32)
+    gamma = (rng.random((p.B, p.S, p.cuts.n)) * 0.1).astype(np.float32)
+    check_bound(p, alpha=alpha, gamma=gamma)
+
+
+def test_config2_small_batch_bf16_close_to_oracle():
+    p = gen.make_config(2, 0, B=3)
+    check_bound(p, mode=1, tol=2e-2, grads=False)
+
+
+def test_no_cuts_no_splits_edge_case():
+    p = gen.make_tiny("mlp", 3, B=2, splits=(0, 0), n_cuts=0)
+    check_bound(p)
+
+
+def test_single_row():
+    p = gen.make_tiny("mlp", 4, B=1, splits=(1, 1), n_cuts=2, S=1)
+    check_bound(p)
+
+
+def test_invalid_inputs_raise():
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny("mlp", 0, B=2, splits=(1, 2), n_cuts=3)
+    P = upload(p)
+    a, b, c, *_ = params(p, P)
+    bad = a.clone()
+    bad[0, 0] = 1.5
+    with pytest.raises(B.GcpError) as ei:
+        B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, bad, b, c, validate=True)
+    assert ei.value.code == -2
+    bad = c.clone()
+    bad[0, 0] = float("nan")
+    with pytest.raises(B.GcpError) as ei:
+        B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, bad, validate=True)
+    assert ei.value.code == -3
+    with pytest.raises(B.GcpError):
+        B.bound(P.net, P.x0, -1.0, P.C, P.splits, P.cuts, a, b, c)
+    # a split on a root-stable neuron is rejected at packing time
+    prep = O.Prepared(p)
+    q = prep.relu[0]
+    stable = int(np.nonzero(prep.cls[q] != 2)[0][0])
+    sp = gen.Splits(np.array([[q]], np.int32), np.array([[stable]], np.int32), np.array([[1]], np.int8))
+    with pytest.raises(B.GcpError):
+        B.Splits(P.net, sp)
+    torch.cuda.synchronize()
+
+
+def test_autograd_function_matches_adjoint():
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny("mlp", 1, B=3, splits=(1, 2), n_cuts=4)
+    P = upload(p)
+    a, b, c, *_ = params(p, P)
+    a.requires_grad_(True); b.requires_grad_(True); c.requires_grad_(True)
+    w = torch.linspace(0.5, 1.5, P.M, device=a.device, dtype=torch.float64)
+    out = B.gcp_bound_autograd(P, a, b, c)
+    (out * w).sum().backward()
+    _, _, g = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a.detach(), b.detach(), c.detach(), grads=True)
+    wf = w.float()[:, None]
+    assert torch.allclose(a.grad, g[0] * wf) and torch.allclose(c.grad, g[2] * wf)
+    assert torch.allclose(b.grad, g[1] * wf)

@@ -200,6 +200,7 @@ def ibp_bounds(net: Net, x0: np.ndarray, eps: float):
             else:
                 l += _apply_edge(e, lo[e.src], sh, True) + _apply_edge(e, hi[e.src], sh, False)
                 u += _apply_edge(e, hi[e.src], sh, True) + _apply_edge(e, lo[e.src], sh, False)
+        l, u = _f32_down(l), _f32_up(u)
         lu.append((l[0].copy(), u[0].copy()))
         lo[i] = np.maximum(l, 0.0)
         hi[i] = np.maximum(u, 0.0)
@@ -228,8 +229,26 @@ def num_relu_neurons(net: Net) -> int:
 # Network builders
 # ---------------------------------------------------------------------------
 
+def _f32(a):
+    """Values exactly representable in fp32 (kept as float64), so a device
+    copy in fp32 holds the very same numbers the fp64 oracle uses."""
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _f32_down(a):
+    f = np.asarray(a, np.float64).astype(np.float32)
+    f = np.where(f.astype(np.float64) > a, np.nextafter(f, np.float32(-np.inf)), f)
+    return f.astype(np.float64)
+
+
+def _f32_up(a):
+    f = np.asarray(a, np.float64).astype(np.float32)
+    f = np.where(f.astype(np.float64) < a, np.nextafter(f, np.float32(np.inf)), f)
+    return f.astype(np.float64)
+
+
 def _bias(rng, n, var=0.1):
-    return rng.normal(0.0, math.sqrt(var), n)
+    return _f32(rng.normal(0.0, math.sqrt(var), n))
 
 
 def mlp_net(rng, dims, w_var_num=2.0, b_var=0.1) -> Net:
@@ -237,7 +256,7 @@ def mlp_net(rng, dims, w_var_num=2.0, b_var=0.1) -> Net:
     nodes = []
     for k in range(1, len(dims)):
         fan_in = dims[k - 1]
-        W = rng.normal(0.0, math.sqrt(w_var_num / fan_in), (dims[k], fan_in))
+        W = _f32(rng.normal(0.0, math.sqrt(w_var_num / fan_in), (dims[k], fan_in)))
         nodes.append(Node((dims[k],), _bias(rng, dims[k], b_var),
                           [Edge(k - 2, "dense", W)], relu=(k < len(dims) - 1)))
     return Net((dims[0],), nodes)
@@ -248,7 +267,7 @@ def _conv_out(h, k, s, p):
 
 
 def _conv_w(rng, co, ci, k):
-    return rng.normal(0.0, math.sqrt(2.0 / (ci * k * k)), (co, ci, k, k))
+    return _f32(rng.normal(0.0, math.sqrt(2.0 / (ci * k * k)), (co, ci, k, k)))
 
 
 def cnn_net(rng, in_shape=(3, 32, 32), convs=((16, 4, 2, 1), (32, 4, 2, 1)), fcs=(100, 10)) -> Net:
@@ -264,7 +283,7 @@ def cnn_net(rng, in_shape=(3, 32, 32), convs=((16, 4, 2, 1), (32, 4, 2, 1)), fcs
         c, h = co, ho
     d = c * h * h
     for i, f in enumerate(fcs):
-        nodes.append(Node((f,), _bias(rng, f), [Edge(src, "dense", rng.normal(0, math.sqrt(2.0 / d), (f, d)))],
+        nodes.append(Node((f,), _bias(rng, f), [Edge(src, "dense", _f32(rng.normal(0, math.sqrt(2.0 / d), (f, d))))],
                           relu=(i < len(fcs) - 1)))
         src = len(nodes) - 1
         d = f
@@ -300,7 +319,7 @@ def resnet_net(rng, stem=16, stages=(16, 32, 64), hw=32, in_ch=3) -> Net:
         src = len(nodes) - 1
         c, h = co, ho
     d = c * h * h
-    nodes.append(Node((10,), _bias(rng, 10), [Edge(src, "dense", rng.normal(0, math.sqrt(2.0 / d), (10, d)))],
+    nodes.append(Node((10,), _bias(rng, 10), [Edge(src, "dense", _f32(rng.normal(0, math.sqrt(2.0 / d), (10, d))))],
                       relu=False))
     return Net((in_ch, hw, hw), nodes)
 
@@ -443,6 +462,7 @@ def make_problem(name, net, x0, eps, S, B, kmin_split, kmax_split, n_cuts,
                  cut_kmin, cut_kmax, streams, alpha_init="crown",
                  beta_dist="uniform", gamma_dist="zero", input_terms=0) -> Problem:
     r_cut, r_split, r_par = streams
+    x0 = _f32(x0)
     lu = ibp_bounds(net, x0, eps)
     rel = net.relu_nodes
     C = margin_spec(net, x0, S)
@@ -453,14 +473,14 @@ def make_problem(name, net, x0, eps, S, B, kmin_split, kmax_split, n_cuts,
     S = C.shape[0]
     alpha = None
     if alpha_init == "given":
-        alpha = r_par.random((B, S, n_I))
+        alpha = _f32(r_par.random((B, S, n_I)))
     K = splits.K
     if beta_dist == "uniform":
-        beta = r_par.random((B, S, K)) * (splits.node >= 0)[:, None, :]
+        beta = _f32(r_par.random((B, S, K))) * (splits.node >= 0)[:, None, :]
     else:
         beta = np.zeros((B, S, K))
     if gamma_dist == "uniform":
-        gamma = r_par.random((B, S, cuts.n))
+        gamma = _f32(r_par.random((B, S, cuts.n)))
     else:
         gamma = np.zeros((B, S, cuts.n))
     return Problem(name, net, lu, x0, float(eps), C, splits, cuts, alpha_init,
