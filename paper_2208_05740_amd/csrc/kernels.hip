@@ -610,12 +610,16 @@ hipError_t launch_gamma_update(int M, int N, const int32_t* row_ptr, const float
   return hipGetLastError();
 }
 
-// Per-iteration Adam constants from the device step counter t, then t += 1
-// (reset: t = 0 first).  consts = {lr_a decay^t, lr_m decay^t, 1-b1^(t+1), 1-b2^(t+1)}.
+// Per-iteration Adam constants from the device step counter t, then t += 1;
+// with reset the counter is only set to 0.  consts = {lr_a decay^t, lr_m decay^t, 1-b1^(t+1), 1-b2^(t+1)}.
 __global__ void adam_prepare_kernel(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                     float b2, float* consts) {
   if (threadIdx.x != 0) return;
-  int t = reset ? 0 : *step;
+  if (reset) {            // start of an optimisation: t = 0, no constants written
+    *step = 0;
+    return;
+  }
+  int t = *step;
   double dec = pow((double)decay, (double)t);
   consts[0] = (float)(lr_alpha * dec);
   consts[1] = (float)(lr_mult * dec);
@@ -625,6 +629,7 @@ __global__ void adam_prepare_kernel(int* step, int reset, float lr_alpha, float 
 }
 hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                float b2, float* consts, hipStream_t st) {
+  if (step == nullptr || (!reset && consts == nullptr)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(adam_prepare_kernel, dim3(1), dim3(64), 0, st, step, reset, lr_alpha, lr_mult, decay, b1,
                      b2, consts);
   return hipGetLastError();

@@ -149,3 +149,63 @@ def test_autograd_function_matches_adjoint():
     wf = w.float()[:, None]
     assert torch.allclose(a.grad, g[0] * wf) and torch.allclose(c.grad, g[2] * wf)
     assert torch.allclose(b.grad, g[1] * wf)
+
+
+def _optimize(prob, P, mode, iters=20, a=None, b=None, c=None):
+    import torch
+    from paper_2208_05740_amd import binding as B
+    a0, b0, c0, *_ = params(prob, P)
+    a = a0.clone() if a is None else a
+    b = b0.clone() if b is None else b
+    c = c0.clone() if c is None else c
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+    o = prob.opt
+    out, ver = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=iters,
+                          lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], mode=mode)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), a, b, c
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("mlp", 2)])
+def test_optimize_zero_iterations_is_the_certified_bound(kind, seed):
+    p = gen.make_tiny(kind, seed, B=3, splits=(1, 2), n_cuts=4)
+    P = upload(p)
+    g, a, b, c = _optimize(p, P, 0, iters=0)
+    ref = O.bound(p).reshape(-1)
+    T = O.error_scale(p).reshape(-1)
+    assert rel_err(g, ref, T).max() <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "cfg2"])
+def test_optimize_fp32_matches_oracle_optimisation(cfg):
+    p = gen.make_tiny("mlp", 1, B=4, splits=(1, 2), n_cuts=6, gamma_dist="zero") if cfg == "tiny" \
+        else gen.make_config(2, 0, B=2)
+    P = upload(p)
+    g, a, b, c = _optimize(p, P, 0)
+    # certifying pass = the oracle's bound at the device's final parameters
+    a64, b64, c64 = (x.cpu().numpy().astype(np.float64).reshape(p.B, p.S, -1) for x in (a, b, c))
+    ref = O.bound(p, a64, b64, c64).reshape(-1)
+    T = O.error_scale(p, a64, b64, c64).reshape(-1)
+    assert rel_err(g, ref, T).max() <= 1e-5
+    assert np.all(a64 >= 0) and np.all(a64 <= 1) and np.all(b64 >= 0) and np.all(c64 >= 0)
+    # the same 20 Adam steps in fp64 end at (nearly) the same bound
+    go, *_ = O.optimize(p)
+    To = O.error_scale(p).reshape(-1)
+    assert rel_err(g, go.reshape(-1), To).max() <= 1e-3, rel_err(g, go.reshape(-1), To).max()
+    # and the optimisation improved on the starting point
+    g0 = O.bound(p).reshape(-1)
+    assert np.mean(g) > np.mean(g0)
+
+
+def test_optimize_bf16_final_bound_close_to_fp32():
+    p = gen.make_config(2, 0, B=4)
+    P = upload(p)
+    g32, *_ = _optimize(p, P, 0)
+    g16, a, b, c = _optimize(p, P, 1)
+    rel = np.abs(g16 - g32) / np.abs(g32)
+    assert np.median(rel) <= 1e-3, (np.median(rel), rel.max())
+    # the bf16-optimised parameters are certified exactly (fp32/fp64 pass)
+    a64, b64, c64 = (x.cpu().numpy().astype(np.float64).reshape(p.B, p.S, -1) for x in (a, b, c))
+    ref = O.bound(p, a64, b64, c64).reshape(-1)
+    T = O.error_scale(p, a64, b64, c64).reshape(-1)
+    assert rel_err(g16, ref, T).max() <= 1e-5
