@@ -184,9 +184,11 @@ typedef struct {
  * the device: each iteration runs the bound pass (GEMMs in `mode`), the
  * adjoint, and the Adam update of alpha (clamped to [0,1]), beta and gamma
  * (clamped >= 0) with lr_t = lr * decay^t.  alpha, beta, gamma are updated
- * in place.  adam_state: device fp32 [2][M][n_I + K + N] (first and second
- * moments, caller-owned so optimisation can resume); must be zero for a
- * fresh start.  Finally the bound at the final parameters is recomputed
+ * in place.  adam_state: device fp32, 2*M*(n_I + K + N) floats holding the
+ * first and second moments, in this order: m_alpha [M][n_I], v_alpha
+ * [M][n_I], m_beta [M][K], v_beta [M][K], m_gamma [N][M], v_gamma [N][M]
+ * (caller-owned so optimisation can resume; zero for a fresh start).
+ * Finally the bound at the final parameters is recomputed
  * with fp32 GEMMs and fp64 reductions (the certifying pass) into
  * bound/verified. */
 int gcp_optimize(const gcp_net* net, const double* x0, double eps,

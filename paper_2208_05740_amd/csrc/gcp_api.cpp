@@ -99,6 +99,7 @@ struct NodeH {
   std::vector<int> in_edges;      // edges whose dst is this node
   std::vector<int> consumers;     // edges whose src is this node
   DBuf bias, l, u, inv_ul, cls, rank;
+  std::vector<int32_t> rank_h;    // host copy of rank
   int n_unst = 0, rank0 = 0;
   NodeDev dev() const {
     return NodeDev{size, ld, bias.as<float>(), l.as<float>(), u.as<float>(), inv_ul.as<float>(),
@@ -120,9 +121,10 @@ struct gcp_net {
   std::vector<int> in_consumers;
   // ---- workspace (grown on demand)
   struct WS {
-    int M = 0, S = 0, nnz = 0;
+    int M = 0, S = 0, nnz = 0, N = 0;
     std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
-    DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in;
+    DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in, gammaT;
+    DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
     std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
     int n_slots = 0;
   } ws;
@@ -237,6 +239,7 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
       }
       n.n_unst = rank0 - n.rank0;
       n.l.upload(l); n.u.upload(u); n.inv_ul.upload(iul); n.cls.upload(cls); n.rank.upload(rank);
+      n.rank_h = rank;
       net->n_relu += n.size;
     }
     for (int e = 0; e < nd.n_edges; ++e) {
@@ -309,23 +312,61 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
 }
 
 // ------------------------------------------------------------------ tile choice
+// Tile shapes come from a small autotuner: the first time a GEMM shape is
+// launched on a net, every candidate tile runs a few times as an idempotent
+// trial (same inputs, outputs that the real launch overwrites, or scratch)
+// timed with HIP events, and the fastest is cached per (kind, precision,
+// sign input, M, N, K).  GCP_AUTOTUNE=0 selects a fixed heuristic instead.
+const int kTileCandidates[] = {0, 1, 2, 4, 5};   // 128x128 spills with the fused epilogues
 
-int pick_cfg(gcp_net* net, int bf16, int M, int N, int K) {
-  auto key = std::make_tuple(bf16, M, N, K);
-  auto it = net->tile_cache.find(key);
-  if (it != net->tile_cache.end()) return it->second;
-  // Heuristic default: the largest tile that still yields >= 2 workgroups per CU.
-  static const int order[] = {3, 1, 2, 0, 4};
-  int best = 4;
+bool autotune_enabled() {
+  const char* e = std::getenv("GCP_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+int heuristic_cfg(int M, int N) {
+  static const int order[] = {1, 2, 0, 4, 5};
   for (int c : order) {
     int bm, bn;
     gemm_config_tile(c, &bm, &bn);
     long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
-    if (tiles >= 512) { best = c; break; }
+    if (tiles >= 1024) return c;
+  }
+  return 5;
+}
+
+template <class Trial>
+int choose_cfg(gcp_net* net, int kind, int bf16, int sign, int M, int N, int K, hipStream_t st, Trial trial) {
+  auto key = std::make_tuple(kind * 4 + bf16 * 2 + sign, M, N, K);
+  auto it = net->tile_cache.find(key);
+  if (it != net->tile_cache.end()) return it->second;
+  int best = heuristic_cfg(M, N);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(st, &cs);
+  if (autotune_enabled() && cs == hipStreamCaptureStatusNone) {
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float best_ms = 1e30f;
+    for (int c : kTileCandidates) {
+      hip_check(trial(c), "autotune trial");
+      hip_check(hipEventRecord(e0, st), "hipEventRecord");
+      for (int rep = 0; rep < 3; ++rep) hip_check(trial(c), "autotune trial");
+      hip_check(hipEventRecord(e1, st), "hipEventRecord");
+      hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
   net->tile_cache[key] = best;
   return best;
 }
+
+int slots_for_gemm(int N) { return (N + 31) / 32; }
+int slots_for_elementwise(int N) { return (N + 255) / 256; }
 
 }  // namespace
 
@@ -471,11 +512,9 @@ extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const
       int j = neuron[i];
       if (j < 0 || j >= n.size) fail(GCP_EINVAL, "split neuron out of range");
       if (sign[i] != 1 && sign[i] != -1) fail(GCP_EINVAL, "split sign must be +1 or -1");
-      // rank lookup on the host copy of the class vector
-      std::vector<int32_t> rk(n.size);
-      hip_check(hipMemcpy(rk.data(), n.rank.p, n.size * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
-      if (rk[j] < 0) fail(GCP_EINVAL, "split neuron is not root-unstable");
-      int8_t& mm = mask[(size_t)b * net->n_I + rk[j]];
+      const int rk = n.rank_h[j];
+      if (rk < 0) fail(GCP_EINVAL, "split neuron is not root-unstable");
+      int8_t& mm = mask[(size_t)b * net->n_I + rk];
       if (mm != 0) fail(GCP_EINVAL, "neuron split twice in one domain");
       mm = (int8_t)(sign[i] > 0 ? (k + 1) : -(k + 1));
     }
@@ -508,15 +547,16 @@ struct Call {
   RowParams rp;
   hipStream_t st;
   int nnz;
+  int N;
 };
 
 void ensure_ws(Call& c) {
   gcp_net* net = c.net;
   auto& ws = net->ws;
   const int nn = (int)net->nodes.size();
-  bool grow = c.M > ws.M || c.nnz > ws.nnz || c.S > ws.S || ws.lam.empty();
+  bool grow = c.M > ws.M || c.nnz > ws.nnz || c.S > ws.S || c.N > ws.N || ws.lam.empty();
   if (!grow) return;
-  int M = std::max(c.M, ws.M), S = std::max(c.S, ws.S), nnz = std::max(c.nnz, ws.nnz);
+  int M = std::max(c.M, ws.M), S = std::max(c.S, ws.S), nnz = std::max(c.nnz, ws.nnz), Nc = std::max(c.N, ws.N);
   ws.lam.clear(); ws.ahat.clear(); ws.dahat.clear(); ws.acc.clear(); ws.addv.clear();
   for (int i = 0; i < nn; ++i) {
     const NodeH& n = net->nodes[i];
@@ -530,7 +570,9 @@ void ensure_ws(Call& c) {
     ws.addv.push_back(mk(n.relu ? (size_t)n.ld * 4 : 0));
   }
   ws.sign.alloc((size_t)M * net->in_ld);
-  ws.contrib.alloc((size_t)M * std::max(nnz, 1) * 4);
+  const int mp = round_up(M, 16);
+  ws.contrib.alloc((size_t)mp * std::max(nnz, 1) * 4);
+  ws.gammaT.alloc((size_t)mp * std::max(Nc, 1) * 4);
   ws.chat_off.assign(nn, -1);
   size_t chat_floats = 0;
   for (int eid : net->nodes[net->out].in_edges) {
@@ -544,7 +586,7 @@ void ensure_ws(Call& c) {
   ws.step.alloc(16);
   ws.flags.alloc(16);
   ws.acc_in.alloc((size_t)M * net->in_ld * 4);
-  ws.M = M; ws.S = S; ws.nnz = nnz;
+  ws.M = M; ws.S = S; ws.nnz = nnz; ws.N = Nc;
   ws.n_slots = 0;
   ws.partial.release();
 }
@@ -553,6 +595,26 @@ CutCol cut_col(const Call& c, int node) {
   if (!c.cuts) return CutCol{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int idx = node < 0 ? (int)c.net->nodes.size() : node;
   return c.cuts->cols[idx].dev();
+}
+
+float* tune_store(Call& c) {
+  auto& ws = c.net->ws;
+  size_t need = 0;
+  for (auto& n : c.net->nodes) need = std::max(need, (size_t)c.M * n.ld * 4);
+  if (ws.tune_store.bytes < need) ws.tune_store.alloc(need);
+  return ws.tune_store.as<float>();
+}
+float* tune_alpha(Call& c) {
+  auto& ws = c.net->ws;
+  size_t need = (size_t)c.M * std::max(c.rp.n_I, 1) * 4;
+  if (ws.tune_alpha.bytes < need) ws.tune_alpha.alloc(need);
+  return ws.tune_alpha.as<float>();
+}
+float* tune_beta(Call& c) {
+  auto& ws = c.net->ws;
+  size_t need = (size_t)c.M * std::max(c.rp.K, 1) * 4;
+  if (ws.tune_beta.bytes < need) ws.tune_beta.alloc(need);
+  return ws.tune_beta.as<float>();
 }
 
 const void* wt_bound(const EdgeH& E, int bf16) { return bf16 ? E.WT16.p : E.WT32.p; }
@@ -613,10 +675,10 @@ struct BoundPass {
       // the output is p's only consumer (checked at creation): fused relaxation
       pushes_left[p]--;
       BoundEpiArgs a = bound_args(p, false);
-      int nslot = (net->nodes[p].size + 255) / 256;
+      int nslot = slots_for_elementwise(net->nodes[p].size);
       if (!dry)
         check(launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], a, ws.partial.as<double>(),
-                                       ws.n_slots, slot, c.st));
+                                       slot, c.st));
       slot += nslot;
     }
     for (int i = net->out - 1; i >= 0; --i) {
@@ -654,20 +716,32 @@ struct BoundPass {
       g.A = ws.lam[E.dst]->p; g.lda = dn.ld;
       g.Bt = wt_bound(E, bf16); g.ldb = dn.ld;
       g.a_is_sign = 0;
-      int cfg = pick_cfg(net, bf16, g.M, g.N, g.K);
-      int bm, bn;
-      gemm_config_tile(cfg, &bm, &bn);
+      g.mp = c.rp.mp;
       if (!last) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         g.partial = nullptr;
-        if (!dry) check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+        if (!dry) {
+          int cfg = choose_cfg(net, EPI_STORE, bf16, 0, g.M, g.N, g.K, c.st, [&](int cf) {
+            StoreEpiArgs t = s;
+            t.acc_in = nullptr;
+            t.out = tune_store(c);
+            return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
+          });
+          check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+        }
         return;
       }
-      int nslot = (d_src + bn - 1) / bn;
-      g.partial = ws.partial.as<double>(); g.n_slots = ws.n_slots; g.slot0 = slot;
+      int nslot = slots_for_gemm(d_src);
       if (p >= 0) {
         BoundEpiArgs a = bound_args(p, has_acc);
-        if (!dry) check(launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st));
+        if (!dry) {
+          GemmArgs gt = g;
+          gt.partial = nullptr;
+          int cfg = choose_cfg(net, EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st,
+                               [&](int cf) { return launch_gemm(bf16, cf, EPI_BOUND, gt, &a, c.st); });
+          g.partial = ws.partial.as<double>(); g.slot0 = slot;
+          check(launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st));
+        }
       } else {
         if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
         ConcEpiArgs a{};
@@ -676,7 +750,14 @@ struct BoundPass {
         a.sign_out = keep_ahat ? ws.sign.as<int8_t>() : nullptr;
         a.contrib = want_contrib ? ws.contrib.as<float>() : nullptr;
         a.nnz_e = c.nnz;
-        if (!dry) check(launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st));
+        if (!dry) {
+          GemmArgs gt = g;
+          gt.partial = nullptr;
+          int cfg = choose_cfg(net, EPI_CONC, bf16, 0, g.M, g.N, g.K, c.st,
+                               [&](int cf) { return launch_gemm(bf16, cf, EPI_CONC, gt, &a, c.st); });
+          g.partial = ws.partial.as<double>(); g.slot0 = slot;
+          check(launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st));
+        }
       }
       slot += nslot;
       return;
@@ -696,10 +777,10 @@ struct AdjPass {
 
   void check(hipError_t e) { hip_check(e, "kernel launch (adjoint)"); }
 
-  void run() {
+  // add vectors: bias (+ A x0 for edges from the input); once per call
+  void prepare() {
     gcp_net* net = c.net;
     auto& ws = net->ws;
-    // add vectors: bias (+ A x0 for edges from the input)
     for (int i = 0; i < net->out; ++i) {
       const NodeH& n = net->nodes[i];
       bool seeded = false;
@@ -715,7 +796,10 @@ struct AdjPass {
         hip_check(hipMemcpyAsync(ws.addv[i]->p, n.bias.p, n.size * 4, hipMemcpyDeviceToDevice, c.st),
                   "hipMemcpyAsync");
     }
-    for (int i = 0; i < net->out; ++i) node(i);
+  }
+
+  void run() {
+    for (int i = 0; i < c.net->out; ++i) node(i);
   }
 
   void node(int i) {
@@ -744,12 +828,25 @@ struct AdjPass {
         g.A = A; g.lda = lda;
         g.Bt = w_adj(E, bf16); g.ldb = lda;
         g.a_is_sign = sign;
-        int cfg = pick_cfg(net, bf16, g.M, g.N, g.K);
+        g.mp = c.rp.mp;
         if (!last) {
           StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
+          int cfg = choose_cfg(net, EPI_STORE, bf16, sign, g.M, g.N, g.K, c.st, [&](int cf) {
+            StoreEpiArgs t = s;
+            t.acc_in = nullptr;
+            t.out = tune_store(c);
+            return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
+          });
           check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
         } else {
           AdjEpiArgs a = epi(i, has_acc ? accbuf : nullptr, scale);
+          int cfg = choose_cfg(net, EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, [&](int cf) {
+            AdjEpiArgs t = a;     // gradient-only trial into scratch: no parameter moves
+            t.adam.enabled = 0;
+            t.d_alpha = tune_alpha(c);
+            t.d_beta = tune_beta(c);
+            return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
+          });
           check(launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st));
         }
       } else {
@@ -804,25 +901,20 @@ void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const dou
   if (M > (1LL << 30)) fail(GCP_EINVAL, "too many rows");
   c.M = (int)M;
   c.nnz = c.cuts ? c.cuts->nnz_e : 0;
-  c.rp = RowParams{c.M, S, alpha, net->n_I, beta, splits->K, gamma, N,
-                   splits->K > 0 ? splits->mask.as<int8_t>() : nullptr};
   c.st = (hipStream_t)stream;
+  c.N = N;
   ensure_ws(c);
+  c.rp = RowParams{c.M, S, round_up(c.M, 16), alpha, net->n_I, beta, splits->K, net->ws.gammaT.as<float>(), N,
+                   splits->K > 0 ? splits->mask.as<int8_t>() : nullptr};
 }
 
 void size_partials(Call& c, int bf16, bool keep, bool contrib) {
   BoundPass dry(c, bf16, keep, contrib, true);
   dry.run();
   auto& ws = c.net->ws;
-  if (dry.slot > ws.n_slots || !ws.partial.p) {
-    ws.partial.alloc((size_t)ws.M * std::max(dry.slot, 1) * 8);
-    ws.n_slots = dry.slot;
-  }
-  // slot count must match exactly for the row reduction
-  if (dry.slot != ws.n_slots) {
-    ws.partial.alloc((size_t)ws.M * std::max(dry.slot, 1) * 8);
-    ws.n_slots = dry.slot;
-  }
+  const size_t need = (size_t)round_up(ws.M, 16) * std::max(dry.slot, 1) * 8;
+  if (need > ws.partial.bytes) ws.partial.alloc(need);
+  ws.n_slots = dry.slot;
 }
 
 void validate_params(Call& c, const float* alpha, const float* beta, const float* gamma) {
@@ -831,7 +923,7 @@ void validate_params(Call& c, const float* alpha, const float* beta, const float
   int* f = ws.flags.as<int>();
   hip_check(launch_validate(alpha, (int64_t)c.M * c.rp.n_I, 0.f, 1.f, f, c.st), "validate");
   hip_check(launch_validate(beta, (int64_t)c.M * c.rp.K, 0.f, INFINITY, f, c.st), "validate");
-  hip_check(launch_validate(gamma, (int64_t)c.M * c.rp.N, 0.f, INFINITY, f, c.st), "validate");
+  hip_check(launch_validate(gamma, (int64_t)c.M * c.N, 0.f, INFINITY, f, c.st), "validate");
   int h = 0;
   hip_check(hipMemcpyAsync(&h, f, 4, hipMemcpyDeviceToHost, c.st), "hipMemcpyAsync");
   hip_check(hipStreamSynchronize(c.st), "hipStreamSynchronize");
@@ -844,8 +936,9 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
   BoundPass bp(c, bf16, keep_ahat, contrib, false);
   bp.run();
   auto& ws = c.net->ws;
-  hip_check(launch_reduce_rows(c.M, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(), c.rp.gamma,
-                               c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound, verified, c.st),
+  hip_check(launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
+                               c.rp.gammaT, c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound, verified,
+                               c.st),
             "reduce");
 }
 
@@ -868,14 +961,16 @@ extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, con
       fail(GCP_EINVAL, "pass all gradient outputs or none");
   }
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
+  if (c.N > 0) hip_check(launch_transpose(gamma, c.M, c.N, c.N, net->ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
   bound_pass(c, bf16, grads, grads && c.nnz > 0, bound, verified);
   if (grads) {
     if (splits->K > 0) hip_check(launch_fill_f32(d_beta, (int64_t)c.M * splits->K, 0.f, c.st), "fill");
     AdjPass ap{c, bf16, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, d_alpha, d_beta, nullptr, nullptr,
                nullptr, nullptr, nullptr, nullptr};
+    ap.prepare();
     ap.run();
     if (c.rp.N > 0)
-      hip_check(launch_gamma_update(c.M, c.rp.N, c.cuts->row_ptr.as<int32_t>(), net->ws.contrib.as<float>(), c.nnz,
+      hip_check(launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), net->ws.contrib.as<float>(),
                                     c.cuts->d.as<double>(), nullptr, d_gamma, nullptr, nullptr,
                                     AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st),
                 "gamma gradient");
@@ -909,7 +1004,12 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
   float* vg = mg + M * N;
   AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.consts.as<float>()};
   hip_check(launch_adam_prepare(ws.step.as<int>(), 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam reset");
+  if (N > 0) hip_check(launch_transpose(gamma, c.M, (int)N, (int)N, ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
   size_partials(c, bf16, true, c.nnz > 0);
+  {
+    AdjPass prep{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+    prep.prepare();
+  }
   for (int it = 0; it < opt->iters; ++it) {
     hip_check(launch_adam_prepare(ws.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
                                   opt->adam_b2, ws.consts.as<float>(), c.st),
@@ -919,10 +1019,11 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
     AdjPass ap{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
     ap.run();
     if (N > 0)
-      hip_check(launch_gamma_update(c.M, (int)N, c.cuts->row_ptr.as<int32_t>(), ws.contrib.as<float>(), c.nnz,
-                                    c.cuts->d.as<double>(), gamma, nullptr, mg, vg, adam, c.st),
+      hip_check(launch_gamma_update(c.M, c.rp.mp, (int)N, c.cuts->row_ptr.as<int32_t>(), ws.contrib.as<float>(),
+                                    c.cuts->d.as<double>(), ws.gammaT.as<float>(), nullptr, mg, vg, adam, c.st),
                 "gamma update");
   }
+  if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   bound_pass(c, 0, false, false, bound, verified);
   g_err.clear();

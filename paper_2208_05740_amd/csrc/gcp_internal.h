@@ -35,12 +35,14 @@ struct CutCol {
   const float* cQ;
 };
 
-// Per-row parameters of one call.
+// Per-row parameters of one call.  Row-indexed internal buffers use the
+// "row-minor" layout [x][mp] (mp = M rounded up to 16) so that the rows a
+// lane owns (4 consecutive per MFMA fragment) are one 16-byte access.
 struct RowParams {
-  int M, S;
-  const float* alpha; int n_I;      // [M][n_I]
-  const float* beta;  int K;        // [M][K]
-  const float* gamma; int N;        // [M][N]
+  int M, S, mp;
+  const float* alpha; int n_I;      // [M][n_I]   (caller layout)
+  const float* beta;  int K;        // [M][K]     (caller layout)
+  const float* gammaT; int N;       // [N][mp]    (internal transposed copy)
   const int8_t* mask;               // [B][n_I]: 0, +(slot+1) x>=0, -(slot+1) x<=0
 };
 
@@ -67,7 +69,7 @@ struct ConcEpiArgs {        // concretisation over the input box
   const double* x0; double eps;
   CutCol cc; RowParams rp;  // input-variable cuts (G on x)
   int8_t* sign_out;         // optional [M][ld] sign of v
-  float* contrib;           // optional [M][nnz_e] gamma-gradient pieces
+  float* contrib;           // optional [nnz_e][mp] gamma-gradient pieces
   int nnz_e;
 };
 struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
@@ -77,7 +79,7 @@ struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
   const float* add_vec;     // [size] added to dLambda (bias, or W x0 + b)
   const float* ahat;        // [M][ld] stored pre-activation coefficients
   void* dahat_out;          // [M][ld] operand type, null if no consumer needs it
-  float* contrib; int nnz_e;
+  float* contrib; int nnz_e;           // [nnz_e][mp]
   float* d_alpha; float* d_beta;      // raw gradient outputs (adam disabled)
   float* m_alpha; float* v_alpha;     // Adam moments (adam enabled)
   float* m_beta;  float* v_beta;
@@ -96,7 +98,8 @@ struct GemmArgs {
   const void* A; int lda;   // [M][lda] (operand type, or int8 sign if a_is_sign)
   const void* Bt; int ldb;  // [N][ldb] operand type
   int a_is_sign;
-  double* partial; int n_slots; int slot0;   // row partial sums (may be null)
+  double* partial; int mp; int slot0;   // row partial sums [slot][mp] (may be null);
+                                        // a launch owns slots slot0 .. slot0 + ceil(N/32) - 1
 };
 
 hipError_t launch_gemm(int bf16, int cfg, EpiKind kind, const GemmArgs& g, const void* epi,
@@ -107,7 +110,7 @@ void gemm_config_tile(int cfg, int* bm, int* bn);
 // Elementwise epilogues (no GEMM): the pre-activation comes from a per-spec
 // broadcast [S][ld] (fp32) plus the optional acc_in of the epilogue args.
 hipError_t launch_bound_elementwise(int bf16, const float* bcast, const BoundEpiArgs& a, double* partial,
-                                    int n_slots, int slot0, hipStream_t st);
+                                    int slot0, hipStream_t st);
 hipError_t launch_adj_elementwise(int bf16, const AdjEpiArgs& a, hipStream_t st);
 
 // Direct (non-GEMM) convolution kernels for conv edges.
@@ -115,7 +118,7 @@ struct ConvGeom { int ci, hi, wi, co, ho, wo, kh, kw, stride, pad; };
 // Bound direction: dst rows [M][co*ho*wo] -> src rows [M][ci*hi*wi]  (transposed conv)
 hipError_t launch_conv_t(int bf16, EpiKind kind, const ConvGeom& cg, int M,
                          const void* lam, int ld_in, const float* W,
-                         const void* epi, double* partial, int n_slots, int slot0,
+                         const void* epi, double* partial, int mp, int slot0,
                          hipStream_t st);
 // Adjoint direction: src rows [M][ci*hi*wi] -> dst rows [M][co*ho*wo]  (conv)
 hipError_t launch_conv_f(int bf16, int a_is_sign, const ConvGeom& cg, int M,
@@ -129,12 +132,17 @@ hipError_t launch_out_const(const double* C, int S, int d_out, const float* bias
                             double* cb, hipStream_t st);
 hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, int d_in,
                       const double* x0, const float* bias, float* out, hipStream_t st);
-hipError_t launch_reduce_rows(int M, int S, const double* partial, int n_slots,
-                              const double* cb, const float* gamma, int N, const double* d,
+hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n_slots,
+                              const double* cb, const float* gammaT, int N, const double* d,
                               double* bound, uint8_t* verified, hipStream_t st);
-hipError_t launch_gamma_update(int M, int N, const int32_t* row_ptr, const float* contrib,
-                               int nnz_e, const double* d, float* gamma, float* d_gamma,
+// d bound/d gamma from the entry pieces; Adam on gammaT (moments m, v are
+// [N][M]) or the raw gradient into d_gamma [M][N].
+hipError_t launch_gamma_update(int M, int mp, int N, const int32_t* row_ptr, const float* contrib,
+                               const double* d, float* gammaT, float* d_gamma,
                                float* m, float* v, AdamArgs adam, hipStream_t st);
+// [rows][cols] (pitch ld_in) -> [cols][ld_out]
+hipError_t launch_transpose(const float* in, int rows, int cols, int ld_in, float* out, int ld_out,
+                            hipStream_t st);
 hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                float b2, float* consts, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);

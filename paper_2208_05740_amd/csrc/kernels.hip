@@ -55,192 +55,361 @@ __device__ inline double wave_sum16(double v) {
   return v;
 }
 
-struct AdamStep {
-  float lr_a, lr_m, b1, b2, eps, bc1, bc2;
-  // consts = {lr_alpha * decay^t, lr_mult * decay^t, 1 - b1^(t+1), 1 - b2^(t+1)},
-  // prepared on the device once per iteration (adam_prepare_kernel).
-  __device__ AdamStep(const AdamArgs& a) {
-    lr_a = a.consts[0]; lr_m = a.consts[1]; bc1 = a.consts[2]; bc2 = a.consts[3];
-    b1 = a.b1; b2 = a.b2; eps = a.eps;
-  }
-  // Ascent step on x with gradient g, then projection onto [lo, hi].
-  __device__ inline void update(float* x, float* m, float* v, float g, float lr, float lo,
-                                float hi) const {
-    float mm = b1 * (*m) + (1.0f - b1) * g;
-    float vv = b2 * (*v) + (1.0f - b2) * g * g;
-    *m = mm;
-    *v = vv;
-    float step = lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-    *x = fminf(fmaxf(*x + step, lo), hi);
-  }
-};
+// ------------------------------------------------------------------ epilogues
+// An epilogue processes the R x TN output elements one lane holds: rows
+// rows[q] (q < R), columns cols[k] (k < TN), GEMM values val[k][q].  Column
+// data (bounds, class, cut entries) is loaded once per column, the cut loop
+// runs outside the row loop so the gamma gathers of all rows are issued
+// together, and every load precedes the stores (no aliasing between them).
+// rs[q] accumulates the element's contribution to its row constant (fp64).
+// Rows >= M or columns >= N are skipped; their addresses are clamped first.
 
-// Split override of one (row, neuron): returns the effective class and the
-// split slot (or -1).
-__device__ inline int split_of(const RowParams& rp, int r, int rank, int cls, int* slot) {
-  *slot = -1;
-  if (rank < 0 || rp.mask == nullptr) return cls;
-  int m = rp.mask[(size_t)(r / rp.S) * rp.n_I + rank];
-  if (m > 0) { *slot = m - 1; return ACTIVE; }
-  if (m < 0) { *slot = -m - 1; return INACTIVE; }
-  return cls;
+// gamma^T X for the lane's rows at column j, X in {G, H, Q}; gamma is read
+// from its transposed copy [N][mp], four consecutive rows per 16-byte load.
+template <int R>
+__device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ gammaT, int mp, int j,
+                                   const int (&rr)[R], float (&sG)[R], float (&sH)[R], float (&sQ)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) sG[q] = sH[q] = sQ[q] = 0.f;
+  if (!cc.col_ptr) return;
+  const int e0 = cc.col_ptr[j], e1 = cc.col_ptr[j + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int ck = cc.cut[e];
+    const float ch = cc.cH[e], cg = cc.cG[e], cq = cc.cQ[e];
+    const float* gk = gammaT + (size_t)ck * mp;
+    float g[R];
+    if constexpr (R % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < R; q += 4) {
+        const float4 v = *(const float4*)(gk + rr[q]);
+        g[q] = v.x; g[q + 1] = v.y; g[q + 2] = v.z; g[q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) g[q] = gk[rr[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      sG[q] += g[q] * cg;
+      sH[q] += g[q] * ch;
+      sQ[q] += g[q] * cq;
+    }
+  }
 }
 
-// ------------------------------------------------------------------ epilogues
-// Each returns the element's contribution to its row's constant (fp64).
+// Row indices of a lane: rv = row is real (< M); rc = row clamped below M,
+// for row-major [M][.] buffers; rr = row for the row-minor [.][mp] buffers,
+// where a group of 4 consecutive rows (starting at a multiple of 4) is kept
+// whole so 16-byte accesses stay aligned -- a group starting below mp lies
+// entirely below mp (mp is a multiple of 16), else it is moved to rows 0..3.
+template <int R>
+__device__ inline void lane_rows(const int (&rows)[R], int M, int mp, int (&rr)[R], int (&rc)[R], bool (&rv)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    rv[q] = rows[q] < M;
+    rc[q] = rv[q] ? rows[q] : 0;
+    if constexpr (R % 4 == 0) rr[q] = rows[q - q % 4] < mp ? rows[q] : q % 4;
+    else rr[q] = rc[q];
+  }
+}
+
+// effective class and split slot of (row, neuron) for the lane's rows
+template <int R>
+__device__ inline void split_classes(const RowParams& rp, int rank, int cls, const int (&rr)[R], int (&c)[R],
+                                     int (&slot)[R]) {
+  int m[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) m[q] = 0;
+  if (rank >= 0 && rp.mask) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) m[q] = rp.mask[(size_t)(rr[q] / rp.S) * rp.n_I + rank];
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    slot[q] = m[q] > 0 ? m[q] - 1 : (m[q] < 0 ? -m[q] - 1 : -1);
+    c[q] = m[q] > 0 ? (int)ACTIVE : (m[q] < 0 ? (int)INACTIVE : cls);
+  }
+}
+
+// Each epilogue is split in two: load() fetches everything that does not
+// depend on the GEMM result (column data, cut gathers, stored a_hat, alpha
+// and its moments, split overrides) and is issued before the K loop, so its
+// latency overlaps the GEMM; apply() combines it with the accumulator and
+// stores.  Frag holds the per-lane state between the two.
 
 template <typename T>
 struct BoundEpi {
   BoundEpiArgs a;
-  __device__ inline double operator()(int r, int j, float acc) const {
+  template <int R, int TN> struct Frag {
+    int rc[R];
+    bool rv[R];
+    float bj[TN], lj[TN], uj[TN], iul[TN];
+    float aoff[TN][R];   // acc_in + gamma^T G: added to the GEMM value -> a_hat
+    float tadd[TN][R];   // gamma^T H and the split term: added to Lambda
+    float sQ[TN][R];     // gamma^T Q
+    float al[TN][R];     // alpha (unstable) or 0
+    int8_t c[TN][R];     // effective class
+  };
+  template <int R, int TN>
+  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
-    size_t ij = (size_t)r * nd.ld + j;
-    float ah = acc;
-    if (a.acc_in) ah += a.acc_in[ij];
-    float sG = 0.f, sH = 0.f, sQ = 0.f;
-    if (a.cc.col_ptr) {
-      int e0 = a.cc.col_ptr[j], e1 = a.cc.col_ptr[j + 1];
-      const float* gr = rp.gamma + (size_t)r * rp.N;
-      for (int e = e0; e < e1; ++e) {
-        float g = gr[a.cc.cut[e]];
-        sG += g * a.cc.cG[e];
-        sH += g * a.cc.cH[e];
-        sQ += g * a.cc.cQ[e];
+    int rr[R];
+    lane_rows<R>(rows, M, rp.mp, rr, f.rc, f.rv);
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k] < N ? cols[k] : 0;
+      f.bj[k] = nd.bias[j]; f.lj[k] = nd.l[j]; f.uj[k] = nd.u[j]; f.iul[k] = nd.inv_ul[j];
+      const int cj = nd.cls[j], rk = nd.rank[j];
+      float sG[R], sH[R];
+      gather_cuts<R>(a.cc, rp.gammaT, rp.mp, j, rr, sG, sH, f.sQ[k]);
+      int c[R], slot[R];
+      split_classes<R>(rp, rk, cj, f.rc, c, slot);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
+        f.aoff[k][q] = pre + sG[q];
+        f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
+        const float bv = slot[q] >= 0 ? rp.beta[(size_t)f.rc[q] * rp.K + slot[q]] : 0.f;
+        f.tadd[k][q] = sH[q] + (c[q] == ACTIVE ? -bv : (c[q] == INACTIVE ? bv : 0.f));
+        f.c[k][q] = (int8_t)c[q];
       }
     }
-    ah += sG;                      // a_hat = Lambda^(i+1) W + gamma^T G
-    int rank = nd.rank[j];
-    int slot;
-    int c = split_of(rp, r, rank, nd.cls[j], &slot);
-    float bterm = 0.f;
-    if (slot >= 0) {
-      float bv = rp.beta[(size_t)r * rp.K + slot];
-      bterm = (c == ACTIVE) ? -bv : bv;
+  }
+  template <int R, int TN>
+  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
+                               double (&rs)[R], int M, int N) const {
+    const NodeDev& nd = a.nd;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k];
+      if (j >= N) continue;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float ah = val[k][q] + f.aoff[k][q];   // a_hat = Lambda^(i+1) W + gamma^T G
+        float lam, konst;
+        if (f.c[k][q] == ACTIVE) {                   // x_hat = x, z = 1
+          lam = ah + f.tadd[k][q];
+          konst = f.sQ[k][q];
+        } else if (f.c[k][q] == INACTIVE) {          // x_hat = 0, z = 0
+          lam = f.tadd[k][q];
+          konst = 0.f;
+        } else {                                     // Lemma A.1, C = [-a_hat]_+, q = -s
+          const float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f), sq = f.sQ[k][q];
+          float pi, h;
+          if (sq >= f.uj[k] * n) { pi = 0.f; h = 0.f; }
+          else if (sq <= f.lj[k] * n) { pi = n; h = sq; }
+          else { pi = (f.uj[k] * n - sq) * f.iul[k]; h = f.lj[k] * pi; }
+          lam = f.al[k][q] * p - pi + f.tadd[k][q];
+          konst = h;
+        }
+        if (f.rv[q]) {
+          const size_t ij = (size_t)f.rc[q] * nd.ld + j;
+          ((T*)a.lam_out)[ij] = to_t<T>(lam);
+          if (a.ahat_out) a.ahat_out[ij] = ah;
+          rs[q] += (double)lam * (double)f.bj[k] + (double)konst;
+        }
+      }
     }
-    float lam, konst;
-    if (c == ACTIVE) {             // x_hat = x, z = 1
-      lam = ah + sH + bterm;
-      konst = sQ;
-    } else if (c == INACTIVE) {    // x_hat = 0, z = 0
-      lam = sH + bterm;
-      konst = 0.f;
-    } else {                       // Lemma A.1 with C = [-a_hat]_+, q = -s
-      float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f);
-      float uu = nd.u[j], ll = nd.l[j];
-      float pi, h;
-      if (sQ >= uu * n) { pi = 0.f; h = 0.f; }
-      else if (sQ <= ll * n) { pi = n; h = sQ; }
-      else { pi = (uu * n - sQ) * nd.inv_ul[j]; h = ll * pi; }
-      lam = rp.alpha[(size_t)r * rp.n_I + rank] * p - pi + sH;
-      konst = h;
-    }
-    ((T*)a.lam_out)[ij] = to_t<T>(lam);
-    if (a.ahat_out) a.ahat_out[ij] = ah;
-    return (double)lam * (double)nd.bias[j] + (double)konst;
   }
 };
 
 struct ConcEpi {
   ConcEpiArgs a;
-  __device__ inline double operator()(int r, int j, float acc) const {
-    float v = acc;
-    if (a.cc.col_ptr) {
-      const float* gr = a.rp.gamma + (size_t)a.rp.N * r;
-      for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e) v += gr[a.cc.cut[e]] * a.cc.cG[e];
+  template <int R, int TN> struct Frag {
+    int rr[R], rc[R];
+    bool rv[R];
+    float sG[TN][R];
+  };
+  template <int R, int TN>
+  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
+    lane_rows<R>(rows, M, a.rp.mp, f.rr, f.rc, f.rv);
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k] < N ? cols[k] : 0;
+      float sH[R], sQ[R];
+      gather_cuts<R>(a.cc, a.rp.gammaT, a.rp.mp, j, f.rr, f.sG[k], sH, sQ);
     }
-    float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
-    if (a.sign_out) a.sign_out[(size_t)r * a.ld + j] = (int8_t)sg;
-    if (a.contrib && a.cc.col_ptr) {
-      float dv = (float)(a.x0[j] - a.eps * (double)sg);
-      for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
-        a.contrib[(size_t)r * a.nnz_e + a.cc.pos[e]] = a.cc.cG[e] * dv;
+  }
+  template <int R, int TN>
+  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
+                               double (&rs)[R], int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k];
+      if (j >= N) continue;
+      const double xj = a.x0[j];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float v = val[k][q] + f.sG[k][q];
+        const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
+        if (!f.rv[q]) continue;
+        if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
+        if (a.contrib && a.cc.col_ptr) {
+          const float dv = (float)(xj - a.eps * (double)sg);
+          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
+            a.contrib[(size_t)a.cc.pos[e] * a.rp.mp + f.rr[q]] = a.cc.cG[e] * dv;
+        }
+        const double vd = (double)v;
+        rs[q] += xj * vd - a.eps * fabs(vd);
+      }
     }
-    double vd = (double)v;
-    return a.x0[j] * vd - a.eps * fabs(vd);
   }
 };
 
 template <typename T>
 struct AdjEpi {
   AdjEpiArgs a;
-  __device__ inline double operator()(int r, int j, float acc) const {
+  template <int R, int TN> struct Frag {
+    int rr[R], rc[R];
+    bool rv[R];
+    float lj[TN], uj[TN], iul[TN], addj[TN];
+    int rk[TN];
+    float ah[TN][R];     // stored a_hat
+    float pre[TN][R];    // acc_in
+    float sQ[TN][R];
+    float al[TN][R], ma[TN][R], va[TN][R];
+    int8_t c[TN][R], slot[TN][R];
+  };
+  template <int R, int TN>
+  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
-    size_t ij = (size_t)r * nd.ld + j;
-    float dL = a.gemm_scale * acc + a.add_vec[j];
-    if (a.acc_in) dL += a.acc_in[ij];
-    float ah = a.ahat[ij];
-    float sQ = 0.f;
-    const float* gr = rp.gamma + (size_t)r * rp.N;
-    int e0 = 0, e1 = 0;
-    if (a.cc.col_ptr) {
-      e0 = a.cc.col_ptr[j];
-      e1 = a.cc.col_ptr[j + 1];
-      for (int e = e0; e < e1; ++e) sQ += gr[a.cc.cut[e]] * a.cc.cQ[e];
-    }
-    int rank = nd.rank[j];
-    int slot;
-    int c = split_of(rp, r, rank, nd.cls[j], &slot);
-    float dA, dS, gA = 0.f;
-    if (c == ACTIVE) {
-      dA = dL; dS = 1.f;
-    } else if (c == INACTIVE) {
-      dA = 0.f; dS = 0.f;
-    } else {
-      float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f);
-      float pos = ah > 0.f ? 1.f : 0.f, neg = ah < 0.f ? 1.f : 0.f;
-      float uu = nd.u[j], ll = nd.l[j], iul = nd.inv_ul[j];
-      float al = rp.alpha[(size_t)r * rp.n_I + rank];
-      float dLda, dhda, dLds, dhds;
-      if (sQ >= uu * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
-      else if (sQ <= ll * n) { dLda = al * pos + neg; dhda = 0.f; dLds = 0.f; dhds = 1.f; }
-      else {
-        dLda = al * pos + uu * iul * neg;
-        dhda = -ll * uu * iul * neg;
-        dLds = iul;
-        dhds = -ll * iul;
-      }
-      dA = dL * dLda + dhda;
-      dS = dL * dLds + dhds;
-      gA = dL * p;
-    }
-    if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
-    if (a.contrib) {
-      for (int e = e0; e < e1; ++e)
-        a.contrib[(size_t)r * a.nnz_e + a.cc.pos[e]] = a.cc.cG[e] * dA + a.cc.cH[e] * dL + a.cc.cQ[e] * dS;
-    }
-    if (rank >= 0) {
-      size_t ia = (size_t)r * rp.n_I + rank;
-      if (a.adam.enabled) {
-        AdamStep st(a.adam);
-        st.update(a.alpha_rw + ia, a.m_alpha + ia, a.v_alpha + ia, gA, st.lr_a, 0.f, 1.f);
-      } else {
-        a.d_alpha[ia] = gA;
+    lane_rows<R>(rows, M, rp.mp, f.rr, f.rc, f.rv);
+    const bool adam = a.adam.enabled;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k] < N ? cols[k] : 0;
+      f.lj[k] = nd.l[j]; f.uj[k] = nd.u[j]; f.iul[k] = nd.inv_ul[j]; f.addj[k] = a.add_vec[j];
+      const int cj = nd.cls[j], rk = nd.rank[j];
+      f.rk[k] = rk;
+      float sG[R], sH[R];
+      gather_cuts<R>(a.cc, rp.gammaT, rp.mp, j, f.rr, sG, sH, f.sQ[k]);
+      int c[R], slot[R];
+      split_classes<R>(rp, rk, cj, f.rc, c, slot);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
+        f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
+        const size_t ia = (size_t)f.rc[q] * rp.n_I + (rk >= 0 ? rk : 0);
+        f.al[k][q] = rk >= 0 ? rp.alpha[ia] : 0.f;
+        f.ma[k][q] = (rk >= 0 && adam) ? a.m_alpha[ia] : 0.f;
+        f.va[k][q] = (rk >= 0 && adam) ? a.v_alpha[ia] : 0.f;
+        f.c[k][q] = (int8_t)c[q];
+        f.slot[k][q] = (int8_t)slot[q];
       }
     }
-    if (slot >= 0) {
-      size_t ib = (size_t)r * rp.K + slot;
-      float gB = (c == ACTIVE) ? -dL : dL;
-      if (a.adam.enabled) {
-        AdamStep st(a.adam);
-        st.update(a.beta_rw + ib, a.m_beta + ib, a.v_beta + ib, gB, st.lr_m, 0.f, INFINITY);
-      } else {
-        a.d_beta[ib] = gB;
+  }
+  template <int R, int TN>
+  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
+                               double (&rs)[R], int M, int N) const {
+    const NodeDev& nd = a.nd;
+    const RowParams& rp = a.rp;
+    float lr_a = 0.f, lr_m = 0.f, bc1 = 1.f, bc2 = 1.f;
+    if (a.adam.enabled) {
+      lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; bc1 = a.adam.consts[2]; bc2 = a.adam.consts[3];
+    }
+    const float b1 = a.adam.b1, b2 = a.adam.b2, aeps = a.adam.eps;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k];
+      if (j >= N) continue;
+      const int rk = f.rk[k];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float dL = a.gemm_scale * val[k][q] + f.addj[k] + f.pre[k][q];
+        float dA, dS, gA = 0.f;
+        const int c = f.c[k][q];
+        if (c == ACTIVE) {
+          dA = dL; dS = 1.f;
+        } else if (c == INACTIVE) {
+          dA = 0.f; dS = 0.f;
+        } else {
+          const float x = f.ah[k][q], n = fmaxf(-x, 0.f), p = fmaxf(x, 0.f), sq = f.sQ[k][q];
+          const float pos = x > 0.f ? 1.f : 0.f, neg = x < 0.f ? 1.f : 0.f;
+          const float uj = f.uj[k], lj = f.lj[k], iul = f.iul[k], al = f.al[k][q];
+          float dLda, dhda, dLds, dhds;
+          if (sq >= uj * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
+          else if (sq <= lj * n) { dLda = al * pos + neg; dhda = 0.f; dLds = 0.f; dhds = 1.f; }
+          else {
+            dLda = al * pos + uj * iul * neg;
+            dhda = -lj * uj * iul * neg;
+            dLds = iul;
+            dhds = -lj * iul;
+          }
+          dA = dL * dLda + dhda;
+          dS = dL * dLds + dhds;
+          gA = dL * p;
+        }
+        if (!f.rv[q]) continue;
+        const size_t ij = (size_t)f.rc[q] * nd.ld + j;
+        if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
+        if (a.contrib && a.cc.col_ptr) {
+          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
+            a.contrib[(size_t)a.cc.pos[e] * rp.mp + f.rr[q]] = a.cc.cG[e] * dA + a.cc.cH[e] * dL + a.cc.cQ[e] * dS;
+        }
+        if (rk >= 0) {
+          const size_t ia = (size_t)f.rc[q] * rp.n_I + rk;
+          if (a.adam.enabled) {
+            const float mm = b1 * f.ma[k][q] + (1.f - b1) * gA;
+            const float vv = b2 * f.va[k][q] + (1.f - b2) * gA * gA;
+            a.m_alpha[ia] = mm;
+            a.v_alpha[ia] = vv;
+            const float stp = lr_a * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            a.alpha_rw[ia] = fminf(fmaxf(f.al[k][q] + stp, 0.f), 1.f);
+          } else {
+            a.d_alpha[ia] = gA;
+          }
+        }
+        const int sl = f.slot[k][q];
+        if (sl >= 0) {
+          const size_t ib = (size_t)f.rc[q] * rp.K + sl;
+          const float gB = (c == ACTIVE) ? -dL : dL;
+          if (a.adam.enabled) {
+            const float mm = b1 * a.m_beta[ib] + (1.f - b1) * gB;
+            const float vv = b2 * a.v_beta[ib] + (1.f - b2) * gB * gB;
+            a.m_beta[ib] = mm;
+            a.v_beta[ib] = vv;
+            const float stp = lr_m * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            a.beta_rw[ib] = fmaxf(a.beta_rw[ib] + stp, 0.f);
+          } else {
+            a.d_beta[ib] = gB;
+          }
+        }
       }
     }
-    return 0.0;
   }
 };
 
 struct StoreEpi {
   StoreEpiArgs a;
-  __device__ inline double operator()(int r, int j, float acc) const {
-    size_t ij = (size_t)r * a.ld + j;
-    float v = a.scale * acc;
-    if (a.acc_in) v += a.acc_in[ij];
-    a.out[ij] = v;
-    return 0.0;
+  template <int R, int TN> struct Frag {
+    int rc[R];
+    bool rv[R];
+    float pre[TN][R];
+  };
+  template <int R, int TN>
+  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
+#pragma unroll
+    for (int q = 0; q < R; ++q) { f.rv[q] = rows[q] < M; f.rc[q] = f.rv[q] ? rows[q] : 0; }
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k] < N ? cols[k] : 0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * a.ld + j] : 0.f;
+    }
+  }
+  template <int R, int TN>
+  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
+                               double (&rs)[R], int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      const int j = cols[k];
+      if (j >= N) continue;
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (f.rv[q]) a.out[(size_t)f.rc[q] * a.ld + j] = a.scale * val[k][q] + f.pre[k][q];
+    }
   }
 };
 
@@ -337,6 +506,23 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   const int bcol = wn * (BN / WN) + (lane & 15);
   const int kq = (lane >> 4) * VEC;
 
+  // output coordinates of this lane and the epilogue operands that do not
+  // depend on the GEMM result, fetched before the K loop
+  constexpr int R = TM * 4;
+  int rows[R], cols[TN];
+  {
+    const int row0 = m0 + wm * (BM / WM) + (lane >> 4) * 4;
+    const int col0 = n0 + wn * (BN / WN) + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rows[i * 4 + v] = row0 + i * 16 + v;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) cols[k] = col0 + k * 16;
+  }
+  typename Epi::template Frag<R, TN> fr;
+  epi.template load<R, TN>(fr, rows, cols, g.M, g.N);
+
   if (g.K > 0) load_stage(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
@@ -358,31 +544,39 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   }
 
   // Epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of each 16x16 tile.
+  {
+    double rs[R];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+    for (int q = 0; q < R; ++q) rs[q] = 0.0;
+    float val[TN][R];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int rl = wm * (BM / WM) + i * 16 + (lane >> 4) * 4 + v;
-      int r = m0 + rl;
-      double rs = 0.0;
+    for (int k = 0; k < TN; ++k)
 #pragma unroll
-      for (int k = 0; k < TN; ++k) {
-        int j = n0 + wn * (BN / WN) + k * 16 + (lane & 15);
-        if (r < g.M && j < g.N) rs += epi(r, j, acc[i][k][v]);
-      }
-      rs = wave_sum16(rs);
-      if ((lane & 15) == 0) red[wn][rl] = rs;
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) val[k][i * 4 + v] = acc[i][k][v];
+    epi.template apply<R, TN>(fr, cols, val, rs, g.M, g.N);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double t = wave_sum16(rs[q]);
+      if ((lane & 15) == 0) red[wn][rows[q] - m0] = t;
     }
   }
   if (g.partial) {
+    // row partials: one slot per 32 output columns, independent of the tile;
+    // this block's sum goes to its first slot, zeros to the others it covers
     __syncthreads();
+    const int nsl = (g.N + 31) / 32;
+    const int s0 = blockIdx.x * (BN / 32);
     for (int rl = tid; rl < BM; rl += NT) {
       int r = m0 + rl;
       if (r < g.M) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < WN; ++w) s += red[w][rl];
-        g.partial[(size_t)r * g.n_slots + g.slot0 + blockIdx.x] = s;
+#pragma unroll
+        for (int t = 0; t < BN / 32; ++t)
+          if (s0 + t < nsl) g.partial[(size_t)(g.slot0 + s0 + t) * g.mp + r] = t == 0 ? s : 0.0;
       }
     }
   }
@@ -390,13 +584,14 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
 
 // Tile configurations available to the autotuner: (BM, BN, WM, WN).
 struct TileCfg { int bm, bn; };
-static const TileCfg kCfgs[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}};
+static const TileCfg kCfgs[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {32, 32}};
+static_assert(sizeof(kCfgs) / sizeof(kCfgs[0]) == 6, "tile table");
 int gemm_num_configs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 void gemm_config_tile(int cfg, int* bm, int* bn) { *bm = kCfgs[cfg].bm; *bn = kCfgs[cfg].bn; }
 
 template <typename T, int BM, int BN, int WM, int WN, bool SIGN, class Epi>
 static hipError_t launch_cfg(const GemmArgs& g, const Epi& epi, hipStream_t st) {
-  constexpr int BK = (sizeof(T) == 4) ? 32 : 64;
+  constexpr int BK = (sizeof(T) == 4) ? 64 : 128;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
   hipLaunchKernelGGL((gemm_epi_kernel<T, BM, BN, WM, WN, BK, SIGN, Epi>), grid, dim3(WM * WN * 64), 0, st,
                      g, epi);
@@ -410,7 +605,8 @@ static hipError_t launch_any(int cfg, const GemmArgs& g, const Epi& epi, hipStre
     case 1: return launch_cfg<T, 128, 64, 2, 2, SIGN>(g, epi, st);
     case 2: return launch_cfg<T, 64, 128, 2, 2, SIGN>(g, epi, st);
     case 3: return launch_cfg<T, 128, 128, 2, 2, SIGN>(g, epi, st);
-    case 4: return launch_cfg<T, 32, 64, 1, 2, SIGN>(g, epi, st);
+    case 4: return launch_cfg<T, 32, 64, 2, 2, SIGN>(g, epi, st);
+    case 5: return launch_cfg<T, 32, 32, 2, 2, SIGN>(g, epi, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -440,30 +636,32 @@ hipError_t launch_gemm(int bf16_mode, int cfg, EpiKind kind, const GemmArgs& g, 
 // One block = one row x 256 columns; row partial per column block.
 template <typename T>
 __global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, BoundEpiArgs a, double* partial,
-                                                         int n_slots, int slot0) {
+                                                         int slot0) {
   __shared__ double red[4];
   const int r = blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
   BoundEpi<T> epi{a};
-  double rs = 0.0;
-  if (j < a.nd.size) {
-    float pre = bcast ? bcast[(size_t)(r % a.rp.S) * a.nd.ld + j] : 0.f;
-    rs = epi(r, j, pre);
-  }
-  for (int o = 32; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
+  int rows[1] = {r}, cols[1] = {j};
+  float val[1][1] = {{(bcast && j < a.nd.size) ? bcast[(size_t)(r % a.rp.S) * a.nd.ld + j] : 0.f}};
+  double rs[1] = {0.0};
+  typename BoundEpi<T>::template Frag<1, 1> fr;
+  epi.template load<1, 1>(fr, rows, cols, a.rp.M, a.nd.size);
+  epi.template apply<1, 1>(fr, cols, val, rs, a.rp.M, a.nd.size);
+  double t = rs[0];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0 && partial)
-    partial[(size_t)r * n_slots + slot0 + blockIdx.y] = (red[0] + red[1]) + (red[2] + red[3]);
+    partial[(size_t)(slot0 + blockIdx.y) * a.rp.mp + r] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const BoundEpiArgs& a,
-                                          double* partial, int n_slots, int slot0, hipStream_t st) {
+                                          double* partial, int slot0, hipStream_t st) {
   dim3 grid(a.rp.M, (a.nd.size + 255) / 256);
   if (bf16_mode)
-    hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, a, partial, n_slots, slot0);
+    hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, a, partial, slot0);
   else
-    hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, a, partial, n_slots, slot0);
+    hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, a, partial, slot0);
   return hipGetLastError();
 }
 
@@ -472,7 +670,12 @@ __global__ void __launch_bounds__(256) adj_elem_kernel(AdjEpiArgs a) {
   const int r = blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
   AdjEpi<T> epi{a};
-  if (j < a.nd.size) epi(r, j, 0.f);
+  int rows[1] = {r}, cols[1] = {j};
+  float val[1][1] = {{0.f}};
+  double rs[1] = {0.0};
+  typename AdjEpi<T>::template Frag<1, 1> fr;
+  epi.template load<1, 1>(fr, rows, cols, a.rp.M, a.nd.size);
+  epi.template apply<1, 1>(fr, cols, val, rs, a.rp.M, a.nd.size);
 }
 
 hipError_t launch_adj_elementwise(int bf16_mode, const AdjEpiArgs& a, hipStream_t st) {
@@ -521,92 +724,120 @@ hipError_t launch_out_const(const double* C, int S, int d_out, const float* bias
   return hipGetLastError();
 }
 
-// out[j] = bias[j] + (A x0)_j for an edge from the network input (fp64 sums).
-__global__ void wx0_kernel(ConvGeom cg, int kind, const float* W, int d_out, int d_in, const double* x0,
-                           const float* bias, float* out) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
+// out[j] = (bias ? bias[j] : out[j]) + (A x0)_j for an edge from the network
+// input, fp64 sums; one wave per output, lanes stride over the inputs.
+__global__ void __launch_bounds__(256) wx0_kernel(ConvGeom cg, int kind, const float* W, int d_out, int d_in,
+                                                  const double* x0, const float* bias, float* out) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= d_out) return;
-  double acc = bias ? (double)bias[j] : 0.0;
+  double acc = 0.0;
   if (kind == 0) {
-    for (int k = 0; k < d_in; ++k) acc += (double)W[(size_t)j * d_in + k] * x0[k];
+    for (int k = lane; k < d_in; k += 64) acc += (double)W[(size_t)j * d_in + k] * x0[k];
   } else if (kind == 1) {
-    int o = j / (cg.ho * cg.wo), y = (j / cg.wo) % cg.ho, x = j % cg.wo;
-    for (int c = 0; c < cg.ci; ++c)
-      for (int ky = 0; ky < cg.kh; ++ky) {
-        int iy = y * cg.stride - cg.pad + ky;
-        if (iy < 0 || iy >= cg.hi) continue;
-        for (int kx = 0; kx < cg.kw; ++kx) {
-          int ix = x * cg.stride - cg.pad + kx;
-          if (ix < 0 || ix >= cg.wi) continue;
-          acc += (double)W[((size_t)(o * cg.ci + c) * cg.kh + ky) * cg.kw + kx] * x0[(c * cg.hi + iy) * cg.wi + ix];
-        }
-      }
-  } else {
-    acc += x0[j];
+    const int o = j / (cg.ho * cg.wo), y = (j / cg.wo) % cg.ho, x = j % cg.wo;
+    const int taps = cg.ci * cg.kh * cg.kw;
+    for (int t = lane; t < taps; t += 64) {
+      const int c = t / (cg.kh * cg.kw), ky = (t / cg.kw) % cg.kh, kx = t % cg.kw;
+      const int iy = y * cg.stride - cg.pad + ky, ix = x * cg.stride - cg.pad + kx;
+      if (iy < 0 || iy >= cg.hi || ix < 0 || ix >= cg.wi) continue;
+      acc += (double)W[((size_t)(o * cg.ci + c) * cg.kh + ky) * cg.kw + kx] * x0[(c * cg.hi + iy) * cg.wi + ix];
+    }
+  } else if (lane == 0) {
+    acc = x0[j];
   }
-  out[j] = (float)acc;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) out[j] = (float)((bias ? (double)bias[j] : (double)out[j]) + acc);
 }
 
 hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, int d_in, const double* x0,
                       const float* bias, float* out, hipStream_t st) {
   ConvGeom g = cg ? *cg : ConvGeom{};
-  hipLaunchKernelGGL(wx0_kernel, dim3((d_out + 255) / 256), dim3(256), 0, st, g, kind, W, d_out, d_in, x0, bias,
-                     out);
+  hipLaunchKernelGGL(wx0_kernel, dim3((d_out + 3) / 4), dim3(256), 0, st, g, kind, W, d_out, d_in, x0, bias, out);
   return hipGetLastError();
 }
 
-// bound[r] = sum_slots partial[r][.] + c_s.b_out - gamma_r.d   (one wave per row)
-__global__ void __launch_bounds__(256) reduce_rows_kernel(int M, int S, const double* partial, int n_slots,
-                                                          const double* cb, const float* gamma, int N,
+// bound[r] = sum_slots partial[slot][r] + c_s.b_out - gamma_r.d, fixed
+// summation order (thread per row, coalesced over rows).
+__global__ void __launch_bounds__(256) reduce_rows_kernel(int M, int mp, int S, const double* partial, int n_slots,
+                                                          const double* cb, const float* gammaT, int N,
                                                           const double* d, double* bound, uint8_t* verified) {
-  int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= M) return;
   double s = 0.0;
-  for (int k = lane; k < n_slots; k += 64) s += partial[(size_t)r * n_slots + k];
-  for (int k = lane; k < N; k += 64) s -= (double)gamma[(size_t)r * N + k] * d[k];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) {
-    double b = s + cb[r % S];
-    bound[r] = b;
-    if (verified) verified[r] = (b >= 0.0) ? 1 : 0;
-  }
+  for (int k = 0; k < n_slots; ++k) s += partial[(size_t)k * mp + r];
+  double gd = 0.0;
+  for (int k = 0; k < N; ++k) gd += (double)gammaT[(size_t)k * mp + r] * d[k];
+  const double b = s + cb[r % S] - gd;
+  bound[r] = b;
+  if (verified) verified[r] = (b >= 0.0) ? 1 : 0;
 }
 
-hipError_t launch_reduce_rows(int M, int S, const double* partial, int n_slots, const double* cb,
-                              const float* gamma, int N, const double* d, double* bound, uint8_t* verified,
+hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n_slots, const double* cb,
+                              const float* gammaT, int N, const double* d, double* bound, uint8_t* verified,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3((M + 3) / 4), dim3(256), 0, st, M, S, partial, n_slots, cb, gamma,
-                     N, d, bound, verified);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((M + 255) / 256), dim3(256), 0, st, M, mp, S, partial, n_slots, cb,
+                     gammaT, N, d, bound, verified);
   return hipGetLastError();
 }
 
-// d bound / d gamma[r][k] = -d_k + sum of the cut's entry contributions;
-// then the Adam ascent step (gamma >= 0) or the raw gradient.
-__global__ void __launch_bounds__(256) gamma_kernel(int M, int N, const int32_t* row_ptr, const float* contrib,
-                                                    int nnz_e, const double* d, float* gamma, float* d_gamma,
-                                                    float* m, float* v, AdamArgs adam) {
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)M * N) return;
-  int r = (int)(idx / N), k = (int)(idx % N);
+// d bound / d gamma[r][k] = -d_k + sum of the cut's entry pieces (entries of
+// cut k are contiguous in the cut-major order); then the Adam ascent step on
+// gammaT (gamma >= 0, moments [N][M]) or the raw gradient into d_gamma[M][N].
+// Thread per (k, r), rows fastest.
+__global__ void __launch_bounds__(256) gamma_kernel(int M, int mp, int N, const int32_t* row_ptr,
+                                                    const float* contrib, const double* d, float* gammaT,
+                                                    float* d_gamma, float* m, float* v, AdamArgs adam) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= M) return;
   double g = -d[k];
-  const float* cr = contrib + (size_t)r * nnz_e;
-  for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e) g += (double)cr[e];
+  for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e) g += (double)contrib[(size_t)e * mp + r];
   if (adam.enabled) {
-    AdamStep st(adam);
-    st.update(gamma + idx, m + idx, v + idx, (float)g, st.lr_m, 0.f, INFINITY);
+    const float lr = adam.consts[1], bc1 = adam.consts[2], bc2 = adam.consts[3];
+    const float gf = (float)g;
+    const size_t im = (size_t)k * M + r;
+    const float mm = adam.b1 * m[im] + (1.f - adam.b1) * gf;
+    const float vv = adam.b2 * v[im] + (1.f - adam.b2) * gf * gf;
+    m[im] = mm;
+    v[im] = vv;
+    float* gp = gammaT + (size_t)k * mp + r;
+    *gp = fmaxf(*gp + lr * (mm / bc1) / (sqrtf(vv / bc2) + adam.eps), 0.f);
   } else {
-    d_gamma[idx] = (float)g;
+    d_gamma[(size_t)r * N + k] = (float)g;
   }
 }
 
-hipError_t launch_gamma_update(int M, int N, const int32_t* row_ptr, const float* contrib, int nnz_e,
-                               const double* d, float* gamma, float* d_gamma, float* m, float* v, AdamArgs adam,
-                               hipStream_t st) {
-  size_t n = (size_t)M * N;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, row_ptr, contrib,
-                     nnz_e, d, gamma, d_gamma, m, v, adam);
+hipError_t launch_gamma_update(int M, int mp, int N, const int32_t* row_ptr, const float* contrib, const double* d,
+                               float* gammaT, float* d_gamma, float* m, float* v, AdamArgs adam, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  dim3 grid((M + 255) / 256, N);
+  hipLaunchKernelGGL(gamma_kernel, grid, dim3(256), 0, st, M, mp, N, row_ptr, contrib, d, gammaT, d_gamma, m, v,
+                     adam);
+  return hipGetLastError();
+}
+
+// [rows][cols] (pitch ld_in) -> [cols][ld_out], 32x32 tiles through LDS
+__global__ void __launch_bounds__(256) transpose_kernel(const float* in, int rows, int cols, int ld_in, float* out,
+                                                        int ld_out) {
+  __shared__ float t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, c = c0 + tx;
+    t[y][tx] = (r < rows && c < cols) ? in[(size_t)r * ld_in + c] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int c = c0 + y, r = r0 + tx;
+    if (c < cols && r < rows) out[(size_t)c * ld_out + r] = t[tx][y];
+  }
+}
+
+hipError_t launch_transpose(const float* in, int rows, int cols, int ld_in, float* out, int ld_out, hipStream_t st) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, in, rows, cols, ld_in, out, ld_out);
   return hipGetLastError();
 }
 
