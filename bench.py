@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--domains", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp32-mode comparison run")
-    ap.add_argument("--cpu-domains", type=int, default=128)
+    ap.add_argument("--cpu-domains", type=int, default=1024)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     return ap.parse_args()
 
 
@@ -87,8 +90,23 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mode = B.GCP_MODE_BF16 if args.mode == "bf16" else B.GCP_MODE_FP32
     dt = timed(mode, args.steps, args.warmup)
+    kprof = None
+    if not args.no_profile:
+        # the same K steps again with every library launch bracketed by HIP
+        # events on its stream (the markers slow the run, so `value` comes
+        # from the uninstrumented region above)
+        B.profile_enable(True)
+        dt_prof = timed(mode, args.steps, 0)
+        B.profile_enable(False)
+        kprof = B.profile_read()
     bound_main = bound.cpu().numpy().copy()
     value = args.domains * args.steps / dt
     out = {
@@ -112,6 +130,11 @@ def main():
             "domain_iters_per_s": value * o["iters"],
         },
     }
+    if kprof:
+        out["roofline"] = roofline(kprof, args.mode)
+        out["roofline"]["instrumented_ms_per_step"] = dt_prof * 1000.0 / args.steps
+        out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
+                                    for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     if not args.no_compare:
         other = B.GCP_MODE_FP32 if mode == B.GCP_MODE_BF16 else B.GCP_MODE_BF16
         dt2 = timed(other, max(1, args.steps // 2), 1)
@@ -126,6 +149,48 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_domains)
     print(json.dumps(out))
+
+
+def roofline(kprof, dtype):
+    """Dominant kernel class (largest total time in the timed region): its
+    algorithmic bytes or FLOPs per launch over its average event-timed
+    duration, against the published MI355X peak for the bound its
+    arithmetic intensity implies."""
+    name, k = max(kprof.items(), key=lambda kv: kv[1]["ms"])
+    secs = k["ms"] * 1e-3
+    mf_peak = PEAKS["bf16_TFLOPs"] if ".bf16" in name else PEAKS["fp32_TFLOPs"]
+    ridge = mf_peak * 1e12 / (PEAKS["hbm_GBps"] * 1e9)
+    ai = k["flops"] / k["bytes"] if k["bytes"] else float("inf")
+    per_launch_bytes = k["bytes"] / k["launches"]
+    r = {"kernel": name, "launches": k["launches"], "avg_us": 1e6 * secs / k["launches"],
+         "algorithmic_bytes_per_launch": per_launch_bytes, "flops_per_launch": k["flops"] / k["launches"],
+         "arith_intensity": ai}
+    if ai < ridge:
+        ach = k["bytes"] / secs / 1e9
+        r.update(bound="hbm", achieved=ach, peak=PEAKS["hbm_GBps"], unit="GB/s", frac=ach / PEAKS["hbm_GBps"])
+    else:
+        ach = k["flops"] / secs / 1e12
+        r.update(bound="mfma", achieved=ach, peak=mf_peak, unit="TFLOP/s", frac=ach / mf_peak)
+    r["traffic"] = measured_traffic(name)
+    return r
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size), or None when no record exists
+    for this kernel or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    from paper_2208_05740_amd.profiling import source_sha
+    if rec.get("source_sha") != source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["fetch_kib"] * 1024 * rec["fetch_scale"] + k["write_kib"] * 1024 * rec["write_scale"]
 
 
 def cpu_baseline(prob, nd):

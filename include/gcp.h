@@ -198,6 +198,21 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  const gcp_opt* opt, int32_t mode,
                  double* bound, uint8_t* verified, void* stream);
 
+/* ------------------------------------------------------------ profiling */
+/* Kernel timing for roofline reports.  While enabled, every kernel the
+ * library launches is bracketed by HIP events on the stream it runs on and
+ * attributed to a class (one class per kernel instantiation: epilogue kind,
+ * operand type, sign input, tile shape); each launch also records its
+ * algorithmic HBM bytes (operands read once, results written once) and
+ * FLOPs.  gcp_profile_enable(1) resets the records, (0) stops recording.
+ * gcp_profile_read synchronises the recorded events and returns class idx
+ * (0-based, GCP_EINVAL past the last class): its name (NUL-terminated,
+ * truncated to name_len), launches, total milliseconds, bytes and FLOPs.
+ * Autotuner trial launches are never recorded. */
+int gcp_profile_enable(int32_t on);
+int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64_t* launches,
+                     double* total_ms, double* bytes, double* flops);
+
 /* Last error message of this thread ("" if none). */
 const char* gcp_last_error(void);
 

@@ -59,8 +59,8 @@ class OptDesc(C.Structure):
 
 _LIB = None
 EXPORTS = ["gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
-           "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_last_error",
-           "gcp_version"]
+           "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
+           "gcp_profile_read", "gcp_last_error", "gcp_version"]
 
 
 def lib():
@@ -81,10 +81,14 @@ def lib():
     L.gcp_splits_destroy.argtypes = [vp]
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
+    L.gcp_profile_enable.argtypes = [i32]
+    L.gcp_profile_read.argtypes = [i32, C.c_char_p, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.gcp_last_error.restype = C.c_char_p
     L.gcp_version.restype = C.c_char_p
     for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
-              "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize"):
+              "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
+              "gcp_profile_read"):
         getattr(L, f).restype = C.c_int
     _LIB = L
     return L
@@ -294,3 +298,23 @@ def gcp_bound_autograd(P, alpha, beta, gamma, mode=GCP_MODE_FP32):
     if _GCPBound is None:
         _GCPBound = _bound_autograd()
     return _GCPBound.apply(P, alpha, beta, gamma, mode)
+
+
+def profile_enable(on: bool = True):
+    """Start (reset) or stop the library's per-kernel event timing."""
+    _check(lib().gcp_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """Per kernel class: {name: dict(launches, ms, bytes, flops)}."""
+    out = {}
+    i = 0
+    buf = C.create_string_buffer(256)
+    while True:
+        n, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        rc = lib().gcp_profile_read(i, buf, 256, C.byref(n), C.byref(ms), C.byref(by), C.byref(fl))
+        if rc != 0:
+            break
+        out[buf.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+        i += 1
+    return out

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -41,6 +42,65 @@ void hip_check(hipError_t e, const char* what) {
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ profiler
+// Process-wide record of kernel launches bracketed by HIP events (only while
+// enabled).  Aggregation happens at read time.
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  struct Rec { int cls; hipEvent_t e0, e1; double bytes, flops; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> names;
+  std::map<std::string, int> ids;
+  struct Agg { int64_t n = 0; double ms = 0, bytes = 0, flops = 0; };
+  std::vector<Agg> agg;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+  void flush() {   // fold recorded events into the aggregates
+    for (auto& r : recs) {
+      hip_check(hipEventSynchronize(r.e1), "hipEventSynchronize");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, r.e0, r.e1), "hipEventElapsedTime");
+      if ((int)agg.size() <= r.cls) agg.resize(r.cls + 1);
+      agg[r.cls].n++; agg[r.cls].ms += ms; agg[r.cls].bytes += r.bytes; agg[r.cls].flops += r.flops;
+      pool.push_back(r.e0); pool.push_back(r.e1);
+    }
+    recs.clear();
+  }
+};
+Profiler& prof() { static Profiler p; return p; }
+
+// Launch `f` on `st`; while profiling, bracket it with events under `name`.
+template <class F>
+hipError_t timed(hipStream_t st, const std::string& name, double bytes, double flops, F f) {
+  Profiler& P = prof();
+  if (!P.on) return f();
+  std::lock_guard<std::mutex> lk(P.mu);
+  hipEvent_t e0 = P.get(), e1 = P.get();
+  hip_check(hipEventRecord(e0, st), "hipEventRecord");
+  hipError_t err = f();
+  hip_check(hipEventRecord(e1, st), "hipEventRecord");
+  auto it = P.ids.find(name);
+  int cls;
+  if (it == P.ids.end()) { cls = (int)P.names.size(); P.ids[name] = cls; P.names.push_back(name); }
+  else cls = it->second;
+  P.recs.push_back(Profiler::Rec{cls, e0, e1, bytes, flops});
+  return err;
+}
+
+std::string cls_name(const char* kind, int bf16, int sign, int cfg) {
+  int bm = 0, bn = 0;
+  if (cfg >= 0) gemm_config_tile(cfg, &bm, &bn);
+  std::string n = std::string(kind) + (bf16 ? ".bf16" : ".fp32") + (sign ? ".sign" : "");
+  if (cfg >= 0) n += ".t" + std::to_string(bm) + "x" + std::to_string(bn);
+  return n;
+}
 
 // Owned device allocation (zero-filled at allocation).
 struct DBuf {
@@ -128,7 +188,6 @@ struct gcp_net {
     std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
     int n_slots = 0;
   } ws;
-  std::map<std::tuple<int, int, int, int>, int> tile_cache;   // (bf16, M, N, K) -> cfg
 };
 
 struct gcp_cuts {
@@ -146,6 +205,7 @@ struct gcp_cuts {
     }
   };
   std::vector<Col> cols;   // per node; index n_nodes is the network input
+  std::vector<int> nnz_node;   // merged entries per node (same indexing)
   const gcp_net* net = nullptr;
 };
 
@@ -317,7 +377,7 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
 // trial (same inputs, outputs that the real launch overwrites, or scratch)
 // timed with HIP events, and the fastest is cached per (kind, precision,
 // sign input, M, N, K).  GCP_AUTOTUNE=0 selects a fixed heuristic instead.
-const int kTileCandidates[] = {0, 1, 2, 4, 5};   // 128x128 spills with the fused epilogues
+const int kTileCandidates[] = {0, 1, 2, 4, 5, 6, 7};   // 128x128 spills with the fused epilogues
 
 bool autotune_enabled() {
   const char* e = std::getenv("GCP_AUTOTUNE");
@@ -325,21 +385,62 @@ bool autotune_enabled() {
 }
 
 int heuristic_cfg(int M, int N) {
-  static const int order[] = {1, 2, 0, 4, 5};
+  static const int order[] = {1, 2, 0, 4, 5, 6, 7};
   for (int c : order) {
     int bm, bn;
     gemm_config_tile(c, &bm, &bn);
     long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
     if (tiles >= 1024) return c;
   }
-  return 5;
+  return 7;
 }
+
+// Process-wide tile cache.  With GCP_TILE_CACHE=<file> decisions are read
+// from the file at first use and every new decision is appended, so a later
+// process (for example a profiler run) launches exactly the same tiles.
+struct TileCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, int> m;
+  const char* path() { return std::getenv("GCP_TILE_CACHE"); }
+  void load() {
+    if (loaded) return;
+    loaded = true;
+    const char* p = path();
+    if (!p) return;
+    FILE* f = std::fopen(p, "r");
+    if (!f) return;
+    char key[128];
+    int cfg;
+    while (std::fscanf(f, "%127s %d", key, &cfg) == 2)
+      if (cfg >= 0 && cfg < gemm_num_configs()) m[key] = cfg;
+    std::fclose(f);
+  }
+  void store(const std::string& key, int cfg) {
+    m[key] = cfg;
+    const char* p = path();
+    if (!p) return;
+    FILE* f = std::fopen(p, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), cfg);
+    std::fclose(f);
+  }
+};
+TileCache& tile_cache() { static TileCache t; return t; }
 
 template <class Trial>
 int choose_cfg(gcp_net* net, int kind, int bf16, int sign, int M, int N, int K, hipStream_t st, Trial trial) {
-  auto key = std::make_tuple(kind * 4 + bf16 * 2 + sign, M, N, K);
-  auto it = net->tile_cache.find(key);
-  if (it != net->tile_cache.end()) return it->second;
+  (void)net;
+  char kb[128];
+  std::snprintf(kb, sizeof kb, "k%d.b%d.s%d.M%d.N%d.K%d", kind, bf16, sign, M, N, K);
+  const std::string key(kb);
+  TileCache& TC = tile_cache();
+  {
+    std::lock_guard<std::mutex> lk(TC.mu);
+    TC.load();
+    auto it = TC.m.find(key);
+    if (it != TC.m.end()) return it->second;
+  }
   int best = heuristic_cfg(M, N);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(st, &cs);
@@ -361,7 +462,8 @@ int choose_cfg(gcp_net* net, int kind, int bf16, int sign, int M, int N, int K, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
-  net->tile_cache[key] = best;
+  std::lock_guard<std::mutex> lk(TC.mu);
+  TC.store(key, best);
   return best;
 }
 
@@ -463,6 +565,8 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   std::vector<double> dv(d ? d : (const double*)nullptr, d ? d + n_cuts : (const double*)nullptr);
   C->d.upload(dv);
   C->cols.resize(n_nodes + 1);
+  C->nnz_node.assign(n_nodes + 1, 0);
+  for (auto& e : ents) C->nnz_node[e.nd < 0 ? n_nodes : e.nd]++;
   for (int nd = -1; nd < n_nodes; ++nd) {
     if (nd >= 0 && !net->nodes[nd].relu) continue;
     int sz = nd < 0 ? net->in_size : net->nodes[nd].size;
@@ -597,6 +701,12 @@ CutCol cut_col(const Call& c, int node) {
   return c.cuts->cols[idx].dev();
 }
 
+double nnz_of(const Call& c, int node) {
+  if (!c.cuts) return 0.0;
+  return (double)c.cuts->nnz_node[node < 0 ? (int)c.net->nodes.size() : node];
+}
+double unst_of(const Call& c, int node) { return node < 0 ? 0.0 : (double)c.net->nodes[node].n_unst; }
+
 float* tune_store(Call& c) {
   auto& ws = c.net->ws;
   size_t need = 0;
@@ -677,8 +787,15 @@ struct BoundPass {
       BoundEpiArgs a = bound_args(p, false);
       int nslot = slots_for_elementwise(net->nodes[p].size);
       if (!dry)
-        check(launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], a, ws.partial.as<double>(),
-                                       slot, c.st));
+      {
+        const double M = c.M, d = net->nodes[p].size, esz = bf16 ? 2 : 4;
+        const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
+                             (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
+        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
+          return launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], a, ws.partial.as<double>(),
+                                          slot, c.st);
+        }));
+      }
       slot += nslot;
     }
     for (int i = net->out - 1; i >= 0; --i) {
@@ -727,7 +844,10 @@ struct BoundPass {
             t.out = tune_store(c);
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
-          check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+          const double esz = bf16 ? 2 : 4;
+          const double bytes = (double)g.M * g.K * esz + (double)g.N * g.K * esz + (double)g.M * g.N * 4 * (first ? 1 : 2);
+          check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                      [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         }
         return;
       }
@@ -740,7 +860,12 @@ struct BoundPass {
           int cfg = choose_cfg(net, EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st,
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_BOUND, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
-          check(launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st));
+          const double M = g.M, esz = bf16 ? 2 : 4, dp = g.N;
+          const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * 4 : 0) +
+                               M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
+                               (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
+          check(timed(c.st, cls_name("bound", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                      [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
         }
       } else {
         if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
@@ -756,7 +881,11 @@ struct BoundPass {
           int cfg = choose_cfg(net, EPI_CONC, bf16, 0, g.M, g.N, g.K, c.st,
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_CONC, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
-          check(launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st));
+          const double M = g.M, esz = bf16 ? 2 : 4;
+          const double bytes = M * g.K * esz + (double)g.N * g.K * esz + (keep_ahat ? M * g.N : 0) +
+                               M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
+          check(timed(c.st, cls_name("conc", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                      [&] { return launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st); }));
         }
       }
       slot += nslot;
@@ -837,7 +966,11 @@ struct AdjPass {
             t.out = tune_store(c);
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
-          check(launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st));
+          const double esz = bf16 ? 2 : 4;
+          const double bytes = (double)g.M * g.K * (sign ? 1 : esz) + (double)g.N * g.K * esz +
+                               (double)g.M * g.N * 4 * (first ? 1 : 2);
+          check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                      [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, has_acc ? accbuf : nullptr, scale);
           int cfg = choose_cfg(net, EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, [&](int cf) {
@@ -847,7 +980,12 @@ struct AdjPass {
             t.d_beta = tune_beta(c);
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
-          check(launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st));
+          const double M = g.M, esz = bf16 ? 2 : 4, di = g.N;
+          const double bytes = M * g.K * (sign ? 1 : esz) + (double)g.N * g.K * esz + M * di * 4 +
+                               M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
+                               M * nnz_of(c, i) * 8 + M * di * esz + (has_acc ? M * di * 4 : 0);
+          check(timed(c.st, cls_name("adj", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                      [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
       } else {
         fail(GCP_EUNSUPPORTED, "edge kind not supported yet in the adjoint");
@@ -936,9 +1074,12 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
   BoundPass bp(c, bf16, keep_ahat, contrib, false);
   bp.run();
   auto& ws = c.net->ws;
-  hip_check(launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
-                               c.rp.gammaT, c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound, verified,
-                               c.st),
+  const double rb = (double)c.M * (ws.n_slots * 8.0 + c.rp.N * 4.0 + 8.0 + (verified ? 1 : 0));
+  hip_check(timed(c.st, "reduce_rows", rb, 0.0, [&] {
+              return launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
+                                        c.rp.gammaT, c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound,
+                                        verified, c.st);
+            }),
             "reduce");
 }
 
@@ -970,9 +1111,11 @@ extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, con
     ap.prepare();
     ap.run();
     if (c.rp.N > 0)
-      hip_check(launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), net->ws.contrib.as<float>(),
-                                    c.cuts->d.as<double>(), nullptr, d_gamma, nullptr, nullptr,
-                                    AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st),
+      hip_check(timed(c.st, "gamma_grad", (double)c.M * (c.nnz * 4.0 + c.rp.N * 4.0), 0.0, [&] {
+                  return launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(),
+                                             net->ws.contrib.as<float>(), c.cuts->d.as<double>(), nullptr, d_gamma,
+                                             nullptr, nullptr, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st);
+                }),
                 "gamma gradient");
   }
   g_err.clear();
@@ -1019,14 +1162,49 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
     AdjPass ap{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
     ap.run();
     if (N > 0)
-      hip_check(launch_gamma_update(c.M, c.rp.mp, (int)N, c.cuts->row_ptr.as<int32_t>(), ws.contrib.as<float>(),
-                                    c.cuts->d.as<double>(), ws.gammaT.as<float>(), nullptr, mg, vg, adam, c.st),
+      hip_check(timed(c.st, "gamma_adam", (double)c.M * (c.nnz * 4.0 + N * 24.0), 0.0, [&] {
+                  return launch_gamma_update(c.M, c.rp.mp, (int)N, c.cuts->row_ptr.as<int32_t>(),
+                                             ws.contrib.as<float>(), c.cuts->d.as<double>(), ws.gammaT.as<float>(),
+                                             nullptr, mg, vg, adam, c.st);
+                }),
                 "gamma update");
   }
   if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   bound_pass(c, 0, false, false, bound, verified);
   g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_profile_enable(int32_t on) {
+  GCP_TRY
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (on) {
+    P.flush();
+    P.agg.clear();
+  }
+  P.on = on != 0;
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64_t* launches, double* total_ms,
+                                double* bytes, double* flops) {
+  GCP_TRY
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.flush();
+  if (idx < 0 || idx >= (int)P.names.size()) fail(GCP_EINVAL, "no such profile class");
+  Profiler::Agg a = idx < (int)P.agg.size() ? P.agg[idx] : Profiler::Agg{};
+  if (name && name_len > 0) {
+    std::snprintf(name, name_len, "%s", P.names[idx].c_str());
+  }
+  if (launches) *launches = a.n;
+  if (total_ms) *total_ms = a.ms;
+  if (bytes) *bytes = a.bytes;
+  if (flops) *flops = a.flops;
   return GCP_OK;
   GCP_CATCH
 }

@@ -440,7 +440,17 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+  // XCDs by linear id, so map the ids an XCD receives onto a contiguous run
+  // of tiles (row panel major) and all column tiles of a row panel share
+  // that XCD's L2 instead of fetching the A panel once per XCD.
+  const int n_col = (g.N + BN - 1) / BN;
+  const int total = n_col * ((g.M + BM - 1) / BM);
+  const int xcd = blockIdx.x % 8, kx = blockIdx.x / 8;
+  const int per = total / 8, rem = total % 8;
+  const int vt = xcd * per + (xcd < rem ? xcd : rem) + kx;
+  const int bx = vt % n_col, by = vt / n_col;
+  const int m0 = by * BM, n0 = bx * BN;
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -567,7 +577,7 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
     // this block's sum goes to its first slot, zeros to the others it covers
     __syncthreads();
     const int nsl = (g.N + 31) / 32;
-    const int s0 = blockIdx.x * (BN / 32);
+    const int s0 = bx * (BN / 32);
     for (int rl = tid; rl < BM; rl += NT) {
       int r = m0 + rl;
       if (r < g.M) {
@@ -584,17 +594,17 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
 
 // Tile configurations available to the autotuner: (BM, BN, WM, WN).
 struct TileCfg { int bm, bn; };
-static const TileCfg kCfgs[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {32, 32}};
-static_assert(sizeof(kCfgs) / sizeof(kCfgs[0]) == 6, "tile table");
+static const TileCfg kCfgs[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {32, 32}, {16, 64}, {16, 32}};
+static_assert(sizeof(kCfgs) / sizeof(kCfgs[0]) == 8, "tile table");
 int gemm_num_configs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 void gemm_config_tile(int cfg, int* bm, int* bn) { *bm = kCfgs[cfg].bm; *bn = kCfgs[cfg].bn; }
 
 template <typename T, int BM, int BN, int WM, int WN, bool SIGN, class Epi>
 static hipError_t launch_cfg(const GemmArgs& g, const Epi& epi, hipStream_t st) {
   constexpr int BK = (sizeof(T) == 4) ? 64 : 128;
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
-  hipLaunchKernelGGL((gemm_epi_kernel<T, BM, BN, WM, WN, BK, SIGN, Epi>), grid, dim3(WM * WN * 64), 0, st,
-                     g, epi);
+  const long tiles = (long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+  hipLaunchKernelGGL((gemm_epi_kernel<T, BM, BN, WM, WN, BK, SIGN, Epi>), dim3((unsigned)tiles),
+                     dim3(WM * WN * 64), 0, st, g, epi);
   return hipGetLastError();
 }
 
@@ -607,6 +617,8 @@ static hipError_t launch_any(int cfg, const GemmArgs& g, const Epi& epi, hipStre
     case 3: return launch_cfg<T, 128, 128, 2, 2, SIGN>(g, epi, st);
     case 4: return launch_cfg<T, 32, 64, 2, 2, SIGN>(g, epi, st);
     case 5: return launch_cfg<T, 32, 32, 2, 2, SIGN>(g, epi, st);
+    case 6: return launch_cfg<T, 16, 64, 1, 4, SIGN>(g, epi, st);
+    case 7: return launch_cfg<T, 16, 32, 1, 2, SIGN>(g, epi, st);
     default: return hipErrorInvalidValue;
   }
 }
