@@ -1,0 +1,472 @@
+// Device-side building blocks shared by the dense and convolution kernels:
+// MFMA operand types and the fused epilogues of the GCP-CROWN passes
+// (arXiv 2208.05740, Theorem 3.1 with Lemma A.1; Adam of Appendix C.1).
+//
+// An epilogue sees the elements one lane holds after the MFMA K loop:
+// R GEMM rows x TN GEMM columns.  LaneCoords maps them to (batch row r,
+// neuron j of the node).  For dense layers (PE = false) the neuron depends
+// on the column only and the R rows come in aligned groups of 4 consecutive
+// batch rows; for convolutions (PE = true) every element has its own neuron
+// (channel x spatial position) and all R rows belong to one batch row.
+//
+// Each epilogue is split in two: load() fetches everything that does not
+// depend on the GEMM result (neuron data, cut gathers, stored a_hat, alpha
+// and its moments, split overrides) and is issued before the K loop so its
+// latency overlaps the GEMM; apply() combines it with the accumulator and
+// stores.  Frag holds the per-lane state between the two.
+#pragma once
+#include "gcp_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace gcp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ MFMA
+template <typename T> struct Op;
+template <> struct Op<float> {
+  static constexpr int VEC = 4;    // elements per 16-byte fragment
+  static constexpr int KC = 16;    // K covered by one fragment per 4 lane groups
+  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
+    // Lane (row i = lane%16, group g = lane/16) holds A[i][4g..4g+3]; step t
+    // feeds element t, so the four steps cover k = 4g + t for all g, t.
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+template <> struct Op<bf16> {
+  static constexpr int VEC = 8;
+  static constexpr int KC = 32;
+  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
+    bf16x8 av = __builtin_bit_cast(bf16x8, a);
+    bf16x8 bv = __builtin_bit_cast(bf16x8, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+
+template <typename T> __device__ inline T to_t(float x);
+template <> __device__ inline float to_t<float>(float x) { return x; }
+template <> __device__ inline bf16 to_t<bf16>(float x) { return (bf16)x; }
+template <typename T> __device__ inline float from_t(T x);
+template <> __device__ inline float from_t<float>(float x) { return x; }
+template <> __device__ inline float from_t<bf16>(bf16 x) { return (float)x; }
+
+// ------------------------------------------------------------------ helpers
+__device__ inline double wave_sum16(double v) {
+  // sum over the 16 lanes that share lane/16 (lane bits 0..3)
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
+template <int R, int TN, bool PE>
+struct LaneCoords {
+  int r[R];        // batch row of GEMM row q (may be >= M in a ragged tile)
+  int j[TN][R];    // neuron of element (k, q); for PE == false only j[k][0] is used
+};
+
+#define GCP_QC(q) (PE ? (q) : 0)
+
+// Row indices of a lane: rv = element row is real (< M); rc = row clamped
+// below M, for row-major [M][.] buffers; rr = row for the row-minor [.][mp]
+// buffers.  Dense lanes keep groups of 4 consecutive rows whole so 16-byte
+// accesses stay aligned -- a group starting below mp lies entirely below mp
+// (mp is a multiple of 16), else it is moved to rows 0..3.
+template <int R, bool PE>
+__device__ inline void lane_rows(const int (&rows)[R], int M, int mp, int (&rr)[R], int (&rc)[R], bool (&rv)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    rv[q] = rows[q] < M;
+    rc[q] = rv[q] ? rows[q] : 0;
+    if constexpr (!PE && R % 4 == 0) rr[q] = rows[q - q % 4] < mp ? rows[q] : q % 4;
+    else rr[q] = rc[q];
+  }
+}
+
+// gamma^T X (X in {G, H, Q}) at the lane's elements of column slot k; gamma
+// is read from its transposed copy [N][mp].  Dense: one cut-entry list per
+// column, four consecutive rows per 16-byte load.  PE: per element.
+template <int R, bool PE>
+__device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ gammaT, int mp, const int (&jq)[R],
+                                   const bool (&jv)[R], const int (&rr)[R], float (&sG)[R], float (&sH)[R],
+                                   float (&sQ)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) sG[q] = sH[q] = sQ[q] = 0.f;
+  if (!cc.col_ptr) return;
+  if constexpr (!PE) {
+    if (!jv[0]) return;
+    const int j = jq[0];
+    const int e0 = cc.col_ptr[j], e1 = cc.col_ptr[j + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int ck = cc.cut[e];
+      const float ch = cc.cH[e], cg = cc.cG[e], cq = cc.cQ[e];
+      const float* gk = gammaT + (size_t)ck * mp;
+      float g[R];
+      if constexpr (R % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < R; q += 4) {
+          const float4 v = *(const float4*)(gk + rr[q]);
+          g[q] = v.x; g[q + 1] = v.y; g[q + 2] = v.z; g[q + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) g[q] = gk[rr[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        sG[q] += g[q] * cg;
+        sH[q] += g[q] * ch;
+        sQ[q] += g[q] * cq;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (!jv[q]) continue;
+      const int j = jq[q];
+      for (int e = cc.col_ptr[j]; e < cc.col_ptr[j + 1]; ++e) {
+        const float g = gammaT[(size_t)cc.cut[e] * mp + rr[q]];
+        sG[q] += g * cc.cG[e];
+        sH[q] += g * cc.cH[e];
+        sQ[q] += g * cc.cQ[e];
+      }
+    }
+  }
+}
+
+// effective class and split slot of each element (row, neuron)
+template <int R>
+__device__ inline void split_class(const RowParams& rp, int rank, int cls, int rc, int* c, int* slot) {
+  int m = 0;
+  if (rank >= 0 && rp.mask) m = rp.mask[(size_t)(rc / rp.S) * rp.n_I + rank];
+  *slot = m > 0 ? m - 1 : (m < 0 ? -m - 1 : -1);
+  *c = m > 0 ? (int)ACTIVE : (m < 0 ? (int)INACTIVE : cls);
+}
+
+// ------------------------------------------------------------------ bound
+// Theorem 3.1 relaxation of one ReLU node: a_hat = GEMM + acc_in + gamma^T G,
+// Lambda and the row constant (bias, h, z-fixed Q terms).
+template <typename T>
+struct BoundEpi {
+  BoundEpiArgs a;
+  template <int R, int TN, bool PE> struct Frag {
+    int rc[R];
+    bool ev[TN][R];                       // element valid
+    float bj[TN][PE ? R : 1], lj[TN][PE ? R : 1], uj[TN][PE ? R : 1], iul[TN][PE ? R : 1];
+    float aoff[TN][R];   // acc_in + gamma^T G: added to the GEMM value -> a_hat
+    float tadd[TN][R];   // gamma^T H and the split term: added to Lambda
+    float sQ[TN][R];     // gamma^T Q
+    float al[TN][R];     // alpha (unstable) or 0
+    int8_t c[TN][R];     // effective class
+  };
+  template <int R, int TN, bool PE>
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+    const NodeDev& nd = a.nd;
+    const RowParams& rp = a.rp;
+    int rr[R];
+    bool rv[R];
+    lane_rows<R, PE>(lc.r, M, rp.mp, rr, f.rc, rv);
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      int jq[R];
+      bool jv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        jv[q] = lc.j[k][GCP_QC(q)] < N;
+        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[q] && rv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < (PE ? R : 1); ++q) {
+        const int j = jq[q];
+        f.bj[k][q] = nd.bias[j]; f.lj[k][q] = nd.l[j]; f.uj[k][q] = nd.u[j]; f.iul[k][q] = nd.inv_ul[j];
+      }
+      float sG[R], sH[R];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, rr, sG, sH, f.sQ[k]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int j = jq[GCP_QC(q)];
+        const int rk = nd.rank[j];
+        int c, slot;
+        split_class<R>(rp, rk, nd.cls[j], f.rc[q], &c, &slot);
+        const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
+        f.aoff[k][q] = pre + sG[q];
+        f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
+        const float bv = slot >= 0 ? rp.beta[(size_t)f.rc[q] * rp.K + slot] : 0.f;
+        f.tadd[k][q] = sH[q] + (c == ACTIVE ? -bv : (c == INACTIVE ? bv : 0.f));
+        f.c[k][q] = (int8_t)c;
+      }
+    }
+  }
+  template <int R, int TN, bool PE>
+  __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                               const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+    const NodeDev& nd = a.nd;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int qc = GCP_QC(q);
+        const float ah = val[k][q] + f.aoff[k][q];   // a_hat = Lambda^(i+1) W + gamma^T G
+        float lam, konst;
+        if (f.c[k][q] == ACTIVE) {                   // x_hat = x, z = 1
+          lam = ah + f.tadd[k][q];
+          konst = f.sQ[k][q];
+        } else if (f.c[k][q] == INACTIVE) {          // x_hat = 0, z = 0
+          lam = f.tadd[k][q];
+          konst = 0.f;
+        } else {                                     // Lemma A.1, C = [-a_hat]_+, q = -s
+          const float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f), sq = f.sQ[k][q];
+          float pi, h;
+          if (sq >= f.uj[k][qc] * n) { pi = 0.f; h = 0.f; }
+          else if (sq <= f.lj[k][qc] * n) { pi = n; h = sq; }
+          else { pi = (f.uj[k][qc] * n - sq) * f.iul[k][qc]; h = f.lj[k][qc] * pi; }
+          lam = f.al[k][q] * p - pi + f.tadd[k][q];
+          konst = h;
+        }
+        if (f.ev[k][q]) {
+          const size_t ij = (size_t)f.rc[q] * nd.ld + lc.j[k][qc];
+          ((T*)a.lam_out)[ij] = to_t<T>(lam);
+          if (a.ahat_out) a.ahat_out[ij] = ah;
+          rs[q] += (double)lam * (double)f.bj[k][qc] + (double)konst;
+        }
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------ concretisation
+// v = GEMM + gamma^T G0 over the input box: x0.v - eps*|v|_1 into the row
+// constant, sign(v) for the adjoint, input-cut gradient pieces.
+struct ConcEpi {
+  ConcEpiArgs a;
+  template <int R, int TN, bool PE> struct Frag {
+    int rr[R], rc[R];
+    bool ev[TN][R];
+    float sG[TN][R];
+  };
+  template <int R, int TN, bool PE>
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+    bool rv[R];
+    lane_rows<R, PE>(lc.r, M, a.rp.mp, f.rr, f.rc, rv);
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      int jq[R];
+      bool jv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        jv[q] = lc.j[k][GCP_QC(q)] < N;
+        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[q] && rv[q];
+      }
+      float sH[R], sQ[R];
+      gather_cuts<R, PE>(a.cc, a.rp.gammaT, a.rp.mp, jq, jv, f.rr, f.sG[k], sH, sQ);
+    }
+  }
+  template <int R, int TN, bool PE>
+  __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                               const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if (!f.ev[k][q]) continue;
+        const int j = lc.j[k][GCP_QC(q)];
+        const double xj = a.x0[j];
+        const float v = val[k][q] + f.sG[k][q];
+        const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
+        if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
+        if (a.contrib && a.cc.col_ptr) {
+          const float dv = (float)(xj - a.eps * (double)sg);
+          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
+            a.contrib[(size_t)a.cc.pos[e] * a.rp.mp + f.rr[q]] = a.cc.cG[e] * dv;
+        }
+        const double vd = (double)v;
+        rs[q] += xj * vd - a.eps * fabs(vd);
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------ adjoint
+// d bound / d Lambda arrives as the GEMM value; the relaxation's derivative
+// gives d bound / d a_hat (operand of the next adjoint GEMM), the gradient
+// pieces of the cuts, and d/d alpha, d/d beta -- applied by projected Adam in
+// place or written out.
+template <typename T>
+struct AdjEpi {
+  AdjEpiArgs a;
+  template <int R, int TN, bool PE> struct Frag {
+    int rr[R], rc[R];
+    bool ev[TN][R];
+    float lj[TN][PE ? R : 1], uj[TN][PE ? R : 1], iul[TN][PE ? R : 1], addj[TN][PE ? R : 1];
+    int rk[TN][R];
+    float ah[TN][R];     // stored a_hat
+    float pre[TN][R];    // acc_in
+    float sQ[TN][R];
+    float al[TN][R], ma[TN][R], va[TN][R];
+    int8_t c[TN][R], slot[TN][R];
+  };
+  template <int R, int TN, bool PE>
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+    const NodeDev& nd = a.nd;
+    const RowParams& rp = a.rp;
+    bool rv[R];
+    lane_rows<R, PE>(lc.r, M, rp.mp, f.rr, f.rc, rv);
+    const bool adam = a.adam.enabled;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      int jq[R];
+      bool jv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        jv[q] = lc.j[k][GCP_QC(q)] < N;
+        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[q] && rv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < (PE ? R : 1); ++q) {
+        const int j = jq[q];
+        f.lj[k][q] = nd.l[j]; f.uj[k][q] = nd.u[j]; f.iul[k][q] = nd.inv_ul[j]; f.addj[k][q] = a.add_vec[j];
+      }
+      float sG[R], sH[R];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, f.rr, sG, sH, f.sQ[k]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int j = jq[GCP_QC(q)];
+        const int rk = nd.rank[j];
+        int c, slot;
+        split_class<R>(rp, rk, nd.cls[j], f.rc[q], &c, &slot);
+        f.rk[k][q] = rk;
+        f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
+        f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
+        const size_t ia = (size_t)f.rc[q] * rp.n_I + (rk >= 0 ? rk : 0);
+        f.al[k][q] = rk >= 0 ? rp.alpha[ia] : 0.f;
+        f.ma[k][q] = (rk >= 0 && adam) ? a.m_alpha[ia] : 0.f;
+        f.va[k][q] = (rk >= 0 && adam) ? a.v_alpha[ia] : 0.f;
+        f.c[k][q] = (int8_t)c;
+        f.slot[k][q] = (int8_t)slot;
+      }
+    }
+  }
+  template <int R, int TN, bool PE>
+  __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                               const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+    const NodeDev& nd = a.nd;
+    const RowParams& rp = a.rp;
+    float lr_a = 0.f, lr_m = 0.f, bc1 = 1.f, bc2 = 1.f;
+    if (a.adam.enabled) {
+      lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; bc1 = a.adam.consts[2]; bc2 = a.adam.consts[3];
+    }
+    const float b1 = a.adam.b1, b2 = a.adam.b2, aeps = a.adam.eps;
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int qc = GCP_QC(q);
+        const float dL = a.gemm_scale * val[k][q] + f.addj[k][qc] + f.pre[k][q];
+        float dA, dS, gA = 0.f;
+        const int c = f.c[k][q];
+        if (c == ACTIVE) {
+          dA = dL; dS = 1.f;
+        } else if (c == INACTIVE) {
+          dA = 0.f; dS = 0.f;
+        } else {
+          const float x = f.ah[k][q], n = fmaxf(-x, 0.f), p = fmaxf(x, 0.f), sq = f.sQ[k][q];
+          const float pos = x > 0.f ? 1.f : 0.f, neg = x < 0.f ? 1.f : 0.f;
+          const float uj = f.uj[k][qc], lj = f.lj[k][qc], iul = f.iul[k][qc], al = f.al[k][q];
+          float dLda, dhda, dLds, dhds;
+          if (sq >= uj * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
+          else if (sq <= lj * n) { dLda = al * pos + neg; dhda = 0.f; dLds = 0.f; dhds = 1.f; }
+          else {
+            dLda = al * pos + uj * iul * neg;
+            dhda = -lj * uj * iul * neg;
+            dLds = iul;
+            dhds = -lj * iul;
+          }
+          dA = dL * dLda + dhda;
+          dS = dL * dLds + dhds;
+          gA = dL * p;
+        }
+        if (!f.ev[k][q]) continue;
+        const int j = lc.j[k][qc];
+        const size_t ij = (size_t)f.rc[q] * nd.ld + j;
+        if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
+        if (a.contrib && a.cc.col_ptr) {
+          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
+            a.contrib[(size_t)a.cc.pos[e] * rp.mp + f.rr[q]] = a.cc.cG[e] * dA + a.cc.cH[e] * dL + a.cc.cQ[e] * dS;
+        }
+        const int rk = f.rk[k][q];
+        if (rk >= 0) {
+          const size_t ia = (size_t)f.rc[q] * rp.n_I + rk;
+          if (a.adam.enabled) {
+            const float mm = b1 * f.ma[k][q] + (1.f - b1) * gA;
+            const float vv = b2 * f.va[k][q] + (1.f - b2) * gA * gA;
+            a.m_alpha[ia] = mm;
+            a.v_alpha[ia] = vv;
+            const float stp = lr_a * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            a.alpha_rw[ia] = fminf(fmaxf(f.al[k][q] + stp, 0.f), 1.f);
+          } else {
+            a.d_alpha[ia] = gA;
+          }
+        }
+        const int sl = f.slot[k][q];
+        if (sl >= 0) {
+          const size_t ib = (size_t)f.rc[q] * rp.K + sl;
+          const float gB = (c == ACTIVE) ? -dL : dL;
+          if (a.adam.enabled) {
+            const float mm = b1 * a.m_beta[ib] + (1.f - b1) * gB;
+            const float vv = b2 * a.v_beta[ib] + (1.f - b2) * gB * gB;
+            a.m_beta[ib] = mm;
+            a.v_beta[ib] = vv;
+            const float stp = lr_m * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            a.beta_rw[ib] = fmaxf(a.beta_rw[ib] + stp, 0.f);
+          } else {
+            a.d_beta[ib] = gB;
+          }
+        }
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------ store
+// out = scale * GEMM (+ acc_in): partial sums of a node with several edges
+struct StoreEpi {
+  StoreEpiArgs a;
+  template <int R, int TN, bool PE> struct Frag {
+    int rc[R];
+    bool ev[TN][R];
+    float pre[TN][R];
+  };
+  template <int R, int TN, bool PE>
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int j = lc.j[k][GCP_QC(q)];
+        f.ev[k][q] = lc.r[q] < M && j < N;
+        f.rc[q] = lc.r[q] < M ? lc.r[q] : 0;
+        f.pre[k][q] = (a.acc_in && f.ev[k][q]) ? a.acc_in[(size_t)f.rc[q] * a.ld + j] : 0.f;
+      }
+  }
+  template <int R, int TN, bool PE>
+  __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                               const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k)
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (f.ev[k][q]) a.out[(size_t)f.rc[q] * a.ld + lc.j[k][GCP_QC(q)]] = a.scale * val[k][q] + f.pre[k][q];
+  }
+};
+
+}  // namespace gcp

@@ -146,11 +146,12 @@ struct EdgeH {
   int kh = 0, kw = 0, stride = 1, pad = 0;
   int d_src = 0, d_dst = 0;
   ConvGeom cg{};
-  DBuf W32;      // adjoint Bt: dense [d_dst][ld_src]; conv: [co][ci][kh][kw]
+  DBuf W32;      // adjoint Bt: dense [d_dst][ld_src]; conv [co][ldk_f]
   DBuf W16;
-  DBuf WT32;     // bound Bt: dense [d_src][ld_dst]
+  DBuf WT32;     // bound Bt: dense [d_src][ld_dst]; conv [ci][ldk_t]
   DBuf WT16;
-  DBuf Wraw;     // dense [d_dst][d_src] unpadded fp32 (for c-hat and W x0)
+  DBuf Wraw;     // dense [d_dst][d_src] unpadded fp32 (for c-hat and W x0); conv: [co][ci][kh][kw]
+  int ldk_f = 0, ldk_t = 0;   // conv: padded K of W32/W16 (adjoint) and WT32/WT16 (bound)
 };
 
 struct NodeH {
@@ -337,11 +338,28 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         if (ho != n.h || wo != n.w) fail(GCP_EINVAL, "conv output shape does not match node " + std::to_string(i));
         E->kh = ed.kh; E->kw = ed.kw; E->stride = ed.stride; E->pad = ed.pad;
         E->cg = ConvGeom{ci, hi, wi, n.c, ho, wo, ed.kh, ed.kw, ed.stride, ed.pad};
+        if ((ho * wo) % 16 != 0 || (hi * wi) % 16 != 0)
+          fail(GCP_EUNSUPPORTED, "conv spatial sizes must be multiples of 16 positions");
         size_t cnt = (size_t)n.c * ci * ed.kh * ed.kw;
         check_finite(ed.W, cnt, "conv weight");
         std::vector<float> raw(ed.W, ed.W + cnt);
-        E->W32.upload(raw);
         E->Wraw.upload(raw);
+        const int taps = ed.kh * ed.kw;
+        // adjoint: Bt[o][(c,ky,kx)] = W[o][c][ky][kx], K padded to 16
+        const int kf = round_up(ci * taps, 16);
+        std::vector<float> fw((size_t)n.c * kf, 0.f);
+        for (int o = 0; o < n.c; ++o)
+          for (int q = 0; q < ci * taps; ++q) fw[(size_t)o * kf + q] = raw[(size_t)o * ci * taps + q];
+        // bound: Bt[c][(o,ky,kx)] = W[o][c][ky][kx]
+        const int kt = round_up(n.c * taps, 16);
+        std::vector<float> ft((size_t)ci * kt, 0.f);
+        for (int o = 0; o < n.c; ++o)
+          for (int cc = 0; cc < ci; ++cc)
+            for (int t = 0; t < taps; ++t) ft[(size_t)cc * kt + o * taps + t] = raw[((size_t)o * ci + cc) * taps + t];
+        E->ldk_f = kf;
+        E->ldk_t = kt;
+        E->W32.upload(fw); E->W16.upload(to_bf16(fw));
+        E->WT32.upload(ft); E->WT16.upload(to_bf16(ft));
       } else if (ed.kind == GCP_EDGE_IDENTITY) {
         if (E->d_src != E->d_dst) fail(GCP_EINVAL, "identity edge between different sizes");
       } else {
@@ -410,10 +428,10 @@ struct TileCache {
     if (!p) return;
     FILE* f = std::fopen(p, "r");
     if (!f) return;
-    char key[128];
+    char key[160];
     int cfg;
-    while (std::fscanf(f, "%127s %d", key, &cfg) == 2)
-      if (cfg >= 0 && cfg < gemm_num_configs()) m[key] = cfg;
+    while (std::fscanf(f, "%159s %d", key, &cfg) == 2)
+      if (cfg >= 0 && cfg < 16) m[key] = cfg;
     std::fclose(f);
   }
   void store(const std::string& key, int cfg) {
@@ -428,11 +446,32 @@ struct TileCache {
 };
 TileCache& tile_cache() { static TileCache t; return t; }
 
+// Candidate list and fallback of one launch family.
+struct Cands {
+  std::vector<int> list;
+  int fallback;
+};
+Cands dense_cands(int M, int N) {
+  return Cands{std::vector<int>(std::begin(kTileCandidates), std::end(kTileCandidates)), heuristic_cfg(M, N)};
+}
+// conv tiles must not straddle batch rows: BM divides the epilogue-side positions
+Cands conv_cands(int spatial) {
+  Cands c{{}, -1};
+  for (int i = 0; i < conv_num_configs(); ++i) {
+    int bm, bn;
+    conv_config_tile(i, &bm, &bn);
+    if (spatial % bm == 0) c.list.push_back(i);
+  }
+  if (c.list.empty()) fail(GCP_EUNSUPPORTED, "no conv tile divides the spatial size");
+  c.fallback = c.list.front();
+  return c;
+}
+
 template <class Trial>
-int choose_cfg(gcp_net* net, int kind, int bf16, int sign, int M, int N, int K, hipStream_t st, Trial trial) {
-  (void)net;
-  char kb[128];
-  std::snprintf(kb, sizeof kb, "k%d.b%d.s%d.M%d.N%d.K%d", kind, bf16, sign, M, N, K);
+int choose_cfg(const char* fam, int kind, int bf16, int sign, int M, int N, int K, hipStream_t st,
+               const Cands& cands, Trial trial) {
+  char kb[160];
+  std::snprintf(kb, sizeof kb, "%s.k%d.b%d.s%d.M%d.N%d.K%d", fam, kind, bf16, sign, M, N, K);
   const std::string key(kb);
   TileCache& TC = tile_cache();
   {
@@ -441,15 +480,15 @@ int choose_cfg(gcp_net* net, int kind, int bf16, int sign, int M, int N, int K, 
     auto it = TC.m.find(key);
     if (it != TC.m.end()) return it->second;
   }
-  int best = heuristic_cfg(M, N);
+  int best = cands.fallback;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(st, &cs);
-  if (autotune_enabled() && cs == hipStreamCaptureStatusNone) {
+  if (autotune_enabled() && cs == hipStreamCaptureStatusNone && cands.list.size() > 1) {
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     float best_ms = 1e30f;
-    for (int c : kTileCandidates) {
+    for (int c : cands.list) {
       hip_check(trial(c), "autotune trial");
       hip_check(hipEventRecord(e0, st), "hipEventRecord");
       for (int rep = 0; rep < 3; ++rep) hip_check(trial(c), "autotune trial");
@@ -669,7 +708,10 @@ void ensure_ws(Call& c) {
     ws.lam.push_back(mk(elems * 4));
     ws.ahat.push_back(mk(elems * 4));
     ws.dahat.push_back(mk(elems * 4));
-    bool multi = n.relu && (n.consumers.size() > 1 || n.in_edges.size() > 1);
+    bool ident = false;
+    for (int eid : n.in_edges) ident |= net->edges[eid]->kind == GCP_EDGE_IDENTITY;
+    for (int eid : n.consumers) ident |= net->edges[eid]->kind == GCP_EDGE_IDENTITY;
+    bool multi = n.relu && (n.consumers.size() > 1 || n.in_edges.size() > 1 || ident);
     ws.acc.push_back(mk(multi ? elems * 4 : 0));
     ws.addv.push_back(mk(n.relu ? (size_t)n.ld * 4 : 0));
   }
@@ -792,7 +834,7 @@ struct BoundPass {
         const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
                              (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
         check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
-          return launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], a, ws.partial.as<double>(),
+          return launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(),
                                           slot, c.st);
         }));
       }
@@ -838,7 +880,7 @@ struct BoundPass {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         g.partial = nullptr;
         if (!dry) {
-          int cfg = choose_cfg(net, EPI_STORE, bf16, 0, g.M, g.N, g.K, c.st, [&](int cf) {
+          int cfg = choose_cfg("gemm", EPI_STORE, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
             StoreEpiArgs t = s;
             t.acc_in = nullptr;
             t.out = tune_store(c);
@@ -857,7 +899,7 @@ struct BoundPass {
         if (!dry) {
           GemmArgs gt = g;
           gt.partial = nullptr;
-          int cfg = choose_cfg(net, EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st,
+          int cfg = choose_cfg("gemm", EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_BOUND, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
           const double M = g.M, esz = bf16 ? 2 : 4, dp = g.N;
@@ -878,7 +920,7 @@ struct BoundPass {
         if (!dry) {
           GemmArgs gt = g;
           gt.partial = nullptr;
-          int cfg = choose_cfg(net, EPI_CONC, bf16, 0, g.M, g.N, g.K, c.st,
+          int cfg = choose_cfg("gemm", EPI_CONC, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_CONC, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
           const double M = g.M, esz = bf16 ? 2 : 4;
@@ -891,7 +933,86 @@ struct BoundPass {
       slot += nslot;
       return;
     }
-    fail(GCP_EUNSUPPORTED, "edge kind not supported yet in the bound pass");
+    if (E.kind == GCP_EDGE_CONV) {
+      const ConvGeom& cg = E.cg;
+      ConvArgs ca{};
+      ca.M = c.M; ca.cg = cg; ca.trans = 1;
+      ca.X = ws.lam[E.dst]->p; ca.ldx = dn.ld; ca.x_is_sign = 0;
+      ca.Bt = bf16 ? E.WT16.p : E.WT32.p; ca.ldb = E.ldk_t;
+      ca.mp = c.rp.mp; ca.partial = nullptr;
+      const int HW = cg.hi * cg.wi;
+      const double M = c.M, esz = bf16 ? 2 : 4;
+      const double flops = 2.0 * M * HW * cg.ci * cg.co * cg.kh * cg.kw;
+      const double wbytes = (double)cg.ci * E.ldk_t * esz;
+      if (!last) {
+        StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
+        if (!dry) {
+          int cfg = choose_cfg("convT", EPI_STORE, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW), [&](int cf) {
+            StoreEpiArgs t = s;
+            t.acc_in = nullptr;
+            t.out = tune_store(c);
+            return launch_conv(bf16, cf, EPI_STORE, ca, &t, c.st);
+          });
+          const double bytes = M * dn.size * esz + wbytes + M * d_src * 4 * (first ? 1 : 2);
+          check(timed(c.st, cls_name("convT_store", bf16, 0, -1), bytes, flops,
+                      [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
+        }
+        return;
+      }
+      const int nslot = conv_slots(HW, cg.ci);
+      if (p >= 0) {
+        BoundEpiArgs a = bound_args(p, has_acc);
+        if (!dry) {
+          int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW),
+                               [&](int cf) { return launch_conv(bf16, cf, EPI_BOUND, ca, &a, c.st); });
+          ConvArgs cr = ca;
+          cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
+          const double bytes = M * dn.size * esz + wbytes + M * d_src * esz + (keep_ahat ? M * d_src * 4 : 0) +
+                               M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
+                               (has_acc ? M * d_src * 4 : 0) + M * nslot * 8;
+          check(timed(c.st, cls_name("convT_bound", bf16, 0, -1), bytes, flops,
+                      [&] { return launch_conv(bf16, cfg, EPI_BOUND, cr, &a, c.st); }));
+        }
+      } else {
+        if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
+        ConcEpiArgs a{};
+        a.size = net->in_size; a.ld = net->in_ld; a.x0 = c.x0; a.eps = c.eps;
+        a.cc = cut_col(c, -1); a.rp = c.rp;
+        a.sign_out = keep_ahat ? ws.sign.as<int8_t>() : nullptr;
+        a.contrib = want_contrib ? ws.contrib.as<float>() : nullptr;
+        a.nnz_e = c.nnz;
+        if (!dry) {
+          int cfg = choose_cfg("convT", EPI_CONC, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW),
+                               [&](int cf) { return launch_conv(bf16, cf, EPI_CONC, ca, &a, c.st); });
+          ConvArgs cr = ca;
+          cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
+          const double bytes = M * dn.size * esz + wbytes + (keep_ahat ? M * d_src : 0) +
+                               M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
+          check(timed(c.st, cls_name("convT_conc", bf16, 0, -1), bytes, flops,
+                      [&] { return launch_conv(bf16, cfg, EPI_CONC, cr, &a, c.st); }));
+        }
+      }
+      slot += nslot;
+      return;
+    }
+    if (E.kind == GCP_EDGE_IDENTITY) {
+      if (p < 0) fail(GCP_EUNSUPPORTED, "identity edge from the network input");
+      if (!last) {
+        if (!dry)
+          check(launch_identity_acc(bf16, c.M, d_src, ws.lam[E.dst]->p, dn.ld, 0, 1.f, first ? nullptr : accbuf,
+                                    accbuf, ld_src, c.st));
+        return;
+      }
+      BoundEpiArgs a = bound_args(p, has_acc);
+      const int nslot = slots_for_elementwise(d_src);
+      if (!dry)
+        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), (double)c.M * d_src * 16, 0.0, [&] {
+          return launch_bound_elementwise(bf16, nullptr, ws.lam[E.dst]->p, a, ws.partial.as<double>(), slot, c.st);
+        }));
+      slot += nslot;
+      return;
+    }
+    fail(GCP_EUNSUPPORTED, "unknown edge kind in the bound pass");
   }
 };
 
@@ -935,13 +1056,19 @@ struct AdjPass {
     gcp_net* net = c.net;
     auto& ws = net->ws;
     const NodeH& n = net->nodes[i];
-    std::vector<int> order;
+    std::vector<int> order;   // identity edges first: they can only accumulate
     for (int eid : n.in_edges)
       if (net->edges[eid]->kind == GCP_EDGE_IDENTITY) order.push_back(eid);
     for (int eid : n.in_edges)
       if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
-    const bool has_acc = order.size() > 1;
-    float* accbuf = has_acc ? ws.acc[i]->as<float>() : nullptr;
+    float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
+    const bool fused_last = net->edges[order.back()]->kind != GCP_EDGE_IDENTITY;
+    const bool use_acc = order.size() > 1 || !fused_last;
+    const double M = c.M, esz = bf16 ? 2 : 4, di = n.size;
+    auto adj_bytes = [&](double a_bytes, double w_bytes) {
+      return a_bytes + w_bytes + M * di * 4 + M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
+             M * nnz_of(c, i) * 8 + M * di * esz + (use_acc ? M * di * 4 : 0);
+    };
     for (size_t q = 0; q < order.size(); ++q) {
       const EdgeH& E = *net->edges[order[q]];
       const bool last = q + 1 == order.size();
@@ -951,6 +1078,7 @@ struct AdjPass {
       const float scale = sign ? (float)(-c.eps) : 1.f;
       const void* A = sign ? ws.sign.p : ws.dahat[p]->p;
       const int lda = sign ? net->in_ld : net->nodes[p].ld;
+      const double a_bytes = M * E.d_src * (sign ? 1 : esz);
       if (E.kind == GCP_EDGE_DENSE) {
         GemmArgs g{};
         g.M = c.M; g.N = n.size; g.K = E.d_src;
@@ -960,35 +1088,66 @@ struct AdjPass {
         g.mp = c.rp.mp;
         if (!last) {
           StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
-          int cfg = choose_cfg(net, EPI_STORE, bf16, sign, g.M, g.N, g.K, c.st, [&](int cf) {
+          int cfg = choose_cfg("gemm", EPI_STORE, bf16, sign, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
             StoreEpiArgs t = s;
             t.acc_in = nullptr;
             t.out = tune_store(c);
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
-          const double esz = bf16 ? 2 : 4;
-          const double bytes = (double)g.M * g.K * (sign ? 1 : esz) + (double)g.N * g.K * esz +
-                               (double)g.M * g.N * 4 * (first ? 1 : 2);
+          const double bytes = a_bytes + (double)g.N * g.K * esz + M * di * 4 * (first ? 1 : 2);
           check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
                       [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
-          AdjEpiArgs a = epi(i, has_acc ? accbuf : nullptr, scale);
-          int cfg = choose_cfg(net, EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, [&](int cf) {
+          AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
+          int cfg = choose_cfg("gemm", EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
             AdjEpiArgs t = a;     // gradient-only trial into scratch: no parameter moves
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);
             t.d_beta = tune_beta(c);
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
-          const double M = g.M, esz = bf16 ? 2 : 4, di = g.N;
-          const double bytes = M * g.K * (sign ? 1 : esz) + (double)g.N * g.K * esz + M * di * 4 +
-                               M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
-                               M * nnz_of(c, i) * 8 + M * di * esz + (has_acc ? M * di * 4 : 0);
-          check(timed(c.st, cls_name("adj", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                      [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
+          check(timed(c.st, cls_name("adj", bf16, sign, cfg), adj_bytes(a_bytes, (double)g.N * g.K * esz),
+                      2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
-      } else {
-        fail(GCP_EUNSUPPORTED, "edge kind not supported yet in the adjoint");
+      } else if (E.kind == GCP_EDGE_CONV) {
+        ConvArgs ca{};
+        ca.M = c.M; ca.cg = E.cg; ca.trans = 0;
+        ca.X = A; ca.ldx = lda; ca.x_is_sign = sign;
+        ca.Bt = bf16 ? E.W16.p : E.W32.p; ca.ldb = E.ldk_f;
+        ca.mp = c.rp.mp; ca.partial = nullptr;
+        const int HW = E.cg.ho * E.cg.wo;
+        const double flops = 2.0 * M * HW * E.cg.co * E.cg.ci * E.cg.kh * E.cg.kw;
+        const double wbytes = (double)E.cg.co * E.ldk_f * esz;
+        if (!last) {
+          StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
+          int cfg = choose_cfg("conv", EPI_STORE, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(HW), [&](int cf) {
+            StoreEpiArgs t = s;
+            t.acc_in = nullptr;
+            t.out = tune_store(c);
+            return launch_conv(bf16, cf, EPI_STORE, ca, &t, c.st);
+          });
+          check(timed(c.st, cls_name("conv_store", bf16, sign, -1), a_bytes + wbytes + M * di * 4 * (first ? 1 : 2),
+                      flops, [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
+        } else {
+          AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
+          int cfg = choose_cfg("conv", EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(HW), [&](int cf) {
+            AdjEpiArgs t = a;
+            t.adam.enabled = 0;
+            t.d_alpha = tune_alpha(c);
+            t.d_beta = tune_beta(c);
+            return launch_conv(bf16, cf, EPI_ADJ, ca, &t, c.st);
+          });
+          check(timed(c.st, cls_name("conv_adj", bf16, sign, -1), adj_bytes(a_bytes, wbytes), flops,
+                      [&] { return launch_conv(bf16, cfg, EPI_ADJ, ca, &a, c.st); }));
+        }
+      } else {   // identity: accumulate; the node's relaxation runs after the last edge
+        check(launch_identity_acc(bf16, c.M, n.size, A, lda, sign, scale, first ? nullptr : accbuf, accbuf, n.ld,
+                                  c.st));
+        if (last) {
+          AdjEpiArgs a = epi(i, accbuf, 0.f);
+          check(timed(c.st, cls_name("adj_elem", bf16, 0, -1), adj_bytes(0, 0), 0.0,
+                      [&] { return launch_adj_elementwise(bf16, a, c.st); }));
+        }
       }
     }
   }

@@ -109,22 +109,33 @@ void gemm_config_tile(int cfg, int* bm, int* bn);
 
 // Elementwise epilogues (no GEMM): the pre-activation comes from a per-spec
 // broadcast [S][ld] (fp32) plus the optional acc_in of the epilogue args.
-hipError_t launch_bound_elementwise(int bf16, const float* bcast, const BoundEpiArgs& a, double* partial,
-                                    int slot0, hipStream_t st);
+hipError_t launch_bound_elementwise(int bf16, const float* bcast, const void* src, const BoundEpiArgs& a,
+                                    double* partial, int slot0, hipStream_t st);
+// Identity edge: out = (acc_in ? acc_in : 0) + scale * src (src operand type or int8 sign)
+hipError_t launch_identity_acc(int bf16, int M, int size, const void* src, int ld_src, int is_sign, float scale,
+                               const float* acc_in, float* out, int ld_out, hipStream_t st);
 hipError_t launch_adj_elementwise(int bf16, const AdjEpiArgs& a, hipStream_t st);
 
-// Direct (non-GEMM) convolution kernels for conv edges.
+// Convolution edges as implicit GEMMs on MFMA (conv_kernels.hip).
 struct ConvGeom { int ci, hi, wi, co, ho, wo, kh, kw, stride, pad; };
-// Bound direction: dst rows [M][co*ho*wo] -> src rows [M][ci*hi*wi]  (transposed conv)
-hipError_t launch_conv_t(int bf16, EpiKind kind, const ConvGeom& cg, int M,
-                         const void* lam, int ld_in, const float* W,
-                         const void* epi, double* partial, int mp, int slot0,
-                         hipStream_t st);
-// Adjoint direction: src rows [M][ci*hi*wi] -> dst rows [M][co*ho*wo]  (conv)
-hipError_t launch_conv_f(int bf16, int a_is_sign, const ConvGeom& cg, int M,
-                         const void* x, int ld_in, const float* W,
-                         const void* epi, hipStream_t st);
-// Identity edge: rows copied (bound direction uses BoundEpi/StoreEpi).
+// Bound direction (transposed conv): rows of Lambda over the node's
+// (co, ho, wo) -> epilogue over the source's (ci, hi, wi);
+// Bt = [ci][co*kh*kw] (ldb) rearranged weights.
+// Adjoint direction (conv): rows over the source's (ci, hi, wi) (operand type,
+// or int8 signs) -> epilogue over the node's (co, ho, wo); Bt = W [co][ci*kh*kw].
+struct ConvArgs {
+  int M;                  // batch rows
+  ConvGeom cg;
+  int trans;              // 1: transposed (bound direction)
+  const void* X; int ldx; int x_is_sign;
+  const void* Bt; int ldb;
+  double* partial; int mp; int slot0;
+};
+hipError_t launch_conv(int bf16, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st);
+int conv_num_configs();
+void conv_config_tile(int cfg, int* bm, int* bn);
+// row-partial slots a conv launch owns: (epilogue-side positions / 16) * ceil(channels / 16)
+inline int conv_slots(int spatial, int channels) { return (spatial / 16) * ((channels + 15) / 16); }
 
 hipError_t launch_chat(const double* C, int S, int d_out, const float* W, int d_in,
                        int kind, float* chat, int ld, hipStream_t st);

@@ -8,410 +8,12 @@
 //   bound direction  a_hat^(p) = Lambda^(i) W      uses Bt = W^T  [d_p][d_i]
 //   adjoint          dLambda^(i) = da_hat^(p) W^T  uses Bt = W    [d_i][d_p]
 #include "gcp_internal.h"
+#include "epilogues.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 namespace gcp {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// ------------------------------------------------------------------ MFMA
-template <typename T> struct Op;
-template <> struct Op<float> {
-  static constexpr int VEC = 4;    // elements per 16-byte fragment
-  static constexpr int KC = 16;    // K covered by one fragment per 4 lane groups
-  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
-    // Lane (row i = lane%16, group g = lane/16) holds A[i][4g..4g+3]; step t
-    // feeds element t, so the four steps cover k = 4g + t for all g, t.
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
-  }
-};
-template <> struct Op<bf16> {
-  static constexpr int VEC = 8;
-  static constexpr int KC = 32;
-  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
-    bf16x8 av = __builtin_bit_cast(bf16x8, a);
-    bf16x8 bv = __builtin_bit_cast(bf16x8, b);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-  }
-};
-
-template <typename T> __device__ inline T to_t(float x);
-template <> __device__ inline float to_t<float>(float x) { return x; }
-template <> __device__ inline bf16 to_t<bf16>(float x) { return (bf16)x; }
-
-// ------------------------------------------------------------------ helpers
-__device__ inline double wave_sum16(double v) {
-  // sum over the 16 lanes that share lane/16 (lane bits 0..3)
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
-  return v;
-}
-
-// ------------------------------------------------------------------ epilogues
-// An epilogue processes the R x TN output elements one lane holds: rows
-// rows[q] (q < R), columns cols[k] (k < TN), GEMM values val[k][q].  Column
-// data (bounds, class, cut entries) is loaded once per column, the cut loop
-// runs outside the row loop so the gamma gathers of all rows are issued
-// together, and every load precedes the stores (no aliasing between them).
-// rs[q] accumulates the element's contribution to its row constant (fp64).
-// Rows >= M or columns >= N are skipped; their addresses are clamped first.
-
-// gamma^T X for the lane's rows at column j, X in {G, H, Q}; gamma is read
-// from its transposed copy [N][mp], four consecutive rows per 16-byte load.
-template <int R>
-__device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ gammaT, int mp, int j,
-                                   const int (&rr)[R], float (&sG)[R], float (&sH)[R], float (&sQ)[R]) {
-#pragma unroll
-  for (int q = 0; q < R; ++q) sG[q] = sH[q] = sQ[q] = 0.f;
-  if (!cc.col_ptr) return;
-  const int e0 = cc.col_ptr[j], e1 = cc.col_ptr[j + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int ck = cc.cut[e];
-    const float ch = cc.cH[e], cg = cc.cG[e], cq = cc.cQ[e];
-    const float* gk = gammaT + (size_t)ck * mp;
-    float g[R];
-    if constexpr (R % 4 == 0) {
-#pragma unroll
-      for (int q = 0; q < R; q += 4) {
-        const float4 v = *(const float4*)(gk + rr[q]);
-        g[q] = v.x; g[q + 1] = v.y; g[q + 2] = v.z; g[q + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < R; ++q) g[q] = gk[rr[q]];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      sG[q] += g[q] * cg;
-      sH[q] += g[q] * ch;
-      sQ[q] += g[q] * cq;
-    }
-  }
-}
-
-// Row indices of a lane: rv = row is real (< M); rc = row clamped below M,
-// for row-major [M][.] buffers; rr = row for the row-minor [.][mp] buffers,
-// where a group of 4 consecutive rows (starting at a multiple of 4) is kept
-// whole so 16-byte accesses stay aligned -- a group starting below mp lies
-// entirely below mp (mp is a multiple of 16), else it is moved to rows 0..3.
-template <int R>
-__device__ inline void lane_rows(const int (&rows)[R], int M, int mp, int (&rr)[R], int (&rc)[R], bool (&rv)[R]) {
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    rv[q] = rows[q] < M;
-    rc[q] = rv[q] ? rows[q] : 0;
-    if constexpr (R % 4 == 0) rr[q] = rows[q - q % 4] < mp ? rows[q] : q % 4;
-    else rr[q] = rc[q];
-  }
-}
-
-// effective class and split slot of (row, neuron) for the lane's rows
-template <int R>
-__device__ inline void split_classes(const RowParams& rp, int rank, int cls, const int (&rr)[R], int (&c)[R],
-                                     int (&slot)[R]) {
-  int m[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) m[q] = 0;
-  if (rank >= 0 && rp.mask) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) m[q] = rp.mask[(size_t)(rr[q] / rp.S) * rp.n_I + rank];
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    slot[q] = m[q] > 0 ? m[q] - 1 : (m[q] < 0 ? -m[q] - 1 : -1);
-    c[q] = m[q] > 0 ? (int)ACTIVE : (m[q] < 0 ? (int)INACTIVE : cls);
-  }
-}
-
-// Each epilogue is split in two: load() fetches everything that does not
-// depend on the GEMM result (column data, cut gathers, stored a_hat, alpha
-// and its moments, split overrides) and is issued before the K loop, so its
-// latency overlaps the GEMM; apply() combines it with the accumulator and
-// stores.  Frag holds the per-lane state between the two.
-
-template <typename T>
-struct BoundEpi {
-  BoundEpiArgs a;
-  template <int R, int TN> struct Frag {
-    int rc[R];
-    bool rv[R];
-    float bj[TN], lj[TN], uj[TN], iul[TN];
-    float aoff[TN][R];   // acc_in + gamma^T G: added to the GEMM value -> a_hat
-    float tadd[TN][R];   // gamma^T H and the split term: added to Lambda
-    float sQ[TN][R];     // gamma^T Q
-    float al[TN][R];     // alpha (unstable) or 0
-    int8_t c[TN][R];     // effective class
-  };
-  template <int R, int TN>
-  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
-    const NodeDev& nd = a.nd;
-    const RowParams& rp = a.rp;
-    int rr[R];
-    lane_rows<R>(rows, M, rp.mp, rr, f.rc, f.rv);
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k] < N ? cols[k] : 0;
-      f.bj[k] = nd.bias[j]; f.lj[k] = nd.l[j]; f.uj[k] = nd.u[j]; f.iul[k] = nd.inv_ul[j];
-      const int cj = nd.cls[j], rk = nd.rank[j];
-      float sG[R], sH[R];
-      gather_cuts<R>(a.cc, rp.gammaT, rp.mp, j, rr, sG, sH, f.sQ[k]);
-      int c[R], slot[R];
-      split_classes<R>(rp, rk, cj, f.rc, c, slot);
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
-        f.aoff[k][q] = pre + sG[q];
-        f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
-        const float bv = slot[q] >= 0 ? rp.beta[(size_t)f.rc[q] * rp.K + slot[q]] : 0.f;
-        f.tadd[k][q] = sH[q] + (c[q] == ACTIVE ? -bv : (c[q] == INACTIVE ? bv : 0.f));
-        f.c[k][q] = (int8_t)c[q];
-      }
-    }
-  }
-  template <int R, int TN>
-  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
-                               double (&rs)[R], int M, int N) const {
-    const NodeDev& nd = a.nd;
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k];
-      if (j >= N) continue;
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const float ah = val[k][q] + f.aoff[k][q];   // a_hat = Lambda^(i+1) W + gamma^T G
-        float lam, konst;
-        if (f.c[k][q] == ACTIVE) {                   // x_hat = x, z = 1
-          lam = ah + f.tadd[k][q];
-          konst = f.sQ[k][q];
-        } else if (f.c[k][q] == INACTIVE) {          // x_hat = 0, z = 0
-          lam = f.tadd[k][q];
-          konst = 0.f;
-        } else {                                     // Lemma A.1, C = [-a_hat]_+, q = -s
-          const float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f), sq = f.sQ[k][q];
-          float pi, h;
-          if (sq >= f.uj[k] * n) { pi = 0.f; h = 0.f; }
-          else if (sq <= f.lj[k] * n) { pi = n; h = sq; }
-          else { pi = (f.uj[k] * n - sq) * f.iul[k]; h = f.lj[k] * pi; }
-          lam = f.al[k][q] * p - pi + f.tadd[k][q];
-          konst = h;
-        }
-        if (f.rv[q]) {
-          const size_t ij = (size_t)f.rc[q] * nd.ld + j;
-          ((T*)a.lam_out)[ij] = to_t<T>(lam);
-          if (a.ahat_out) a.ahat_out[ij] = ah;
-          rs[q] += (double)lam * (double)f.bj[k] + (double)konst;
-        }
-      }
-    }
-  }
-};
-
-struct ConcEpi {
-  ConcEpiArgs a;
-  template <int R, int TN> struct Frag {
-    int rr[R], rc[R];
-    bool rv[R];
-    float sG[TN][R];
-  };
-  template <int R, int TN>
-  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
-    lane_rows<R>(rows, M, a.rp.mp, f.rr, f.rc, f.rv);
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k] < N ? cols[k] : 0;
-      float sH[R], sQ[R];
-      gather_cuts<R>(a.cc, a.rp.gammaT, a.rp.mp, j, f.rr, f.sG[k], sH, sQ);
-    }
-  }
-  template <int R, int TN>
-  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
-                               double (&rs)[R], int M, int N) const {
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k];
-      if (j >= N) continue;
-      const double xj = a.x0[j];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const float v = val[k][q] + f.sG[k][q];
-        const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
-        if (!f.rv[q]) continue;
-        if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
-        if (a.contrib && a.cc.col_ptr) {
-          const float dv = (float)(xj - a.eps * (double)sg);
-          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
-            a.contrib[(size_t)a.cc.pos[e] * a.rp.mp + f.rr[q]] = a.cc.cG[e] * dv;
-        }
-        const double vd = (double)v;
-        rs[q] += xj * vd - a.eps * fabs(vd);
-      }
-    }
-  }
-};
-
-template <typename T>
-struct AdjEpi {
-  AdjEpiArgs a;
-  template <int R, int TN> struct Frag {
-    int rr[R], rc[R];
-    bool rv[R];
-    float lj[TN], uj[TN], iul[TN], addj[TN];
-    int rk[TN];
-    float ah[TN][R];     // stored a_hat
-    float pre[TN][R];    // acc_in
-    float sQ[TN][R];
-    float al[TN][R], ma[TN][R], va[TN][R];
-    int8_t c[TN][R], slot[TN][R];
-  };
-  template <int R, int TN>
-  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
-    const NodeDev& nd = a.nd;
-    const RowParams& rp = a.rp;
-    lane_rows<R>(rows, M, rp.mp, f.rr, f.rc, f.rv);
-    const bool adam = a.adam.enabled;
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k] < N ? cols[k] : 0;
-      f.lj[k] = nd.l[j]; f.uj[k] = nd.u[j]; f.iul[k] = nd.inv_ul[j]; f.addj[k] = a.add_vec[j];
-      const int cj = nd.cls[j], rk = nd.rank[j];
-      f.rk[k] = rk;
-      float sG[R], sH[R];
-      gather_cuts<R>(a.cc, rp.gammaT, rp.mp, j, f.rr, sG, sH, f.sQ[k]);
-      int c[R], slot[R];
-      split_classes<R>(rp, rk, cj, f.rc, c, slot);
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
-        f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
-        const size_t ia = (size_t)f.rc[q] * rp.n_I + (rk >= 0 ? rk : 0);
-        f.al[k][q] = rk >= 0 ? rp.alpha[ia] : 0.f;
-        f.ma[k][q] = (rk >= 0 && adam) ? a.m_alpha[ia] : 0.f;
-        f.va[k][q] = (rk >= 0 && adam) ? a.v_alpha[ia] : 0.f;
-        f.c[k][q] = (int8_t)c[q];
-        f.slot[k][q] = (int8_t)slot[q];
-      }
-    }
-  }
-  template <int R, int TN>
-  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
-                               double (&rs)[R], int M, int N) const {
-    const NodeDev& nd = a.nd;
-    const RowParams& rp = a.rp;
-    float lr_a = 0.f, lr_m = 0.f, bc1 = 1.f, bc2 = 1.f;
-    if (a.adam.enabled) {
-      lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; bc1 = a.adam.consts[2]; bc2 = a.adam.consts[3];
-    }
-    const float b1 = a.adam.b1, b2 = a.adam.b2, aeps = a.adam.eps;
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k];
-      if (j >= N) continue;
-      const int rk = f.rk[k];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const float dL = a.gemm_scale * val[k][q] + f.addj[k] + f.pre[k][q];
-        float dA, dS, gA = 0.f;
-        const int c = f.c[k][q];
-        if (c == ACTIVE) {
-          dA = dL; dS = 1.f;
-        } else if (c == INACTIVE) {
-          dA = 0.f; dS = 0.f;
-        } else {
-          const float x = f.ah[k][q], n = fmaxf(-x, 0.f), p = fmaxf(x, 0.f), sq = f.sQ[k][q];
-          const float pos = x > 0.f ? 1.f : 0.f, neg = x < 0.f ? 1.f : 0.f;
-          const float uj = f.uj[k], lj = f.lj[k], iul = f.iul[k], al = f.al[k][q];
-          float dLda, dhda, dLds, dhds;
-          if (sq >= uj * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
-          else if (sq <= lj * n) { dLda = al * pos + neg; dhda = 0.f; dLds = 0.f; dhds = 1.f; }
-          else {
-            dLda = al * pos + uj * iul * neg;
-            dhda = -lj * uj * iul * neg;
-            dLds = iul;
-            dhds = -lj * iul;
-          }
-          dA = dL * dLda + dhda;
-          dS = dL * dLds + dhds;
-          gA = dL * p;
-        }
-        if (!f.rv[q]) continue;
-        const size_t ij = (size_t)f.rc[q] * nd.ld + j;
-        if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
-        if (a.contrib && a.cc.col_ptr) {
-          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
-            a.contrib[(size_t)a.cc.pos[e] * rp.mp + f.rr[q]] = a.cc.cG[e] * dA + a.cc.cH[e] * dL + a.cc.cQ[e] * dS;
-        }
-        if (rk >= 0) {
-          const size_t ia = (size_t)f.rc[q] * rp.n_I + rk;
-          if (a.adam.enabled) {
-            const float mm = b1 * f.ma[k][q] + (1.f - b1) * gA;
-            const float vv = b2 * f.va[k][q] + (1.f - b2) * gA * gA;
-            a.m_alpha[ia] = mm;
-            a.v_alpha[ia] = vv;
-            const float stp = lr_a * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
-            a.alpha_rw[ia] = fminf(fmaxf(f.al[k][q] + stp, 0.f), 1.f);
-          } else {
-            a.d_alpha[ia] = gA;
-          }
-        }
-        const int sl = f.slot[k][q];
-        if (sl >= 0) {
-          const size_t ib = (size_t)f.rc[q] * rp.K + sl;
-          const float gB = (c == ACTIVE) ? -dL : dL;
-          if (a.adam.enabled) {
-            const float mm = b1 * a.m_beta[ib] + (1.f - b1) * gB;
-            const float vv = b2 * a.v_beta[ib] + (1.f - b2) * gB * gB;
-            a.m_beta[ib] = mm;
-            a.v_beta[ib] = vv;
-            const float stp = lr_m * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
-            a.beta_rw[ib] = fmaxf(a.beta_rw[ib] + stp, 0.f);
-          } else {
-            a.d_beta[ib] = gB;
-          }
-        }
-      }
-    }
-  }
-};
-
-struct StoreEpi {
-  StoreEpiArgs a;
-  template <int R, int TN> struct Frag {
-    int rc[R];
-    bool rv[R];
-    float pre[TN][R];
-  };
-  template <int R, int TN>
-  __device__ inline void load(Frag<R, TN>& f, const int (&rows)[R], const int (&cols)[TN], int M, int N) const {
-#pragma unroll
-    for (int q = 0; q < R; ++q) { f.rv[q] = rows[q] < M; f.rc[q] = f.rv[q] ? rows[q] : 0; }
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k] < N ? cols[k] : 0;
-#pragma unroll
-      for (int q = 0; q < R; ++q) f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * a.ld + j] : 0.f;
-    }
-  }
-  template <int R, int TN>
-  __device__ inline void apply(const Frag<R, TN>& f, const int (&cols)[TN], const float (&val)[TN][R],
-                               double (&rs)[R], int M, int N) const {
-#pragma unroll
-    for (int k = 0; k < TN; ++k) {
-      const int j = cols[k];
-      if (j >= N) continue;
-#pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (f.rv[q]) a.out[(size_t)f.rc[q] * a.ld + j] = a.scale * val[k][q] + f.pre[k][q];
-    }
-  }
-};
 
 // ------------------------------------------------------------------ tile GEMM
 // C[M][N] = A[M][K] * Bt[N][K]^T on MFMA, epilogue per element, row partial
@@ -519,19 +121,19 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   // output coordinates of this lane and the epilogue operands that do not
   // depend on the GEMM result, fetched before the K loop
   constexpr int R = TM * 4;
-  int rows[R], cols[TN];
+  LaneCoords<R, TN, false> lc;
   {
     const int row0 = m0 + wm * (BM / WM) + (lane >> 4) * 4;
     const int col0 = n0 + wn * (BN / WN) + (lane & 15);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) rows[i * 4 + v] = row0 + i * 16 + v;
+      for (int v = 0; v < 4; ++v) lc.r[i * 4 + v] = row0 + i * 16 + v;
 #pragma unroll
-    for (int k = 0; k < TN; ++k) cols[k] = col0 + k * 16;
+    for (int k = 0; k < TN; ++k) lc.j[k][0] = col0 + k * 16;
   }
-  typename Epi::template Frag<R, TN> fr;
-  epi.template load<R, TN>(fr, rows, cols, g.M, g.N);
+  typename Epi::template Frag<R, TN, false> fr;
+  epi.template load<R, TN, false>(fr, lc, g.M, g.N);
 
   if (g.K > 0) load_stage(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
@@ -565,11 +167,11 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) val[k][i * 4 + v] = acc[i][k][v];
-    epi.template apply<R, TN>(fr, cols, val, rs, g.M, g.N);
+    epi.template apply<R, TN, false>(fr, lc, val, rs, g.M, g.N);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       double t = wave_sum16(rs[q]);
-      if ((lane & 15) == 0) red[wn][rows[q] - m0] = t;
+      if ((lane & 15) == 0) red[wn][lc.r[q] - m0] = t;
     }
   }
   if (g.partial) {
@@ -647,18 +249,25 @@ hipError_t launch_gemm(int bf16_mode, int cfg, EpiKind kind, const GemmArgs& g, 
 // ------------------------------------------------------------------ elementwise
 // One block = one row x 256 columns; row partial per column block.
 template <typename T>
-__global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, BoundEpiArgs a, double* partial,
-                                                         int slot0) {
+__global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, const void* src, BoundEpiArgs a,
+                                                         double* partial, int slot0) {
   __shared__ double red[4];
   const int r = blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
   BoundEpi<T> epi{a};
-  int rows[1] = {r}, cols[1] = {j};
-  float val[1][1] = {{(bcast && j < a.nd.size) ? bcast[(size_t)(r % a.rp.S) * a.nd.ld + j] : 0.f}};
+  LaneCoords<1, 1, false> lc;
+  lc.r[0] = r;
+  lc.j[0][0] = j;
+  float pre = 0.f;
+  if (j < a.nd.size) {
+    if (bcast) pre += bcast[(size_t)(r % a.rp.S) * a.nd.ld + j];
+    if (src) pre += from_t<T>(((const T*)src)[(size_t)r * a.nd.ld + j]);
+  }
+  float val[1][1] = {{pre}};
   double rs[1] = {0.0};
-  typename BoundEpi<T>::template Frag<1, 1> fr;
-  epi.template load<1, 1>(fr, rows, cols, a.rp.M, a.nd.size);
-  epi.template apply<1, 1>(fr, cols, val, rs, a.rp.M, a.nd.size);
+  typename BoundEpi<T>::template Frag<1, 1, false> fr;
+  epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
+  epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
   double t = rs[0];
   for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
@@ -667,13 +276,13 @@ __global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, Bou
     partial[(size_t)(slot0 + blockIdx.y) * a.rp.mp + r] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const BoundEpiArgs& a,
-                                          double* partial, int slot0, hipStream_t st) {
+hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const void* src, const BoundEpiArgs& a,
+                                    double* partial, int slot0, hipStream_t st) {
   dim3 grid(a.rp.M, (a.nd.size + 255) / 256);
   if (bf16_mode)
-    hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, a, partial, slot0);
+    hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   else
-    hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, a, partial, slot0);
+    hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   return hipGetLastError();
 }
 
@@ -682,12 +291,14 @@ __global__ void __launch_bounds__(256) adj_elem_kernel(AdjEpiArgs a) {
   const int r = blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
   AdjEpi<T> epi{a};
-  int rows[1] = {r}, cols[1] = {j};
+  LaneCoords<1, 1, false> lc;
+  lc.r[0] = r;
+  lc.j[0][0] = j;
   float val[1][1] = {{0.f}};
   double rs[1] = {0.0};
-  typename AdjEpi<T>::template Frag<1, 1> fr;
-  epi.template load<1, 1>(fr, rows, cols, a.rp.M, a.nd.size);
-  epi.template apply<1, 1>(fr, cols, val, rs, a.rp.M, a.nd.size);
+  typename AdjEpi<T>::template Frag<1, 1, false> fr;
+  epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
+  epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
 }
 
 hipError_t launch_adj_elementwise(int bf16_mode, const AdjEpiArgs& a, hipStream_t st) {
@@ -696,6 +307,32 @@ hipError_t launch_adj_elementwise(int bf16_mode, const AdjEpiArgs& a, hipStream_
     hipLaunchKernelGGL(adj_elem_kernel<bf16>, grid, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(adj_elem_kernel<float>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// out[r][j] = (acc_in ? acc_in[r][j] : 0) + scale * src[r][j]  (identity edge);
+// src is the operand type, or int8 signs when is_sign.
+template <typename T>
+__global__ void __launch_bounds__(256) identity_acc_kernel(int M, int size, const void* src, int ld_src, int is_sign,
+                                                           float scale, const float* acc_in, float* out, int ld_out) {
+  const int r = blockIdx.x;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= size) return;
+  const float x = is_sign ? (float)((const int8_t*)src)[(size_t)r * ld_src + j]
+                          : from_t<T>(((const T*)src)[(size_t)r * ld_src + j]);
+  out[(size_t)r * ld_out + j] = (acc_in ? acc_in[(size_t)r * ld_out + j] : 0.f) + scale * x;
+}
+
+hipError_t launch_identity_acc(int bf16_mode, int M, int size, const void* src, int ld_src, int is_sign, float scale,
+                               const float* acc_in, float* out, int ld_out, hipStream_t st) {
+  if (M == 0 || size == 0) return hipSuccess;
+  dim3 grid(M, (size + 255) / 256);
+  if (bf16_mode)
+    hipLaunchKernelGGL(identity_acc_kernel<bf16>, grid, dim3(256), 0, st, M, size, src, ld_src, is_sign, scale,
+                       acc_in, out, ld_out);
+  else
+    hipLaunchKernelGGL(identity_acc_kernel<float>, grid, dim3(256), 0, st, M, size, src, ld_src, is_sign, scale,
+                       acc_in, out, ld_out);
   return hipGetLastError();
 }
 

@@ -209,3 +209,46 @@ def test_optimize_bf16_final_bound_close_to_fp32():
     ref = O.bound(p, a64, b64, c64).reshape(-1)
     T = O.error_scale(p, a64, b64, c64).reshape(-1)
     assert rel_err(g16, ref, T).max() <= 1e-5
+
+
+# ------------------------------------------------------------------ conv / residual nets
+
+@pytest.mark.parametrize("kind,seed", [("cnn16", 0), ("cnn16", 3), ("res16", 1), ("res16", 2)])
+def test_conv_and_residual_fp32_bound_and_gradients(kind, seed):
+    p = gen.make_tiny(kind, seed, B=3, splits=(1, 3), n_cuts=6, input_terms=1)
+    check_bound(p)
+
+
+def test_conv_bf16_close_to_oracle():
+    p = gen.make_tiny("cnn16", 5, B=4, splits=(1, 3), n_cuts=6)
+    check_bound(p, mode=1, tol=2e-2, grads=False)
+
+
+def test_config3_cnn_small_batch_fp32():
+    # Conv(3,16,4,s2,p1) - Conv(16,32,4,s2,p1) - 2048-100-10 with 500 cuts
+    p = gen.make_config(3, 0, B=2)
+    rng = np.random.default_rng(1)
+    prep = O.Prepared(p)
+    alpha = rng.random((p.B, p.S, prep.n_I)).astype(np.float32)
+    gamma = (rng.random((p.B, p.S, p.cuts.n)) * 0.05).astype(np.float32)
+    check_bound(p, alpha=alpha, gamma=gamma)
+
+
+def test_config5_resnet_single_domain_fp32():
+    p = gen.make_config(5, 0, B=1)
+    rng = np.random.default_rng(2)
+    gamma = (rng.random((p.B, p.S, p.cuts.n)) * 0.05).astype(np.float32)
+    check_bound(p, gamma=gamma)
+
+
+def test_optimize_conv_matches_oracle():
+    p = gen.make_tiny("res16", 3, B=2, splits=(1, 2), n_cuts=5, gamma_dist="zero")
+    P = upload(p)
+    g, a, b, c = _optimize(p, P, 0)
+    a64, b64, c64 = (x.cpu().numpy().astype(np.float64).reshape(p.B, p.S, -1) for x in (a, b, c))
+    ref = O.bound(p, a64, b64, c64).reshape(-1)
+    T = O.error_scale(p, a64, b64, c64).reshape(-1)
+    assert rel_err(g, ref, T).max() <= 1e-5
+    go, *_ = O.optimize(p)
+    To = O.error_scale(p).reshape(-1)
+    assert rel_err(g, go.reshape(-1), To).max() <= 1e-3

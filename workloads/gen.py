@@ -561,15 +561,22 @@ def make_tiny(kind: str, seed: int = 0, B: int = 1, splits=(0, 0), n_cuts: int =
               alpha_init: str = "given", gamma_dist: str = "uniform",
               beta_dist: str = "uniform", input_terms: int = 0) -> Problem:
     """Small problems for exact (LP / MIP / enumeration) checks.
-    kind: 'mlp' (6-8-8-3), 'cnn' (1x6x6, two convs, dense 5, out 3) or
-    'res' (1x4x4 stem, identity block, stride-2 block, out 3)."""
+    kind: 'mlp' (6-8-8-3), 'cnn' (1x6x6, two convs, dense 5, out 3),
+    'res' (1x4x4 stem, identity block, stride-2 block, out 3), or 'cnn16' /
+    'res16' (the same structures on an 8x8 input, every spatial size a
+    multiple of 16 positions)."""
     r_w, r_x, r_cut, r_split, r_par = _streams([seed, 99])
     if kind == "mlp":
         net = mlp_net(r_w, [6, 8, 8, 3], w_var_num=1.0)
     elif kind == "cnn":
         net = cnn_net(r_w, (1, 6, 6), ((2, 3, 2, 1), (3, 3, 1, 1)), (5, 3))
-    elif kind == "res":
-        net = resnet_net(r_w, stem=1, stages=(1, 2), hw=4, in_ch=1)
+    elif kind == "cnn16":    # spatial sizes multiples of 16 positions
+        net = cnn_net(r_w, (1, 8, 8), ((2, 4, 2, 1), (3, 3, 1, 1)), (5, 3))
+    elif kind in ("res", "res16"):
+        if kind == "res":
+            net = resnet_net(r_w, stem=1, stages=(1, 2), hw=4, in_ch=1)
+        else:
+            net = resnet_net(r_w, stem=2, stages=(2, 3), hw=8, in_ch=1)
         last = net.nodes[-1]
         W = last.edges[0].W
         net.nodes[-1] = Node((3,), last.bias[:3], [Edge(last.edges[0].src, "dense", W[:3])], relu=False)
