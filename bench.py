@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
     return ap.parse_args()
 
 
@@ -70,6 +71,7 @@ def main():
     bound = torch.empty(M, dtype=torch.float64, device=dev)
     ver = torch.empty(M, dtype=torch.uint8, device=dev)
     o = prob.opt
+    use_graph = [args.graph]
 
     def step(mode):
         alpha.copy_(alpha0)
@@ -78,7 +80,8 @@ def main():
         state.zero_()
         B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, state, iters=o["iters"],
                    lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
-                   b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode, bound_out=bound, verified_out=ver)
+                   b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode, bound_out=bound, verified_out=ver,
+                   use_graph=use_graph[0])
 
     def timed(mode, steps, warmup):
         for _ in range(warmup):
@@ -104,7 +107,9 @@ def main():
         # events on its stream (the markers slow the run, so `value` comes
         # from the uninstrumented region above)
         B.profile_enable(True)
+        use_graph[0] = False     # per-kernel events need eager launches
         dt_prof = timed(mode, args.steps, 0)
+        use_graph[0] = args.graph
         B.profile_enable(False)
         kprof = B.profile_read()
     bound_main = bound.cpu().numpy().copy()
@@ -126,7 +131,7 @@ def main():
             "workload": "GCP-CROWN bound optimisation, MLP 784-256x6-10, 1024 BaB domains x 9 spec rows, "
                         "200 cuts, 1-8 splits/domain, 20 Adam iterations + fp32/fp64 certifying pass",
             "domains": args.domains, "spec_rows": prob.S, "rows": M, "n_unstable": P.n_I,
-            "cuts": P.N, "split_slots": P.K, "iters": o["iters"],
+            "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
         },
     }

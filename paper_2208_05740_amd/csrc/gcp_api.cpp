@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -81,6 +82,9 @@ template <class F>
 hipError_t timed(hipStream_t st, const std::string& name, double bytes, double flops, F f) {
   Profiler& P = prof();
   if (!P.on) return f();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(st, &cs);
+  if (cs != hipStreamCaptureStatusNone) return f();   // graph replays are not timed per kernel
   std::lock_guard<std::mutex> lk(P.mu);
   hipEvent_t e0 = P.get(), e1 = P.get();
   hip_check(hipEventRecord(e0, st), "hipEventRecord");
@@ -171,6 +175,10 @@ struct NodeH {
 }  // namespace
 
 struct gcp_net {
+  ~gcp_net() {
+    if (ws.gexec) (void)hipGraphExecDestroy(ws.gexec);
+    if (ws.gstream) (void)hipStreamDestroy(ws.gstream);
+  }
   int device = 0;
   int in_c, in_h, in_w, in_size, in_ld;
   std::vector<NodeH> nodes;
@@ -186,6 +194,11 @@ struct gcp_net {
     std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
     DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in, gammaT;
     DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
+    // captured Adam iteration of gcp_optimize (valid for one argument set)
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uintptr_t> gkey;
+    uint64_t gen = 0;   // bumped whenever a workspace buffer is reallocated
     std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
     int n_slots = 0;
   } ws;
@@ -733,6 +746,7 @@ void ensure_ws(Call& c) {
   ws.flags.alloc(16);
   ws.acc_in.alloc((size_t)M * net->in_ld * 4);
   ws.M = M; ws.S = S; ws.nnz = nnz; ws.N = Nc;
+  ws.gen++;
   ws.n_slots = 0;
   ws.partial.release();
 }
@@ -1210,7 +1224,10 @@ void size_partials(Call& c, int bf16, bool keep, bool contrib) {
   dry.run();
   auto& ws = c.net->ws;
   const size_t need = (size_t)round_up(ws.M, 16) * std::max(dry.slot, 1) * 8;
-  if (need > ws.partial.bytes) ws.partial.alloc(need);
+  if (need > ws.partial.bytes) {
+    ws.partial.alloc(need);
+    ws.gen++;
+  }
   ws.n_slots = dry.slot;
 }
 
@@ -1312,22 +1329,67 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
     AdjPass prep{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
     prep.prepare();
   }
-  for (int it = 0; it < opt->iters; ++it) {
+  auto iteration = [&](Call& cc) {
     hip_check(launch_adam_prepare(ws.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
-                                  opt->adam_b2, ws.consts.as<float>(), c.st),
+                                  opt->adam_b2, ws.consts.as<float>(), cc.st),
               "adam prepare");
-    BoundPass bp(c, bf16, true, c.nnz > 0, false);
+    BoundPass bp(cc, bf16, true, cc.nnz > 0, false);
     bp.run();
-    AdjPass ap{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+    AdjPass ap{cc, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
     ap.run();
     if (N > 0)
-      hip_check(timed(c.st, "gamma_adam", (double)c.M * (c.nnz * 4.0 + N * 24.0), 0.0, [&] {
-                  return launch_gamma_update(c.M, c.rp.mp, (int)N, c.cuts->row_ptr.as<int32_t>(),
-                                             ws.contrib.as<float>(), c.cuts->d.as<double>(), ws.gammaT.as<float>(),
-                                             nullptr, mg, vg, adam, c.st);
+      hip_check(timed(cc.st, "gamma_adam", (double)cc.M * (cc.nnz * 4.0 + N * 24.0), 0.0, [&] {
+                  return launch_gamma_update(cc.M, cc.rp.mp, (int)N, cc.cuts->row_ptr.as<int32_t>(),
+                                             ws.contrib.as<float>(), cc.cuts->d.as<double>(), ws.gammaT.as<float>(),
+                                             nullptr, mg, vg, adam, cc.st);
                 }),
                 "gamma update");
+  };
+  int done = 0;
+  if (opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
+    iteration(c);
+    done = 1;
   }
+  if (opt->use_graph && opt->iters > 1) {
+    std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits, (uintptr_t)cuts,
+                                  (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)adam_state,
+                                  (uintptr_t)S, (uintptr_t)bf16, (uintptr_t)c.M,
+                                  (uintptr_t)std::hash<double>()(eps), (uintptr_t)ws.gen};
+    for (float v : {opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, opt->adam_eps}) {
+      uint32_t b;
+      std::memcpy(&b, &v, 4);
+      key.push_back(b);
+    }
+    if (!ws.gstream) hip_check(hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking), "hipStreamCreate");
+    hipEvent_t ev;
+    hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventRecord(ev, c.st), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(ws.gstream, ev, 0), "hipStreamWaitEvent");
+    if (!ws.gexec || ws.gkey != key) {
+      if (ws.gexec) { (void)hipGraphExecDestroy(ws.gexec); ws.gexec = nullptr; }
+      Call cg = c;
+      cg.st = ws.gstream;
+      hipGraph_t graph;
+      hip_check(hipStreamBeginCapture(ws.gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        iteration(cg);
+      } catch (...) {
+        hipGraph_t g2;
+        (void)hipStreamEndCapture(ws.gstream, &g2);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(ws.gstream, &graph), "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&ws.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      hip_check(ie, "hipGraphInstantiate");
+      ws.gkey = key;
+    }
+    for (; done < opt->iters; ++done) hip_check(hipGraphLaunch(ws.gexec, ws.gstream), "hipGraphLaunch");
+    hip_check(hipEventRecord(ev, ws.gstream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(c.st, ev, 0), "hipStreamWaitEvent");
+    (void)hipEventDestroy(ev);
+  }
+  for (; done < opt->iters; ++done) iteration(c);
   if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   bound_pass(c, 0, false, false, bound, verified);

@@ -19,8 +19,6 @@ import sqlite3
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# tile configurations, as in the kernel table: cfg -> (BM, BN); all use 2x2 waves
-TILES = {(64, 64), (128, 64), (64, 128), (128, 128), (32, 64), (32, 32), (16, 64), (16, 32)}
 EPI = {"bound": "BoundEpi", "conc": "ConcEpi", "adj": "AdjEpi", "store": "StoreEpi"}
 
 
@@ -93,10 +91,14 @@ def cmd_summary(a):
 
 
 def source_sha():
+    """Hash of every device-code source (kernels and the headers they use)."""
     h = hashlib.sha1()
-    for f in ("kernels.hip", "gcp_internal.h"):
-        with open(os.path.join(ROOT, "paper_2208_05740_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    d = os.path.join(ROOT, "paper_2208_05740_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()
 
 

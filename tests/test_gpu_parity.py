@@ -252,3 +252,32 @@ def test_optimize_conv_matches_oracle():
     go, *_ = O.optimize(p)
     To = O.error_scale(p).reshape(-1)
     assert rel_err(g, go.reshape(-1), To).max() <= 1e-3
+
+
+def test_graph_replayed_optimisation_equals_eager():
+    # One Adam iteration captured in a hipGraph and replayed must give the
+    # same final parameters and bound as the eager loop, on every call, with
+    # eager work in between.
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_config(2, 1, B=3)
+    P = upload(p)
+    a0, b0, c0, *_ = params(p, P)
+    o = p.opt
+
+    def run(graph):
+        a, b, c = a0.clone(), b0.clone(), c0.clone()
+        st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+        out, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=o["iters"],
+                            lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], use_graph=graph)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), a.cpu().numpy(), c.cpu().numpy()
+
+    ref = run(False)
+    for rep in range(3):
+        got = run(True)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), rep
+        eager = run(False)
+        for x, y in zip(eager, ref):
+            assert np.array_equal(x, y), rep
