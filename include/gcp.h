@@ -198,6 +198,31 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  const gcp_opt* opt, int32_t mode,
                  double* bound, uint8_t* verified, void* stream);
 
+/* ------------------------------------------------------------ batching */
+/* One verification instance of a batched optimisation: the arguments of
+ * gcp_optimize for that instance. */
+typedef struct {
+  const gcp_net* net;
+  const double* x0; double eps;
+  const double* C; int32_t S;
+  const gcp_splits* splits; const gcp_cuts* cuts;
+  float* alpha; float* beta; float* gamma; float* adam_state;
+  double* bound; uint8_t* verified;
+} gcp_batch_item;
+
+/* gcp_optimize_batch: gcp_optimize of every item with the same settings and mode, but each Adam iteration of
+ * all instances runs as a few grouped launches -- launches of the same kernel
+ * at the same position of each instance's schedule become one launch whose
+ * workgroups look up their instance in a device table -- instead of one
+ * launch per layer per instance.  The first call with an argument set runs
+ * iteration 0 per instance (tuning tiles, recording the schedule) and builds
+ * the tables; calls with the same argument set reuse them.  With
+ * opt->use_graph the grouped iteration is captured once and replayed.
+ * Results equal per-instance gcp_optimize calls with the same tiles.  Every
+ * item needs its own net handle; dense networks only (EUNSUPPORTED for conv
+ * or identity edges).  Calls from several threads are serialised. */
+int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode, void* stream);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel timing for roofline reports.  While enabled, every kernel the
  * library launches is bracketed by HIP events on the stream it runs on and

@@ -57,10 +57,16 @@ class OptDesc(C.Structure):
                 ("adam_eps", C.c_float), ("use_graph", C.c_int32)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("net", C.c_void_p), ("x0", C.c_void_p), ("eps", C.c_double), ("C", C.c_void_p), ("S", C.c_int32),
+                ("splits", C.c_void_p), ("cuts", C.c_void_p), ("alpha", C.c_void_p), ("beta", C.c_void_p),
+                ("gamma", C.c_void_p), ("adam_state", C.c_void_p), ("bound", C.c_void_p), ("verified", C.c_void_p)]
+
+
 _LIB = None
 EXPORTS = ["gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
-           "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
-           "gcp_profile_read", "gcp_last_error", "gcp_version"]
+           "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_optimize_batch",
+           "gcp_profile_enable", "gcp_profile_read", "gcp_last_error", "gcp_version"]
 
 
 def lib():
@@ -81,6 +87,7 @@ def lib():
     L.gcp_splits_destroy.argtypes = [vp]
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
+    L.gcp_optimize_batch.argtypes = [i32, C.POINTER(BatchItem), C.POINTER(OptDesc), i32, vp]
     L.gcp_profile_enable.argtypes = [i32]
     L.gcp_profile_read.argtypes = [i32, C.c_char_p, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -88,7 +95,7 @@ def lib():
     L.gcp_version.restype = C.c_char_p
     for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
               "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
-              "gcp_profile_read"):
+              "gcp_profile_read", "gcp_optimize_batch"):
         getattr(L, f).restype = C.c_int
     _LIB = L
     return L
@@ -240,6 +247,24 @@ def optimize(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cut
                               _ptr(gamma) if gamma.numel() else None, _ptr(adam_state), C.byref(o), mode,
                               _ptr(out), _ptr(ver), _stream()))
     return out, ver
+
+
+def optimize_batch(items, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.9, b2=0.999, adam_eps=1e-8,
+                   mode: int = GCP_MODE_FP32, use_graph: bool = False):
+    """gcp_optimize_batch over a list of dicts with keys P (a Problem),
+    alpha, beta, gamma, state, bound, verified (device tensors; updated /
+    written in place)."""
+    arr = (BatchItem * len(items))()
+    for i, it in enumerate(items):
+        P = it["P"]
+        arr[i] = BatchItem(P.net.h.value, _ptr(P.x0), float(P.eps), _ptr(P.C), P.S, P.splits.h.value,
+                           P.cuts.h.value if P.cuts else None,
+                           _ptr(it["alpha"]) if it["alpha"].numel() else None,
+                           _ptr(it["beta"]) if it["beta"].numel() else None,
+                           _ptr(it["gamma"]) if it["gamma"].numel() else None,
+                           _ptr(it["state"]), _ptr(it["bound"]), _ptr(it["verified"]))
+    o = OptDesc(iters, lr_alpha, lr_mult, decay, b1, b2, adam_eps, int(use_graph))
+    _check(lib().gcp_optimize_batch(len(items), arr, C.byref(o), mode, _stream()))
 
 
 def adam_state_size(M, n_I, K, N):

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -43,6 +44,14 @@ void hip_check(hipError_t e, const char* what) {
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Workspace generations are unique across nets, so a cached launch table or
+// graph keyed by (handle address, generation) never matches a new net that
+// reuses a freed address.
+uint64_t next_generation() {
+  static std::atomic<uint64_t> g{1};
+  return g.fetch_add(1);
+}
 
 // ------------------------------------------------------------------ profiler
 // Process-wide record of kernel launches bracketed by HIP events (only while
@@ -198,7 +207,7 @@ struct gcp_net {
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<uintptr_t> gkey;
-    uint64_t gen = 0;   // bumped whenever a workspace buffer is reallocated
+    uint64_t gen = 0;   // new process-unique value whenever a workspace buffer is reallocated
     std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
     int n_slots = 0;
   } ws;
@@ -692,7 +701,25 @@ extern "C" int gcp_splits_destroy(gcp_splits* s) {
 
 namespace {
 
+// One recorded launch of an iteration (batched optimisation): a dense GEMM
+// with its epilogue arguments, or an elementwise relaxation.
+struct Rec {
+  int type;            // 0 GEMM, 1 elementwise bound
+  int bf16, cfg, kind, sign;
+  GemmArgs g;
+  alignas(16) unsigned char epi[sizeof(AdjEpiArgs) > sizeof(BoundEpiArgs) ? sizeof(AdjEpiArgs) : sizeof(BoundEpiArgs)];
+  ElemBoundJob ej;
+  int tiles;           // workgroups of this problem
+};
+static_assert(sizeof(ConcEpiArgs) <= sizeof(Rec::epi) && sizeof(StoreEpiArgs) <= sizeof(Rec::epi), "epi blob");
+struct Recorder {
+  std::vector<Rec> bound, adj;   // in launch order
+  bool in_adj = false;
+  void push(const Rec& r) { (in_adj ? adj : bound).push_back(r); }
+};
+
 struct Call {
+  Recorder* rec = nullptr;
   gcp_net* net;
   const gcp_cuts* cuts;
   const gcp_splits* splits;
@@ -746,7 +773,7 @@ void ensure_ws(Call& c) {
   ws.flags.alloc(16);
   ws.acc_in.alloc((size_t)M * net->in_ld * 4);
   ws.M = M; ws.S = S; ws.nnz = nnz; ws.N = Nc;
-  ws.gen++;
+  ws.gen = next_generation();
   ws.n_slots = 0;
   ws.partial.release();
 }
@@ -781,6 +808,24 @@ float* tune_beta(Call& c) {
   size_t need = (size_t)c.M * std::max(c.rp.K, 1) * 4;
   if (ws.tune_beta.bytes < need) ws.tune_beta.alloc(need);
   return ws.tune_beta.as<float>();
+}
+
+// In recording mode a GEMM launch is stored instead of issued.
+template <class A>
+bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a) {
+  if (!c.rec) return false;
+  Rec r{};
+  r.type = 0; r.bf16 = bf16; r.cfg = cfg; r.kind = kind; r.sign = g.a_is_sign;
+  r.g = g;
+  std::memcpy(r.epi, &a, sizeof(A));
+  int bm, bn;
+  gemm_config_tile(cfg, &bm, &bn);
+  r.tiles = ((g.N + bn - 1) / bn) * ((g.M + bm - 1) / bm);
+  c.rec->push(r);
+  return true;
+}
+void no_record(const Call& c, const char* what) {
+  if (c.rec) fail(GCP_EUNSUPPORTED, std::string("batched optimisation supports dense edges only (") + what + ")");
 }
 
 const void* wt_bound(const EdgeH& E, int bf16) { return bf16 ? E.WT16.p : E.WT32.p; }
@@ -826,7 +871,7 @@ struct BoundPass {
     pushes_left[nn] = (int)net->in_consumers.size();
     // output node: c-hat = C W (per spec row), constant C b_out
     const NodeH& on = net->nodes[net->out];
-    if (!dry) {
+    if (!dry && !c.rec) {
       check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
       for (int eid : on.in_edges) {
         const EdgeH& E = *net->edges[eid];
@@ -842,7 +887,13 @@ struct BoundPass {
       pushes_left[p]--;
       BoundEpiArgs a = bound_args(p, false);
       int nslot = slots_for_elementwise(net->nodes[p].size);
-      if (!dry)
+      if (!dry && c.rec) {
+        Rec r{};
+        r.type = 1; r.bf16 = bf16; r.cfg = -1; r.kind = EPI_BOUND; r.sign = 0;
+        r.ej = ElemBoundJob{ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(), slot};
+        r.tiles = c.M * ((net->nodes[p].size + 255) / 256);
+        c.rec->push(r);
+      } else if (!dry)
       {
         const double M = c.M, d = net->nodes[p].size, esz = bf16 ? 2 : 4;
         const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
@@ -902,8 +953,9 @@ struct BoundPass {
           });
           const double esz = bf16 ? 2 : 4;
           const double bytes = (double)g.M * g.K * esz + (double)g.N * g.K * esz + (double)g.M * g.N * 4 * (first ? 1 : 2);
-          check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                      [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s))
+            check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                        [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         }
         return;
       }
@@ -920,8 +972,9 @@ struct BoundPass {
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * 4 : 0) +
                                M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
-          check(timed(c.st, cls_name("bound", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                      [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
+          if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a))
+            check(timed(c.st, cls_name("bound", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                        [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
         }
       } else {
         if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
@@ -940,14 +993,16 @@ struct BoundPass {
           const double M = g.M, esz = bf16 ? 2 : 4;
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + (keep_ahat ? M * g.N : 0) +
                                M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
-          check(timed(c.st, cls_name("conc", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                      [&] { return launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st); }));
+          if (!record_gemm(c, bf16, cfg, EPI_CONC, g, a))
+            check(timed(c.st, cls_name("conc", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                        [&] { return launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st); }));
         }
       }
       slot += nslot;
       return;
     }
     if (E.kind == GCP_EDGE_CONV) {
+      no_record(c, "conv");
       const ConvGeom& cg = E.cg;
       ConvArgs ca{};
       ca.M = c.M; ca.cg = cg; ca.trans = 1;
@@ -1010,6 +1065,7 @@ struct BoundPass {
       return;
     }
     if (E.kind == GCP_EDGE_IDENTITY) {
+      no_record(c, "identity");
       if (p < 0) fail(GCP_EUNSUPPORTED, "identity edge from the network input");
       if (!last) {
         if (!dry)
@@ -1109,8 +1165,9 @@ struct AdjPass {
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
           const double bytes = a_bytes + (double)g.N * g.K * esz + M * di * 4 * (first ? 1 : 2);
-          check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                      [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s))
+            check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                        [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
           int cfg = choose_cfg("gemm", EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
@@ -1120,10 +1177,12 @@ struct AdjPass {
             t.d_beta = tune_beta(c);
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
-          check(timed(c.st, cls_name("adj", bf16, sign, cfg), adj_bytes(a_bytes, (double)g.N * g.K * esz),
-                      2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
+          if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a))
+            check(timed(c.st, cls_name("adj", bf16, sign, cfg), adj_bytes(a_bytes, (double)g.N * g.K * esz),
+                        2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
       } else if (E.kind == GCP_EDGE_CONV) {
+        no_record(c, "conv");
         ConvArgs ca{};
         ca.M = c.M; ca.cg = E.cg; ca.trans = 0;
         ca.X = A; ca.ldx = lda; ca.x_is_sign = sign;
@@ -1155,6 +1214,7 @@ struct AdjPass {
                       [&] { return launch_conv(bf16, cfg, EPI_ADJ, ca, &a, c.st); }));
         }
       } else {   // identity: accumulate; the node's relaxation runs after the last edge
+        no_record(c, "identity");
         check(launch_identity_acc(bf16, c.M, n.size, A, lda, sign, scale, first ? nullptr : accbuf, accbuf, n.ld,
                                   c.st));
         if (last) {
@@ -1226,7 +1286,7 @@ void size_partials(Call& c, int bf16, bool keep, bool contrib) {
   const size_t need = (size_t)round_up(ws.M, 16) * std::max(dry.slot, 1) * 8;
   if (need > ws.partial.bytes) {
     ws.partial.alloc(need);
-    ws.gen++;
+    ws.gen = next_generation();
   }
   ws.n_slots = dry.slot;
 }
@@ -1426,6 +1486,272 @@ extern "C" int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64
   if (total_ms) *total_ms = a.ms;
   if (bytes) *bytes = a.bytes;
   if (flops) *flops = a.flops;
+  return GCP_OK;
+  GCP_CATCH
+}
+
+// ====================================================================== batch
+
+namespace {
+
+// constants of the output layer for one call (c-hat = C W, C b_out)
+void launch_constants(Call& c) {
+  gcp_net* net = c.net;
+  auto& ws = net->ws;
+  const NodeH& on = net->nodes[net->out];
+  hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");
+  for (int eid : on.in_edges) {
+    const EdgeH& E = *net->edges[eid];
+    hip_check(launch_chat(c.C, c.S, on.size, E.Wraw.as<float>(), E.d_src, E.kind == GCP_EDGE_IDENTITY ? 2 : 0,
+                          ws.chat.as<float>() + ws.chat_off[E.src], net->nodes[E.src].ld, c.st),
+              "c-hat");
+  }
+}
+
+// Grouped launches of one iteration, tables in one device buffer.
+struct Group {
+  int type, bf16, cfg, kind, sign;
+  int np, total;
+  size_t off_args, off_epi, off_prefix;   // byte offsets into the plan buffer
+};
+struct BatchPlan {
+  std::vector<uintptr_t> key;
+  DBuf buf;
+  std::vector<Group> groups;              // in launch order
+  size_t off_gjobs = 0, off_gprefix = 0;
+  int g_np = 0, g_total = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gstream = nullptr;
+  ~BatchPlan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
+};
+std::mutex g_batch_mu;
+// One cached plan (the last argument set).  Deliberately never destroyed at
+// process exit: its graph and buffers must not be released after the HIP
+// runtime has shut down; a new argument set replaces it.
+BatchPlan* g_batch = nullptr;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void build_plan(BatchPlan& plan, std::vector<Recorder>& recs, std::vector<GammaJob>& gj) {
+  // waves: the w-th recorded launch of every instance, bound part then adjoint
+  // part; within a wave, one group per kernel instantiation
+  std::vector<std::vector<const Rec*>> waves;
+  size_t maxb = 0, maxa = 0;
+  for (auto& r : recs) { maxb = std::max(maxb, r.bound.size()); maxa = std::max(maxa, r.adj.size()); }
+  for (size_t w = 0; w < maxb; ++w) {
+    waves.emplace_back();
+    for (auto& r : recs) if (w < r.bound.size()) waves.back().push_back(&r.bound[w]);
+  }
+  for (size_t w = 0; w < maxa; ++w) {
+    waves.emplace_back();
+    for (auto& r : recs) if (w < r.adj.size()) waves.back().push_back(&r.adj[w]);
+  }
+  std::vector<unsigned char> host;
+  auto put = [&](const void* p, size_t n) {
+    size_t off = align_up(host.size(), 16);
+    host.resize(off + n);
+    std::memcpy(host.data() + off, p, n);
+    return off;
+  };
+  for (auto& wave : waves) {
+    std::map<std::tuple<int, int, int, int, int>, std::vector<const Rec*>> by;
+    for (const Rec* r : wave) by[std::make_tuple(r->type, r->bf16, r->cfg, r->kind, r->sign)].push_back(r);
+    for (auto& kv : by) {
+      const auto& v = kv.second;
+      Group G{};
+      G.type = v[0]->type; G.bf16 = v[0]->bf16; G.cfg = v[0]->cfg; G.kind = v[0]->kind; G.sign = v[0]->sign;
+      G.np = (int)v.size();
+      std::vector<int> prefix(1, 0);
+      for (const Rec* r : v) prefix.push_back(prefix.back() + r->tiles);
+      G.total = prefix.back();
+      if (G.type == 0) {
+        std::vector<GemmArgs> ga;
+        for (const Rec* r : v) ga.push_back(r->g);
+        G.off_args = put(ga.data(), ga.size() * sizeof(GemmArgs));
+        size_t esz = G.kind == EPI_BOUND ? sizeof(BoundEpiArgs)
+                   : G.kind == EPI_CONC ? sizeof(ConcEpiArgs)
+                   : G.kind == EPI_ADJ ? sizeof(AdjEpiArgs) : sizeof(StoreEpiArgs);
+        std::vector<unsigned char> eb(esz * v.size());
+        for (size_t i = 0; i < v.size(); ++i) std::memcpy(eb.data() + i * esz, v[i]->epi, esz);
+        G.off_epi = put(eb.data(), eb.size());
+      } else {
+        std::vector<ElemBoundJob> jb;
+        for (const Rec* r : v) jb.push_back(r->ej);
+        G.off_args = put(jb.data(), jb.size() * sizeof(ElemBoundJob));
+      }
+      G.off_prefix = put(prefix.data(), prefix.size() * sizeof(int));
+      plan.groups.push_back(G);
+    }
+  }
+  if (!gj.empty()) {
+    std::vector<int> prefix(1, 0);
+    for (auto& j : gj) prefix.push_back(prefix.back() + j.N * ((j.M + 255) / 256));
+    plan.off_gjobs = put(gj.data(), gj.size() * sizeof(GammaJob));
+    plan.off_gprefix = put(prefix.data(), prefix.size() * sizeof(int));
+    plan.g_np = (int)gj.size();
+    plan.g_total = prefix.back();
+  }
+  plan.buf.alloc(std::max<size_t>(host.size(), 16));
+  hip_check(hipMemcpy(plan.buf.p, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+void run_grouped_iteration(BatchPlan& plan, int* step, float* consts, const gcp_opt* opt, AdamArgs adam,
+                           hipStream_t st) {
+  unsigned char* b = (unsigned char*)plan.buf.p;
+  hip_check(launch_adam_prepare(step, 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, consts,
+                                st),
+            "adam prepare");
+  for (const Group& G : plan.groups) {
+    if (G.type == 0)
+      hip_check(timed(st, cls_name("grouped", G.bf16, G.sign, G.cfg), 0.0, 0.0, [&] {
+                  return launch_gemm_grouped(G.bf16, G.cfg, (EpiKind)G.kind, G.sign,
+                                             (const GemmArgs*)(b + G.off_args), b + G.off_epi,
+                                             (const int*)(b + G.off_prefix), G.np, G.total, st);
+                }),
+                "grouped gemm");
+    else
+      hip_check(launch_bound_elementwise_grouped(G.bf16, (const ElemBoundJob*)(b + G.off_args),
+                                                 (const int*)(b + G.off_prefix), G.np, G.total, st),
+                "grouped elementwise");
+  }
+  if (plan.g_np)
+    hip_check(launch_gamma_grouped((const GammaJob*)(b + plan.off_gjobs), (const int*)(b + plan.off_gprefix),
+                                   plan.g_np, plan.g_total, adam, st),
+              "grouped gamma");
+}
+
+}  // namespace
+
+extern "C" int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode,
+                                  void* stream) {
+  GCP_TRY
+  if (n <= 0 || !items) fail(GCP_EINVAL, "empty batch");
+  if (!opt || opt->iters < 0) fail(GCP_EINVAL, "bad optimiser settings");
+  const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
+  if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<Call> calls(n);
+  for (int i = 0; i < n; ++i) {
+    const gcp_batch_item& it = items[i];
+    for (int k = 0; k < i; ++k)
+      if (items[k].net == it.net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
+    if (!it.adam_state || !it.bound) fail(GCP_EINVAL, "null adam_state or bound");
+    prepare_call(calls[i], const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
+                 it.beta, it.gamma, stream);
+    if (mode & GCP_FLAG_VALIDATE) validate_params(calls[i], it.alpha, it.beta, it.gamma);
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  // shared Adam counter and constants: the first instance's workspace
+  auto& ws0 = calls[0].net->ws;
+  AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws0.consts.as<float>()};
+  struct Moments { float *ma, *va, *mb, *vb, *mg, *vg; };
+  std::vector<Moments> mom(n);
+  std::vector<uintptr_t> key = {(uintptr_t)n, (uintptr_t)bf16};
+  for (int i = 0; i < n; ++i) {
+    Call& c = calls[i];
+    const gcp_batch_item& it = items[i];
+    const size_t M = c.M, nI = c.rp.n_I, K = c.rp.K, N = c.rp.N;
+    Moments& m = mom[i];
+    m.ma = it.adam_state; m.va = m.ma + M * nI; m.mb = m.va + M * nI; m.vb = m.mb + M * K;
+    m.mg = m.vb + M * K; m.vg = m.mg + M * N;
+    if (N > 0) hip_check(launch_transpose(it.gamma, c.M, (int)N, (int)N, c.net->ws.gammaT.as<float>(), c.rp.mp, st),
+                         "transpose");
+    size_partials(c, bf16, true, c.nnz > 0);
+    launch_constants(c);
+    AdjPass prep{c, bf16, adam, nullptr, nullptr, it.alpha, it.beta, m.ma, m.va, m.mb, m.vb};
+    prep.prepare();
+    for (uintptr_t v : {(uintptr_t)it.net, (uintptr_t)it.x0, (uintptr_t)it.C, (uintptr_t)it.S,
+                        (uintptr_t)it.splits, (uintptr_t)it.cuts, (uintptr_t)it.alpha, (uintptr_t)it.beta,
+                        (uintptr_t)it.gamma, (uintptr_t)it.adam_state, (uintptr_t)std::hash<double>()(it.eps),
+                        (uintptr_t)c.net->ws.gen})
+      key.push_back(v);
+  }
+  hip_check(launch_adam_prepare(ws0.step.as<int>(), 1, 0, 0, 0, 0, 0, nullptr, st), "adam reset");
+  auto eager_iteration = [&]() {
+    hip_check(launch_adam_prepare(ws0.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
+                                  opt->adam_b2, ws0.consts.as<float>(), st),
+              "adam prepare");
+    for (int i = 0; i < n; ++i) {
+      Call& c = calls[i];
+      BoundPass bp(c, bf16, true, c.nnz > 0, false);
+      bp.run();
+      AdjPass ap{c, bf16, adam, nullptr, nullptr, items[i].alpha, items[i].beta, mom[i].ma, mom[i].va, mom[i].mb,
+                 mom[i].vb};
+      ap.run();
+      if (c.rp.N > 0)
+        hip_check(launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(),
+                                      c.net->ws.contrib.as<float>(), c.cuts->d.as<double>(),
+                                      c.net->ws.gammaT.as<float>(), nullptr, mom[i].mg, mom[i].vg, adam, st),
+                  "gamma update");
+    }
+  };
+  int done = 0;
+  const bool cached = g_batch && g_batch->key == key;
+  if (!cached && opt->iters > 0) {
+    eager_iteration();      // tunes tiles and sizes buffers of every instance
+    done = 1;
+    auto plan = std::make_unique<BatchPlan>();
+    plan->key = key;
+    std::vector<Recorder> recs(n);
+    std::vector<GammaJob> gj;
+    for (int i = 0; i < n; ++i) {
+      Call c = calls[i];
+      c.rec = &recs[i];
+      BoundPass bp(c, bf16, true, c.nnz > 0, false);
+      bp.run();
+      recs[i].in_adj = true;
+      AdjPass ap{c, bf16, adam, nullptr, nullptr, items[i].alpha, items[i].beta, mom[i].ma, mom[i].va, mom[i].mb,
+                 mom[i].vb};
+      ap.run();
+      if (c.rp.N > 0)
+        gj.push_back(GammaJob{c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), c.net->ws.contrib.as<float>(),
+                              c.cuts->d.as<double>(), c.net->ws.gammaT.as<float>(), mom[i].mg, mom[i].vg});
+    }
+    build_plan(*plan, recs, gj);
+    delete g_batch;
+    g_batch = plan.release();
+  }
+  BatchPlan& plan = *g_batch;
+  if (opt->use_graph && opt->iters - done > 1) {
+    if (!plan.gstream) hip_check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "hipStreamCreate");
+    hipEvent_t ev;
+    hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventRecord(ev, st), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(plan.gstream, ev, 0), "hipStreamWaitEvent");
+    if (!plan.gexec) {
+      hipGraph_t graph;
+      hip_check(hipStreamBeginCapture(plan.gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        run_grouped_iteration(plan, ws0.step.as<int>(), ws0.consts.as<float>(), opt, adam, plan.gstream);
+      } catch (...) {
+        hipGraph_t g2;
+        (void)hipStreamEndCapture(plan.gstream, &g2);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(plan.gstream, &graph), "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&plan.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      hip_check(ie, "hipGraphInstantiate");
+    }
+    for (; done < opt->iters; ++done) hip_check(hipGraphLaunch(plan.gexec, plan.gstream), "hipGraphLaunch");
+    hip_check(hipEventRecord(ev, plan.gstream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(st, ev, 0), "hipStreamWaitEvent");
+    (void)hipEventDestroy(ev);
+  }
+  for (; done < opt->iters; ++done)
+    run_grouped_iteration(plan, ws0.step.as<int>(), ws0.consts.as<float>(), opt, adam, st);
+  // certifying pass per instance, then gamma back to the caller's layout
+  for (int i = 0; i < n; ++i) {
+    Call& c = calls[i];
+    bound_pass(c, 0, false, false, items[i].bound, items[i].verified);
+    if (c.rp.N > 0)
+      hip_check(launch_transpose(c.net->ws.gammaT.as<float>(), c.rp.N, c.M, c.rp.mp, items[i].gamma, c.rp.N, st),
+                "transpose");
+  }
+  g_err.clear();
   return GCP_OK;
   GCP_CATCH
 }

@@ -106,11 +106,32 @@ hipError_t launch_gemm(int bf16, int cfg, EpiKind kind, const GemmArgs& g, const
                        hipStream_t st);
 int gemm_num_configs();
 void gemm_config_tile(int cfg, int* bm, int* bn);
+// Several GEMM problems of one instantiation (cfg, kind, sign, precision) in
+// one launch: device tables d_gs[np], d_epis[np] (the kind's *EpiArgs) and
+// d_prefix[np + 1] of cumulative tile counts (total_tiles = d_prefix[np]).
+hipError_t launch_gemm_grouped(int bf16, int cfg, EpiKind kind, int sign, const GemmArgs* d_gs, const void* d_epis,
+                               const int* d_prefix, int np, int total_tiles, hipStream_t st);
 
 // Elementwise epilogues (no GEMM): the pre-activation comes from a per-spec
 // broadcast [S][ld] (fp32) plus the optional acc_in of the epilogue args.
 hipError_t launch_bound_elementwise(int bf16, const float* bcast, const void* src, const BoundEpiArgs& a,
                                     double* partial, int slot0, hipStream_t st);
+// Grouped elementwise relaxation: job p has M rows x ceil(size/256) blocks.
+struct ElemBoundJob {
+  const float* bcast; const void* src;
+  BoundEpiArgs a;
+  double* partial; int slot0;
+};
+hipError_t launch_bound_elementwise_grouped(int bf16, const ElemBoundJob* d_jobs, const int* d_prefix, int np,
+                                            int total_blocks, hipStream_t st);
+// Grouped gamma Adam update: job p has N x ceil(M/256) blocks.
+struct GammaJob {
+  int M, mp, N;
+  const int32_t* row_ptr; const float* contrib; const double* d;
+  float* gammaT; float* m; float* v;
+};
+hipError_t launch_gamma_grouped(const GammaJob* d_jobs, const int* d_prefix, int np, int total_blocks, AdamArgs adam,
+                                hipStream_t st);
 // Identity edge: out = (acc_in ? acc_in : 0) + scale * src (src operand type or int8 sign)
 hipError_t launch_identity_acc(int bf16, int M, int size, const void* src, int ld_src, int is_sign, float scale,
                                const float* acc_in, float* out, int ld_out, hipStream_t st);

@@ -19,9 +19,33 @@ namespace gcp {
 // C[M][N] = A[M][K] * Bt[N][K]^T on MFMA, epilogue per element, row partial
 // sums reduced deterministically (lanes, then waves through LDS) into
 // partial[r][slot0 + blockIdx.x].
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs by linear id, so the ids an XCD receives map onto a contiguous run of
+// tiles (row panel major) and all column tiles of a row panel share that
+// XCD's L2 instead of fetching the A panel once per XCD.
+__device__ inline int xcd_tile(int id, int total) {
+  const int xcd = id % 8, kx = id / 8;
+  const int per = total / 8, rem = total % 8;
+  return xcd * per + (xcd < rem ? xcd : rem) + kx;
+}
+
+// Keep the first `keep` elements of a 16-byte operand vector, zero the rest:
+// columns >= K of a row are padding whose bytes may hold data of the other
+// operand precision (buffers are shared by the bf16 and fp32 passes), so the
+// K tail is masked explicitly instead of relying on zero padding.
+template <typename T>
+__device__ inline uint4 mask_tail(uint4 v, int keep) {
+  T e[16 / sizeof(T)];
+  *(uint4*)e = v;
+#pragma unroll
+  for (int q = 0; q < (int)(16 / sizeof(T)); ++q)
+    if (q >= keep) e[q] = to_t<T>(0.f);
+  return *(const uint4*)e;
+}
+
+// One output tile (linear index vt, row panel major) of one GEMM problem.
 template <typename T, int BM, int BN, int WM, int WN, int BK, bool SIGN, class Epi>
-__global__ void __launch_bounds__(WM * WN * 64)
-gemm_epi_kernel(GemmArgs g, Epi epi) {
+__device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
   constexpr int NT = WM * WN * 64;
   constexpr int VEC = Op<T>::VEC;
   constexpr int KC = Op<T>::KC;
@@ -42,15 +66,7 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
-  // XCDs by linear id, so map the ids an XCD receives onto a contiguous run
-  // of tiles (row panel major) and all column tiles of a row panel share
-  // that XCD's L2 instead of fetching the A panel once per XCD.
   const int n_col = (g.N + BN - 1) / BN;
-  const int total = n_col * ((g.M + BM - 1) / BM);
-  const int xcd = blockIdx.x % 8, kx = blockIdx.x / 8;
-  const int per = total / 8, rem = total % 8;
-  const int vt = xcd * per + (xcd < rem ? xcd : rem) + kx;
   const int bx = vt % n_col, by = vt / n_col;
   const int m0 = by * BM, n0 = bx * BN;
 
@@ -79,6 +95,7 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
           } else {
             val = *(const uint4*)((const T*)g.A + (size_t)gr * g.lda + gk);
           }
+          if (gk + VEC > g.K) val = mask_tail<T>(val, g.K - gk);
         }
       }
       ra[it] = val;
@@ -90,7 +107,10 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
       if (v < BV) {
         int row = v / (BK / VEC), kk = (v % (BK / VEC)) * VEC;
         int gn = n0 + row, gk = k0 + kk;
-        if (gn < g.N && gk < g.ldb) val = *(const uint4*)((const T*)g.Bt + (size_t)gn * g.ldb + gk);
+        if (gn < g.N && gk < g.ldb) {
+          val = *(const uint4*)((const T*)g.Bt + (size_t)gn * g.ldb + gk);
+          if (gk + VEC > g.K) val = mask_tail<T>(val, g.K - gk);
+        }
       }
       rb[it] = val;
     }
@@ -194,6 +214,29 @@ gemm_epi_kernel(GemmArgs g, Epi epi) {
   }
 }
 
+template <typename T, int BM, int BN, int WM, int WN, int BK, bool SIGN, class Epi>
+__global__ void __launch_bounds__(WM * WN * 64) gemm_epi_kernel(GemmArgs g, Epi epi) {
+  const int total = ((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+  gemm_tile<T, BM, BN, WM, WN, BK, SIGN, Epi>(g, epi, xcd_tile(blockIdx.x, total));
+}
+
+// Several independent GEMM problems of one kernel instantiation in one
+// launch: tiles of problem p occupy [prefix[p], prefix[p+1]) of the linear
+// tile space; each workgroup finds its problem by binary search.
+template <typename T, int BM, int BN, int WM, int WN, int BK, bool SIGN, class Epi>
+__global__ void __launch_bounds__(WM * WN * 64)
+gemm_epi_grouped(const GemmArgs* __restrict__ gs, const Epi* __restrict__ es, const int* __restrict__ prefix, int np) {
+  const int t = xcd_tile(blockIdx.x, prefix[np]);
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const GemmArgs g = gs[lo];
+  const Epi e = es[lo];
+  gemm_tile<T, BM, BN, WM, WN, BK, SIGN, Epi>(g, e, t - prefix[lo]);
+}
+
 // Tile configurations available to the autotuner: (BM, BN, WM, WN).
 struct TileCfg { int bm, bn; };
 static const TileCfg kCfgs[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {32, 32}, {16, 64}, {16, 32}};
@@ -201,41 +244,59 @@ static_assert(sizeof(kCfgs) / sizeof(kCfgs[0]) == 8, "tile table");
 int gemm_num_configs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 void gemm_config_tile(int cfg, int* bm, int* bn) { *bm = kCfgs[cfg].bm; *bn = kCfgs[cfg].bn; }
 
-template <typename T, int BM, int BN, int WM, int WN, bool SIGN, class Epi>
-static hipError_t launch_cfg(const GemmArgs& g, const Epi& epi, hipStream_t st) {
+// Launch target: a single problem (GemmArgs by value) or a group (device
+// tables of arguments and tile prefix sums).
+struct GemmLaunch {
+  const GemmArgs* g;          // single: host pointer to the arguments
+  const void* epi;            // single: host pointer to the epilogue arguments
+  const GemmArgs* d_gs;       // grouped: device tables
+  const void* d_es;
+  const int* d_prefix;
+  int np, total_tiles;
+};
+
+template <typename T, int BM, int BN, int WM, int WN, bool SIGN, class Epi, class Args>
+static hipError_t launch_cfg(const GemmLaunch& L, hipStream_t st) {
   constexpr int BK = (sizeof(T) == 4) ? 64 : 128;
+  if (L.d_gs) {
+    if (L.total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_epi_grouped<T, BM, BN, WM, WN, BK, SIGN, Epi>), dim3((unsigned)L.total_tiles),
+                       dim3(WM * WN * 64), 0, st, L.d_gs, (const Epi*)L.d_es, L.d_prefix, L.np);
+    return hipGetLastError();
+  }
+  const GemmArgs& g = *L.g;
   const long tiles = (long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
   hipLaunchKernelGGL((gemm_epi_kernel<T, BM, BN, WM, WN, BK, SIGN, Epi>), dim3((unsigned)tiles),
-                     dim3(WM * WN * 64), 0, st, g, epi);
+                     dim3(WM * WN * 64), 0, st, g, Epi{*(const Args*)L.epi});
   return hipGetLastError();
 }
 
-template <typename T, bool SIGN, class Epi>
-static hipError_t launch_any(int cfg, const GemmArgs& g, const Epi& epi, hipStream_t st) {
+template <typename T, bool SIGN, class Epi, class Args>
+static hipError_t launch_any(int cfg, const GemmLaunch& L, hipStream_t st) {
   switch (cfg) {
-    case 0: return launch_cfg<T, 64, 64, 2, 2, SIGN>(g, epi, st);
-    case 1: return launch_cfg<T, 128, 64, 2, 2, SIGN>(g, epi, st);
-    case 2: return launch_cfg<T, 64, 128, 2, 2, SIGN>(g, epi, st);
-    case 3: return launch_cfg<T, 128, 128, 2, 2, SIGN>(g, epi, st);
-    case 4: return launch_cfg<T, 32, 64, 2, 2, SIGN>(g, epi, st);
-    case 5: return launch_cfg<T, 32, 32, 2, 2, SIGN>(g, epi, st);
-    case 6: return launch_cfg<T, 16, 64, 1, 4, SIGN>(g, epi, st);
-    case 7: return launch_cfg<T, 16, 32, 1, 2, SIGN>(g, epi, st);
+    case 0: return launch_cfg<T, 64, 64, 2, 2, SIGN, Epi, Args>(L, st);
+    case 1: return launch_cfg<T, 128, 64, 2, 2, SIGN, Epi, Args>(L, st);
+    case 2: return launch_cfg<T, 64, 128, 2, 2, SIGN, Epi, Args>(L, st);
+    case 3: return launch_cfg<T, 128, 128, 2, 2, SIGN, Epi, Args>(L, st);
+    case 4: return launch_cfg<T, 32, 64, 2, 2, SIGN, Epi, Args>(L, st);
+    case 5: return launch_cfg<T, 32, 32, 2, 2, SIGN, Epi, Args>(L, st);
+    case 6: return launch_cfg<T, 16, 64, 1, 4, SIGN, Epi, Args>(L, st);
+    case 7: return launch_cfg<T, 16, 32, 1, 2, SIGN, Epi, Args>(L, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
-static hipError_t launch_typed(int cfg, EpiKind kind, const GemmArgs& g, const void* epi, hipStream_t st) {
+static hipError_t launch_typed(int cfg, EpiKind kind, int sign, const GemmLaunch& L, hipStream_t st) {
   switch (kind) {
-    case EPI_BOUND: return launch_any<T, false>(cfg, g, BoundEpi<T>{*(const BoundEpiArgs*)epi}, st);
-    case EPI_CONC: return launch_any<T, false>(cfg, g, ConcEpi{*(const ConcEpiArgs*)epi}, st);
+    case EPI_BOUND: return launch_any<T, false, BoundEpi<T>, BoundEpiArgs>(cfg, L, st);
+    case EPI_CONC: return launch_any<T, false, ConcEpi, ConcEpiArgs>(cfg, L, st);
     case EPI_STORE:
-      if (g.a_is_sign) return launch_any<T, true>(cfg, g, StoreEpi{*(const StoreEpiArgs*)epi}, st);
-      return launch_any<T, false>(cfg, g, StoreEpi{*(const StoreEpiArgs*)epi}, st);
+      if (sign) return launch_any<T, true, StoreEpi, StoreEpiArgs>(cfg, L, st);
+      return launch_any<T, false, StoreEpi, StoreEpiArgs>(cfg, L, st);
     case EPI_ADJ:
-      if (g.a_is_sign) return launch_any<T, true>(cfg, g, AdjEpi<T>{*(const AdjEpiArgs*)epi}, st);
-      return launch_any<T, false>(cfg, g, AdjEpi<T>{*(const AdjEpiArgs*)epi}, st);
+      if (sign) return launch_any<T, true, AdjEpi<T>, AdjEpiArgs>(cfg, L, st);
+      return launch_any<T, false, AdjEpi<T>, AdjEpiArgs>(cfg, L, st);
   }
   return hipErrorInvalidValue;
 }
@@ -243,7 +304,15 @@ static hipError_t launch_typed(int cfg, EpiKind kind, const GemmArgs& g, const v
 hipError_t launch_gemm(int bf16_mode, int cfg, EpiKind kind, const GemmArgs& g, const void* epi,
                        hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  return bf16_mode ? launch_typed<bf16>(cfg, kind, g, epi, st) : launch_typed<float>(cfg, kind, g, epi, st);
+  GemmLaunch L{&g, epi, nullptr, nullptr, nullptr, 0, 0};
+  return bf16_mode ? launch_typed<bf16>(cfg, kind, g.a_is_sign, L, st)
+                   : launch_typed<float>(cfg, kind, g.a_is_sign, L, st);
+}
+
+hipError_t launch_gemm_grouped(int bf16_mode, int cfg, EpiKind kind, int sign, const GemmArgs* d_gs,
+                               const void* d_epis, const int* d_prefix, int np, int total_tiles, hipStream_t st) {
+  GemmLaunch L{nullptr, nullptr, d_gs, d_epis, d_prefix, np, total_tiles};
+  return bf16_mode ? launch_typed<bf16>(cfg, kind, sign, L, st) : launch_typed<float>(cfg, kind, sign, L, st);
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -283,6 +352,56 @@ hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const voi
     hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   else
     hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
+  return hipGetLastError();
+}
+
+// Grouped elementwise relaxation: block b of job p covers row (b / nb) and
+// columns 256 * (b % nb) .. of that job, nb = ceil(size / 256).
+template <typename T>
+__global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __restrict__ jobs,
+                                                          const int* __restrict__ prefix, int np) {
+  __shared__ double red[4];
+  const int t = blockIdx.x;
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const ElemBoundJob& jb = jobs[lo];
+  const BoundEpiArgs a = jb.a;
+  const int nb = (a.nd.size + 255) / 256;
+  const int b = t - prefix[lo];
+  const int r = b / nb, cb = b % nb;
+  const int j = cb * 256 + threadIdx.x;
+  BoundEpi<T> epi{a};
+  LaneCoords<1, 1, false> lc;
+  lc.r[0] = r;
+  lc.j[0][0] = j;
+  float pre = 0.f;
+  if (j < a.nd.size) {
+    if (jb.bcast) pre += jb.bcast[(size_t)(r % a.rp.S) * a.nd.ld + j];
+    if (jb.src) pre += from_t<T>(((const T*)jb.src)[(size_t)r * a.nd.ld + j]);
+  }
+  float val[1][1] = {{pre}};
+  double rs[1] = {0.0};
+  typename BoundEpi<T>::template Frag<1, 1, false> fr;
+  epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
+  epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
+  double tt = rs[0];
+  for (int o = 32; o > 0; o >>= 1) tt += __shfl_xor(tt, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tt;
+  __syncthreads();
+  if (threadIdx.x == 0 && jb.partial)
+    jb.partial[(size_t)(jb.slot0 + cb) * a.rp.mp + r] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_bound_elementwise_grouped(int bf16_mode, const ElemBoundJob* d_jobs, const int* d_prefix, int np,
+                                            int total_blocks, hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  if (bf16_mode)
+    hipLaunchKernelGGL(bound_elem_grouped<bf16>, dim3(total_blocks), dim3(256), 0, st, d_jobs, d_prefix, np);
+  else
+    hipLaunchKernelGGL(bound_elem_grouped<float>, dim3(total_blocks), dim3(256), 0, st, d_jobs, d_prefix, np);
   return hipGetLastError();
 }
 
@@ -455,6 +574,42 @@ __global__ void __launch_bounds__(256) gamma_kernel(int M, int mp, int N, const 
   } else {
     d_gamma[(size_t)r * N + k] = (float)g;
   }
+}
+
+// Grouped gamma update: block b of job p covers rows 256 * (b % nr) .. of cut
+// b / nr, nr = ceil(M / 256); same arithmetic as gamma_kernel.
+__global__ void __launch_bounds__(256) gamma_grouped(const GammaJob* __restrict__ jobs, const int* __restrict__ prefix,
+                                                     int np, AdamArgs adam) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const GammaJob jb = jobs[lo];
+  const int nr = (jb.M + 255) / 256;
+  const int b = t - prefix[lo];
+  const int k = b / nr;
+  const int r = (b % nr) * 256 + threadIdx.x;
+  if (r >= jb.M) return;
+  double g = -jb.d[k];
+  for (int e = jb.row_ptr[k]; e < jb.row_ptr[k + 1]; ++e) g += (double)jb.contrib[(size_t)e * jb.mp + r];
+  const float lr = adam.consts[1], bc1 = adam.consts[2], bc2 = adam.consts[3];
+  const float gf = (float)g;
+  const size_t im = (size_t)k * jb.M + r;
+  const float mm = adam.b1 * jb.m[im] + (1.f - adam.b1) * gf;
+  const float vv = adam.b2 * jb.v[im] + (1.f - adam.b2) * gf * gf;
+  jb.m[im] = mm;
+  jb.v[im] = vv;
+  float* gp = jb.gammaT + (size_t)k * jb.mp + r;
+  *gp = fmaxf(*gp + lr * (mm / bc1) / (sqrtf(vv / bc2) + adam.eps), 0.f);
+}
+
+hipError_t launch_gamma_grouped(const GammaJob* d_jobs, const int* d_prefix, int np, int total_blocks, AdamArgs adam,
+                                hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_grouped, dim3(total_blocks), dim3(256), 0, st, d_jobs, d_prefix, np, adam);
+  return hipGetLastError();
 }
 
 hipError_t launch_gamma_update(int M, int mp, int N, const int32_t* row_ptr, const float* contrib, const double* d,
