@@ -1,14 +1,18 @@
 """Benchmark: GCP-CROWN domains bounded per second on one MI355X.
 
-Workload (MLP 784-256x6-10, weights N(0, 2/fan_in), x0 ~ U[0,1]^784,
-eps = 0.015, 9 margin spec rows, 1024 BaB domains with 1-8 splits each,
-200 LP-implied cuts over 2-6 neurons of >= 2 layers).  One step bounds one
-batch: it resets alpha/beta/gamma and the Adam state to their starting
-values, runs 20 projected Adam iterations (bound pass + adjoint + update,
-all on the device) and the certifying pass (fp32 GEMMs, fp64 reductions,
-margin check).  value = domains per second over the timed steps.
+Default workload (--config 2): MLP 784-256x6-10, weights N(0, 2/fan_in),
+x0 ~ U[0,1]^784, eps = 0.015, 9 margin spec rows, 1024 BaB domains with 1-8
+splits each, 200 LP-implied cuts over 2-6 neurons of >= 2 layers.  One step
+bounds one batch: it resets alpha/beta/gamma and the Adam state to their
+starting values, runs 20 projected Adam iterations (bound pass + adjoint +
+update, all on the device) and the certifying pass (fp32 GEMMs, fp64
+reductions, margin check).  value = domains per second over the timed steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode bf16|fp32]
+Other workloads: --config 3 (CNN-A shape, 2048 domains, 500 cuts),
+--config 5 (ResNet, 4096 domains, 1000 cuts), --config 4 (64 uneven MLP
+instances in grouped launches, compared with one gcp_optimize per instance).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode bf16|fp32] [--config 2|3|4|5]
 """
 import argparse
 import json
@@ -33,15 +37,31 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["bf16", "fp32"], default="bf16")
-    ap.add_argument("--domains", type=int, default=1024)
+    ap.add_argument("--domains", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp32-mode comparison run")
-    ap.add_argument("--cpu-domains", type=int, default=1024)
+    ap.add_argument("--cpu-domains", type=int, default=None)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
-    return ap.parse_args()
+    ap.add_argument("--config", type=int, choices=[2, 3, 4, 5], default=2)
+    a = ap.parse_args()
+    if a.domains is None:
+        a.domains = {2: 1024, 3: 2048, 5: 4096, 4: 0}[a.config]
+    if a.cpu_domains is None:
+        a.cpu_domains = {2: 1024, 3: 16, 5: 1, 4: 0}[a.config]
+    return a
+
+
+WORKLOADS = {
+    2: "GCP-CROWN bound optimisation, MLP 784-256x6-10, {B} BaB domains x 9 spec rows, 200 cuts, "
+       "1-8 splits/domain, 20 Adam iterations + fp32/fp64 certifying pass",
+    3: "GCP-CROWN bound optimisation, CNN Conv(3,16,4,s2)-Conv(16,32,4,s2)-2048-100-10 on 3x32x32, {B} BaB "
+       "domains x 9 spec rows, 500 cuts, 1-8 splits/domain, 20 Adam iterations + certifying pass",
+    5: "GCP-CROWN bound optimisation, ResNet stem16-blocks16/32/64-linear10 on 3x32x32, {B} BaB domains x 9 "
+       "spec rows, 1000 cuts, 1-8 splits/domain, 20 Adam iterations + certifying pass",
+}
 
 
 def main():
@@ -58,7 +78,9 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
-    prob = gen.make_config(2, 0, B=args.domains)
+    if args.config == 4:
+        return bench_batch(args)
+    prob = gen.make_config(args.config, 0, B=args.domains)
     P = B.Problem(prob, device=dev)
     M = P.M
     # starting point: CROWN-adaptive alpha, beta ~ U[0,1] on used split slots, gamma = 0
@@ -128,8 +150,7 @@ def main():
         "dtype": args.mode,
         "data": "synthetic",
         "config": {
-            "workload": "GCP-CROWN bound optimisation, MLP 784-256x6-10, 1024 BaB domains x 9 spec rows, "
-                        "200 cuts, 1-8 splits/domain, 20 Adam iterations + fp32/fp64 certifying pass",
+            "workload": WORKLOADS[args.config].format(B=args.domains),
             "domains": args.domains, "spec_rows": prob.S, "rows": M, "n_unstable": P.n_I,
             "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
@@ -152,7 +173,7 @@ def main():
             "final_bound_rel_diff_median": float(np.median(rel)),
         }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_domains)
+        out["cpu_baseline"] = cpu_baseline([prob], args.cpu_domains)
     print(json.dumps(out))
 
 
@@ -198,20 +219,136 @@ def measured_traffic(kernel):
     return k["fetch_kib"] * 1024 * rec["fetch_scale"] + k["write_kib"] * 1024 * rec["write_scale"]
 
 
-def cpu_baseline(prob, nd):
-    """The FP64 oracle (as it stands) on the first `nd` domains of the same
-    workload, 20 Adam iterations + final bound, on the host cores."""
+def oracle_start(prob, rows):
+    """Starting parameters of the bench for a row subset, in float64: the
+    CROWN-adaptive alpha, the problem's beta and gamma."""
+    import numpy as np
+
+    from workloads import gen
+    a = np.broadcast_to(gen.crown_alpha_init(prob.lu), (rows.size, len(gen.crown_alpha_init(prob.lu)))).copy()
+    b = prob.beta.reshape(prob.B * prob.S, -1)[rows].astype(np.float64)
+    c = prob.gamma.reshape(prob.B * prob.S, -1)[rows].astype(np.float64)
+    return a, b, c
+
+
+def cpu_baseline(probs, nd):
+    """The FP64 oracle (as it stands) on the first `nd` domains of each given
+    problem, the same 20-iteration optimisation + final bound, host cores."""
     import numpy as np
     import torch
 
     from oracle import gcp_oracle as O
-    rows = np.arange(nd * prob.S)
     t0 = time.perf_counter()
-    O.optimize(prob, rows=rows)
+    total = 0
+    for prob in probs:
+        k = min(nd, prob.B)
+        rows = np.arange(k * prob.S)
+        a, b, c = oracle_start(prob, rows)
+        O.optimize(prob, alpha=a, beta=b, gamma=c, rows=rows, flat=True)
+        total += k
     dt = time.perf_counter() - t0
-    return {"value": nd / dt, "unit": "domains/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"first {nd} of {prob.B} domains ({nd * prob.S} rows), same 20-iteration optimisation "
+    what = probs[0].name if len(probs) == 1 else f"{len(probs)} instances"
+    return {"value": total / dt, "unit": "domains/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"first {nd} domains of {what} ({total} domains), same 20-iteration optimisation "
                       f"+ final bound in float64, {dt:.1f} s"}
+
+
+def bench_batch(args):
+    """Config 4: 64 uneven MLP instances.  value = domains/s of the grouped
+    batch (gcp_optimize_batch); the same steps with one gcp_optimize call per
+    instance are timed beside it, and their final bounds must be identical."""
+    import numpy as np
+    import torch
+
+    from paper_2208_05740_amd import binding as B
+    from workloads import gen
+    dev = torch.device("cuda:0")
+    probs = gen.make_batch_config(seed=0)
+    Ps = [B.Problem(p, device=dev) for p in probs]
+    o = probs[0].opt
+    mode = B.GCP_MODE_BF16 if args.mode == "bf16" else B.GCP_MODE_FP32
+    items = []
+    for p, P in zip(probs, Ps):
+        a0 = torch.tensor(gen.crown_alpha_init(p.lu), dtype=torch.float32, device=dev).expand(P.M, -1).contiguous()
+        b0 = torch.tensor(p.beta.reshape(P.M, -1), dtype=torch.float32, device=dev)
+        items.append(dict(P=P, a0=a0, b0=b0, alpha=a0.clone(), beta=b0.clone(),
+                          gamma=torch.zeros(P.M, P.N, dtype=torch.float32, device=dev),
+                          state=torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=dev),
+                          bound=torch.empty(P.M, dtype=torch.float64, device=dev),
+                          verified=torch.empty(P.M, dtype=torch.uint8, device=dev)))
+
+    def reset():
+        for it in items:
+            it["alpha"].copy_(it["a0"])
+            it["beta"].copy_(it["b0"])
+            it["gamma"].zero_()
+            it["state"].zero_()
+
+    use_graph = [args.graph]
+
+    def step_batched():
+        reset()
+        B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                         b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode,
+                         use_graph=use_graph[0])
+
+    def step_single():
+        reset()
+        for it in items:
+            P = it["P"]
+            B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, it["alpha"], it["beta"], it["gamma"], it["state"],
+                       iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                       b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode,
+                       bound_out=it["bound"], verified_out=it["verified"])
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = timed(step_batched, args.steps, args.warmup)
+    bounds_b = [it["bound"].cpu().numpy().copy() for it in items]
+    kprof = None
+    if not args.no_profile:
+        B.profile_enable(True)
+        use_graph[0] = False
+        dt_prof = timed(step_batched, args.steps, 0)
+        use_graph[0] = args.graph
+        B.profile_enable(False)
+        kprof = B.profile_read()
+    dts = timed(step_single, args.steps, 1)
+    bounds_s = [it["bound"].cpu().numpy().copy() for it in items]
+    same = all(np.array_equal(x, y) for x, y in zip(bounds_b, bounds_s))
+    dom = sum(p.B for p in probs)
+    value = dom * args.steps / dt
+    out = {
+        "metric": "BaB domains bounded/sec (fwd+adjoint iter) at fixed bound accuracy; % MFMA/HBM peak",
+        "value": value, "unit": "domains/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1000.0 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
+        "config": {
+            "workload": f"GCP-CROWN batch: {len(probs)} MLP instances (depth 3-9, width 64-1024, input 784/3072, "
+                        f"16-4096 domains log-uniform, 50-1000 cuts, 9 spec rows), grouped launches, 20 Adam "
+                        f"iterations + certifying pass",
+            "instances": len(probs), "domains": dom, "rows": sum(P.M for P in Ps), "graph_replay": args.graph,
+            "per_instance_launches": {"value": dom * args.steps / dts, "ms_per_step": dts * 1000.0 / args.steps},
+            "speedup_vs_per_instance": dts / dt,
+            "final_bounds_identical": bool(same),
+        },
+    }
+    if kprof:
+        out["roofline"] = roofline(kprof, args.mode)
+        out["roofline"]["instrumented_ms_per_step"] = dt_prof * 1000.0 / args.steps
+        out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
+                                    for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs[:8], 2)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -308,19 +308,20 @@ def adam_step(x, grad, m, v, t, lr, b1, b2, eps, lo, hi):
 
 
 def optimize(prob, iters=None, alpha=None, beta=None, gamma=None, rows=None, opt=None, prep=None,
-             history=False):
+             history=False, flat=False):
     """Gradient ascent on alpha (lr 0.1), beta and gamma (lr 0.02) with Adam,
     learning rates decayed by 0.9 per iteration (Appendix C.1), projecting
     alpha into [0, 1] and the multipliers onto >= 0 after every step; the
     objective is the sum of the rows' bounds (rows are independent).
     Returns (bound at the final parameters [M], alpha, beta, gamma) as flat
-    [M, .] arrays over ``rows`` (all rows when None)."""
+    [M, .] arrays over ``rows`` (all rows when None).  With ``flat`` the
+    starting parameters are given already restricted to ``rows``."""
     prep = prep or Prepared(prob)
     o = dict(prob.opt)
     o.update(opt or {})
     iters = o["iters"] if iters is None else iters
     rows = np.arange(prob.B * prob.S) if rows is None else np.asarray(rows)
-    a, b, c = (x.numpy().copy() for x in _params(prob, alpha, beta, gamma, rows, prep))
+    a, b, c = (x.numpy().copy() for x in _params(prob, alpha, beta, gamma, rows, prep, flat))
     ma, va = np.zeros_like(a), np.zeros_like(a)
     mb, vb = np.zeros_like(b), np.zeros_like(b)
     mc, vc = np.zeros_like(c), np.zeros_like(c)

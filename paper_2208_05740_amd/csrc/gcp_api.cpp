@@ -710,6 +710,7 @@ struct Rec {
   alignas(16) unsigned char epi[sizeof(AdjEpiArgs) > sizeof(BoundEpiArgs) ? sizeof(AdjEpiArgs) : sizeof(BoundEpiArgs)];
   ElemBoundJob ej;
   int tiles;           // workgroups of this problem
+  double bytes, flops; // algorithmic HBM bytes and FLOPs of this launch
 };
 static_assert(sizeof(ConcEpiArgs) <= sizeof(Rec::epi) && sizeof(StoreEpiArgs) <= sizeof(Rec::epi), "epi blob");
 struct Recorder {
@@ -812,11 +813,13 @@ float* tune_beta(Call& c) {
 
 // In recording mode a GEMM launch is stored instead of issued.
 template <class A>
-bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a) {
+bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a, double bytes) {
   if (!c.rec) return false;
   Rec r{};
   r.type = 0; r.bf16 = bf16; r.cfg = cfg; r.kind = kind; r.sign = g.a_is_sign;
   r.g = g;
+  r.bytes = bytes;
+  r.flops = 2.0 * g.M * g.N * g.K;
   std::memcpy(r.epi, &a, sizeof(A));
   int bm, bn;
   gemm_config_tile(cfg, &bm, &bn);
@@ -887,17 +890,17 @@ struct BoundPass {
       pushes_left[p]--;
       BoundEpiArgs a = bound_args(p, false);
       int nslot = slots_for_elementwise(net->nodes[p].size);
+      const double M = c.M, d = net->nodes[p].size, esz = bf16 ? 2 : 4;
+      const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
+                           (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
       if (!dry && c.rec) {
         Rec r{};
         r.type = 1; r.bf16 = bf16; r.cfg = -1; r.kind = EPI_BOUND; r.sign = 0;
         r.ej = ElemBoundJob{ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(), slot};
         r.tiles = c.M * ((net->nodes[p].size + 255) / 256);
+        r.bytes = bytes;
         c.rec->push(r);
-      } else if (!dry)
-      {
-        const double M = c.M, d = net->nodes[p].size, esz = bf16 ? 2 : 4;
-        const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
-                             (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
+      } else if (!dry) {
         check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
           return launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(),
                                           slot, c.st);
@@ -953,7 +956,7 @@ struct BoundPass {
           });
           const double esz = bf16 ? 2 : 4;
           const double bytes = (double)g.M * g.K * esz + (double)g.N * g.K * esz + (double)g.M * g.N * 4 * (first ? 1 : 2);
-          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s))
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, bytes))
             check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         }
@@ -972,7 +975,7 @@ struct BoundPass {
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * 4 : 0) +
                                M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
-          if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a))
+          if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a, bytes))
             check(timed(c.st, cls_name("bound", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
         }
@@ -993,7 +996,7 @@ struct BoundPass {
           const double M = g.M, esz = bf16 ? 2 : 4;
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + (keep_ahat ? M * g.N : 0) +
                                M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
-          if (!record_gemm(c, bf16, cfg, EPI_CONC, g, a))
+          if (!record_gemm(c, bf16, cfg, EPI_CONC, g, a, bytes))
             check(timed(c.st, cls_name("conc", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st); }));
         }
@@ -1165,7 +1168,7 @@ struct AdjPass {
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
           const double bytes = a_bytes + (double)g.N * g.K * esz + M * di * 4 * (first ? 1 : 2);
-          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s))
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, bytes))
             check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
@@ -1177,9 +1180,9 @@ struct AdjPass {
             t.d_beta = tune_beta(c);
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
-          if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a))
-            check(timed(c.st, cls_name("adj", bf16, sign, cfg), adj_bytes(a_bytes, (double)g.N * g.K * esz),
-                        2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
+          const double bytes = adj_bytes(a_bytes, (double)g.N * g.K * esz);
+          if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a, bytes))
+            check(timed(c.st, cls_name("adj", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
       } else if (E.kind == GCP_EDGE_CONV) {
         no_record(c, "conv");
@@ -1512,6 +1515,7 @@ void launch_constants(Call& c) {
 struct Group {
   int type, bf16, cfg, kind, sign;
   int np, total;
+  double bytes, flops;                    // summed over the group's problems
   size_t off_args, off_epi, off_prefix;   // byte offsets into the plan buffer
 };
 struct BatchPlan {
@@ -1520,6 +1524,7 @@ struct BatchPlan {
   std::vector<Group> groups;              // in launch order
   size_t off_gjobs = 0, off_gprefix = 0;
   int g_np = 0, g_total = 0;
+  double g_bytes = 0.0;                   // algorithmic bytes of the grouped gamma update
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
   ~BatchPlan() {
@@ -1565,7 +1570,11 @@ void build_plan(BatchPlan& plan, std::vector<Recorder>& recs, std::vector<GammaJ
       G.type = v[0]->type; G.bf16 = v[0]->bf16; G.cfg = v[0]->cfg; G.kind = v[0]->kind; G.sign = v[0]->sign;
       G.np = (int)v.size();
       std::vector<int> prefix(1, 0);
-      for (const Rec* r : v) prefix.push_back(prefix.back() + r->tiles);
+      for (const Rec* r : v) {
+        prefix.push_back(prefix.back() + r->tiles);
+        G.bytes += r->bytes;
+        G.flops += r->flops;
+      }
       G.total = prefix.back();
       if (G.type == 0) {
         std::vector<GemmArgs> ga;
@@ -1604,22 +1613,27 @@ void run_grouped_iteration(BatchPlan& plan, int* step, float* consts, const gcp_
   hip_check(launch_adam_prepare(step, 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, consts,
                                 st),
             "adam prepare");
+  static const char* grp_names[] = {"store_grp", "bound_grp", "conc_grp", "adj_grp"};   // by EpiKind
   for (const Group& G : plan.groups) {
     if (G.type == 0)
-      hip_check(timed(st, cls_name("grouped", G.bf16, G.sign, G.cfg), 0.0, 0.0, [&] {
+      hip_check(timed(st, cls_name(grp_names[G.kind], G.bf16, G.sign, G.cfg), G.bytes, G.flops, [&] {
                   return launch_gemm_grouped(G.bf16, G.cfg, (EpiKind)G.kind, G.sign,
                                              (const GemmArgs*)(b + G.off_args), b + G.off_epi,
                                              (const int*)(b + G.off_prefix), G.np, G.total, st);
                 }),
                 "grouped gemm");
     else
-      hip_check(launch_bound_elementwise_grouped(G.bf16, (const ElemBoundJob*)(b + G.off_args),
-                                                 (const int*)(b + G.off_prefix), G.np, G.total, st),
+      hip_check(timed(st, cls_name("bound_elem_grp", G.bf16, 0, -1), G.bytes, 0.0, [&] {
+                  return launch_bound_elementwise_grouped(G.bf16, (const ElemBoundJob*)(b + G.off_args),
+                                                          (const int*)(b + G.off_prefix), G.np, G.total, st);
+                }),
                 "grouped elementwise");
   }
   if (plan.g_np)
-    hip_check(launch_gamma_grouped((const GammaJob*)(b + plan.off_gjobs), (const int*)(b + plan.off_gprefix),
-                                   plan.g_np, plan.g_total, adam, st),
+    hip_check(timed(st, "gamma_adam_grp", plan.g_bytes, 0.0, [&] {
+                return launch_gamma_grouped((const GammaJob*)(b + plan.off_gjobs), (const int*)(b + plan.off_gprefix),
+                                            plan.g_np, plan.g_total, adam, st);
+              }),
               "grouped gamma");
 }
 
@@ -1706,9 +1720,11 @@ extern "C" int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const 
       AdjPass ap{c, bf16, adam, nullptr, nullptr, items[i].alpha, items[i].beta, mom[i].ma, mom[i].va, mom[i].mb,
                  mom[i].vb};
       ap.run();
-      if (c.rp.N > 0)
+      if (c.rp.N > 0) {
+        plan->g_bytes += (double)c.M * (c.nnz * 4.0 + c.rp.N * 24.0);
         gj.push_back(GammaJob{c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), c.net->ws.contrib.as<float>(),
                               c.cuts->d.as<double>(), c.net->ws.gammaT.as<float>(), mom[i].mg, mom[i].vg});
+      }
     }
     build_plan(*plan, recs, gj);
     delete g_batch;
