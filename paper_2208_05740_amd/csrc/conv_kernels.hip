@@ -1,246 +1,402 @@
 // Convolution edges of the GCP-CROWN passes as implicit GEMMs on MFMA.
 //
 // Bound direction (a_hat^(src) = Lambda^(node) A, A the conv's matrix): a
-// transposed convolution.  GEMM rows = (batch row r, source position y, x),
-// columns = source channel c, K = (node channel o, ky, kx):
-//   A[(r,y,x)][(o,ky,kx)] = Lambda[r][o][(y+p-ky)/s][(x+p-kx)/s]  when the
-//   division is exact and inside the node's spatial range, else 0;
-//   B[(o,ky,kx)][c] = W[o][c][ky][kx].
-// Adjoint direction (dLambda^(node) = A da_hat^(src)): a convolution.  GEMM
-// rows = (r, oy, ox), columns = node channel o, K = (c, ky, kx):
-//   A[(r,oy,ox)][(c,ky,kx)] = X[r][c][oy*s-p+ky][ox*s-p+kx] (0 outside),
-//   B[(c,ky,kx)][o] = W[o][c][ky][kx].
-// A tiles are gathered element-wise into the same LDS layout the dense
-// kernel uses; B (weights, K contiguous) streams with 16-byte loads.  The
-// spatial size of the epilogue side is a multiple of the tile height, so a
-// tile never straddles two batch rows and its row constant goes to one
-// partial slot: slot0 + (spatial_tile16) * ceil(C/16) + channel_tile16.
+// transposed convolution.  Output position (y, x) of the source grid meets
+// the node grid only through taps with ky = (y + pad) mod s (+ s a) and
+// likewise for kx, so the positions split into s^2 phases; within a phase
+// every tap is real and
+//   a_hat[c][y][x] = sum_(o,a,b) Lambda[o][Yb - a][Xb - b] Wph[c][(o,a,b)],
+//   Yb = (y + pad - ry) / s,  Xb = (x + pad - rx) / s.
+// Adjoint direction (dLambda^(node) = A da_hat^(src)): a convolution,
+//   out[o][y][x] = sum_(c,ky,kx) X[c][y s - pad + ky][x s - pad + kx] W[o][(c,ky,kx)].
+// Both are "slab GEMMs": one workgroup takes one batch row and one band of
+// output rows, copies the source rows the band reads into LDS once (zero
+// halo, so the inner loop has no bounds checks), and forms MFMA A fragments
+// by gathering from the slab at base(position) + koff(k), with koff
+// precomputed per K index.  B fragments (weights, K contiguous) are read
+// from global memory, where the few KB of weights stay cached.  The MFMA
+// results of the band go to a second LDS buffer; the fused epilogue then
+// walks the band's neurons in memory order (a band of rows is a contiguous
+// run of each channel plane), so its loads and stores are coalesced and
+// every lane holds real neurons.  The row constant of a band goes to one
+// partial slot: slot0 + band.
 #include "gcp_internal.h"
 #include "epilogues.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace gcp {
 
-template <typename T, int BM, int BN, int WM, int WN, int BK, bool TRANS, bool SIGN, class Epi>
-__global__ void __launch_bounds__(WM * WN * 64) conv_epi_kernel(ConvArgs c, Epi epi) {
-  constexpr int NT = WM * WN * 64;
+namespace {
+constexpr int kSlabBudget = 48 * 1024;   // bytes of fp32 slab + result band a workgroup may use
+constexpr int kEpiRows = 4;              // neurons per lane in one epilogue round
+constexpr int kLdsLimit = 64 * 1024;
+__host__ __device__ inline int align16(int b) { return (b + 15) & ~15; }
+}  // namespace
+
+// Rows of phase ph inside band [yb0, yb1): source-side positions
+// (yf + st*iy, xf + st*ix), iy < ny, ix < nx, st = s for the transposed
+// direction (one phase per residue of y + pad and x + pad mod s), else 1.
+__host__ __device__ inline void phase_rows(const ConvPlan& P, int ph, int yb0, int yb1, bool trans, int* yf, int* ny,
+                                           int* xf, int* nx) {
+  if (trans) {
+    const int s = P.s, p = P.p, ry = ph / s, rx = ph % s;
+    *yf = yb0 + (((ry - (yb0 + p)) % s) + s) % s;
+    *ny = *yf < yb1 ? (yb1 - 1 - *yf) / s + 1 : 0;
+    *xf = (((rx - p) % s) + s) % s;
+    *nx = *xf < P.We ? (P.We - 1 - *xf) / s + 1 : 0;
+  } else {
+    *yf = yb0; *ny = yb1 - yb0; *xf = 0; *nx = P.We;
+  }
+}
+
+ConvPlan conv_plan(const ConvGeom& g, int trans) {
+  ConvPlan P{};
+  const int s = g.stride;
+  P.s = s;
+  P.p = g.pad;
+  if (trans) {
+    P.He = g.hi; P.We = g.wi; P.Nch = g.ci; P.Kch = g.co; P.hs = g.ho; P.ws = g.wo;
+    P.A = (g.kh + s - 1) / s;
+    P.Bn = (g.kw + s - 1) / s;
+    P.n_phase = s * s;
+    P.Kreal = g.co * P.A * P.Bn;
+    P.xl = P.Bn - 1;
+    const int xmax = (g.wi - 1 + g.pad) / s;           // largest Xb
+    P.Wp = P.xl + std::max(xmax + 1, g.wo);
+  } else {
+    P.He = g.ho; P.We = g.wo; P.Nch = g.co; P.Kch = g.ci; P.hs = g.hi; P.ws = g.wi;
+    P.A = g.kh;
+    P.Bn = g.kw;
+    P.n_phase = 1;
+    P.Kreal = g.ci * g.kh * g.kw;
+    P.xl = g.pad;
+    P.Wp = P.xl + std::max(g.wi, (g.wo - 1) * s - g.pad + g.kw);
+  }
+  P.KP = (P.Kreal + 31) / 32 * 32;
+  auto rows_for = [&](int bh) { return trans ? (bh - 1) / s + 1 + P.A : (bh - 1) * s + g.kh; };
+  auto bytes_for = [&](int bh) { return ((long)P.Kch * rows_for(bh) * P.Wp + (long)P.Nch * (bh * P.We + 1)) * 4; };
+  int bh = P.He;
+  while (bh > 1 && bytes_for(bh) > kSlabBudget) --bh;
+  P.n_bands = (P.He + bh - 1) / bh;
+  P.BH = (P.He + P.n_bands - 1) / P.n_bands;           // balance the bands
+  P.rows_max = rows_for(P.BH);
+  P.CHS = P.rows_max * P.Wp;
+  P.OS = P.BH * P.We + 1;                              // odd: channel planes on different banks
+  P.MT = 0;
+  for (int b = 0; b < P.n_bands; ++b) {
+    const int yb0 = b * P.BH, yb1 = std::min(P.He, yb0 + P.BH);
+    int nt = 0;
+    for (int ph = 0; ph < P.n_phase; ++ph) {
+      int yf, ny, xf, nx;
+      phase_rows(P, ph, yb0, yb1, trans != 0, &yf, &ny, &xf, &nx);
+      nt += (ny * nx + 15) / 16;
+    }
+    P.MT = std::max(P.MT, nt);
+  }
+  return P;
+}
+
+int conv_ldb(const ConvGeom& g, int trans) { return conv_plan(g, trans).KP; }
+
+void conv_pack_weights(const ConvGeom& g, int trans, const float* raw, float* out) {
+  const ConvPlan P = conv_plan(g, trans);
+  const int ldb = P.KP, s = g.stride;
+  auto w = [&](int o, int c, int ky, int kx) { return raw[(((size_t)o * g.ci + c) * g.kh + ky) * g.kw + kx]; };
+  if (!trans) {
+    for (int o = 0; o < g.co; ++o)
+      for (int k = 0; k < ldb; ++k) {
+        float v = 0.f;
+        if (k < P.Kreal) {
+          const int c = k / (g.kh * g.kw), ky = (k / g.kw) % g.kh, kx = k % g.kw;
+          v = w(o, c, ky, kx);
+        }
+        out[(size_t)o * ldb + k] = v;
+      }
+    return;
+  }
+  for (int ph = 0; ph < P.n_phase; ++ph) {
+    const int ry = ph / s, rx = ph % s;
+    for (int c = 0; c < g.ci; ++c)
+      for (int k = 0; k < ldb; ++k) {
+        float v = 0.f;
+        if (k < P.Kreal) {
+          const int o = k / (P.A * P.Bn), a = (k / P.Bn) % P.A, b = k % P.Bn;
+          const int ky = ry + s * a, kx = rx + s * b;
+          if (ky < g.kh && kx < g.kw) v = w(o, c, ky, kx);
+        }
+        out[((size_t)ph * g.ci + c) * ldb + k] = v;
+      }
+  }
+}
+
+static int conv_lds_bytes(const ConvPlan& P, int esz, int nw) {
+  return align16(P.KP * 4) + align16(nw * 8) + align16(P.MT * 4) + P.MT * 16 * 8 + align16(P.Kch * P.CHS * esz) +
+         align16(P.Nch * P.OS * 4);
+}
+
+// ---------------------------------------------------------------- slab fill
+template <typename T, bool SIGN> struct SlabLoad;
+template <> struct SlabLoad<bf16, false> {
+  __device__ static inline void vec(const void* X, size_t off, bf16* d) {
+    const uint4 v = *(const uint4*)((const bf16*)X + off);
+    const bf16x8 e = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) d[q] = e[q];
+  }
+  __device__ static inline bf16 one(const void* X, size_t off) { return ((const bf16*)X)[off]; }
+};
+template <> struct SlabLoad<float, false> {
+  __device__ static inline void vec(const void* X, size_t off, float* d) {
+    const float4 v = *(const float4*)((const float*)X + off);
+    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+  }
+  __device__ static inline float one(const void* X, size_t off) { return ((const float*)X)[off]; }
+};
+template <> struct SlabLoad<bf16, true> {
+  __device__ static inline void vec(const void* X, size_t off, bf16* d) {
+    const uint2 v = *(const uint2*)((const int8_t*)X + off);
+    const int8_t* e = (const int8_t*)&v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) d[q] = (bf16)(float)e[q];
+  }
+  __device__ static inline bf16 one(const void* X, size_t off) { return (bf16)(float)((const int8_t*)X)[off]; }
+};
+template <> struct SlabLoad<float, true> {
+  __device__ static inline void vec(const void* X, size_t off, float* d) {
+    const uint32_t v = *(const uint32_t*)((const int8_t*)X + off);
+    const int8_t* e = (const int8_t*)&v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = (float)e[q];
+  }
+  __device__ static inline float one(const void* X, size_t off) { return (float)((const int8_t*)X)[off]; }
+};
+
+// A fragment of one lane: VEC consecutive K indices of its GEMM row, gathered
+// from the slab (uint4 in the MFMA operand layout).
+template <typename T> struct Gather;
+template <> struct Gather<bf16> {
+  __device__ static inline uint4 get(const bf16* slab, int base, const int* ko) {
+    const unsigned short* S = (const unsigned short*)slab;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = (uint32_t)S[base + ko[2 * q]] | ((uint32_t)S[base + ko[2 * q + 1]] << 16);
+    return uint4{w[0], w[1], w[2], w[3]};
+  }
+};
+template <> struct Gather<float> {
+  __device__ static inline uint4 get(const float* slab, int base, const int* ko) {
+    const uint32_t* S = (const uint32_t*)slab;
+    return uint4{S[base + ko[0]], S[base + ko[1]], S[base + ko[2]], S[base + ko[3]]};
+  }
+};
+
+template <typename T, int NW, int TN, bool TRANS, bool SIGN, class Epi>
+__global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan P, Epi epi) {
+  constexpr int NT = NW * 64;
   constexpr int VEC = Op<T>::VEC;
   constexpr int KC = Op<T>::KC;
-  constexpr int LDS_LD = BK + VEC;
-  constexpr int TM = BM / WM / 16;
-  constexpr int TN = BN / WN / 16;
-  constexpr int AV = BM * BK / VEC;
-  constexpr int BV = BN * BK / VEC;
-  constexpr int AIT = (AV + NT - 1) / NT;
-  constexpr int BIT = (BV + NT - 1) / NT;
-  static_assert(BK % KC == 0, "BK must be a multiple of the fragment K");
-  static_assert(BM % 16 == 0 && BN % 16 == 0, "tile");
-
-  __shared__ __attribute__((aligned(16))) T As[BM * LDS_LD];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * LDS_LD];
-  __shared__ double red[NT / 64];
-
-  const ConvGeom& g = c.cg;
-  const int HW = TRANS ? g.hi * g.wi : g.ho * g.wo;     // positions on the epilogue side
-  const int Wd = TRANS ? g.wi : g.wo;
-  const int Nch = TRANS ? g.ci : g.co;                   // GEMM columns
-  const int Kch = TRANS ? g.co : g.ci;                   // channels summed over
-  const int KK = Kch * g.kh * g.kw;
-  const int Mg = c.M * HW;
-  const int node_size = Nch * HW;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* sp = smem;
+  int* koff = (int*)sp;        sp += align16(P.KP * 4);
+  double* red = (double*)sp;   sp += align16(NW * 8);
+  int* tph = (int*)sp;         sp += align16(P.MT * 4);        // phase of each 16-row tile
+  int2* desc = (int2*)sp;      sp += P.MT * 16 * 8;            // per GEMM row: {slab base, result offset or -1}
+  T* slab = (T*)sp;            sp += align16(P.Kch * P.CHS * (int)sizeof(T));
+  float* outs = (float*)sp;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int n_col = (Nch + BN - 1) / BN;
-  const int total = n_col * ((Mg + BM - 1) / BM);
-  const int xcd = blockIdx.x % 8, kx8 = blockIdx.x / 8;
-  const int per = total / 8, rem = total % 8;
-  const int vt = xcd * per + (xcd < rem ? xcd : rem) + kx8;
-  const int bx = vt % n_col, by = vt / n_col;
-  const int m0 = by * BM, n0 = bx * BN;
+  const int r = blockIdx.x / P.n_bands, band = blockIdx.x % P.n_bands;
+  const int s = P.s, p = P.p;
+  const int yb0 = band * P.BH, yb1 = min(P.He, yb0 + P.BH);
+  const int sy0 = TRANS ? (yb0 + p) / s - (P.A - 1) : yb0 * s - p;   // source row of slab row 0
+  const int HWe = P.He * P.We;
+  const int node_size = P.Nch * HWe;
+  const int safe_base = TRANS ? (P.A - 1) * P.Wp + P.Bn - 1 : 0;    // in-slab for every koff
 
-  f4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int k = 0; k < TN; ++k) acc[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-
-  // epilogue coordinates: row m -> (r, position), column n -> neuron n*HW + position
-  constexpr int R = TM * 4;
-  LaneCoords<R, TN, true> lc;
+  // K index -> slab offset relative to a row's base
+  for (int k = tid; k < P.KP; k += NT) {
+    int o = 0;
+    if (k < P.Kreal) {
+      const int ch = k / (P.A * P.Bn), a = (k / P.Bn) % P.A, b = k % P.Bn;
+      o = TRANS ? ch * P.CHS - a * P.Wp - b : ch * P.CHS + a * P.Wp + b;
+    }
+    koff[k] = o;
+  }
+  // GEMM rows of the band, phase by phase, each phase padded to whole tiles
+  int ntile = 0;
+  for (int ph = 0; ph < P.n_phase; ++ph) {
+    int yf, ny, xf, nx;
+    phase_rows(P, ph, yb0, yb1, TRANS, &yf, &ny, &xf, &nx);
+    const int npos = ny * nx, nt = (npos + 15) / 16;
+    int base0, rstep, cstep;
+    if constexpr (TRANS) {
+      const int ry = ph / s, rx = ph % s;
+      base0 = ((yf + p - ry) / s - sy0) * P.Wp + (xf + p - rx) / s + P.xl;
+      rstep = P.Wp; cstep = 1;
+    } else {
+      base0 = (yf * s - p - sy0) * P.Wp + xf * s - p + P.xl;
+      rstep = s * P.Wp; cstep = s;
+    }
+    const int st = TRANS ? s : 1;
+    const int out0 = (yf - yb0) * P.We + xf;
+    for (int i = tid; i < nt * 16; i += NT) {
+      int2 d = make_int2(safe_base, -1);
+      if (i < npos) {
+        const int iy = i / nx, ix = i - iy * nx;
+        d = make_int2(base0 + iy * rstep + ix * cstep, out0 + iy * st * P.We + ix * st);
+      }
+      desc[ntile * 16 + i] = d;
+    }
+    for (int i = tid; i < nt; i += NT) tph[ntile + i] = ph;
+    ntile += nt;
+  }
   {
-    const int row0 = m0 + wm * (BM / WM) + (lane >> 4) * 4;
-    const int col0 = n0 + wn * (BN / WN) + (lane & 15);
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = i * 4 + v, m = row0 + i * 16 + v;
-        const int sp = m % HW;
-        lc.r[q] = m < Mg ? m / HW : c.M;
-#pragma unroll
-        for (int k = 0; k < TN; ++k) {
-          const int n = col0 + k * 16;
-          lc.j[k][q] = n < Nch ? n * HW + sp : node_size;
-        }
-      }
+    uint4* z = (uint4*)slab;
+    const int n16 = align16(P.Kch * P.CHS * (int)sizeof(T)) / 16;
+    for (int v = tid; v < n16; v += NT) z[v] = uint4{0u, 0u, 0u, 0u};
   }
-  typename Epi::template Frag<R, TN, true> fr;
-  epi.template load<R, TN, true>(fr, lc, c.M, node_size);
-
-  uint4 ra[AIT], rb[BIT];
-  auto load_stage = [&](int k0) {
-#pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int v = tid + it * NT;
-      T tmp[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) tmp[q] = to_t<T>(0.f);
-      if (v < AV) {
-        const int row = v / (BK / VEC), kk = (v % (BK / VEC)) * VEC;
-        const int m = m0 + row;
-        if (m < Mg) {
-          const int r = m / HW, sp = m % HW, y = sp / Wd, x = sp % Wd;
-          int k = k0 + kk;
-          int ch = k / (g.kh * g.kw), ky = (k / g.kw) % g.kh, kx = k % g.kw;
-#pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            if (k < KK) {
-              int sy, sx, ok;
-              if constexpr (TRANS) {
-                const int ty = y + g.pad - ky, tx = x + g.pad - kx;
-                sy = ty / g.stride; sx = tx / g.stride;
-                ok = ty >= 0 && tx >= 0 && ty % g.stride == 0 && tx % g.stride == 0 && sy < g.ho && sx < g.wo;
-              } else {
-                sy = y * g.stride - g.pad + ky; sx = x * g.stride - g.pad + kx;
-                ok = sy >= 0 && sx >= 0 && sy < g.hi && sx < g.wi;
-              }
-              if (ok) {
-                const int hs = TRANS ? g.ho : g.hi, ws = TRANS ? g.wo : g.wi;
-                const size_t off = (size_t)r * c.ldx + (size_t)(ch * hs + sy) * ws + sx;
-                if constexpr (SIGN) tmp[q] = to_t<T>((float)((const int8_t*)c.X)[off]);
-                else tmp[q] = ((const T*)c.X)[off];
-              }
-            }
-            ++k;
-            if (++kx == g.kw) { kx = 0; if (++ky == g.kh) { ky = 0; ++ch; } }
-          }
-        }
-      }
-      ra[it] = *(const uint4*)tmp;
-    }
-#pragma unroll
-    for (int it = 0; it < BIT; ++it) {
-      const int v = tid + it * NT;
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (v < BV) {
-        const int row = v / (BK / VEC), kk = (v % (BK / VEC)) * VEC;
-        const int gn = n0 + row, gk = k0 + kk;
-        if (gn < Nch && gk < c.ldb) val = *(const uint4*)((const T*)c.Bt + (size_t)gn * c.ldb + gk);
-      }
-      rb[it] = val;
-    }
-  };
-  auto store_stage = [&]() {
-#pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int v = tid + it * NT;
-      if (v < AV) *(uint4*)(As + (v / (BK / VEC)) * LDS_LD + (v % (BK / VEC)) * VEC) = ra[it];
-    }
-#pragma unroll
-    for (int it = 0; it < BIT; ++it) {
-      const int v = tid + it * NT;
-      if (v < BV) *(uint4*)(Bs + (v / (BK / VEC)) * LDS_LD + (v % (BK / VEC)) * VEC) = rb[it];
-    }
-  };
-
-  const int arow = wm * (BM / WM) + (lane & 15);
-  const int bcol = wn * (BN / WN) + (lane & 15);
-  const int kq = (lane >> 4) * VEC;
-  if (KK > 0) load_stage(0);
-  for (int k0 = 0; k0 < KK; k0 += BK) {
-    __syncthreads();
-    store_stage();
-    __syncthreads();
-    if (k0 + BK < KK) load_stage(k0 + BK);
-#pragma unroll
-    for (int kc = 0; kc < BK; kc += KC) {
-      uint4 fa[TM], fb[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) fa[i] = *(const uint4*)(As + (arow + i * 16) * LDS_LD + kc + kq);
-#pragma unroll
-      for (int k = 0; k < TN; ++k) fb[k] = *(const uint4*)(Bs + (bcol + k * 16) * LDS_LD + kc + kq);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int k = 0; k < TN; ++k) Op<T>::mma(fa[i], fb[k], acc[i][k]);
-    }
-  }
-
-  double rs[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) rs[q] = 0.0;
+  __syncthreads();
   {
-    float val[TN][R];
+    const size_t xrow = (size_t)r * c.ldx;
+    const bool vec = P.ws % VEC == 0;
+    const int cw = vec ? VEC : 1;
+    const int nchunk = P.ws / cw;
+    const int total = P.Kch * P.rows_max * nchunk;
+    for (int v = tid; v < total; v += NT) {
+      const int xc = v % nchunk, rest = v / nchunk;
+      const int rho = rest % P.rows_max, ch = rest / P.rows_max;
+      const int sy = sy0 + rho;
+      if (sy < 0 || sy >= P.hs) continue;
+      const size_t src = xrow + ((size_t)ch * P.hs + sy) * P.ws + (size_t)xc * cw;
+      T* dst = slab + ch * P.CHS + rho * P.Wp + P.xl + xc * cw;
+      if (vec) {
+        T tmp[VEC];
+        SlabLoad<T, SIGN>::vec(c.X, src, tmp);
 #pragma unroll
-    for (int k = 0; k < TN; ++k)
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) val[k][i * 4 + v] = acc[i][k][v];
-    epi.template apply<R, TN, true>(fr, lc, val, rs, c.M, node_size);
+        for (int q = 0; q < VEC; ++q) dst[q] = tmp[q];
+      } else {
+        dst[0] = SlabLoad<T, SIGN>::one(c.X, src);
+      }
+    }
   }
+  __syncthreads();
+
+  // MFMA tiles: (16-row tile, column chunk of 16*TN channels) -> LDS result band
+  const int nck = (P.Nch + 16 * TN - 1) / (16 * TN);
+  const int g = lane >> 4;
+  for (int t = wave; t < ntile * nck; t += NW) {
+    const int tt = nck == 1 ? t : t / nck, ck = nck == 1 ? 0 : t - tt * nck;
+    const int ph = __builtin_amdgcn_readfirstlane(tph[tt]);
+    const int base = desc[tt * 16 + (lane & 15)].x;
+    f4 acc[TN];
+#pragma unroll
+    for (int k = 0; k < TN; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+    const T* Bp = (const T*)c.Bt + (size_t)ph * P.Nch * c.ldb;
+    int nb[TN];
+#pragma unroll
+    for (int k = 0; k < TN; ++k) nb[k] = ck * 16 * TN + k * 16 + (lane & 15);
+    for (int k0 = 0; k0 < P.KP; k0 += KC) {
+      int ko[VEC];
+      const int4* kp = (const int4*)(koff + k0 + VEC * g);
+#pragma unroll
+      for (int q = 0; q < VEC / 4; ++q) {
+        const int4 t4 = kp[q];
+        ko[4 * q] = t4.x; ko[4 * q + 1] = t4.y; ko[4 * q + 2] = t4.z; ko[4 * q + 3] = t4.w;
+      }
+      const uint4 fa = Gather<T>::get(slab, base, ko);
+#pragma unroll
+      for (int k = 0; k < TN; ++k) {
+        uint4 fb = {0u, 0u, 0u, 0u};
+        if (nb[k] < P.Nch) fb = *(const uint4*)(Bp + (size_t)nb[k] * c.ldb + k0 + VEC * g);
+        Op<T>::mma(fa, fb, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int o = desc[tt * 16 + g * 4 + v].y;
+      if (o < 0) continue;
+#pragma unroll
+      for (int k = 0; k < TN; ++k)
+        if (nb[k] < P.Nch) outs[nb[k] * P.OS + o] = acc[k][v];
+    }
+  }
+  __syncthreads();
+
+  // fused epilogue over the band's neurons in memory order
+  double rs[kEpiRows];
+#pragma unroll
+  for (int q = 0; q < kEpiRows; ++q) rs[q] = 0.0;
+  {
+    const int per_ch = (yb1 - yb0) * P.We;
+    const int nel = P.Nch * per_ch;
+    const int j0 = yb0 * P.We;
+    const float inv_pc = 1.f / (float)per_ch;
+    for (int e0 = wave * 64 * kEpiRows; e0 < nel; e0 += NT * kEpiRows) {
+      LaneCoords<kEpiRows, 1, true> lc;
+      float val[1][kEpiRows];
+#pragma unroll
+      for (int q = 0; q < kEpiRows; ++q) {
+        const int e = e0 + q * 64 + lane;
+        const bool ok = e < nel;
+        // e = n * per_ch + off; the float quotient is within one of n
+        int n = (int)((float)e * inv_pc), off = e - n * per_ch;
+        if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
+        lc.r[q] = ok ? r : c.M;
+        lc.j[0][q] = ok ? n * HWe + j0 + off : node_size;
+        val[0][q] = ok ? outs[n * P.OS + off] : 0.f;
+      }
+      typename Epi::template Frag<kEpiRows, 1, true> fr;
+      epi.template load<kEpiRows, 1, true>(fr, lc, c.M, node_size);
+      epi.template apply<kEpiRows, 1, true>(fr, lc, val, rs, c.M, node_size);
+    }
+  }
+
   if (c.partial) {
-    // the whole tile belongs to batch row m0 / HW: sum lane, wave, block
-    double t = 0.0;
+    double tsum = 0.0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) t += rs[q];
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if (lane == 0) red[wave] = t;
+    for (int q = 0; q < kEpiRows; ++q) tsum += rs[q];
+    for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+    if (lane == 0) red[wave] = tsum;
     __syncthreads();
-    if (tid == 0 && m0 < Mg) {
-      double s = 0.0;
-      for (int w = 0; w < NT / 64; ++w) s += red[w];
-      const int r = m0 / HW;
-      const int ncol16 = (Nch + 15) / 16;
-      const int srow = (m0 % HW) / 16, scol = n0 / 16;
-      for (int a = 0; a < BM / 16; ++a)
-        for (int b = 0; b < BN / 16; ++b)
-          if (scol + b < ncol16)
-            c.partial[(size_t)(c.slot0 + (srow + a) * ncol16 + scol + b) * c.mp + r] = (a == 0 && b == 0) ? s : 0.0;
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[w];
+      c.partial[(size_t)(c.slot0 + band) * c.mp + r] = sum;
     }
   }
 }
 
-struct CTile { int bm, bn; };
-static const CTile kConv[] = {{64, 16}, {64, 32}, {64, 64}, {32, 32}, {32, 16}, {16, 16}, {16, 32}};
+// launch configurations: waves per workgroup x column tiles per wave
+struct CCfg { int nw, tn; };
+static const CCfg kConv[] = {{4, 1}, {4, 2}, {8, 1}, {8, 2}, {4, 4}, {2, 1}};
 int conv_num_configs() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }
-void conv_config_tile(int cfg, int* bm, int* bn) { *bm = kConv[cfg].bm; *bn = kConv[cfg].bn; }
 
-template <typename T, int BM, int BN, int WM, int WN, bool TRANS, bool SIGN, class Epi>
-static hipError_t conv_cfg(const ConvArgs& c, const Epi& epi, hipStream_t st) {
-  constexpr int BK = (sizeof(T) == 4) ? 64 : 128;
-  const ConvGeom& g = c.cg;
-  const int HW = TRANS ? g.hi * g.wi : g.ho * g.wo;
-  const int Nch = TRANS ? g.ci : g.co;
-  if (HW % BM != 0) return hipErrorInvalidValue;   // a tile must not straddle batch rows
-  const long tiles = (long)((Nch + BN - 1) / BN) * (((long)c.M * HW + BM - 1) / BM);
-  hipLaunchKernelGGL((conv_epi_kernel<T, BM, BN, WM, WN, BK, TRANS, SIGN, Epi>), dim3((unsigned)tiles),
-                     dim3(WM * WN * 64), 0, st, c, epi);
+template <typename T, int NW, int TN, bool TRANS, bool SIGN, class Epi>
+static hipError_t conv_go(const ConvArgs& c, const ConvPlan& P, const Epi& epi, hipStream_t st) {
+  const int lds = conv_lds_bytes(P, (int)sizeof(T), NW);
+  if (lds > kLdsLimit) return hipErrorInvalidValue;
+  const long grid = (long)c.M * P.n_bands;
+  if (grid <= 0 || grid > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((conv_slab_kernel<T, NW, TN, TRANS, SIGN, Epi>), dim3((unsigned)grid), dim3(NW * 64),
+                     (unsigned)lds, st, c, P, epi);
   return hipGetLastError();
 }
 
 template <typename T, bool TRANS, bool SIGN, class Epi>
 static hipError_t conv_any(int cfg, const ConvArgs& c, const Epi& epi, hipStream_t st) {
+  const ConvPlan P = conv_plan(c.cg, TRANS ? 1 : 0);
+  if (c.ldb < P.KP || c.ldb % 32 != 0) return hipErrorInvalidValue;
   switch (cfg) {
-    case 0: return conv_cfg<T, 64, 16, 4, 1, TRANS, SIGN>(c, epi, st);
-    case 1: return conv_cfg<T, 64, 32, 2, 2, TRANS, SIGN>(c, epi, st);
-    case 2: return conv_cfg<T, 64, 64, 2, 2, TRANS, SIGN>(c, epi, st);
-    case 3: return conv_cfg<T, 32, 32, 2, 2, TRANS, SIGN>(c, epi, st);
-    case 4: return conv_cfg<T, 32, 16, 2, 1, TRANS, SIGN>(c, epi, st);
-    case 5: return conv_cfg<T, 16, 16, 1, 1, TRANS, SIGN>(c, epi, st);
-    case 6: return conv_cfg<T, 16, 32, 1, 2, TRANS, SIGN>(c, epi, st);
+    case 0: return conv_go<T, 4, 1, TRANS, SIGN>(c, P, epi, st);
+    case 1: return conv_go<T, 4, 2, TRANS, SIGN>(c, P, epi, st);
+    case 2: return conv_go<T, 8, 1, TRANS, SIGN>(c, P, epi, st);
+    case 3: return conv_go<T, 8, 2, TRANS, SIGN>(c, P, epi, st);
+    case 4: return conv_go<T, 4, 4, TRANS, SIGN>(c, P, epi, st);
+    case 5: return conv_go<T, 2, 1, TRANS, SIGN>(c, P, epi, st);
     default: return hipErrorInvalidValue;
   }
 }

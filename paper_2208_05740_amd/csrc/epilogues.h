@@ -99,15 +99,14 @@ __device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ g
                                    float (&sQ)[R]) {
 #pragma unroll
   for (int q = 0; q < R; ++q) sG[q] = sH[q] = sQ[q] = 0.f;
-  if (!cc.col_ptr) return;
+  if (!cc.rng) return;
   if constexpr (!PE) {
     if (!jv[0]) return;
-    const int j = jq[0];
-    const int e0 = cc.col_ptr[j], e1 = cc.col_ptr[j + 1];
-    for (int e = e0; e < e1; ++e) {
-      const int ck = cc.cut[e];
-      const float ch = cc.cH[e], cg = cc.cG[e], cq = cc.cQ[e];
-      const float* gk = gammaT + (size_t)ck * mp;
+    const int2 rg = cc.rng[jq[0]];
+    for (int e = rg.x; e < rg.y; ++e) {
+      const float4 en = cc.ent[e];
+      const float ch = en.x, cg = en.y, cq = en.z;
+      const float* gk = gammaT + (size_t)__float_as_int(en.w) * mp;
       float g[R];
       if constexpr (R % 4 == 0) {
 #pragma unroll
@@ -127,15 +126,17 @@ __device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ g
       }
     }
   } else {
+    int2 rg[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rg[q] = jv[q] ? cc.rng[jq[q]] : make_int2(0, 0);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      if (!jv[q]) continue;
-      const int j = jq[q];
-      for (int e = cc.col_ptr[j]; e < cc.col_ptr[j + 1]; ++e) {
-        const float g = gammaT[(size_t)cc.cut[e] * mp + rr[q]];
-        sG[q] += g * cc.cG[e];
-        sH[q] += g * cc.cH[e];
-        sQ[q] += g * cc.cQ[e];
+      for (int e = rg[q].x; e < rg[q].y; ++e) {
+        const float4 en = cc.ent[e];
+        const float g = gammaT[(size_t)__float_as_int(en.w) * mp + rr[q]];
+        sG[q] += g * en.y;
+        sH[q] += g * en.x;
+        sQ[q] += g * en.z;
       }
     }
   }
@@ -183,19 +184,22 @@ struct BoundEpi {
         jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
         f.ev[k][q] = jv[q] && rv[q];
       }
+      int kv[PE ? R : 1];
 #pragma unroll
       for (int q = 0; q < (PE ? R : 1); ++q) {
         const int j = jq[q];
-        f.bj[k][q] = nd.bias[j]; f.lj[k][q] = nd.l[j]; f.uj[k][q] = nd.u[j]; f.iul[k][q] = nd.inv_ul[j];
+        const float4 nr = nd.rec[j];
+        f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.bj[k][q] = nr.w;
+        kv[q] = nd.kind[j];
       }
       float sG[R], sH[R];
       gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, rr, sG, sH, f.sQ[k]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int j = jq[GCP_QC(q)];
-        const int rk = nd.rank[j];
+        const int rk = kind_rank(kv[GCP_QC(q)]);
         int c, slot;
-        split_class<R>(rp, rk, nd.cls[j], f.rc[q], &c, &slot);
+        split_class<R>(rp, rk, kind_cls(kv[GCP_QC(q)]), f.rc[q], &c, &slot);
         const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
         f.aoff[k][q] = pre + sG[q];
         f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
@@ -283,10 +287,11 @@ struct ConcEpi {
         const float v = val[k][q] + f.sG[k][q];
         const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
         if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
-        if (a.contrib && a.cc.col_ptr) {
+        if (a.contrib && a.cc.rng) {
           const float dv = (float)(xj - a.eps * (double)sg);
-          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
-            a.contrib[(size_t)a.cc.pos[e] * a.rp.mp + f.rr[q]] = a.cc.cG[e] * dv;
+          const int2 rg = a.cc.rng[j];
+          for (int e = rg.x; e < rg.y; ++e)
+            a.contrib[(size_t)a.cc.pos[e] * a.rp.mp + f.rr[q]] = a.cc.ent[e].y * dv;
         }
         const double vd = (double)v;
         rs[q] += xj * vd - a.eps * fabs(vd);
@@ -331,19 +336,22 @@ struct AdjEpi {
         jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
         f.ev[k][q] = jv[q] && rv[q];
       }
+      int kv[PE ? R : 1];
 #pragma unroll
       for (int q = 0; q < (PE ? R : 1); ++q) {
         const int j = jq[q];
-        f.lj[k][q] = nd.l[j]; f.uj[k][q] = nd.u[j]; f.iul[k][q] = nd.inv_ul[j]; f.addj[k][q] = a.add_vec[j];
+        const float4 nr = nd.rec[j];
+        f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.addj[k][q] = a.add_vec[j];
+        kv[q] = nd.kind[j];
       }
       float sG[R], sH[R];
       gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, f.rr, sG, sH, f.sQ[k]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int j = jq[GCP_QC(q)];
-        const int rk = nd.rank[j];
+        const int rk = kind_rank(kv[GCP_QC(q)]);
         int c, slot;
-        split_class<R>(rp, rk, nd.cls[j], f.rc[q], &c, &slot);
+        split_class<R>(rp, rk, kind_cls(kv[GCP_QC(q)]), f.rc[q], &c, &slot);
         f.rk[k][q] = rk;
         f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
         f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
@@ -399,9 +407,12 @@ struct AdjEpi {
         const int j = lc.j[k][qc];
         const size_t ij = (size_t)f.rc[q] * nd.ld + j;
         if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
-        if (a.contrib && a.cc.col_ptr) {
-          for (int e = a.cc.col_ptr[j]; e < a.cc.col_ptr[j + 1]; ++e)
-            a.contrib[(size_t)a.cc.pos[e] * rp.mp + f.rr[q]] = a.cc.cG[e] * dA + a.cc.cH[e] * dL + a.cc.cQ[e] * dS;
+        if (a.contrib && a.cc.rng) {
+          const int2 rg = a.cc.rng[j];
+          for (int e = rg.x; e < rg.y; ++e) {
+            const float4 en = a.cc.ent[e];
+            a.contrib[(size_t)a.cc.pos[e] * rp.mp + f.rr[q]] = en.y * dA + en.x * dL + en.z * dS;
+          }
         }
         const int rk = f.rk[k][q];
         if (rk >= 0) {

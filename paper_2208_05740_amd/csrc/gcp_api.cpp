@@ -172,13 +172,10 @@ struct NodeH {
   bool relu;
   std::vector<int> in_edges;      // edges whose dst is this node
   std::vector<int> consumers;     // edges whose src is this node
-  DBuf bias, l, u, inv_ul, cls, rank;
+  DBuf bias, rec, kind;
   std::vector<int32_t> rank_h;    // host copy of rank
   int n_unst = 0, rank0 = 0;
-  NodeDev dev() const {
-    return NodeDev{size, ld, bias.as<float>(), l.as<float>(), u.as<float>(), inv_ul.as<float>(),
-                   cls.as<int8_t>(), rank.as<int32_t>()};
-  }
+  NodeDev dev() const { return NodeDev{size, ld, rec.as<float4>(), kind.as<int32_t>()}; }
 };
 
 }  // namespace
@@ -219,12 +216,11 @@ struct gcp_cuts {
   DBuf row_ptr;     // [N + 1] over merged entries in cut-major order
   DBuf d;           // fp64 [N]
   struct Col {
-    DBuf col_ptr, cut, pos, cH, cG, cQ;
+    DBuf rng, ent, pos;
     bool any = false;
     CutCol dev() const {
-      if (!any) return CutCol{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-      return CutCol{col_ptr.as<int32_t>(), cut.as<int32_t>(), pos.as<int32_t>(), cH.as<float>(), cG.as<float>(),
-                    cQ.as<float>()};
+      if (!any) return CutCol{nullptr, nullptr, nullptr};
+      return CutCol{rng.as<int2>(), ent.as<float4>(), pos.as<int32_t>()};
     }
   };
   std::vector<Col> cols;   // per node; index n_nodes is the network input
@@ -299,6 +295,9 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
     check_finite(nd.bias, n.size, "bias");
     std::vector<float> b(nd.bias, nd.bias + n.size);
     n.bias.upload(b);
+    std::vector<float4> rec(n.size);
+    std::vector<int32_t> kind(n.size, 0);
+    for (int j = 0; j < n.size; ++j) rec[j] = make_float4(0.f, 0.f, 0.f, b[j]);
     if (nd.n_edges <= 0 || !nd.edges) fail(GCP_EINVAL, "node " + std::to_string(i) + " has no input edge");
     if (n.relu) {
       if (!nd.lower || !nd.upper) fail(GCP_EINVAL, "missing root bounds at node " + std::to_string(i));
@@ -321,10 +320,15 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         }
       }
       n.n_unst = rank0 - n.rank0;
-      n.l.upload(l); n.u.upload(u); n.inv_ul.upload(iul); n.cls.upload(cls); n.rank.upload(rank);
+      for (int j = 0; j < n.size; ++j) {
+        rec[j] = make_float4(l[j], u[j], iul[j], b[j]);
+        kind[j] = (rank[j] + 1) * 4 + cls[j];
+      }
       n.rank_h = rank;
       net->n_relu += n.size;
     }
+    n.rec.upload(rec);
+    n.kind.upload(kind);
     for (int e = 0; e < nd.n_edges; ++e) {
       const gcp_edge_desc& ed = nd.edges[e];
       if (ed.src < -1 || ed.src >= i) fail(GCP_EINVAL, "edge source must be an earlier node or the input");
@@ -360,24 +364,19 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         if (ho != n.h || wo != n.w) fail(GCP_EINVAL, "conv output shape does not match node " + std::to_string(i));
         E->kh = ed.kh; E->kw = ed.kw; E->stride = ed.stride; E->pad = ed.pad;
         E->cg = ConvGeom{ci, hi, wi, n.c, ho, wo, ed.kh, ed.kw, ed.stride, ed.pad};
-        if ((ho * wo) % 16 != 0 || (hi * wi) % 16 != 0)
-          fail(GCP_EUNSUPPORTED, "conv spatial sizes must be multiples of 16 positions");
         size_t cnt = (size_t)n.c * ci * ed.kh * ed.kw;
         check_finite(ed.W, cnt, "conv weight");
         std::vector<float> raw(ed.W, ed.W + cnt);
         E->Wraw.upload(raw);
-        const int taps = ed.kh * ed.kw;
-        // adjoint: Bt[o][(c,ky,kx)] = W[o][c][ky][kx], K padded to 16
-        const int kf = round_up(ci * taps, 16);
-        std::vector<float> fw((size_t)n.c * kf, 0.f);
-        for (int o = 0; o < n.c; ++o)
-          for (int q = 0; q < ci * taps; ++q) fw[(size_t)o * kf + q] = raw[(size_t)o * ci * taps + q];
-        // bound: Bt[c][(o,ky,kx)] = W[o][c][ky][kx]
-        const int kt = round_up(n.c * taps, 16);
-        std::vector<float> ft((size_t)ci * kt, 0.f);
-        for (int o = 0; o < n.c; ++o)
-          for (int cc = 0; cc < ci; ++cc)
-            for (int t = 0; t < taps; ++t) ft[(size_t)cc * kt + o * taps + t] = raw[((size_t)o * ci + cc) * taps + t];
+        // kernel layouts: adjoint [co][ldk_f], bound [phase][ci][ldk_t]
+        const int kf = conv_ldb(E->cg, 0), kt = conv_ldb(E->cg, 1);
+        const int nph = ed.stride * ed.stride;
+        std::vector<float> fw((size_t)n.c * kf), ft((size_t)nph * ci * kt);
+        conv_pack_weights(E->cg, 0, raw.data(), fw.data());
+        conv_pack_weights(E->cg, 1, raw.data(), ft.data());
+        const ConvPlan pf = conv_plan(E->cg, 0), pt = conv_plan(E->cg, 1);
+        if (pf.rows_max * pf.Wp * pf.Kch * 4 > 48 * 1024 || pt.rows_max * pt.Wp * pt.Kch * 4 > 48 * 1024)
+          fail(GCP_EUNSUPPORTED, "conv rows too wide for an LDS slab");
         E->ldk_f = kf;
         E->ldk_t = kt;
         E->W32.upload(fw); E->W16.upload(to_bf16(fw));
@@ -476,16 +475,9 @@ struct Cands {
 Cands dense_cands(int M, int N) {
   return Cands{std::vector<int>(std::begin(kTileCandidates), std::end(kTileCandidates)), heuristic_cfg(M, N)};
 }
-// conv tiles must not straddle batch rows: BM divides the epilogue-side positions
-Cands conv_cands(int spatial) {
-  Cands c{{}, -1};
-  for (int i = 0; i < conv_num_configs(); ++i) {
-    int bm, bn;
-    conv_config_tile(i, &bm, &bn);
-    if (spatial % bm == 0) c.list.push_back(i);
-  }
-  if (c.list.empty()) fail(GCP_EUNSUPPORTED, "no conv tile divides the spatial size");
-  c.fallback = c.list.front();
+Cands conv_cands() {
+  Cands c{{}, 0};
+  for (int i = 0; i < conv_num_configs(); ++i) c.list.push_back(i);
   return c;
 }
 
@@ -637,16 +629,19 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
     auto& col = C->cols[nd < 0 ? n_nodes : nd];
     if (mine.empty()) continue;
     std::stable_sort(mine.begin(), mine.end(), [](const Ent& a, const Ent& b) { return a.j < b.j; });
-    std::vector<int32_t> cp(sz + 1, 0), ck, cpos;
-    std::vector<float> ch, cg, cq;
+    std::vector<int32_t> cp(sz + 1, 0), cpos;
+    std::vector<float4> en;
     for (auto& e : mine) {
       cp[e.j + 1]++;
-      ck.push_back(e.k); cpos.push_back(e.pos);
-      ch.push_back(e.h); cg.push_back(e.g); cq.push_back(e.q);
+      cpos.push_back(e.pos);
+      float kb;
+      std::memcpy(&kb, &e.k, 4);
+      en.push_back(make_float4(e.h, e.g, e.q, kb));
     }
     for (int j = 0; j < sz; ++j) cp[j + 1] += cp[j];
-    col.col_ptr.upload(cp); col.cut.upload(ck); col.pos.upload(cpos);
-    col.cH.upload(ch); col.cG.upload(cg); col.cQ.upload(cq);
+    std::vector<int2> rg(sz);
+    for (int j = 0; j < sz; ++j) rg[j] = make_int2(cp[j], cp[j + 1]);
+    col.rng.upload(rg); col.ent.upload(en); col.pos.upload(cpos);
     col.any = true;
   }
   *out = C.release();
@@ -780,7 +775,7 @@ void ensure_ws(Call& c) {
 }
 
 CutCol cut_col(const Call& c, int node) {
-  if (!c.cuts) return CutCol{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!c.cuts) return CutCol{nullptr, nullptr, nullptr};
   int idx = node < 0 ? (int)c.net->nodes.size() : node;
   return c.cuts->cols[idx].dev();
 }
@@ -1012,14 +1007,14 @@ struct BoundPass {
       ca.X = ws.lam[E.dst]->p; ca.ldx = dn.ld; ca.x_is_sign = 0;
       ca.Bt = bf16 ? E.WT16.p : E.WT32.p; ca.ldb = E.ldk_t;
       ca.mp = c.rp.mp; ca.partial = nullptr;
-      const int HW = cg.hi * cg.wi;
       const double M = c.M, esz = bf16 ? 2 : 4;
-      const double flops = 2.0 * M * HW * cg.ci * cg.co * cg.kh * cg.kw;
-      const double wbytes = (double)cg.ci * E.ldk_t * esz;
+      // every multiply-add of the forward conv appears once in its transpose
+      const double flops = 2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw;
+      const double wbytes = (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz;
       if (!last) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         if (!dry) {
-          int cfg = choose_cfg("convT", EPI_STORE, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW), [&](int cf) {
+          int cfg = choose_cfg("convT", EPI_STORE, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(), [&](int cf) {
             StoreEpiArgs t = s;
             t.acc_in = nullptr;
             t.out = tune_store(c);
@@ -1031,11 +1026,11 @@ struct BoundPass {
         }
         return;
       }
-      const int nslot = conv_slots(HW, cg.ci);
+      const int nslot = conv_slots(cg, 1);
       if (p >= 0) {
         BoundEpiArgs a = bound_args(p, has_acc);
         if (!dry) {
-          int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW),
+          int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(),
                                [&](int cf) { return launch_conv(bf16, cf, EPI_BOUND, ca, &a, c.st); });
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
@@ -1054,7 +1049,7 @@ struct BoundPass {
         a.contrib = want_contrib ? ws.contrib.as<float>() : nullptr;
         a.nnz_e = c.nnz;
         if (!dry) {
-          int cfg = choose_cfg("convT", EPI_CONC, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(HW),
+          int cfg = choose_cfg("convT", EPI_CONC, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(),
                                [&](int cf) { return launch_conv(bf16, cf, EPI_CONC, ca, &a, c.st); });
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
@@ -1196,7 +1191,7 @@ struct AdjPass {
         const double wbytes = (double)E.cg.co * E.ldk_f * esz;
         if (!last) {
           StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
-          int cfg = choose_cfg("conv", EPI_STORE, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(HW), [&](int cf) {
+          int cfg = choose_cfg("conv", EPI_STORE, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(), [&](int cf) {
             StoreEpiArgs t = s;
             t.acc_in = nullptr;
             t.out = tune_store(c);
@@ -1206,7 +1201,7 @@ struct AdjPass {
                       flops, [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
-          int cfg = choose_cfg("conv", EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(HW), [&](int cf) {
+          int cfg = choose_cfg("conv", EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(), [&](int cf) {
             AdjEpiArgs t = a;
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);

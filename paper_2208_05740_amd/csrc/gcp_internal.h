@@ -14,25 +14,23 @@ enum Cls : int8_t { INACTIVE = 0, ACTIVE = 1, UNSTABLE = 2 };
 struct NodeDev {
   int size;          // neurons
   int ld;            // row pitch of per-row activation buffers (multiple of 16)
-  const float* bias;     // [size]
-  const float* l;        // root lower bound (fp32, outward rounded)
-  const float* u;        // root upper bound
-  const float* inv_ul;   // 1 / (u - l) for unstable neurons, else 0
-  const int8_t* cls;     // root class
-  const int32_t* rank;   // column in an alpha row, or -1
+  // per neuron {l, u, 1/(u-l), bias}: root bounds (fp32, outward rounded),
+  // the reciprocal width for unstable neurons (else 0), the layer bias
+  const float4* rec;
+  const int32_t* kind;   // (rank + 1) * 4 + root class; rank = column in an alpha row, or -1
 };
+__host__ __device__ inline int kind_rank(int v) { return (v >> 2) - 1; }
+__host__ __device__ inline int kind_cls(int v) { return v & 3; }
 
 // Cut entries of one node in column (neuron) order: entries
-// col_ptr[j] .. col_ptr[j+1]-1 touch neuron j.  Each merged entry carries the
-// three coefficients of one (cut, node, neuron) and its position in the
-// cut-major order used by the gamma gradient.
+// rng[j].x .. rng[j].y-1 touch neuron j.  Each merged entry carries the
+// three coefficients of one (cut, node, neuron) and the cut index,
+// {cH, cG, cQ, cut as int bits}, and its position in the cut-major order
+// used by the gamma gradient.
 struct CutCol {
-  const int32_t* col_ptr;  // [size + 1], null if the node has no entries
-  const int32_t* cut;      // cut index
-  const int32_t* pos;      // position in cut-major order
-  const float* cH;
-  const float* cG;
-  const float* cQ;
+  const int2* rng;         // [size], null if the node has no entries
+  const float4* ent;
+  const int32_t* pos;
 };
 
 // Per-row parameters of one call.  Row-indexed internal buffers use the
@@ -139,11 +137,16 @@ hipError_t launch_adj_elementwise(int bf16, const AdjEpiArgs& a, hipStream_t st)
 
 // Convolution edges as implicit GEMMs on MFMA (conv_kernels.hip).
 struct ConvGeom { int ci, hi, wi, co, ho, wo, kh, kw, stride, pad; };
-// Bound direction (transposed conv): rows of Lambda over the node's
-// (co, ho, wo) -> epilogue over the source's (ci, hi, wi);
-// Bt = [ci][co*kh*kw] (ldb) rearranged weights.
-// Adjoint direction (conv): rows over the source's (ci, hi, wi) (operand type,
-// or int8 signs) -> epilogue over the node's (co, ho, wo); Bt = W [co][ci*kh*kw].
+// Bound direction (transposed conv): Lambda over the node's (co, ho, wo) ->
+// epilogue over the source's (ci, hi, wi).  The source positions split into
+// stride^2 phases by (y + pad) mod stride; in phase (ry, rx) only the taps
+// ky = ry + stride*a, kx = rx + stride*b meet the node grid, so
+// Bt = [phase][ci][ldb], entry (o, a, b) = W[o][c][ry + s a][rx + s b]
+// (0 past the kernel), K = co * ceil(kh/s) * ceil(kw/s) padded to ldb.
+// Adjoint direction (conv): rows over the source's (ci, hi, wi) (operand
+// type, or int8 signs) -> epilogue over the node's (co, ho, wo);
+// Bt = W [co][ldb], entry (c, ky, kx), K = ci*kh*kw padded to ldb.
+// ldb is a multiple of 32 in both.
 struct ConvArgs {
   int M;                  // batch rows
   ConvGeom cg;
@@ -152,11 +155,27 @@ struct ConvArgs {
   const void* Bt; int ldb;
   double* partial; int mp; int slot0;
 };
+// Work split of one conv launch: the epilogue-side rows form bands of BH
+// rows; one workgroup stages the source rows a band reads (with a zero halo)
+// in LDS for one batch row, produces every output of that band into a second
+// LDS buffer and runs the epilogue over it.
+struct ConvPlan {
+  int He, We, Nch, Kch, hs, ws;   // epilogue side (He x We, Nch channels), source side (Kch x hs x ws)
+  int s, p, A, Bn;                // stride, pad; taps per phase and dimension
+  int n_phase, Kreal, KP;         // phases; GEMM K per phase, padded
+  int BH, n_bands;
+  int rows_max, xl, Wp, CHS;      // LDS slab: rows per channel, left halo, pitch, channel stride
+  int OS;                         // LDS result band: channel stride
+  int MT;                         // most 16-row GEMM tiles in one band (phases padded to 16 rows)
+};
+ConvPlan conv_plan(const ConvGeom& g, int trans);
+// conv weights laid out as the kernels read them (Bt above); raw is [co][ci][kh][kw]
+int conv_ldb(const ConvGeom& g, int trans);
+void conv_pack_weights(const ConvGeom& g, int trans, const float* raw, float* out);
 hipError_t launch_conv(int bf16, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st);
 int conv_num_configs();
-void conv_config_tile(int cfg, int* bm, int* bn);
-// row-partial slots a conv launch owns: (epilogue-side positions / 16) * ceil(channels / 16)
-inline int conv_slots(int spatial, int channels) { return (spatial / 16) * ((channels + 15) / 16); }
+// row-partial slots a conv launch owns: one per band
+inline int conv_slots(const ConvGeom& g, int trans) { return conv_plan(g, trans).n_bands; }
 
 hipError_t launch_chat(const double* C, int S, int d_out, const float* W, int d_in,
                        int kind, float* chat, int ld, hipStream_t st);
