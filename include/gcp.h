@@ -210,17 +210,21 @@ typedef struct {
   double* bound; uint8_t* verified;
 } gcp_batch_item;
 
-/* gcp_optimize_batch: gcp_optimize of every item with the same settings and mode, but each Adam iteration of
- * all instances runs as a few grouped launches -- launches of the same kernel
- * at the same position of each instance's schedule become one launch whose
- * workgroups look up their instance in a device table -- instead of one
- * launch per layer per instance.  The first call with an argument set runs
- * iteration 0 per instance (tuning tiles, recording the schedule) and builds
- * the tables; calls with the same argument set reuse them.  With
- * opt->use_graph the grouped iteration is captured once and replayed.
- * Results equal per-instance gcp_optimize calls with the same tiles.  Every
- * item needs its own net handle; dense networks only (EUNSUPPORTED for conv
- * or identity edges).  Calls from several threads are serialised. */
+/* gcp_optimize_batch: gcp_optimize of every item with the same settings and mode.
+ * Instances large enough to fill the device with their own launches (batch
+ * rows x widest layer >= 2^20 elements; the environment variable
+ * GCP_BATCH_ALONE_WORK overrides the threshold) run exactly as gcp_optimize.
+ * The others run each Adam iteration as a few grouped launches -- launches
+ * of the same kernel at the same position of each instance's schedule become
+ * one launch whose workgroups look up their instance in a device table --
+ * instead of one launch per layer per instance.  The first call with an
+ * argument set runs iteration 0 per instance (tuning tiles, recording the
+ * schedule) and builds the tables; calls with the same argument set reuse
+ * them.  With opt->use_graph the grouped iteration is captured once and
+ * replayed.  Results equal per-instance gcp_optimize calls with the same
+ * tiles.  Every item needs its own net handle; grouped instances must be
+ * dense networks (EUNSUPPORTED for conv or identity edges).  Calls from
+ * several threads are serialised. */
 int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode, void* stream);
 
 /* ------------------------------------------------------------ profiling */

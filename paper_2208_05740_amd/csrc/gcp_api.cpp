@@ -1634,19 +1634,56 @@ void run_grouped_iteration(BatchPlan& plan, int* step, float* consts, const gcp_
 
 }  // namespace
 
-extern "C" int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode,
+namespace {
+// An instance whose widest layer holds at least this many (row, neuron)
+// elements fills the chip with its own launches (about four 32x32 tiles per
+// compute unit); grouping it with others only mixes more weights in the L2.
+// GCP_BATCH_ALONE_WORK overrides the threshold.
+long batch_alone_work() {
+  const char* e = std::getenv("GCP_BATCH_ALONE_WORK");
+  return e && *e ? std::atol(e) : (1L << 20);
+}
+long instance_work(const gcp_batch_item& it) {
+  if (!it.net || !it.splits) return 0;
+  int width = 0;
+  for (const NodeH& nd : it.net->nodes) width = std::max(width, nd.ld);
+  return (long)it.splits->B * it.S * width;
+}
+}  // namespace
+
+extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all, const gcp_opt* opt, int32_t mode,
                                   void* stream) {
   GCP_TRY
-  if (n <= 0 || !items) fail(GCP_EINVAL, "empty batch");
+  if (n_all <= 0 || !items_all) fail(GCP_EINVAL, "empty batch");
   if (!opt || opt->iters < 0) fail(GCP_EINVAL, "bad optimiser settings");
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < n_all; ++i)
+    for (int k = 0; k < i; ++k)
+      if (items_all[k].net == items_all[i].net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
+  // large instances: their own launches (the same kernels and tiles as gcp_optimize)
+  const long alone = batch_alone_work();
+  std::vector<gcp_batch_item> grouped;
+  for (int i = 0; i < n_all; ++i) {
+    const gcp_batch_item& it = items_all[i];
+    if (instance_work(it) < alone) {
+      grouped.push_back(it);
+      continue;
+    }
+    const int rc = gcp_optimize(it.net, it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha, it.beta, it.gamma,
+                                it.adam_state, opt, mode, it.bound, it.verified, stream);
+    if (rc != GCP_OK) return rc;
+  }
+  if (grouped.empty()) {
+    g_err.clear();
+    return GCP_OK;
+  }
+  const int n = (int)grouped.size();
+  const gcp_batch_item* items = grouped.data();
   std::vector<Call> calls(n);
   for (int i = 0; i < n; ++i) {
     const gcp_batch_item& it = items[i];
-    for (int k = 0; k < i; ++k)
-      if (items[k].net == it.net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
     if (!it.adam_state || !it.bound) fail(GCP_EINVAL, "null adam_state or bound");
     prepare_call(calls[i], const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
                  it.beta, it.gamma, stream);

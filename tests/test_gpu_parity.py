@@ -327,6 +327,34 @@ def test_batched_optimisation_equals_per_instance(mode):
             assert np.array_equal(it["gamma"].cpu().numpy(), c)
 
 
+def test_batched_optimisation_mixed_alone_and_grouped(monkeypatch):
+    # instances above the work threshold run their own launches, the rest are
+    # grouped; either way the results equal per-instance gcp_optimize
+    import torch
+    from paper_2208_05740_amd import binding as B
+    probs = gen.make_batch_config(seed=6, n_inst=6, bmax=48)
+    work = sorted(p.B * p.S * max((n.size + 15) // 16 * 16 for n in p.net.nodes) for p in probs)
+    thr = (work[2] + work[3]) // 2
+    assert work[0] < thr <= work[-1]
+    monkeypatch.setenv("GCP_BATCH_ALONE_WORK", str(thr))
+    Ps = [upload(p) for p in probs]
+    o = probs[0].opt
+    ref = []
+    for p, P in zip(probs, Ps):
+        g, a, b, c = _optimize(p, P, 1)
+        ref.append((g, a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()))
+    for graph in (False, True):
+        items = _batch_items(probs, Ps)
+        B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                         mode=1, use_graph=graph)
+        torch.cuda.synchronize()
+        for it, (g, a, b, c) in zip(items, ref):
+            assert np.array_equal(it["bound"].cpu().numpy(), g)
+            assert np.array_equal(it["alpha"].cpu().numpy(), a)
+            assert np.array_equal(it["beta"].cpu().numpy(), b)
+            assert np.array_equal(it["gamma"].cpu().numpy(), c)
+
+
 def test_batched_optimisation_certified_bound_matches_oracle():
     import torch
     from paper_2208_05740_amd import binding as B
