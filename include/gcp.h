@@ -148,6 +148,15 @@ int gcp_splits_destroy(gcp_splits* splits);
 #define GCP_MODE_BF16   1   /* GEMM operands bf16, fp32 accumulation          */
 #define GCP_FLAG_VALIDATE 0x100  /* check alpha/beta/gamma ranges on device
                                     (synchronises the stream)               */
+/* Pre-activation coefficients a_hat of every ReLU layer (Theorem 3.1) are
+ * needed again by the adjoint.  By default they are stored by the bound pass
+ * unless the stored copies of all layers would exceed GCP_AHAT_BUDGET_MB
+ * (environment, default 8192 MiB); then a layer whose a_hat comes from a
+ * single dense or conv consumer recomputes it in the adjoint from that
+ * consumer's Lambda (one more GEMM, one layer's a_hat live at a time).
+ * Results are identical either way.  The flags force one policy. */
+#define GCP_FLAG_RECOMPUTE   0x200  /* recompute a_hat wherever possible      */
+#define GCP_FLAG_STORE_AHAT  0x400  /* store a_hat of every layer             */
 /* In every mode the row reductions (concretisation v.x0 - eps*|v|_1, bias,
  * h and cut-offset sums, gamma.d) accumulate in fp64; the bound is fp64. */
 

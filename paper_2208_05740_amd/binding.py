@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libgcp.so")
 GCP_MODE_FP32 = 0
 GCP_MODE_BF16 = 1
 GCP_FLAG_VALIDATE = 0x100
+GCP_FLAG_RECOMPUTE = 0x200     # recompute a_hat in the adjoint wherever possible
+GCP_FLAG_STORE_AHAT = 0x400    # store a_hat of every layer
 EDGE_KIND = {"dense": 0, "conv": 1, "identity": 2}
 ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE", -6: "EUNSUPPORTED"}
 

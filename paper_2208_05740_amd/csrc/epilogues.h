@@ -246,6 +246,53 @@ struct BoundEpi {
   }
 };
 
+// ------------------------------------------------------------------ a_hat only
+// a_hat = GEMM + acc_in + gamma^T G recomputed for the adjoint instead of
+// stored by the bound pass: the same sum as BoundEpi forms, written to
+// a.ahat_out; nothing else is read or written.
+struct AhatEpi {
+  BoundEpiArgs a;
+  template <int R, int TN, bool PE> struct Frag {
+    int rc[R];
+    bool ev[TN][R];
+    float aoff[TN][R];
+  };
+  template <int R, int TN, bool PE>
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+    const RowParams& rp = a.rp;
+    int rr[R];
+    bool rv[R];
+    lane_rows<R, PE>(lc.r, M, rp.mp, rr, f.rc, rv);
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      int jq[R];
+      bool jv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        jv[q] = lc.j[k][GCP_QC(q)] < N;
+        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[q] && rv[q];
+      }
+      float sG[R], sH[R], sQ[R];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, rr, sG, sH, sQ);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * a.nd.ld + jq[GCP_QC(q)]] : 0.f;
+        f.aoff[k][q] = pre + sG[q];
+      }
+    }
+  }
+  template <int R, int TN, bool PE>
+  __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                               const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+#pragma unroll
+    for (int k = 0; k < TN; ++k)
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (f.ev[k][q]) a.ahat_out[(size_t)f.rc[q] * a.nd.ld + lc.j[k][GCP_QC(q)]] = val[k][q] + f.aoff[k][q];
+  }
+};
+
 // ------------------------------------------------------------------ concretisation
 // v = GEMM + gamma^T G0 over the input box: x0.v - eps*|v|_1 into the row
 // constant, sign(v) for the adjoint, input-cut gradient pieces.

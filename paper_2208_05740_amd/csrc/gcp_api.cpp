@@ -200,6 +200,7 @@ struct gcp_net {
     std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
     DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in, gammaT;
     DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
+    DBuf ahat_tmp;      // a_hat of the node being differentiated, when recomputed
     // captured Adam iteration of gcp_optimize (valid for one argument set)
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -727,6 +728,7 @@ struct Call {
   hipStream_t st;
   int nnz;
   int N;
+  std::vector<uint8_t> recompute;   // per node: a_hat recomputed in the adjoint instead of stored
 };
 
 void ensure_ws(Call& c) {
@@ -742,7 +744,7 @@ void ensure_ws(Call& c) {
     size_t elems = n.relu ? (size_t)M * n.ld : 0;
     auto mk = [&](size_t bytes) { auto b = std::make_unique<DBuf>(); b->alloc(bytes); return b; };
     ws.lam.push_back(mk(elems * 4));
-    ws.ahat.push_back(mk(elems * 4));
+    ws.ahat.push_back(mk(0));         // sized by plan_ahat: stored only where not recomputed
     ws.dahat.push_back(mk(elems * 4));
     bool ident = false;
     for (int eid : n.in_edges) ident |= net->edges[eid]->kind == GCP_EDGE_IDENTITY;
@@ -854,7 +856,8 @@ struct BoundPass {
     a.rp = c.rp;
     a.acc_in = has_acc ? ws.acc[p]->as<float>() : nullptr;
     a.lam_out = ws.lam[p]->p;
-    a.ahat_out = keep_ahat ? ws.ahat[p]->as<float>() : nullptr;
+    const bool rec = !c.recompute.empty() && c.recompute[p];
+    a.ahat_out = (keep_ahat && !rec) ? ws.ahat[p]->as<float>() : nullptr;
     return a;
   }
 
@@ -1120,10 +1123,54 @@ struct AdjPass {
     for (int i = 0; i < c.net->out; ++i) node(i);
   }
 
+  // a_hat of node i again from its consumer's Lambda: the bound pass's GEMM
+  // (same operands, same tile configuration) with only the a_hat epilogue
+  void recompute_ahat(int i) {
+    gcp_net* net = c.net;
+    auto& ws = net->ws;
+    if (c.rec) fail(GCP_EUNSUPPORTED, "a_hat recomputation in grouped launches");
+    const NodeH& n = net->nodes[i];
+    const EdgeH& E = *net->edges[n.consumers[0]];
+    const NodeH& dn = net->nodes[E.dst];
+    BoundEpiArgs a{};
+    a.nd = n.dev();
+    a.cc = cut_col(c, i);
+    a.rp = c.rp;
+    a.ahat_out = ws.ahat_tmp.as<float>();
+    const double M = c.M, esz = bf16 ? 2 : 4;
+    if (E.kind == GCP_EDGE_DENSE) {
+      GemmArgs g{};
+      g.M = c.M; g.N = E.d_src; g.K = dn.size;
+      g.A = ws.lam[E.dst]->p; g.lda = dn.ld;
+      g.Bt = wt_bound(E, bf16); g.ldb = dn.ld;
+      g.mp = c.rp.mp;
+      const int cfg = choose_cfg("gemm", EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
+                                 [&](int cf) { return launch_gemm(bf16, cf, EPI_AHAT, g, &a, c.st); });
+      const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * g.N * 4 + M * nnz_of(c, i) * 4;
+      check(timed(c.st, cls_name("ahat", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+                  [&] { return launch_gemm(bf16, cfg, EPI_AHAT, g, &a, c.st); }));
+    } else {
+      ConvArgs ca{};
+      ca.M = c.M; ca.cg = E.cg; ca.trans = 1;
+      ca.X = ws.lam[E.dst]->p; ca.ldx = dn.ld; ca.x_is_sign = 0;
+      ca.Bt = bf16 ? E.WT16.p : E.WT32.p; ca.ldb = E.ldk_t;
+      ca.mp = c.rp.mp; ca.partial = nullptr;
+      const ConvGeom& cg = E.cg;
+      const int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, E.d_src, dn.size, c.st, conv_cands(),
+                                 [&](int cf) { return launch_conv(bf16, cf, EPI_AHAT, ca, &a, c.st); });
+      const double bytes = M * dn.size * esz + (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz +
+                           M * E.d_src * 4 + M * nnz_of(c, i) * 4;
+      check(timed(c.st, cls_name("convT_ahat", bf16, 0, -1), bytes,
+                  2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw,
+                  [&] { return launch_conv(bf16, cfg, EPI_AHAT, ca, &a, c.st); }));
+    }
+  }
+
   void node(int i) {
     gcp_net* net = c.net;
     auto& ws = net->ws;
     const NodeH& n = net->nodes[i];
+    if (!c.recompute.empty() && c.recompute[i]) recompute_ahat(i);
     std::vector<int> order;   // identity edges first: they can only accumulate
     for (int eid : n.in_edges)
       if (net->edges[eid]->kind == GCP_EDGE_IDENTITY) order.push_back(eid);
@@ -1235,7 +1282,7 @@ struct AdjPass {
     a.acc_in = acc_in;
     a.gemm_scale = scale;
     a.add_vec = ws.addv[i]->as<float>();
-    a.ahat = ws.ahat[i]->as<float>();
+    a.ahat = c.recompute.empty() || !c.recompute[i] ? ws.ahat[i]->as<float>() : ws.ahat_tmp.as<float>();
     a.dahat_out = ws.dahat[i]->p;
     a.contrib = c.nnz ? ws.contrib.as<float>() : nullptr;
     a.nnz_e = c.nnz;
@@ -1275,6 +1322,49 @@ void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const dou
   ensure_ws(c);
   c.rp = RowParams{c.M, S, round_up(c.M, 16), alpha, net->n_I, beta, splits->K, net->ws.gammaT.as<float>(), N,
                    splits->K > 0 ? splits->mask.as<int8_t>() : nullptr};
+}
+
+// Which nodes recompute a_hat in the adjoint (Theorem 3.1 needs a_hat of
+// every ReLU layer there): a node whose a_hat comes from a single dense or
+// conv consumer can rebuild it from that consumer's stored Lambda with one
+// more GEMM, so only one layer's a_hat is live at a time instead of all of
+// them.  GCP_FLAG_RECOMPUTE forces it, GCP_FLAG_STORE_AHAT disables it;
+// otherwise it is used when the stored a_hat of all layers would exceed
+// GCP_AHAT_BUDGET_MB (default 8192 MiB).  Sizes the buffers either way.
+bool ahat_recomputable(const gcp_net* net, int i) {
+  const NodeH& n = net->nodes[i];
+  if (!n.relu || n.consumers.size() != 1) return false;
+  const EdgeH& E = *net->edges[n.consumers[0]];
+  return (E.kind == GCP_EDGE_DENSE || E.kind == GCP_EDGE_CONV) && E.dst != net->out;
+}
+void plan_ahat(Call& c, int32_t mode) {
+  gcp_net* net = c.net;
+  auto& ws = net->ws;
+  const int nn = (int)net->nodes.size();
+  size_t stored = 0;
+  for (int i = 0; i < nn; ++i)
+    if (net->nodes[i].relu) stored += (size_t)c.M * net->nodes[i].ld * 4;
+  const char* e = std::getenv("GCP_AHAT_BUDGET_MB");
+  const double budget = (e && *e ? std::atof(e) : 8192.0) * 1048576.0;
+  const bool want = (mode & GCP_FLAG_RECOMPUTE) || (!(mode & GCP_FLAG_STORE_AHAT) && (double)stored > budget);
+  c.recompute.assign(nn, 0);
+  size_t tmp = 0;
+  for (int i = 0; i < nn; ++i) {
+    const NodeH& n = net->nodes[i];
+    if (!n.relu) continue;
+    const size_t bytes = (size_t)c.M * n.ld * 4;
+    if (want && ahat_recomputable(net, i)) {
+      c.recompute[i] = 1;
+      tmp = std::max(tmp, bytes);
+    } else if (ws.ahat[i]->bytes < bytes) {
+      ws.ahat[i]->alloc(bytes);
+      ws.gen = next_generation();
+    }
+  }
+  if (ws.ahat_tmp.bytes < tmp) {
+    ws.ahat_tmp.alloc(tmp);
+    ws.gen = next_generation();
+  }
 }
 
 void size_partials(Call& c, int bf16, bool keep, bool contrib) {
@@ -1337,6 +1427,7 @@ extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, con
   }
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
   if (c.N > 0) hip_check(launch_transpose(gamma, c.M, c.N, c.N, net->ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
+  if (grads) plan_ahat(c, mode);
   bound_pass(c, bf16, grads, grads && c.nnz > 0, bound, verified);
   if (grads) {
     if (splits->K > 0) hip_check(launch_fill_f32(d_beta, (int64_t)c.M * splits->K, 0.f, c.st), "fill");
@@ -1371,6 +1462,7 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
   if (!adam_state) fail(GCP_EINVAL, "null adam_state");
   if (!bound) fail(GCP_EINVAL, "null bound output");
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
+  plan_ahat(c, mode);
   auto& ws = net->ws;
   const size_t M = c.M, nI = c.rp.n_I, K = c.rp.K, N = c.rp.N;
   float* ma = adam_state;
@@ -1413,6 +1505,7 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
                                   (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)adam_state,
                                   (uintptr_t)S, (uintptr_t)bf16, (uintptr_t)c.M,
                                   (uintptr_t)std::hash<double>()(eps), (uintptr_t)ws.gen};
+    for (uint8_t r : c.recompute) key.push_back(r);
     for (float v : {opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, opt->adam_eps}) {
       uint32_t b;
       std::memcpy(&b, &v, 4);
@@ -1688,6 +1781,7 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     prepare_call(calls[i], const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
                  it.beta, it.gamma, stream);
     if (mode & GCP_FLAG_VALIDATE) validate_params(calls[i], it.alpha, it.beta, it.gamma);
+    plan_ahat(calls[i], GCP_FLAG_STORE_AHAT);   // grouped launches replay a stored schedule
   }
   std::lock_guard<std::mutex> lk(g_batch_mu);
   // shared Adam counter and constants: the first instance's workspace

@@ -54,7 +54,7 @@ struct AdamArgs {
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 
 // Epilogue selection for the tile GEMM.
-enum EpiKind { EPI_STORE = 0, EPI_BOUND = 1, EPI_CONC = 2, EPI_ADJ = 3 };
+enum EpiKind { EPI_STORE = 0, EPI_BOUND = 1, EPI_CONC = 2, EPI_ADJ = 3, EPI_AHAT = 4 };
 
 struct BoundEpiArgs {       // Theorem 3.1 relaxation of one ReLU node
   NodeDev nd; CutCol cc; RowParams rp;
@@ -62,6 +62,8 @@ struct BoundEpiArgs {       // Theorem 3.1 relaxation of one ReLU node
   void* lam_out;            // [M][ld] in the GEMM operand type
   float* ahat_out;          // optional [M][ld] fp32 (kept for the adjoint)
 };
+// EPI_AHAT (recomputing a_hat for the adjoint) takes BoundEpiArgs and writes
+// only ahat_out.
 struct ConcEpiArgs {        // concretisation over the input box
   int size, ld;
   const double* x0; double eps;

@@ -327,6 +327,30 @@ def test_batched_optimisation_equals_per_instance(mode):
             assert np.array_equal(it["gamma"].cpu().numpy(), c)
 
 
+@pytest.mark.parametrize("kind,mode", [("mlp", 1), ("mlp", 0), ("cnn16", 1), ("res16", 1), ("res16", 0)])
+def test_recomputed_ahat_equals_stored(kind, mode):
+    # a_hat rebuilt in the adjoint from the consumer's Lambda (same GEMM, same
+    # tiles) must give exactly the results of storing it in the bound pass
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny(kind, 1, B=5, splits=(1, 3), n_cuts=6)
+    P = upload(p)
+    o = p.opt
+    outs = []
+    for flag in (B.GCP_FLAG_STORE_AHAT, B.GCP_FLAG_RECOMPUTE):
+        a, b, c, *_ = params(p, P)
+        st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+        g, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=5,
+                          lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], mode=mode | flag)
+        a2, b2, c2, *_ = params(p, P)
+        _, _, grads = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a2, b2, c2, mode=mode | flag, grads=True)
+        torch.cuda.synchronize()
+        outs.append([g.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()] +
+                    [x.cpu().numpy() for x in grads])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
 def test_batched_optimisation_mixed_alone_and_grouped(monkeypatch):
     # instances above the work threshold run their own launches, the rest are
     # grouped; either way the results equal per-instance gcp_optimize
