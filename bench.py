@@ -159,6 +159,8 @@ def main():
     if kprof:
         out["roofline"] = roofline(kprof, args.mode)
         out["roofline"]["instrumented_ms_per_step"] = dt_prof * 1000.0 / args.steps
+        if out["roofline"]["bound"] == "hbm":
+            out["roofline"]["achievable_copy_GBps"] = copy_bandwidth()
         out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
                                     for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     if not args.no_compare:
@@ -175,6 +177,26 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline([prob], args.cpu_domains)
     print(json.dumps(out))
+
+
+def copy_bandwidth(mib=2048, reps=5):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of `mib` MiB (read + write bytes over the best of `reps` event-timed runs)."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None or ms < best else best
+    del src, dst
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
 
 
 def roofline(kprof, dtype):

@@ -82,7 +82,7 @@ typedef struct {
 
 typedef struct {
   int32_t in_c, in_h, in_w;
-  int32_t n_nodes;               /* >= 2: at least one ReLU node + output   */
+  int32_t n_nodes;               /* >= 1: ReLU nodes, then the output        */
   const gcp_node_desc* nodes;    /* topological order: edges point backward */
 } gcp_net_desc;
 
@@ -206,6 +206,24 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  float* alpha, float* beta, float* gamma, float* adam_state,
                  const gcp_opt* opt, int32_t mode,
                  double* bound, uint8_t* verified, void* stream);
+
+/* ------------------------------------------------------------ intermediate bounds */
+/* gcp_crown_bounds: pre-activation bounds l, u of every ReLU node of the
+ * network `desc` (its lower/upper fields are ignored) over the L-inf box
+ * ||x - x0|| <= eps, computed on the device layer by layer with CROWN
+ * (Theorem 3.1 with beta = gamma = 0 and no splits): for node k the prefix
+ * network ending at node k's pre-activation is bounded with spec rows +e_j
+ * and -e_j by gcp_bound, the ReLU nodes before k using the bounds already
+ * found and CROWN-adaptive lower slopes (alpha = 1 where u >= -l, else 0).
+ * The first node's bounds are the exact concretisation of its affine map.
+ * x0: device fp64 [d_0].  lower[k], upper[k]: host fp64 arrays of node k's
+ * size for every ReLU node k (k < n_nodes - 1), written on success; their
+ * values can be passed as the root bounds of gcp_net_create.  mode: the
+ * GEMM precision (GCP_MODE_FP32 recommended: the bounds are then computed
+ * like a certifying pass).  Synchronises `stream`.  Errors: as gcp_net_create
+ * and gcp_bound. */
+int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, double eps, double* const* lower,
+                     double* const* upper, int32_t mode, void* stream);
 
 /* ------------------------------------------------------------ batching */
 /* One verification instance of a batched optimisation: the arguments of

@@ -52,3 +52,34 @@ def crown_bound(net, lu, x0, eps, c, alpha_per_node):
         spread(node, lam)
     w = coef.get(-1, np.zeros(net.in_size))
     return float(w @ x0 - eps * np.abs(w).sum() + const)
+
+
+def crown_intermediate_bounds(net, x0, eps, lu_given=None):
+    """Layer-by-layer CROWN bounds on every ReLU node's pre-activation
+    (intermediate bounds of Sec. 2, computed as in CROWN: the bounds of node k
+    are the CROWN bounds of the prefix network that ends at node k's
+    pre-activation, for the spec rows +e_j and -e_j, with the bounds of the
+    earlier nodes and CROWN-adaptive lower slopes alpha = 1 where u >= -l,
+    else 0).  Returns [(l, u)] per ReLU node.
+
+    With lu_given, node k uses lu_given[:k] for the earlier nodes instead of
+    its own results (to compare one layer at a time with another
+    implementation)."""
+    import dataclasses
+
+    relu = [i for i, n in enumerate(net.nodes) if n.relu]
+    lu = []
+    for pos, k in enumerate(relu):
+        node = net.nodes[k]
+        prev = list(lu_given[:pos]) if lu_given is not None else list(lu)
+        prefix = type(net)(net.in_shape, list(net.nodes[:k]) + [dataclasses.replace(node, relu=False)])
+        apn = [np.where(u >= -l, 1.0, 0.0) for l, u in prev]
+        lo = np.empty(node.size)
+        hi = np.empty(node.size)
+        for j in range(node.size):
+            e = np.zeros(node.size)
+            e[j] = 1.0
+            lo[j] = crown_bound(prefix, prev, x0, eps, e, apn)
+            hi[j] = -crown_bound(prefix, prev, x0, eps, -e, apn)
+        lu.append((lo, hi))
+    return lu

@@ -68,7 +68,7 @@ class BatchItem(C.Structure):
 _LIB = None
 EXPORTS = ["gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
            "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_optimize_batch",
-           "gcp_profile_enable", "gcp_profile_read", "gcp_last_error", "gcp_version"]
+           "gcp_crown_bounds", "gcp_profile_enable", "gcp_profile_read", "gcp_last_error", "gcp_version"]
 
 
 def lib():
@@ -90,6 +90,7 @@ def lib():
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
     L.gcp_optimize_batch.argtypes = [i32, C.POINTER(BatchItem), C.POINTER(OptDesc), i32, vp]
+    L.gcp_crown_bounds.argtypes = [C.POINTER(NetDesc), vp, dbl, C.POINTER(vp), C.POINTER(vp), i32, vp]
     L.gcp_profile_enable.argtypes = [i32]
     L.gcp_profile_read.argtypes = [i32, C.c_char_p, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -97,7 +98,7 @@ def lib():
     L.gcp_version.restype = C.c_char_p
     for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
               "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
-              "gcp_profile_read", "gcp_optimize_batch"):
+              "gcp_profile_read", "gcp_optimize_batch", "gcp_crown_bounds"):
         getattr(L, f).restype = C.c_int
     _LIB = L
     return L
@@ -122,47 +123,54 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _net_desc(net, lu):
+    """gcp_net_desc of a workloads.Net (root bounds from lu, or none); returns
+    the descriptor and the host arrays it points into."""
+    keep = []
+
+    def f32(a):
+        a = np.ascontiguousarray(a, np.float32)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def f64(a):
+        a = np.ascontiguousarray(a, np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    nodes = (NodeDesc * len(net.nodes))()
+    relu_pos = 0
+    edge_arrays = []
+    for i, n in enumerate(net.nodes):
+        shape = tuple(n.shape) if len(n.shape) == 3 else (n.size, 1, 1)
+        edges = (EdgeDesc * len(n.edges))()
+        for k, e in enumerate(n.edges):
+            edges[k].src = e.src
+            edges[k].kind = EDGE_KIND[e.kind]
+            if e.W is not None:
+                edges[k].W = f32(e.W)
+            if e.kind == "conv":
+                edges[k].kh, edges[k].kw = e.W.shape[2], e.W.shape[3]
+            edges[k].stride, edges[k].pad = e.stride, e.pad
+        edge_arrays.append(edges)
+        nodes[i].c, nodes[i].h, nodes[i].w = shape
+        nodes[i].bias = f32(n.bias)
+        if n.relu and lu is not None:
+            nodes[i].lower = f64(lu[relu_pos][0])
+            nodes[i].upper = f64(lu[relu_pos][1])
+            relu_pos += 1
+        nodes[i].n_edges = len(n.edges)
+        nodes[i].edges = edges
+    ins = tuple(net.in_shape) if len(net.in_shape) == 3 else (net.in_size, 1, 1)
+    keep += [nodes, edge_arrays]
+    return NetDesc(ins[0], ins[1], ins[2], len(net.nodes), nodes), keep
+
+
 class Net:
     """Device copy of a workloads.Net with its root bounds."""
 
     def __init__(self, net, lu):
-        keep = []
-
-        def f32(a):
-            a = np.ascontiguousarray(a, np.float32)
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_float))
-
-        def f64(a):
-            a = np.ascontiguousarray(a, np.float64)
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_double))
-
-        nodes = (NodeDesc * len(net.nodes))()
-        relu_pos = 0
-        edge_arrays = []
-        for i, n in enumerate(net.nodes):
-            shape = tuple(n.shape) if len(n.shape) == 3 else (n.size, 1, 1)
-            edges = (EdgeDesc * len(n.edges))()
-            for k, e in enumerate(n.edges):
-                edges[k].src = e.src
-                edges[k].kind = EDGE_KIND[e.kind]
-                if e.W is not None:
-                    edges[k].W = f32(e.W)
-                if e.kind == "conv":
-                    edges[k].kh, edges[k].kw = e.W.shape[2], e.W.shape[3]
-                edges[k].stride, edges[k].pad = e.stride, e.pad
-            edge_arrays.append(edges)
-            nodes[i].c, nodes[i].h, nodes[i].w = shape
-            nodes[i].bias = f32(n.bias)
-            if n.relu:
-                nodes[i].lower = f64(lu[relu_pos][0])
-                nodes[i].upper = f64(lu[relu_pos][1])
-                relu_pos += 1
-            nodes[i].n_edges = len(n.edges)
-            nodes[i].edges = edges
-        ins = tuple(net.in_shape) if len(net.in_shape) == 3 else (net.in_size, 1, 1)
-        desc = NetDesc(ins[0], ins[1], ins[2], len(net.nodes), nodes)
+        desc, keep = _net_desc(net, lu)
         h = C.c_void_p()
         _check(lib().gcp_net_create(C.byref(desc), C.byref(h)))
         self.h = h
@@ -175,6 +183,20 @@ class Net:
         if getattr(self, "h", None) and _LIB is not None:
             _LIB.gcp_net_destroy(self.h)
             self.h = None
+
+
+def crown_bounds(net, x0, eps: float, mode: int = GCP_MODE_FP32):
+    """gcp_crown_bounds: CROWN pre-activation bounds of every ReLU node of a
+    workloads.Net over the box around x0 (a device fp64 tensor), computed on
+    the device; returns [(l, u)] as host fp64 arrays, one pair per ReLU node."""
+    desc, keep = _net_desc(net, None)
+    relu = [n for n in net.nodes if n.relu]
+    lo = [np.empty(n.size, np.float64) for n in relu]
+    hi = [np.empty(n.size, np.float64) for n in relu]
+    lp = (C.c_void_p * len(relu))(*[a.ctypes.data for a in lo])
+    up = (C.c_void_p * len(relu))(*[a.ctypes.data for a in hi])
+    _check(lib().gcp_crown_bounds(C.byref(desc), _ptr(x0), float(eps), lp, up, mode, _stream()))
+    return list(zip(lo, hi))
 
 
 class Cuts:

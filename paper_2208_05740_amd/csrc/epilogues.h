@@ -174,38 +174,49 @@ struct BoundEpi {
     int rr[R];
     bool rv[R];
     lane_rows<R, PE>(lc.r, M, rp.mp, rr, f.rc, rv);
+    // issue order: loads that need no other load first, then those addressed
+    // by the neuron's rank or split slot, then the cut gathers
+    int jq[TN][R], kv[TN][PE ? R : 1];
+    bool jv[TN][R];
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
-      int jq[R];
-      bool jv[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        jv[q] = lc.j[k][GCP_QC(q)] < N;
-        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
-        f.ev[k][q] = jv[q] && rv[q];
+        jv[k][q] = lc.j[k][GCP_QC(q)] < N;
+        jq[k][q] = jv[k][q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[k][q] && rv[q];
       }
-      int kv[PE ? R : 1];
 #pragma unroll
       for (int q = 0; q < (PE ? R : 1); ++q) {
-        const int j = jq[q];
+        const int j = jq[k][q];
         const float4 nr = nd.rec[j];
         f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.bj[k][q] = nr.w;
-        kv[q] = nd.kind[j];
+        kv[k][q] = nd.kind[j];
       }
-      float sG[R], sH[R];
-      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, rr, sG, sH, f.sQ[k]);
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        f.aoff[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + jq[k][GCP_QC(q)]] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < TN; ++k)
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const int j = jq[GCP_QC(q)];
-        const int rk = kind_rank(kv[GCP_QC(q)]);
+        const int rk = kind_rank(kv[k][GCP_QC(q)]);
         int c, slot;
-        split_class<R>(rp, rk, kind_cls(kv[GCP_QC(q)]), f.rc[q], &c, &slot);
-        const float pre = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
-        f.aoff[k][q] = pre + sG[q];
+        split_class<R>(rp, rk, kind_cls(kv[k][GCP_QC(q)]), f.rc[q], &c, &slot);
         f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
         const float bv = slot >= 0 ? rp.beta[(size_t)f.rc[q] * rp.K + slot] : 0.f;
-        f.tadd[k][q] = sH[q] + (c == ACTIVE ? -bv : (c == INACTIVE ? bv : 0.f));
+        f.tadd[k][q] = c == ACTIVE ? -bv : (c == INACTIVE ? bv : 0.f);   // split term
         f.c[k][q] = (int8_t)c;
+      }
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      float sG[R], sH[R];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], rr, sG, sH, f.sQ[k]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        f.aoff[k][q] = f.aoff[k][q] + sG[q];     // acc_in + gamma^T G
+        f.tadd[k][q] = sH[q] + f.tadd[k][q];     // gamma^T H + split term
       }
     }
   }
@@ -373,35 +384,40 @@ struct AdjEpi {
     bool rv[R];
     lane_rows<R, PE>(lc.r, M, rp.mp, f.rr, f.rc, rv);
     const bool adam = a.adam.enabled;
+    // issue order: loads that need no other load first, then those addressed
+    // by the neuron's rank, then the cut gathers
+    int jq[TN][R], kv[TN][PE ? R : 1];
+    bool jv[TN][R];
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
-      int jq[R];
-      bool jv[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        jv[q] = lc.j[k][GCP_QC(q)] < N;
-        jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
-        f.ev[k][q] = jv[q] && rv[q];
+        jv[k][q] = lc.j[k][GCP_QC(q)] < N;
+        jq[k][q] = jv[k][q] ? lc.j[k][GCP_QC(q)] : 0;
+        f.ev[k][q] = jv[k][q] && rv[q];
       }
-      int kv[PE ? R : 1];
 #pragma unroll
       for (int q = 0; q < (PE ? R : 1); ++q) {
-        const int j = jq[q];
+        const int j = jq[k][q];
         const float4 nr = nd.rec[j];
         f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.addj[k][q] = a.add_vec[j];
-        kv[q] = nd.kind[j];
+        kv[k][q] = nd.kind[j];
       }
-      float sG[R], sH[R];
-      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq, jv, f.rr, sG, sH, f.sQ[k]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const int j = jq[GCP_QC(q)];
-        const int rk = kind_rank(kv[GCP_QC(q)]);
-        int c, slot;
-        split_class<R>(rp, rk, kind_cls(kv[GCP_QC(q)]), f.rc[q], &c, &slot);
-        f.rk[k][q] = rk;
+        const int j = jq[k][GCP_QC(q)];
         f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
         f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TN; ++k)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int rk = kind_rank(kv[k][GCP_QC(q)]);
+        int c, slot;
+        split_class<R>(rp, rk, kind_cls(kv[k][GCP_QC(q)]), f.rc[q], &c, &slot);
+        f.rk[k][q] = rk;
         const size_t ia = (size_t)f.rc[q] * rp.n_I + (rk >= 0 ? rk : 0);
         f.al[k][q] = rk >= 0 ? rp.alpha[ia] : 0.f;
         f.ma[k][q] = (rk >= 0 && adam) ? a.m_alpha[ia] : 0.f;
@@ -409,6 +425,10 @@ struct AdjEpi {
         f.c[k][q] = (int8_t)c;
         f.slot[k][q] = (int8_t)slot;
       }
+#pragma unroll
+    for (int k = 0; k < TN; ++k) {
+      float sG[R], sH[R];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], f.rr, sG, sH, f.sQ[k]);
     }
   }
   template <int R, int TN, bool PE>

@@ -194,6 +194,12 @@ struct gcp_net {
   int out = 0;
   // input consumers (edges with src = -1)
   std::vector<int> in_consumers;
+  // the output's Lambda (= C) is materialised and pushed like any node's,
+  // instead of the c-hat shortcut (C W precomputed, fused relaxation of the
+  // nodes feeding the output): needed for conv edges into the output, an
+  // output fed by the input, or a node feeding the output that has other
+  // consumers
+  bool out_general = false;
   // ---- workspace (grown on demand)
   struct WS {
     int M = 0, S = 0, nnz = 0, N = 0;
@@ -275,7 +281,7 @@ int node_ld_of(const gcp_net* net, int src) { return src < 0 ? net->in_ld : net-
 
 void build_net(const gcp_net_desc* d, gcp_net* net) {
   if (!d || !d->nodes) fail(GCP_EINVAL, "null network description");
-  if (d->n_nodes < 2) fail(GCP_EINVAL, "a network needs at least one ReLU node and an output node");
+  if (d->n_nodes < 1) fail(GCP_EINVAL, "a network needs an output node");
   if (d->in_c <= 0 || d->in_h <= 0 || d->in_w <= 0) fail(GCP_EINVAL, "bad input shape");
   hip_check(hipGetDevice(&net->device), "hipGetDevice");
   net->in_c = d->in_c; net->in_h = d->in_h; net->in_w = d->in_w;
@@ -398,16 +404,17 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
   for (int i = 0; i < net->out; ++i)
     if (net->nodes[i].consumers.empty()) fail(GCP_EUNSUPPORTED, "ReLU node without consumers");
   if (net->in_consumers.empty()) fail(GCP_EINVAL, "network input is unused");
+  const char* og = std::getenv("GCP_OUT_GENERAL");
+  net->out_general = og && *og && std::atoi(og) != 0;
   for (int eid : net->nodes[net->out].in_edges) {
     const EdgeH& E = *net->edges[eid];
-    if (E.kind == GCP_EDGE_CONV) fail(GCP_EUNSUPPORTED, "conv edge into the output node");
-    if (E.src < 0) fail(GCP_EUNSUPPORTED, "output node fed directly by the input");
+    if (E.kind == GCP_EDGE_CONV || E.src < 0) net->out_general = true;
   }
   for (int i = 0; i < net->out; ++i) {
     const NodeH& n = net->nodes[i];
     int outs = 0;
     for (int eid : n.consumers) outs += (net->edges[eid]->dst == net->out);
-    if (outs && n.consumers.size() > 1) fail(GCP_EUNSUPPORTED, "node feeding the output has other consumers");
+    if (outs && n.consumers.size() > 1) net->out_general = true;
   }
 }
 
@@ -741,7 +748,7 @@ void ensure_ws(Call& c) {
   ws.lam.clear(); ws.ahat.clear(); ws.dahat.clear(); ws.acc.clear(); ws.addv.clear();
   for (int i = 0; i < nn; ++i) {
     const NodeH& n = net->nodes[i];
-    size_t elems = n.relu ? (size_t)M * n.ld : 0;
+    size_t elems = (n.relu || (i == net->out && net->out_general)) ? (size_t)M * n.ld : 0;
     auto mk = [&](size_t bytes) { auto b = std::make_unique<DBuf>(); b->alloc(bytes); return b; };
     ws.lam.push_back(mk(elems * 4));
     ws.ahat.push_back(mk(0));         // sized by plan_ahat: stored only where not recomputed
@@ -759,11 +766,12 @@ void ensure_ws(Call& c) {
   ws.gammaT.alloc((size_t)mp * std::max(Nc, 1) * 4);
   ws.chat_off.assign(nn, -1);
   size_t chat_floats = 0;
-  for (int eid : net->nodes[net->out].in_edges) {
-    int p = net->edges[eid]->src;
-    ws.chat_off[p] = (int)chat_floats;
-    chat_floats += (size_t)S * net->nodes[p].ld;
-  }
+  if (!net->out_general)
+    for (int eid : net->nodes[net->out].in_edges) {
+      int p = net->edges[eid]->src;
+      ws.chat_off[p] = (int)chat_floats;
+      chat_floats += (size_t)S * net->nodes[p].ld;
+    }
   ws.chat.alloc(std::max<size_t>(chat_floats, 1) * 4);
   ws.cb.alloc((size_t)S * 8);
   ws.consts.alloc(16);
@@ -872,7 +880,19 @@ struct BoundPass {
     pushes_left[nn] = (int)net->in_consumers.size();
     // output node: c-hat = C W (per spec row), constant C b_out
     const NodeH& on = net->nodes[net->out];
-    if (!dry && !c.rec) {
+    if (net->out_general) {
+      // Lambda^(out) = C on every row, pushed through the output's edges
+      if (c.rec) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
+      if (!dry) {
+        check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
+        check(launch_spec_rows(bf16, c.C, c.S, on.size, c.M, ws.lam[net->out]->p, on.ld, c.st));
+      }
+      for (int eid : on.in_edges)
+        if (net->edges[eid]->kind == GCP_EDGE_IDENTITY) push(eid);
+      for (int eid : on.in_edges)
+        if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) push(eid);
+    }
+    if (!net->out_general && !dry && !c.rec) {
       check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
       for (int eid : on.in_edges) {
         const EdgeH& E = *net->edges[eid];
@@ -881,7 +901,7 @@ struct BoundPass {
                           E.kind == GCP_EDGE_IDENTITY ? 2 : 0, ch, net->nodes[E.src].ld, c.st));
       }
     }
-    for (int eid : on.in_edges) {
+    for (int eid : net->out_general ? std::vector<int>{} : on.in_edges) {
       const EdgeH& E = *net->edges[eid];
       int p = E.src;
       // the output is p's only consumer (checked at creation): fused relaxation
@@ -1589,6 +1609,7 @@ namespace {
 void launch_constants(Call& c) {
   gcp_net* net = c.net;
   auto& ws = net->ws;
+  if (net->out_general) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
   const NodeH& on = net->nodes[net->out];
   hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");
   for (int eid : on.in_edges) {
@@ -1892,6 +1913,106 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     if (c.rp.N > 0)
       hip_check(launch_transpose(c.net->ws.gammaT.as<float>(), c.rp.N, c.M, c.rp.mp, items[i].gamma, c.rp.N, st),
                 "transpose");
+  }
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+// ====================================================================== intermediate bounds
+
+namespace {
+// Owning wrappers for the handles used by gcp_crown_bounds.
+struct NetGuard { gcp_net* p = nullptr; ~NetGuard() { if (p) gcp_net_destroy(p); } };
+struct SplitsGuard { gcp_splits* p = nullptr; ~SplitsGuard() { if (p) gcp_splits_destroy(p); } };
+}  // namespace
+
+extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, double eps, double* const* lower,
+                                double* const* upper, int32_t mode, void* stream) {
+  GCP_TRY
+  if (!desc || !desc->nodes || desc->n_nodes < 2) fail(GCP_EINVAL, "bad network description");
+  if (!x0) fail(GCP_EINVAL, "null x0");
+  if (!lower || !upper) fail(GCP_EINVAL, "null bound outputs");
+  if ((mode & 0xff) != GCP_MODE_FP32 && (mode & 0xff) != GCP_MODE_BF16) fail(GCP_EINVAL, "unknown mode");
+  const int out = desc->n_nodes - 1;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<double>> L(out), U(out);
+  std::vector<gcp_node_desc> nodes(desc->nodes, desc->nodes + desc->n_nodes);
+  constexpr int kRowsPerCall = 4096;
+  for (int k = 0; k < out; ++k) {
+    const gcp_node_desc& nk = desc->nodes[k];
+    const int d = nk.c * nk.h * nk.w;
+    if (d <= 0) fail(GCP_EINVAL, "bad node shape");
+    if (!lower[k] || !upper[k]) fail(GCP_EINVAL, "null bound output of node " + std::to_string(k));
+    // the prefix network: nodes 0..k with node k as its output (the
+    // pre-activation), earlier nodes carrying the bounds found so far
+    gcp_net_desc sub{desc->in_c, desc->in_h, desc->in_w, k + 1, nodes.data()};
+    for (int i = 0; i < k; ++i) {
+      nodes[i].lower = L[i].data();
+      nodes[i].upper = U[i].data();
+    }
+    nodes[k] = nk;
+    nodes[k].lower = nodes[k].upper = nullptr;
+    NetGuard net;
+    {
+      const int rc = gcp_net_create(&sub, &net.p);
+      if (rc != GCP_OK) return rc;
+    }
+    // CROWN-adaptive lower slopes of the prefix's unstable neurons (in alpha
+    // row order: node by node, ascending neuron index)
+    std::vector<float> arow;
+    for (int i = 0; i < k; ++i)
+      for (size_t j = 0; j < L[i].size(); ++j)
+        if (L[i][j] < 0.0 && U[i][j] > 0.0) arow.push_back(U[i][j] >= -L[i][j] ? 1.f : 0.f);
+    const size_t nI = arow.size();
+    SplitsGuard spl;
+    {
+      const int rc = gcp_splits_create(net.p, 1, 0, nullptr, nullptr, nullptr, &spl.p);
+      if (rc != GCP_OK) return rc;
+    }
+    // spec rows: +e_j (lower bound of x_j) then -e_j (minus the upper bound)
+    const int S_all = 2 * d;
+    const int rows = std::min(kRowsPerCall, S_all);
+    DBuf Cd, Ad, Bd;
+    Cd.alloc((size_t)rows * d * 8);
+    Ad.alloc(std::max<size_t>((size_t)rows * nI * 4, 4));
+    Bd.alloc((size_t)rows * 8);
+    std::vector<float> arows((size_t)rows * nI);
+    for (int r = 0; r < rows; ++r) std::copy(arow.begin(), arow.end(), arows.begin() + (size_t)r * nI);
+    if (nI) hip_check(hipMemcpyAsync(Ad.p, arows.data(), arows.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    std::vector<double> Ch((size_t)rows * d), bh(rows);
+    std::vector<double> lo(d), hi(d);
+    for (int s0 = 0; s0 < S_all; s0 += rows) {
+      const int S = std::min(rows, S_all - s0);
+      std::fill(Ch.begin(), Ch.end(), 0.0);
+      for (int r = 0; r < S; ++r) {
+        const int g = s0 + r;
+        Ch[(size_t)r * d + (g < d ? g : g - d)] = g < d ? 1.0 : -1.0;
+      }
+      hip_check(hipMemcpyAsync(Cd.p, Ch.data(), (size_t)S * d * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+      const int rc = gcp_bound(net.p, x0, eps, Cd.as<double>(), S, spl.p, nullptr, nI ? Ad.as<float>() : nullptr,
+                               nullptr, nullptr, mode & 0xff, Bd.as<double>(), nullptr, nullptr, nullptr, nullptr,
+                               stream);
+      if (rc != GCP_OK) return rc;
+      hip_check(hipMemcpyAsync(bh.data(), Bd.p, (size_t)S * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      for (int r = 0; r < S; ++r) {
+        const int g = s0 + r;
+        if (g < d) lo[g] = bh[r];
+        else hi[g - d] = -bh[r];
+      }
+    }
+    for (int j = 0; j < d; ++j) {
+      if (!std::isfinite(lo[j]) || !std::isfinite(hi[j]))
+        fail(GCP_ENONFINITE, "non-finite intermediate bound at node " + std::to_string(k));
+      // an exactly determined pre-activation (l = u in exact arithmetic) can
+      // come out a rounding error apart in the two directions
+      if (lo[j] > hi[j]) std::swap(lo[j], hi[j]);
+    }
+    L[k] = std::move(lo);
+    U[k] = std::move(hi);
+    std::copy(L[k].begin(), L[k].end(), lower[k]);
+    std::copy(U[k].begin(), U[k].end(), upper[k]);
   }
   g_err.clear();
   return GCP_OK;

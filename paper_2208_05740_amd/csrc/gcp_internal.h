@@ -183,6 +183,8 @@ hipError_t launch_chat(const double* C, int S, int d_out, const float* W, int d_
                        int kind, float* chat, int ld, hipStream_t st);
 hipError_t launch_out_const(const double* C, int S, int d_out, const float* bias,
                             double* cb, hipStream_t st);
+// out[r][j] = C[r mod S][j] in the operand type, r < M, j < d
+hipError_t launch_spec_rows(int bf16, const double* C, int S, int d, int M, void* out, int ld, hipStream_t st);
 hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, int d_in,
                       const double* x0, const float* bias, float* out, hipStream_t st);
 hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n_slots,

@@ -152,10 +152,12 @@ __device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
 #pragma unroll
     for (int k = 0; k < TN; ++k) lc.j[k][0] = col0 + k * 16;
   }
+  // the first operand stage is issued before the epilogue's loads so that
+  // both are in flight together
+  if (g.K > 0) load_stage(0);
   typename Epi::template Frag<R, TN, false> fr;
   epi.template load<R, TN, false>(fr, lc, g.M, g.N);
 
-  if (g.K > 0) load_stage(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
     store_stage();
@@ -486,6 +488,30 @@ __global__ void out_const_kernel(const double* C, int S, int d_out, const float*
   double acc = 0.0;
   for (int o = 0; o < d_out; ++o) acc += C[(size_t)s * d_out + o] * (double)bias[o];
   cb[s] = acc;
+}
+
+// Lambda of the output node materialised: row r = C[r mod S] in the operand
+// type (for outputs whose in-edges the c-hat shortcut cannot take).
+template <typename T>
+__global__ void __launch_bounds__(256) spec_rows_kernel(const double* C, int S, int d, int M, int nblk, T* out,
+                                                        int ld) {
+  const long b = blockIdx.x;
+  const int r = (int)(b / nblk);
+  const int j = (int)(b % nblk) * 256 + threadIdx.x;
+  if (r < M && j < d) out[(size_t)r * ld + j] = to_t<T>((float)C[(size_t)(r % S) * d + j]);
+}
+
+hipError_t launch_spec_rows(int bf16_mode, const double* C, int S, int d, int M, void* out, int ld, hipStream_t st) {
+  if (M <= 0 || d <= 0) return hipSuccess;
+  const int nblk = (d + 255) / 256;
+  const long blocks = (long)M * nblk;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  if (bf16_mode)
+    hipLaunchKernelGGL(spec_rows_kernel<bf16>, dim3((unsigned)blocks), dim3(256), 0, st, C, S, d, M, nblk, (bf16*)out, ld);
+  else
+    hipLaunchKernelGGL(spec_rows_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, C, S, d, M, nblk, (float*)out,
+                       ld);
+  return hipGetLastError();
 }
 
 hipError_t launch_out_const(const double* C, int S, int d_out, const float* bias, double* cb, hipStream_t st) {

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import gcp_oracle as O
+from oracle import lp
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -392,3 +393,59 @@ def test_batched_optimisation_certified_bound_matches_oracle():
         ref = O.bound(p, a64, b64, c64).reshape(-1)
         T = O.error_scale(p, a64, b64, c64).reshape(-1)
         assert rel_err(it["bound"].cpu().numpy(), ref, T).max() <= 1e-5
+
+
+# ------------------------------------------------------------ general output form
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("mlp", 3), ("cnn", 1)])
+def test_materialised_output_lambda_matches_oracle(kind, seed, monkeypatch):
+    # the output's Lambda = C pushed through the ordinary kernels (instead of
+    # the C W shortcut) gives the same bounds and gradients
+    monkeypatch.setenv("GCP_OUT_GENERAL", "1")
+    p = gen.make_tiny(kind, seed, B=3, splits=(1, 2), n_cuts=5)
+    check_bound(p, mode=0)
+
+
+# ------------------------------------------------------------ intermediate bounds
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("cnn", 1), ("res", 2), ("cnn16", 3), ("res16", 4)])
+def test_crown_intermediate_bounds_match_oracle(kind, seed):
+    # layer by layer: node k's bounds from the device against the oracle's
+    # CROWN on the same prefix, both given the device's bounds of nodes < k
+    import torch
+    from paper_2208_05740_amd import binding as B
+    from oracle import crown
+    p = gen.make_tiny(kind, seed, eps=0.1)
+    x0 = torch.tensor(p.x0, dtype=torch.float64, device=_dev())
+    got = B.crown_bounds(p.net, x0, p.eps)
+    want = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, lu_given=got)
+    for (gl, gu), (wl, wu) in zip(got, want):
+        scale = np.abs(wl) + np.abs(wu) + 1.0
+        assert (np.abs(gl - wl) / scale).max() <= 1e-5
+        assert (np.abs(gu - wu) / scale).max() <= 1e-5
+    # sound: every sampled point's pre-activations lie inside
+    rng = np.random.default_rng(seed)
+    xs = p.x0[None, :] + p.eps * rng.uniform(-1, 1, size=(2000, p.x0.size))
+    _, pre = lp.plain_forward(p.net, xs, return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    for (l, u), i in zip(got, relu):
+        assert (pre[i] >= l[None, :] - 1e-6).all() and (pre[i] <= u[None, :] + 1e-6).all()
+
+
+def test_crown_intermediate_bounds_as_root_bounds_mlp784():
+    # CROWN bounds of a 784-256x3-10 MLP computed on the device: tighter than
+    # interval bounds on the deeper layers, and usable as root bounds
+    import torch
+    from paper_2208_05740_amd import binding as B
+    from oracle import crown
+    net = gen.mlp_net(np.random.default_rng(11), [784, 256, 256, 256, 10])
+    x0 = np.random.default_rng(12).uniform(0, 1, 784)
+    eps = 0.015
+    got = B.crown_bounds(net, torch.tensor(x0, dtype=torch.float64, device=_dev()), eps)
+    ibp = gen.ibp_bounds(net, x0, eps)
+    assert np.allclose(got[0][0], ibp[0][0], rtol=1e-5, atol=1e-5)
+    for (l, u), (il, iu) in list(zip(got, ibp))[1:]:
+        assert (u - l).mean() < (iu - il).mean()
+    # node 1 against the oracle given the device's node-0 bounds
+    want = crown.crown_intermediate_bounds(type(net)(net.in_shape, net.nodes[:2]), x0, eps, lu_given=got[:1])
+    scale = np.abs(want[1][0]) + np.abs(want[1][1]) + 1.0
+    assert (np.abs(got[1][0] - want[1][0]) / scale).max() <= 1e-5
+    assert (np.abs(got[1][1] - want[1][1]) / scale).max() <= 1e-5

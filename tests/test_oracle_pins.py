@@ -408,3 +408,40 @@ def test_config1_golden_values():
     assert np.allclose(gc, ref["d_gamma"], rtol=1e-12, atol=1e-12)
     assert np.all(g[0] <= np.array(ref["lp_cut"]) + 1e-9)
     assert np.all(np.array(ref["lp_cut"]) <= np.array(ref["mip"]) + 1e-9)
+
+
+# ------------------------------------------------------------ intermediate bounds
+@pytest.mark.parametrize("kind", ["mlp", "cnn", "res"])
+def test_crown_intermediate_bounds_exact_at_zero_radius(kind):
+    # with eps = 0 every bound is the pre-activation at x0 itself
+    p = gen.make_tiny(kind, 0)
+    lu = crown.crown_intermediate_bounds(p.net, p.x0, 0.0)
+    _, pre = lp.plain_forward(p.net, p.x0[None, :], return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    for (l, u), i in zip(lu, relu):
+        assert np.allclose(l, pre[i][0], atol=1e-9) and np.allclose(u, pre[i][0], atol=1e-9)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn", "res"])
+def test_crown_intermediate_bounds_first_layer_is_interval_arithmetic(kind):
+    # node 0 is affine in the input: l, u = A x0 + b -/+ eps * |A| 1
+    p = gen.make_tiny(kind, 1, eps=0.2)
+    lu = crown.crown_intermediate_bounds(p.net, p.x0, p.eps)
+    node = p.net.nodes[0]
+    A = sum(lp.edge_matrix(e, node.shape, p.net.shape_of(e.src)) for e in node.edges)
+    mid = A @ p.x0 + node.bias
+    rad = p.eps * np.abs(A).sum(axis=1)
+    assert np.allclose(lu[0][0], mid - rad, atol=1e-9) and np.allclose(lu[0][1], mid + rad, atol=1e-9)
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 2), ("cnn", 3), ("res", 4)])
+def test_crown_intermediate_bounds_contain_sampled_preactivations(kind, seed):
+    p = gen.make_tiny(kind, seed, eps=0.2)
+    lu = crown.crown_intermediate_bounds(p.net, p.x0, p.eps)
+    rng = np.random.default_rng(seed)
+    xs = p.x0[None, :] + p.eps * rng.uniform(-1, 1, size=(4000, p.x0.size))
+    xs[:64] = p.x0[None, :] + p.eps * np.sign(rng.uniform(-1, 1, size=(64, p.x0.size)))   # box vertices
+    _, pre = lp.plain_forward(p.net, xs, return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    for (l, u), i in zip(lu, relu):
+        assert (pre[i] >= l[None, :] - 1e-9).all() and (pre[i] <= u[None, :] + 1e-9).all()
