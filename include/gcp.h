@@ -106,6 +106,11 @@ typedef struct {
  * node (topological order), ascending neuron index within a node. */
 int gcp_net_get_info(const gcp_net* net, gcp_net_info* info);
 
+/* The root-unstable neurons in alpha row order: node[r], neuron[r] and the
+ * root bounds lower[r], upper[r] as given to gcp_net_create, r < n_unstable
+ * (host arrays; any may be NULL). */
+int gcp_net_get_unstable(const gcp_net* net, int32_t* node, int32_t* neuron, double* lower, double* upper);
+
 /* ------------------------------------------------------------ cuts */
 #define GCP_CUT_H 0   /* coefficient on the pre-activation x_j   */
 #define GCP_CUT_G 1   /* coefficient on the post-activation x_hat_j (node -1: input x_j) */
@@ -127,6 +132,8 @@ int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz,
                     const int8_t* kind, const double* coef, const double* d,
                     gcp_cuts** out);
 int gcp_cuts_destroy(gcp_cuts* cuts);
+/* Number of cut rows N (the length of a gamma row). */
+int gcp_cuts_info(const gcp_cuts* cuts, int32_t* n_cuts);
 
 /* ------------------------------------------------------------ splits */
 typedef struct gcp_splits gcp_splits;
@@ -224,6 +231,50 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
  * and gcp_bound. */
 int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, double eps, double* const* lower,
                      double* const* upper, int32_t mode, void* stream);
+
+/* ------------------------------------------------------------ branch and bound */
+/* gcp_bab: branch and bound on one property c^T f(x) >= 0 over the box
+ * (Appendix B's procedure, easiest domains first as in Sec. 3.3), with
+ * gcp_optimize as the bounding step.  A domain is a set of splits
+ * x_j >= 0 / x_j <= 0 of root-unstable neurons.  Each round bounds up to
+ * `batch` open domains in one gcp_optimize call (the open domains with the
+ * largest parent bound first when more are open), prunes those with a bound
+ * >= 0, and splits each other one on its unsplit neuron of largest root
+ * triangle height u(-l)/(u-l) into two children.  A domain that reaches
+ * max_depth splits (or has no unstable neuron left) with a negative bound is
+ * counted as unresolved after `retries` further rounds from its own
+ * optimum.  The root starts from alpha = CROWN-adaptive (1 where u >= -l),
+ * beta = gamma = 0; a child starts from its parent's optimised alpha, beta
+ * (its new split's multiplier at 0) and gamma, with fresh Adam moments; cuts
+ * apply to every domain.  c: device fp64 [d_out] (one spec row); x0 as gcp_bound.
+ * Synchronises `stream` once per round. */
+typedef struct {
+  int32_t batch;           /* domains per bounding call, >= 1                */
+  int32_t max_depth;       /* splits per domain at most (K slots)            */
+  int64_t max_domains;     /* budget of bounded domains                      */
+  int64_t max_pool;        /* open domains at most; more ends the search     */
+  int32_t retries;         /* extra bounding rounds for a domain that cannot
+                              be split further, each from its own optimum    */
+  gcp_opt opt;             /* the bounding step's optimiser                  */
+  int32_t mode;            /* GCP_MODE_* of the bounding step                */
+} gcp_bab_opt;
+
+#define GCP_BAB_VERIFIED 1  /* every leaf has a bound >= 0                  */
+#define GCP_BAB_UNKNOWN  0  /* budget, pool or depth exhausted               */
+
+typedef struct {
+  int32_t status;          /* GCP_BAB_VERIFIED or GCP_BAB_UNKNOWN            */
+  double lower;            /* verified: smallest leaf bound; otherwise the
+                              smallest bound of an open or unresolved domain */
+  int64_t bounded;         /* domains bounded                                */
+  int64_t rounds;          /* bounding calls                                 */
+  int64_t max_open;        /* largest number of open domains                 */
+  int64_t open;            /* open domains left                              */
+  int64_t unresolved;      /* domains at max_depth with a negative bound     */
+} gcp_bab_result;
+
+int gcp_bab(const gcp_net* net, const double* x0, double eps, const double* c, const gcp_cuts* cuts,
+            const gcp_bab_opt* opt, gcp_bab_result* result, void* stream);
 
 /* ------------------------------------------------------------ batching */
 /* One verification instance of a batched optimisation: the arguments of

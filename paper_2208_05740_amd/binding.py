@@ -65,10 +65,24 @@ class BatchItem(C.Structure):
                 ("gamma", C.c_void_p), ("adam_state", C.c_void_p), ("bound", C.c_void_p), ("verified", C.c_void_p)]
 
 
+class BabOpt(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("max_depth", C.c_int32), ("max_domains", C.c_int64),
+                ("max_pool", C.c_int64), ("retries", C.c_int32), ("opt", OptDesc), ("mode", C.c_int32)]
+
+
+class BabResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("lower", C.c_double), ("bounded", C.c_int64), ("rounds", C.c_int64),
+                ("max_open", C.c_int64), ("open", C.c_int64), ("unresolved", C.c_int64)]
+
+
+GCP_BAB_VERIFIED = 1
+GCP_BAB_UNKNOWN = 0
+
 _LIB = None
 EXPORTS = ["gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
            "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_optimize_batch",
-           "gcp_crown_bounds", "gcp_profile_enable", "gcp_profile_read", "gcp_last_error", "gcp_version"]
+           "gcp_crown_bounds", "gcp_net_get_unstable", "gcp_cuts_info", "gcp_bab", "gcp_profile_enable",
+           "gcp_profile_read", "gcp_last_error", "gcp_version"]
 
 
 def lib():
@@ -91,6 +105,9 @@ def lib():
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
     L.gcp_optimize_batch.argtypes = [i32, C.POINTER(BatchItem), C.POINTER(OptDesc), i32, vp]
     L.gcp_crown_bounds.argtypes = [C.POINTER(NetDesc), vp, dbl, C.POINTER(vp), C.POINTER(vp), i32, vp]
+    L.gcp_net_get_unstable.argtypes = [vp, vp, vp, vp, vp]
+    L.gcp_cuts_info.argtypes = [vp, C.POINTER(i32)]
+    L.gcp_bab.argtypes = [vp, vp, dbl, vp, vp, C.POINTER(BabOpt), C.POINTER(BabResult), vp]
     L.gcp_profile_enable.argtypes = [i32]
     L.gcp_profile_read.argtypes = [i32, C.c_char_p, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -98,7 +115,8 @@ def lib():
     L.gcp_version.restype = C.c_char_p
     for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
               "gcp_splits_create", "gcp_splits_destroy", "gcp_bound", "gcp_optimize", "gcp_profile_enable",
-              "gcp_profile_read", "gcp_optimize_batch", "gcp_crown_bounds"):
+              "gcp_profile_read", "gcp_optimize_batch", "gcp_crown_bounds", "gcp_net_get_unstable",
+              "gcp_cuts_info", "gcp_bab"):
         getattr(L, f).restype = C.c_int
     _LIB = L
     return L
@@ -197,6 +215,28 @@ def crown_bounds(net, x0, eps: float, mode: int = GCP_MODE_FP32):
     up = (C.c_void_p * len(relu))(*[a.ctypes.data for a in hi])
     _check(lib().gcp_crown_bounds(C.byref(desc), _ptr(x0), float(eps), lp, up, mode, _stream()))
     return list(zip(lo, hi))
+
+
+def bab(net: Net, x0, eps: float, c_row, cuts: Optional["Cuts"] = None, batch=64, max_depth=16,
+        max_domains=100000, max_pool=100000, retries=4, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.9,
+        b2=0.999, adam_eps=1e-8, mode: int = GCP_MODE_FP32):
+    """gcp_bab on one spec row c_row (device fp64 [d_out]); returns a dict of
+    the gcp_bab_result fields."""
+    o = BabOpt(batch, max_depth, max_domains, max_pool, retries,
+               OptDesc(iters, lr_alpha, lr_mult, decay, b1, b2, adam_eps, 0), mode)
+    r = BabResult()
+    _check(lib().gcp_bab(net.h, _ptr(x0), float(eps), _ptr(c_row), cuts.h if cuts else None, C.byref(o), C.byref(r),
+                         _stream()))
+    return {k: getattr(r, k) for k, _ in BabResult._fields_}
+
+
+def net_unstable(net: Net):
+    """(node, neuron, lower, upper) of the root-unstable neurons in alpha row order."""
+    n = net.n_I
+    node, neuron = np.empty(n, np.int32), np.empty(n, np.int32)
+    lo, hi = np.empty(n, np.float64), np.empty(n, np.float64)
+    _check(lib().gcp_net_get_unstable(net.h, _ptr(node), _ptr(neuron), _ptr(lo), _ptr(hi)))
+    return node, neuron, lo, hi
 
 
 class Cuts:

@@ -174,6 +174,7 @@ struct NodeH {
   std::vector<int> consumers;     // edges whose src is this node
   DBuf bias, rec, kind;
   std::vector<int32_t> rank_h;    // host copy of rank
+  std::vector<double> l_h, u_h;   // host copies of the root bounds (as given)
   int n_unst = 0, rank0 = 0;
   NodeDev dev() const { return NodeDev{size, ld, rec.as<float4>(), kind.as<int32_t>()}; }
 };
@@ -332,6 +333,8 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         kind[j] = (rank[j] + 1) * 4 + cls[j];
       }
       n.rank_h = rank;
+      n.l_h.assign(nd.lower, nd.lower + n.size);
+      n.u_h.assign(nd.upper, nd.upper + n.size);
       net->n_relu += n.size;
     }
     n.rec.upload(rec);
@@ -580,6 +583,25 @@ extern "C" int gcp_net_get_info(const gcp_net* net, gcp_net_info* info) {
   return GCP_OK;
 }
 
+extern "C" int gcp_net_get_unstable(const gcp_net* net, int32_t* node, int32_t* neuron, double* lower,
+                                    double* upper) {
+  GCP_TRY
+  if (!net) fail(GCP_EINVAL, "null net");
+  for (int i = 0; i < net->out; ++i) {
+    const NodeH& n = net->nodes[i];
+    for (int j = 0; j < n.size; ++j) {
+      const int r = n.rank_h[j];
+      if (r < 0) continue;
+      if (node) node[r] = i;
+      if (neuron) neuron[r] = j;
+      if (lower) lower[r] = n.l_h[j];
+      if (upper) upper[r] = n.u_h[j];
+    }
+  }
+  return GCP_OK;
+  GCP_CATCH
+}
+
 extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, const int32_t* cut,
                                const int32_t* node, const int32_t* neuron, const int8_t* kind,
                                const double* coef, const double* d, gcp_cuts** out) {
@@ -654,6 +676,14 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   }
   *out = C.release();
   g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_cuts_info(const gcp_cuts* cuts, int32_t* n_cuts) {
+  GCP_TRY
+  if (!cuts || !n_cuts) fail(GCP_EINVAL, "null argument");
+  *n_cuts = cuts->N;
   return GCP_OK;
   GCP_CATCH
 }
@@ -2018,3 +2048,8 @@ extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, doub
   return GCP_OK;
   GCP_CATCH
 }
+
+namespace gcp {
+// error text for gcp_last_error from the other host sources of the library
+void set_last_error(const char* m) { g_err = m ? m : ""; }
+}  // namespace gcp

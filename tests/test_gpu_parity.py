@@ -449,3 +449,52 @@ def test_crown_intermediate_bounds_as_root_bounds_mlp784():
     scale = np.abs(want[1][0]) + np.abs(want[1][1]) + 1.0
     assert (np.abs(got[1][0] - want[1][0]) / scale).max() <= 1e-5
     assert (np.abs(got[1][1] - want[1][1]) / scale).max() <= 1e-5
+
+
+# ------------------------------------------------------------ branch and bound
+# (seed, eps, spec row) of tiny MLPs whose root bound is negative after the 20
+# Adam iterations but whose exact minimum (one LP per activation pattern) is
+# positive: only branching can verify them
+BAB_CASES = [(9, 0.1, 0), (21, 0.15, 0), (31, 0.1, 0), (7, 0.1, 1)]
+
+
+def _tiny_plain(seed, eps, n_cuts=0):
+    return gen.make_tiny("mlp", seed, B=1, splits=(0, 0), n_cuts=n_cuts, eps=eps, alpha_init="crown",
+                         gamma_dist="zero", beta_dist="zero")
+
+
+@pytest.mark.parametrize("seed,eps,row", BAB_CASES)
+def test_bab_verifies_properties_that_need_branching(seed, eps, row):
+    from paper_2208_05740_amd import binding as B
+    p = _tiny_plain(seed, eps)
+    exact = lp.mip_value_enum(p, 0, row)
+    root = O.optimize(p)[0][row]
+    assert exact > 0 and root < 0
+    P = upload(p)
+    r = B.bab(P.net, P.x0, P.eps, P.C[row].contiguous(), batch=8, max_depth=16)
+    assert r["status"] == B.GCP_BAB_VERIFIED, r
+    assert r["bounded"] > 1 and r["unresolved"] == 0 and r["open"] == 0
+    assert 0.0 <= r["lower"] <= exact + 1e-6
+
+
+def test_bab_with_cuts_verifies_and_never_verifies_a_false_property():
+    # sound on every row of a few tiny nets (with valid cuts): verified only
+    # when the exact minimum is positive, and the reported lower bound never
+    # exceeds the exact minimum when not verified
+    from paper_2208_05740_amd import binding as B
+    n_false = n_true = 0
+    for seed in range(6):
+        p = _tiny_plain(seed, 0.15, n_cuts=4)
+        if sum(int(((l < 0) & (u > 0)).sum()) for l, u in p.lu) > 12:
+            continue
+        P = upload(p)
+        for row in range(p.S):
+            exact = lp.mip_value_enum(p, 0, row)
+            r = B.bab(P.net, P.x0, P.eps, P.C[row].contiguous(), P.cuts, batch=16, max_depth=16)
+            if r["status"] == B.GCP_BAB_VERIFIED:
+                assert exact > 0 and r["lower"] <= exact + 1e-6
+                n_true += 1
+            else:
+                assert r["lower"] <= exact + 1e-6
+                n_false += exact < 0
+    assert n_true > 0 and n_false > 0
