@@ -11,9 +11,8 @@
 //
 // Each epilogue is split in two: load() fetches everything that does not
 // depend on the GEMM result (neuron data, cut gathers, stored a_hat, alpha
-// and its moments, split overrides) and is issued before the K loop so its
-// latency overlaps the GEMM; apply() combines it with the accumulator and
-// stores.  Frag holds the per-lane state between the two.
+// and its moments, split overrides); apply() combines it with the
+// accumulator and stores.  Frag holds the per-lane state between the two.
 #pragma once
 #include "gcp_internal.h"
 
