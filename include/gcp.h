@@ -291,7 +291,9 @@ typedef struct {
 /* gcp_optimize_batch: gcp_optimize of every item with the same settings and mode.
  * Instances large enough to fill the device with their own launches (batch
  * rows x widest layer >= 2^20 elements; the environment variable
- * GCP_BATCH_ALONE_WORK overrides the threshold) run exactly as gcp_optimize.
+ * GCP_BATCH_ALONE_WORK overrides the threshold) run exactly as gcp_optimize,
+ * concurrently on internal streams (GCP_BATCH_STREAMS, default 2) that are
+ * joined to `stream` by events, longest instances first.
  * The others run each Adam iteration as a few grouped launches -- launches
  * of the same kernel at the same position of each instance's schedule become
  * one launch whose workgroups look up their instance in a device table --

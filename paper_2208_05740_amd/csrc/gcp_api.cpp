@@ -1787,6 +1787,30 @@ long batch_alone_work() {
   const char* e = std::getenv("GCP_BATCH_ALONE_WORK");
   return e && *e ? std::atol(e) : (1L << 20);
 }
+// Internal streams (default priority, one set per device, kept for the life
+// of the process) on which the large instances of a batch run concurrently,
+// joined to the caller's stream by events.  GCP_BATCH_STREAMS sets how many
+// (default 2; 1 runs them one after the other on the caller's stream).
+std::mutex g_side_mu;
+std::map<int, std::vector<hipStream_t>>* g_side = nullptr;
+std::vector<hipStream_t> side_streams(int n) {
+  int dev;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if (!g_side) g_side = new std::map<int, std::vector<hipStream_t>>();
+  auto& v = (*g_side)[dev];
+  while ((int)v.size() < n) {
+    hipStream_t s;
+    hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    v.push_back(s);
+  }
+  return std::vector<hipStream_t>(v.begin(), v.begin() + n);
+}
+int batch_streams() {
+  const char* e = std::getenv("GCP_BATCH_STREAMS");
+  const int n = e && *e ? std::atoi(e) : 2;
+  return std::max(1, std::min(n, 8));
+}
 long instance_work(const gcp_batch_item& it) {
   if (!it.net || !it.splits) return 0;
   int width = 0;
@@ -1806,17 +1830,48 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   for (int i = 0; i < n_all; ++i)
     for (int k = 0; k < i; ++k)
       if (items_all[k].net == items_all[i].net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
-  // large instances: their own launches (the same kernels and tiles as gcp_optimize)
+  // large instances: their own launches (the same kernels and tiles as
+  // gcp_optimize), spread over a few streams by longest-first assignment
   const long alone = batch_alone_work();
   std::vector<gcp_batch_item> grouped;
+  std::vector<std::pair<long, int>> big;
   for (int i = 0; i < n_all; ++i) {
-    const gcp_batch_item& it = items_all[i];
-    if (instance_work(it) < alone) {
-      grouped.push_back(it);
-      continue;
+    const long w = instance_work(items_all[i]);
+    if (w < alone) grouped.push_back(items_all[i]);
+    else big.push_back({w, i});
+  }
+  if (!big.empty()) {
+    const int ns = std::min<int>(batch_streams(), (int)big.size());
+    std::vector<hipStream_t> ss = ns > 1 ? side_streams(ns) : std::vector<hipStream_t>{st};
+    std::sort(big.begin(), big.end(), [](const std::pair<long, int>& a, const std::pair<long, int>& b) {
+      return a.first > b.first || (a.first == b.first && a.second < b.second);
+    });
+    std::vector<double> load(ns, 0.0);
+    hipEvent_t start = nullptr;
+    if (ns > 1) {
+      hip_check(hipEventCreateWithFlags(&start, hipEventDisableTiming), "hipEventCreate");
+      hip_check(hipEventRecord(start, st), "hipEventRecord");
+      for (hipStream_t s : ss) hip_check(hipStreamWaitEvent(s, start, 0), "hipStreamWaitEvent");
     }
-    const int rc = gcp_optimize(it.net, it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha, it.beta, it.gamma,
-                                it.adam_state, opt, mode, it.bound, it.verified, stream);
+    int rc = GCP_OK;
+    for (const auto& b : big) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += (double)b.first;
+      const gcp_batch_item& it = items_all[b.second];
+      rc = gcp_optimize(it.net, it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha, it.beta, it.gamma,
+                        it.adam_state, opt, mode, it.bound, it.verified, ss[k]);
+      if (rc != GCP_OK) break;
+    }
+    if (ns > 1) {   // the caller's stream waits for every side stream
+      for (hipStream_t s : ss) {
+        hipEvent_t done;
+        hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventRecord(done, s), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(st, done, 0), "hipStreamWaitEvent");
+        (void)hipEventDestroy(done);
+      }
+      (void)hipEventDestroy(start);
+    }
     if (rc != GCP_OK) return rc;
   }
   if (grouped.empty()) {
