@@ -337,12 +337,20 @@ def bench_batch(args):
     bounds_b = [it["bound"].cpu().numpy().copy() for it in items]
     kprof = None
     if not args.no_profile:
+        # per-kernel event timing needs kernels that do not overlap: the
+        # instrumented replay runs the large instances one after another
+        prev = os.environ.get("GCP_BATCH_STREAMS")
+        os.environ["GCP_BATCH_STREAMS"] = "1"
         B.profile_enable(True)
         use_graph[0] = False
         dt_prof = timed(step_batched, args.steps, 0)
         use_graph[0] = args.graph
         B.profile_enable(False)
         kprof = B.profile_read()
+        if prev is None:
+            del os.environ["GCP_BATCH_STREAMS"]
+        else:
+            os.environ["GCP_BATCH_STREAMS"] = prev
     dts = timed(step_single, args.steps, 1)
     bounds_s = [it["bound"].cpu().numpy().copy() for it in items]
     same = all(np.array_equal(x, y) for x, y in zip(bounds_b, bounds_s))

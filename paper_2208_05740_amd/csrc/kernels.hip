@@ -320,38 +320,59 @@ hipError_t launch_gemm_grouped(int bf16_mode, int cfg, EpiKind kind, int sign, c
 }
 
 // ------------------------------------------------------------------ elementwise
-// One block = one row x 256 columns; row partial per column block.
+// Elementwise relaxation (no GEMM: a_hat = bcast row + src): one block =
+// four consecutive rows x 256 columns, each thread one column of the four
+// rows, so a neuron's data is read once for them; one row partial per
+// (row, column block), summed over the block in a fixed order.
+template <typename T>
+__device__ inline void bound_elem_rows(const float* bcast, const void* src, const BoundEpiArgs& a, double* partial,
+                                       int slot0, int r0, int cb) {
+  __shared__ double red[4][4];
+  const int j = cb * 256 + threadIdx.x;
+  const int M = a.rp.M;
+  BoundEpi<T> epi{a};
+  LaneCoords<4, 1, false> lc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) lc.r[q] = r0 + q;
+  lc.j[0][0] = j;
+  float val[1][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + q;
+    float pre = 0.f;
+    if (j < a.nd.size && r < M) {
+      if (bcast) pre += bcast[(size_t)(r % a.rp.S) * a.nd.ld + j];
+      if (src) pre += from_t<T>(((const T*)src)[(size_t)r * a.nd.ld + j]);
+    }
+    val[0][q] = pre;
+  }
+  double rs[4] = {0.0, 0.0, 0.0, 0.0};
+  typename BoundEpi<T>::template Frag<4, 1, false> fr;
+  epi.template load<4, 1, false>(fr, lc, M, a.nd.size);
+  epi.template apply<4, 1, false>(fr, lc, val, rs, M, a.nd.size);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double t = rs[q];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && partial) {
+    const int q = threadIdx.x, r = r0 + q;
+    if (r < M) partial[(size_t)(slot0 + cb) * a.rp.mp + r] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, const void* src, BoundEpiArgs a,
                                                          double* partial, int slot0) {
-  __shared__ double red[4];
-  const int r = blockIdx.x;
-  const int j = blockIdx.y * 256 + threadIdx.x;
-  BoundEpi<T> epi{a};
-  LaneCoords<1, 1, false> lc;
-  lc.r[0] = r;
-  lc.j[0][0] = j;
-  float pre = 0.f;
-  if (j < a.nd.size) {
-    if (bcast) pre += bcast[(size_t)(r % a.rp.S) * a.nd.ld + j];
-    if (src) pre += from_t<T>(((const T*)src)[(size_t)r * a.nd.ld + j]);
-  }
-  float val[1][1] = {{pre}};
-  double rs[1] = {0.0};
-  typename BoundEpi<T>::template Frag<1, 1, false> fr;
-  epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
-  epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
-  double t = rs[0];
-  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0 && partial)
-    partial[(size_t)(slot0 + blockIdx.y) * a.rp.mp + r] = (red[0] + red[1]) + (red[2] + red[3]);
+  bound_elem_rows<T>(bcast, src, a, partial, slot0, 4 * blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const void* src, const BoundEpiArgs& a,
                                     double* partial, int slot0, hipStream_t st) {
-  dim3 grid(a.rp.M, (a.nd.size + 255) / 256);
+  if (a.rp.M <= 0) return hipSuccess;
+  dim3 grid((a.rp.M + 3) / 4, (a.nd.size + 255) / 256);
   if (bf16_mode)
     hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   else
@@ -359,12 +380,11 @@ hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const voi
   return hipGetLastError();
 }
 
-// Grouped elementwise relaxation: block b of job p covers row (b / nb) and
-// columns 256 * (b % nb) .. of that job, nb = ceil(size / 256).
+// Grouped elementwise relaxation: block b of job p covers rows 4 * (b / nb)
+// .. + 3 and columns 256 * (b % nb) .. of that job, nb = ceil(size / 256).
 template <typename T>
 __global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __restrict__ jobs,
                                                           const int* __restrict__ prefix, int np) {
-  __shared__ double red[4];
   const int t = blockIdx.x;
   int lo = 0, hi = np - 1;
   while (lo < hi) {
@@ -372,31 +392,9 @@ __global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __
     if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
   }
   const ElemBoundJob& jb = jobs[lo];
-  const BoundEpiArgs a = jb.a;
-  const int nb = (a.nd.size + 255) / 256;
+  const int nb = (jb.a.nd.size + 255) / 256;
   const int b = t - prefix[lo];
-  const int r = b / nb, cb = b % nb;
-  const int j = cb * 256 + threadIdx.x;
-  BoundEpi<T> epi{a};
-  LaneCoords<1, 1, false> lc;
-  lc.r[0] = r;
-  lc.j[0][0] = j;
-  float pre = 0.f;
-  if (j < a.nd.size) {
-    if (jb.bcast) pre += jb.bcast[(size_t)(r % a.rp.S) * a.nd.ld + j];
-    if (jb.src) pre += from_t<T>(((const T*)jb.src)[(size_t)r * a.nd.ld + j]);
-  }
-  float val[1][1] = {{pre}};
-  double rs[1] = {0.0};
-  typename BoundEpi<T>::template Frag<1, 1, false> fr;
-  epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
-  epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
-  double tt = rs[0];
-  for (int o = 32; o > 0; o >>= 1) tt += __shfl_xor(tt, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tt;
-  __syncthreads();
-  if (threadIdx.x == 0 && jb.partial)
-    jb.partial[(size_t)(jb.slot0 + cb) * a.rp.mp + r] = (red[0] + red[1]) + (red[2] + red[3]);
+  bound_elem_rows<T>(jb.bcast, jb.src, jb.a, jb.partial, jb.slot0, 4 * (b / nb), b % nb);
 }
 
 hipError_t launch_bound_elementwise_grouped(int bf16_mode, const ElemBoundJob* d_jobs, const int* d_prefix, int np,
