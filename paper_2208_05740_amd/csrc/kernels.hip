@@ -87,10 +87,14 @@ __device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
         int gr = m0 + row, gk = k0 + kk;
         if (gr < g.M && gk < g.lda) {
           if constexpr (SIGN) {
+            // VEC int8 signs in one load (the row pitch and gk are multiples of VEC)
             const int8_t* src = (const int8_t*)g.A + (size_t)gr * g.lda + gk;
+            int8_t e[VEC];
+            if constexpr (VEC == 8) *(uint2*)e = *(const uint2*)src;
+            else *(uint32_t*)e = *(const uint32_t*)src;
             T tmp[VEC];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) tmp[q] = to_t<T>((float)src[q]);
+            for (int q = 0; q < VEC; ++q) tmp[q] = to_t<T>((float)e[q]);
             val = *(const uint4*)tmp;
           } else {
             val = *(const uint4*)((const T*)g.A + (size_t)gr * g.lda + gk);

@@ -498,3 +498,58 @@ def test_bab_with_cuts_verifies_and_never_verifies_a_false_property():
                 assert r["lower"] <= exact + 1e-6
                 n_false += exact < 0
     assert n_true > 0 and n_false > 0
+
+
+# ------------------------------------------------------------ full sizes, sampled rows
+def _full_size_check(k, B, n_rows, seed=0):
+    # the workload at the size the bench times: bf16-optimised, fp32/fp64
+    # certified bounds of every row on the device; a random sample of rows
+    # recomputed by the oracle at the device's final parameters (fp64)
+    import torch
+    from paper_2208_05740_amd import binding as B_
+    prob = gen.make_config(k, 0, B=B)
+    P = upload(prob)
+    M = P.M
+    a = torch.tensor(gen.crown_alpha_init(prob.lu), dtype=torch.float32, device=_dev()).expand(M, -1).contiguous()
+    b = torch.tensor(prob.beta.reshape(M, -1), dtype=torch.float32, device=_dev())
+    c = torch.zeros(M, P.N, dtype=torch.float32, device=_dev())
+    st = torch.zeros(B_.adam_state_size(M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+    o = prob.opt
+    out, ver = B_.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=o["iters"],
+                           lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], mode=B_.GCP_MODE_BF16)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    assert np.isfinite(g).all()
+    assert np.array_equal(ver.cpu().numpy(), (g >= 0).astype(np.uint8))
+    rows = np.sort(np.random.default_rng(seed).choice(M, size=n_rows, replace=False))
+    f64 = lambda t: t.cpu().numpy().astype(np.float64)[rows]  # noqa: E731
+    ref = O.bound(prob, alpha=f64(a), beta=f64(b), gamma=f64(c), rows=rows, flat=True)
+    T = O.error_scale(prob, alpha=f64(a), beta=f64(b), gamma=f64(c), rows=rows, flat=True)
+    assert rel_err(g[rows], ref, T).max() <= 1e-5
+
+
+def test_config2_full_size_sampled_rows():
+    _full_size_check(2, 1024, 48)
+
+
+def test_config3_full_size_sampled_rows():
+    _full_size_check(3, 2048, 12)
+
+
+def test_config5_full_size_sampled_rows():
+    _full_size_check(5, 4096, 3)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn16", "res16"])
+def test_zero_radius_bound_is_the_network_output(kind):
+    # eps = 0: every neuron is stable at x0 and the bound is c^T f(x0) itself
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny(kind, 2, B=2, eps=0.0, n_cuts=0)
+    P = upload(p)
+    a, b, c, *_ = params(p, P)
+    out, _, _ = B.bound(P.net, P.x0, 0.0, P.C, P.splits, P.cuts, a, b, c, mode=0)
+    torch.cuda.synchronize()
+    f = lp.plain_forward(p.net, p.x0[None, :])[0]
+    want = np.tile(p.C @ f, p.B)
+    assert np.allclose(out.cpu().numpy(), want, rtol=1e-5, atol=1e-5 * (1 + np.abs(f).max()))
