@@ -50,7 +50,7 @@ def parse():
     if a.domains is None:
         a.domains = {2: 1024, 3: 2048, 5: 4096, 4: 0}[a.config]
     if a.cpu_domains is None:
-        a.cpu_domains = {2: 1024, 3: 16, 5: 1, 4: 0}[a.config]
+        a.cpu_domains = {2: 1024, 3: 256, 5: 16, 4: 0}[a.config]
     return a
 
 
@@ -377,7 +377,7 @@ def bench_batch(args):
         out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
                                     for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(probs[:8], 2)
+        out["cpu_baseline"] = cpu_baseline(probs[:8], 16)
     print(json.dumps(out))
 
 

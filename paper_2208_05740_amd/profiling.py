@@ -8,6 +8,10 @@
       HBM bytes per launch from FETCH_SIZE and WRITE_SIZE counter runs, each
       scaled by that counter's reading for a plain device copy of known size
       (bench.py --copy-probe-mb) so that counter units and sampling drop out.
+  python -m paper_2208_05740_amd.profiling mfma --db RUN_results.db --out FILE.md --cmd "..."
+      MFMA work of each GEMM kernel class from SQ_INSTS_VALU_MFMA_MOPS_BF16 /
+      _F32 (units of 512 FLOP): FLOP per dispatch, rate over the dispatch's
+      duration in the counter run, fraction of the dense MFMA peak.
 """
 import argparse
 import collections
@@ -22,9 +26,35 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EPI = {"bound": "BoundEpi", "conc": "ConcEpi", "adj": "AdjEpi", "store": "StoreEpi"}
 
 
+CONV_EPI = {"BoundEpi": "bound", "ConcEpi": "conc", "StoreEpi": "store", "AdjEpi": "adj", "AhatEpi": "ahat"}
+
+
+def conv_class_of(symbol):
+    """Kernel-class name ('convT_bound.bf16.w4x1', 'conv_adj.bf16.sign.w4x1',
+    ...) of a conv_slab instantiation (waves x column tiles), or None."""
+    m = re.search(r"conv_slab_kernelI(DF16b|f)Li(\d+)ELi(\d+)ELb([01])ELb([01])ENS_\d+(\w+?Epi)", symbol)
+    if m:
+        dt, nw, tn, tr, sg, epi = m.groups()
+    else:
+        m = re.search(r"conv_slab_kernel<(float|__bf16), (\d+), (\d+), (true|false), (true|false), gcp::(\w+Epi)",
+                      symbol)
+        if not m:
+            return None
+        dt, nw, tn, tr, sg, epi = m.groups()
+        tr, sg = ("1" if tr == "true" else "0"), ("1" if sg == "true" else "0")
+    kind = CONV_EPI.get(epi)
+    if kind is None:
+        return None
+    name = ("convT_" if tr == "1" else "conv_") + kind + (".bf16" if dt in ("DF16b", "__bf16") else ".fp32")
+    return name + (".sign" if sg == "1" else "") + f".w{nw}x{tn}"
+
+
 def class_of(symbol):
-    """Library kernel-class name ('adj.bf16.t32x32', ...) of a gemm_epi
-    instantiation, from its mangled or demangled symbol; None otherwise."""
+    """Library kernel-class name ('adj.bf16.t32x32', 'convT_bound.bf16.w4x1',
+    ...) of a gemm_epi or conv_slab instantiation, from its mangled or
+    demangled symbol; None otherwise."""
+    if "conv_slab_kernel" in symbol:
+        return conv_class_of(symbol)
     m = re.search(r"gemm_epi_kernelI(DF16b|f)Li(\d+)ELi(\d+)ELi\d+ELi\d+ELi\d+ELb([01])ENS_\d+(\w+?Epi)", symbol)
     if m:
         dt, bm, bn, sg, epi = m.groups()
@@ -129,6 +159,45 @@ def cmd_traffic(a):
     print(json.dumps(rec, indent=1))
 
 
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+
+
+def cmd_mfma(a):
+    con = sqlite3.connect(a.db)
+    cols = [r[1] for r in con.execute("pragma table_info(counters_collection)")]
+    ci = {c: i for i, c in enumerate(cols)}
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    dur, name = {}, {}
+    for r in con.execute("select * from counters_collection"):
+        d = r[ci["dispatch_id"]]
+        per[d][r[ci["counter_name"]]] += r[ci["value"]]
+        dur[d] = r[ci["end"]] - r[ci["start"]]
+        name[d] = r[ci["kernel_name"]]
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    for d, c in per.items():
+        cls = class_of(name[d])
+        if not cls:
+            continue
+        g = agg[cls]
+        g[0] += 1
+        g[1] += c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512
+        g[2] += c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
+        g[3] += dur[d]
+    lines = [f"# MFMA work per GEMM kernel class: {a.title}", "", f"Command: `{a.cmd}`", "",
+             "FLOP from SQ_INSTS_VALU_MFMA_MOPS_* (512 FLOP units, padding included); rate over the average "
+             "dispatch duration of the counter run; peaks: dense bf16 2500, fp32 157.3 TFLOP/s.", "",
+             "| kernel class | dispatches | MFMA GFLOP / dispatch | avg us | TFLOP/s | of peak |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for cls, (n, fb, ff, t) in sorted(agg.items(), key=lambda kv: -kv[1][3]):
+        flop = (fb + ff) / n
+        us = t / n / 1e3
+        dt = "bf16" if fb >= ff else "fp32"
+        rate = flop / (us * 1e-6) / 1e12 if us > 0 else 0.0
+        lines.append(f"| {cls} | {n} | {flop / 1e9:.2f} | {us:.1f} | {rate:.1f} | {100 * rate / PEAK_TFLOPS[dt]:.1f}% |")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -145,7 +214,15 @@ def main():
     t.add_argument("--out", required=True)
     t.add_argument("--cmd-fetch", default="")
     t.add_argument("--cmd-write", default="")
+    m = sub.add_parser("mfma")
+    m.add_argument("--db", required=True)
+    m.add_argument("--out", required=True)
+    m.add_argument("--cmd", default="")
+    m.add_argument("--title", default="")
     a = ap.parse_args()
+    if a.cmd_name == "mfma":
+        cmd_mfma(a)
+        return
     if a.cmd_name == "summary":
         a.cmd = a.cmd
         cmd_summary(a)
