@@ -141,11 +141,26 @@ __device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ g
   }
 }
 
+// floor(r / S) for 0 <= r < 2^31 through a double reciprocal, exact after a
+// one-step correction (cheaper than an integer division)
+__device__ inline int div_rows(int r, int S, double inv_S) {
+  int q = (int)((double)r * inv_S);
+  const int rem = r - q * S;
+  return q + (rem >= S ? 1 : (rem < 0 ? -1 : 0));
+}
+
+// Adam step lr * m_hat / (sqrt(v_hat) + eps): the bias corrections come as
+// reciprocals and the last quotient uses the hardware reciprocal (~1 ulp).
+// The step only moves the iterate; its bound is computed exactly later.
+__device__ inline float adam_step(float lr, float mm, float vv, float ibc1, float ibc2, float eps) {
+  return lr * (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + eps);
+}
+
 // effective class and split slot of each element (row, neuron)
 template <int R>
 __device__ inline void split_class(const RowParams& rp, int rank, int cls, int rc, int* c, int* slot) {
   int m = 0;
-  if (rank >= 0 && rp.mask) m = rp.mask[(size_t)(rc / rp.S) * rp.n_I + rank];
+  if (rank >= 0 && rp.mask) m = rp.mask[(size_t)div_rows(rc, rp.S, rp.inv_S) * rp.n_I + rank];
   *slot = m > 0 ? m - 1 : (m < 0 ? -m - 1 : -1);
   *c = m > 0 ? (int)ACTIVE : (m < 0 ? (int)INACTIVE : cls);
 }
@@ -435,9 +450,9 @@ struct AdjEpi {
                                const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
-    float lr_a = 0.f, lr_m = 0.f, bc1 = 1.f, bc2 = 1.f;
+    float lr_a = 0.f, lr_m = 0.f, ibc1 = 1.f, ibc2 = 1.f;
     if (a.adam.enabled) {
-      lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; bc1 = a.adam.consts[2]; bc2 = a.adam.consts[3];
+      lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; ibc1 = a.adam.consts[2]; ibc2 = a.adam.consts[3];
     }
     const float b1 = a.adam.b1, b2 = a.adam.b2, aeps = a.adam.eps;
 #pragma unroll
@@ -488,7 +503,7 @@ struct AdjEpi {
             const float vv = b2 * f.va[k][q] + (1.f - b2) * gA * gA;
             a.m_alpha[ia] = mm;
             a.v_alpha[ia] = vv;
-            const float stp = lr_a * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            const float stp = adam_step(lr_a, mm, vv, ibc1, ibc2, aeps);
             a.alpha_rw[ia] = fminf(fmaxf(f.al[k][q] + stp, 0.f), 1.f);
           } else {
             a.d_alpha[ia] = gA;
@@ -503,7 +518,7 @@ struct AdjEpi {
             const float vv = b2 * a.v_beta[ib] + (1.f - b2) * gB * gB;
             a.m_beta[ib] = mm;
             a.v_beta[ib] = vv;
-            const float stp = lr_m * (mm / bc1) / (sqrtf(vv / bc2) + aeps);
+            const float stp = adam_step(lr_m, mm, vv, ibc1, ibc2, aeps);
             a.beta_rw[ib] = fmaxf(a.beta_rw[ib] + stp, 0.f);
           } else {
             a.d_beta[ib] = gB;

@@ -42,12 +42,13 @@ struct RowParams {
   const float* beta;  int K;        // [M][K]     (caller layout)
   const float* gammaT; int N;       // [N][mp]    (internal transposed copy)
   const int8_t* mask;               // [B][n_I]: 0, +(slot+1) x>=0, -(slot+1) x<=0
+  double inv_S;                     // 1 / S (domain of a row without an integer division)
 };
 
 struct AdamArgs {
   int enabled;           // 0: write raw gradients instead of updating
   float b1, b2, eps;
-  const float* consts;   // device: {lr_alpha decay^t, lr_mult decay^t, 1-b1^(t+1), 1-b2^(t+1)}
+  const float* consts;   // device: {lr_alpha decay^t, lr_mult decay^t, 1/(1-b1^(t+1)), 1/(1-b2^(t+1))}
 };
 
 // ---------------------------------------------------------------- launchers

@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(256) gamma_kernel(int M, int mp, int N, const 
   double g = -d[k];
   for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e) g += (double)contrib[(size_t)e * mp + r];
   if (adam.enabled) {
-    const float lr = adam.consts[1], bc1 = adam.consts[2], bc2 = adam.consts[3];
+    const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
     const float gf = (float)g;
     const size_t im = (size_t)k * M + r;
     const float mm = adam.b1 * m[im] + (1.f - adam.b1) * gf;
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(256) gamma_kernel(int M, int mp, int N, const 
     m[im] = mm;
     v[im] = vv;
     float* gp = gammaT + (size_t)k * mp + r;
-    *gp = fmaxf(*gp + lr * (mm / bc1) / (sqrtf(vv / bc2) + adam.eps), 0.f);
+    *gp = fmaxf(*gp + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
   } else {
     d_gamma[(size_t)r * N + k] = (float)g;
   }
@@ -624,7 +624,7 @@ __global__ void __launch_bounds__(256) gamma_grouped(const GammaJob* __restrict_
   if (r >= jb.M) return;
   double g = -jb.d[k];
   for (int e = jb.row_ptr[k]; e < jb.row_ptr[k + 1]; ++e) g += (double)jb.contrib[(size_t)e * jb.mp + r];
-  const float lr = adam.consts[1], bc1 = adam.consts[2], bc2 = adam.consts[3];
+  const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
   const float gf = (float)g;
   const size_t im = (size_t)k * jb.M + r;
   const float mm = adam.b1 * jb.m[im] + (1.f - adam.b1) * gf;
@@ -632,7 +632,7 @@ __global__ void __launch_bounds__(256) gamma_grouped(const GammaJob* __restrict_
   jb.m[im] = mm;
   jb.v[im] = vv;
   float* gp = jb.gammaT + (size_t)k * jb.mp + r;
-  *gp = fmaxf(*gp + lr * (mm / bc1) / (sqrtf(vv / bc2) + adam.eps), 0.f);
+  *gp = fmaxf(*gp + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
 }
 
 hipError_t launch_gamma_grouped(const GammaJob* d_jobs, const int* d_prefix, int np, int total_blocks, AdamArgs adam,
@@ -688,8 +688,8 @@ __global__ void adam_prepare_kernel(int* step, int reset, float lr_alpha, float 
   double dec = pow((double)decay, (double)t);
   consts[0] = (float)(lr_alpha * dec);
   consts[1] = (float)(lr_mult * dec);
-  consts[2] = (float)(1.0 - pow((double)b1, (double)(t + 1)));
-  consts[3] = (float)(1.0 - pow((double)b2, (double)(t + 1)));
+  consts[2] = (float)(1.0 / (1.0 - pow((double)b1, (double)(t + 1))));
+  consts[3] = (float)(1.0 / (1.0 - pow((double)b2, (double)(t + 1))));
   *step = t + 1;
 }
 hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
