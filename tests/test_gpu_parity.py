@@ -553,3 +553,76 @@ def test_zero_radius_bound_is_the_network_output(kind):
     f = lp.plain_forward(p.net, p.x0[None, :])[0]
     want = np.tile(p.C @ f, p.B)
     assert np.allclose(out.cpu().numpy(), want, rtol=1e-5, atol=1e-5 * (1 + np.abs(f).max()))
+
+
+# ------------------------------------------------------------ soundness and finite differences
+@pytest.mark.parametrize("k", [1, 2])
+def test_certified_bounds_never_exceed_sampled_minimum(k):
+    # after the bf16-optimised ascent and the fp32/fp64 certifying pass, no
+    # bound is above the minimum of c^T f over sampled points of its domain
+    import torch
+    from paper_2208_05740_amd import binding as B
+    prob = gen.make_config(k, 0, B=None if k == 1 else 16)
+    P = upload(prob)
+    a, b, c, *_ = params(prob, P)
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+    out, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=20, mode=B.GCP_MODE_BF16)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().reshape(prob.B, prob.S)
+    for dom in range(prob.B):
+        smin = lp.sampled_min(prob, b=dom, n=20000 if k == 2 else 100000, seed=dom)
+        assert (g[dom] <= smin + 1e-9).all(), (dom, g[dom], smin)
+
+
+@pytest.mark.parametrize("kind,B_", [("res16", 2), ("cfg5", 1)])
+def test_adjoint_gradient_matches_central_differences(kind, B_):
+    # d bound / d alpha and d gamma from the device adjoint against central
+    # differences of the device bound (fp32 GEMMs, fp64 sums); the bound is
+    # piecewise linear in each coordinate, so coordinates whose one-sided
+    # slopes disagree (a kink within the step) are skipped
+    import torch
+    from paper_2208_05740_amd import binding as B
+    if kind == "cfg5":
+        prob = gen.make_config(5, 0, B=B_)
+    else:
+        prob = gen.make_tiny(kind, 4, B=B_, splits=(1, 2), n_cuts=5)
+    P = upload(prob)
+    a, b, c, *_ = params(prob, P)
+    a = a.clamp(0.05, 0.95)          # interior of the box, so +-h stays feasible
+    _, _, (ga, gb, gc) = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, mode=0, grads=True)
+
+    def total(a_, c_):
+        out, _, _ = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a_, b, c_, mode=0)
+        return float(out.double().sum().cpu())
+
+    # rounding noise of a central difference: fp32 unit roundoff times the
+    # total magnitude of the terms summed into the bound, over the step
+    a64 = a.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    b64 = b.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    c64 = c.cpu().numpy().astype(np.float64).reshape(prob.B, prob.S, -1)
+    T = float(O.error_scale(prob, a64, b64, c64).sum())
+    rng = np.random.default_rng(7)
+    h = 1e-2
+    noise = 4 * 2.0 ** -24 * T / h
+    checked = 0
+    for which, t, g in (("alpha", a, ga), ("gamma", c, gc)):
+        if t.numel() == 0:
+            continue
+        flat = t.view(-1)
+        for idx in rng.choice(flat.numel(), size=min(12, flat.numel()), replace=False):
+            f0 = total(a, c)
+            old = float(flat[idx])
+            flat[idx] = old + h
+            fp = total(a, c)
+            flat[idx] = old - h
+            fm = total(a, c)
+            flat[idx] = old
+            up, down = (fp - f0) / h, (f0 - fm) / h
+            scale = max(abs(up), abs(down), 1.0)
+            if abs(up - down) > 1e-3 * scale + 2 * noise:
+                continue                     # kink within the step
+            fd = (fp - fm) / (2 * h)
+            got = float(g.view(-1)[idx])
+            assert abs(got - fd) <= 1e-3 * max(abs(fd), abs(got)) + noise, (which, idx, got, fd, noise)
+            checked += 1
+    assert checked >= 6
