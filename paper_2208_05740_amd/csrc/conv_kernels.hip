@@ -9,17 +9,19 @@
 //   Yb = (y + pad - ry) / s,  Xb = (x + pad - rx) / s.
 // Adjoint direction (dLambda^(node) = A da_hat^(src)): a convolution,
 //   out[o][y][x] = sum_(c,ky,kx) X[c][y s - pad + ky][x s - pad + kx] W[o][(c,ky,kx)].
-// Both are "slab GEMMs": one workgroup takes one batch row and one band of
-// output rows, copies the source rows the band reads into LDS once (zero
-// halo, so the inner loop has no bounds checks), and forms MFMA A fragments
-// by gathering from the slab at base(position) + koff(k), with koff
-// precomputed per K index.  B fragments (weights, K contiguous) are read
-// from global memory, where the few KB of weights stay cached.  The MFMA
-// results of the band go to a second LDS buffer; the fused epilogue then
-// walks the band's neurons in memory order (a band of rows is a contiguous
-// run of each channel plane), so its loads and stores are coalesced and
-// every lane holds real neurons.  The row constant of a band goes to one
-// partial slot: slot0 + band.
+// Both are "slab GEMMs": one workgroup takes four consecutive batch rows and
+// one band of output rows.  For each batch row in turn it copies the source
+// rows the band reads into LDS (zero halo, so the inner loop has no bounds
+// checks), forms MFMA A fragments by gathering from the slab at
+// base(position) + koff(k), with koff precomputed per K index, and writes
+// the band's results to that row's LDS result buffer.  B fragments (weights,
+// K contiguous) are read from global memory, where the few KB of weights
+// stay cached.  The fused epilogue then walks the band's neurons in memory
+// order (a band of rows is a contiguous run of each channel plane), each
+// lane one neuron of the four batch rows -- the layout of the dense GEMM
+// epilogues, so a neuron's constants are read once for four rows and the
+// row-minor buffers are 16-byte accesses.  The row constant of a band goes
+// to one partial slot per batch row: slot0 + band.
 #include "gcp_internal.h"
 #include "epilogues.h"
 
@@ -30,8 +32,8 @@
 namespace gcp {
 
 namespace {
-constexpr int kSlabBudget = 48 * 1024;   // bytes of fp32 slab + result band a workgroup may use
-constexpr int kEpiRows = 4;              // neurons per lane in one epilogue round
+constexpr int kSlabBudget = 48 * 1024;   // bytes of fp32 slab + result bands a workgroup may use
+constexpr int kRows = 4;                 // batch rows per workgroup
 constexpr int kLdsLimit = 64 * 1024;
 __host__ __device__ inline int align16(int b) { return (b + 15) & ~15; }
 }  // namespace
@@ -77,7 +79,9 @@ ConvPlan conv_plan(const ConvGeom& g, int trans) {
   }
   P.KP = (P.Kreal + 31) / 32 * 32;
   auto rows_for = [&](int bh) { return trans ? (bh - 1) / s + 1 + P.A : (bh - 1) * s + g.kh; };
-  auto bytes_for = [&](int bh) { return ((long)P.Kch * rows_for(bh) * P.Wp + (long)P.Nch * (bh * P.We + 1)) * 4; };
+  auto bytes_for = [&](int bh) {
+    return ((long)P.Kch * rows_for(bh) * P.Wp + (long)kRows * P.Nch * (bh * P.We + 1)) * 4;
+  };
   int bh = P.He;
   while (bh > 1 && bytes_for(bh) > kSlabBudget) --bh;
   P.n_bands = (P.He + bh - 1) / bh;
@@ -133,8 +137,8 @@ void conv_pack_weights(const ConvGeom& g, int trans, const float* raw, float* ou
 }
 
 static int conv_lds_bytes(const ConvPlan& P, int esz, int nw) {
-  return align16(P.KP * 4) + align16(nw * 8) + align16(P.MT * 4) + P.MT * 16 * 8 + align16(P.Kch * P.CHS * esz) +
-         align16(P.Nch * P.OS * 4);
+  return align16(P.KP * 4) + align16(nw * 8 * kRows) + align16(P.MT * 4) + P.MT * 16 * 8 +
+         align16(P.Kch * P.CHS * esz) + kRows * align16(P.Nch * P.OS * 4);
 }
 
 // ---------------------------------------------------------------- slab fill
@@ -202,14 +206,15 @@ __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* sp = smem;
   int* koff = (int*)sp;        sp += align16(P.KP * 4);
-  double* red = (double*)sp;   sp += align16(NW * 8);
+  double* red = (double*)sp;   sp += align16(NW * 8 * kRows);
   int* tph = (int*)sp;         sp += align16(P.MT * 4);        // phase of each 16-row tile
   int2* desc = (int2*)sp;      sp += P.MT * 16 * 8;            // per GEMM row: {slab base, result offset or -1}
   T* slab = (T*)sp;            sp += align16(P.Kch * P.CHS * (int)sizeof(T));
   float* outs = (float*)sp;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = blockIdx.x / P.n_bands, band = blockIdx.x % P.n_bands;
+  const int r0 = (blockIdx.x / P.n_bands) * kRows, band = blockIdx.x % P.n_bands;
+  const int OQ = align16(P.Nch * P.OS * 4) / 4;                    // floats between the rows' result buffers
   const int s = P.s, p = P.p;
   const int yb0 = band * P.BH, yb1 = min(P.He, yb0 + P.BH);
   const int sy0 = TRANS ? (yb0 + p) / s - (P.A - 1) : yb0 * s - p;   // source row of slab row 0
@@ -254,118 +259,121 @@ __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan
     for (int i = tid; i < nt; i += NT) tph[ntile + i] = ph;
     ntile += nt;
   }
-  {
+  {   // the halo stays zero for every row: only interior cells are rewritten
     uint4* z = (uint4*)slab;
     const int n16 = align16(P.Kch * P.CHS * (int)sizeof(T)) / 16;
     for (int v = tid; v < n16; v += NT) z[v] = uint4{0u, 0u, 0u, 0u};
   }
-  __syncthreads();
-  {
-    const size_t xrow = (size_t)r * c.ldx;
-    const bool vec = P.ws % VEC == 0;
-    const int cw = vec ? VEC : 1;
-    const int nchunk = P.ws / cw;
-    const int total = P.Kch * P.rows_max * nchunk;
-    for (int v = tid; v < total; v += NT) {
-      const int xc = v % nchunk, rest = v / nchunk;
-      const int rho = rest % P.rows_max, ch = rest / P.rows_max;
-      const int sy = sy0 + rho;
-      if (sy < 0 || sy >= P.hs) continue;
-      const size_t src = xrow + ((size_t)ch * P.hs + sy) * P.ws + (size_t)xc * cw;
-      T* dst = slab + ch * P.CHS + rho * P.Wp + P.xl + xc * cw;
-      if (vec) {
-        T tmp[VEC];
-        SlabLoad<T, SIGN>::vec(c.X, src, tmp);
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) dst[q] = tmp[q];
-      } else {
-        dst[0] = SlabLoad<T, SIGN>::one(c.X, src);
-      }
-    }
-  }
-  __syncthreads();
-
-  // MFMA tiles: (16-row tile, column chunk of 16*TN channels) -> LDS result band
   const int nck = (P.Nch + 16 * TN - 1) / (16 * TN);
   const int g = lane >> 4;
-  for (int t = wave; t < ntile * nck; t += NW) {
-    const int tt = nck == 1 ? t : t / nck, ck = nck == 1 ? 0 : t - tt * nck;
-    const int ph = __builtin_amdgcn_readfirstlane(tph[tt]);
-    const int base = desc[tt * 16 + (lane & 15)].x;
-    f4 acc[TN];
+  for (int q = 0; q < kRows && r0 + q < c.M; ++q) {
+    const int r = r0 + q;
+    float* outq = outs + q * OQ;
+    __syncthreads();      // tables and zeros written; the previous row's MFMAs done with the slab
+    {
+      const size_t xrow = (size_t)r * c.ldx;
+      const bool vec = P.ws % VEC == 0;
+      const int cw = vec ? VEC : 1;
+      const int nchunk = P.ws / cw;
+      const int total = P.Kch * P.rows_max * nchunk;
+      for (int v = tid; v < total; v += NT) {
+        const int xc = v % nchunk, rest = v / nchunk;
+        const int rho = rest % P.rows_max, ch = rest / P.rows_max;
+        const int sy = sy0 + rho;
+        if (sy < 0 || sy >= P.hs) continue;
+        const size_t src = xrow + ((size_t)ch * P.hs + sy) * P.ws + (size_t)xc * cw;
+        T* dst = slab + ch * P.CHS + rho * P.Wp + P.xl + xc * cw;
+        if (vec) {
+          T tmp[VEC];
+          SlabLoad<T, SIGN>::vec(c.X, src, tmp);
 #pragma unroll
-    for (int k = 0; k < TN; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
-    const T* Bp = (const T*)c.Bt + (size_t)ph * P.Nch * c.ldb;
-    int nb[TN];
-#pragma unroll
-    for (int k = 0; k < TN; ++k) nb[k] = ck * 16 * TN + k * 16 + (lane & 15);
-    for (int k0 = 0; k0 < P.KP; k0 += KC) {
-      int ko[VEC];
-      const int4* kp = (const int4*)(koff + k0 + VEC * g);
-#pragma unroll
-      for (int q = 0; q < VEC / 4; ++q) {
-        const int4 t4 = kp[q];
-        ko[4 * q] = t4.x; ko[4 * q + 1] = t4.y; ko[4 * q + 2] = t4.z; ko[4 * q + 3] = t4.w;
-      }
-      const uint4 fa = Gather<T>::get(slab, base, ko);
-#pragma unroll
-      for (int k = 0; k < TN; ++k) {
-        uint4 fb = {0u, 0u, 0u, 0u};
-        if (nb[k] < P.Nch) fb = *(const uint4*)(Bp + (size_t)nb[k] * c.ldb + k0 + VEC * g);
-        Op<T>::mma(fa, fb, acc[k]);
+          for (int e = 0; e < VEC; ++e) dst[e] = tmp[e];
+        } else {
+          dst[0] = SlabLoad<T, SIGN>::one(c.X, src);
+        }
       }
     }
+    __syncthreads();
+
+    // MFMA tiles: (16-row tile, column chunk of 16*TN channels) -> this row's result band
+    for (int t = wave; t < ntile * nck; t += NW) {
+      const int tt = nck == 1 ? t : t / nck, ck = nck == 1 ? 0 : t - tt * nck;
+      const int ph = __builtin_amdgcn_readfirstlane(tph[tt]);
+      const int base = desc[tt * 16 + (lane & 15)].x;
+      f4 acc[TN];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int o = desc[tt * 16 + g * 4 + v].y;
-      if (o < 0) continue;
+      for (int k = 0; k < TN; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+      const T* Bp = (const T*)c.Bt + (size_t)ph * P.Nch * c.ldb;
+      int nb[TN];
 #pragma unroll
-      for (int k = 0; k < TN; ++k)
-        if (nb[k] < P.Nch) outs[nb[k] * P.OS + o] = acc[k][v];
+      for (int k = 0; k < TN; ++k) nb[k] = ck * 16 * TN + k * 16 + (lane & 15);
+      for (int k0 = 0; k0 < P.KP; k0 += KC) {
+        int ko[VEC];
+        const int4* kp = (const int4*)(koff + k0 + VEC * g);
+#pragma unroll
+        for (int e = 0; e < VEC / 4; ++e) {
+          const int4 t4 = kp[e];
+          ko[4 * e] = t4.x; ko[4 * e + 1] = t4.y; ko[4 * e + 2] = t4.z; ko[4 * e + 3] = t4.w;
+        }
+        const uint4 fa = Gather<T>::get(slab, base, ko);
+#pragma unroll
+        for (int k = 0; k < TN; ++k) {
+          uint4 fb = {0u, 0u, 0u, 0u};
+          if (nb[k] < P.Nch) fb = *(const uint4*)(Bp + (size_t)nb[k] * c.ldb + k0 + VEC * g);
+          Op<T>::mma(fa, fb, acc[k]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = desc[tt * 16 + g * 4 + v].y;
+        if (o < 0) continue;
+#pragma unroll
+        for (int k = 0; k < TN; ++k)
+          if (nb[k] < P.Nch) outq[nb[k] * P.OS + o] = acc[k][v];
+      }
     }
   }
   __syncthreads();
 
-  // fused epilogue over the band's neurons in memory order
-  double rs[kEpiRows];
+  // fused epilogue over the band's neurons in memory order, one neuron of the
+  // four batch rows per lane and step
+  double rs[kRows];
 #pragma unroll
-  for (int q = 0; q < kEpiRows; ++q) rs[q] = 0.0;
+  for (int q = 0; q < kRows; ++q) rs[q] = 0.0;
   {
     const int per_ch = (yb1 - yb0) * P.We;
     const int nel = P.Nch * per_ch;
     const int j0 = yb0 * P.We;
     const float inv_pc = 1.f / (float)per_ch;
-    for (int e0 = wave * 64 * kEpiRows; e0 < nel; e0 += NT * kEpiRows) {
-      LaneCoords<kEpiRows, 1, true> lc;
-      float val[1][kEpiRows];
+    LaneCoords<kRows, 1, false> lc;
 #pragma unroll
-      for (int q = 0; q < kEpiRows; ++q) {
-        const int e = e0 + q * 64 + lane;
-        const bool ok = e < nel;
-        // e = n * per_ch + off; the float quotient is within one of n
-        int n = (int)((float)e * inv_pc), off = e - n * per_ch;
-        if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
-        lc.r[q] = ok ? r : c.M;
-        lc.j[0][q] = ok ? n * HWe + j0 + off : node_size;
-        val[0][q] = ok ? outs[n * P.OS + off] : 0.f;
-      }
-      typename Epi::template Frag<kEpiRows, 1, true> fr;
-      epi.template load<kEpiRows, 1, true>(fr, lc, c.M, node_size);
-      epi.template apply<kEpiRows, 1, true>(fr, lc, val, rs, c.M, node_size);
+    for (int q = 0; q < kRows; ++q) lc.r[q] = r0 + q;
+    for (int e = tid; e < nel; e += NT) {
+      // e = n * per_ch + off; the float quotient is within one of n
+      int n = (int)((float)e * inv_pc), off = e - n * per_ch;
+      if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
+      lc.j[0][0] = n * HWe + j0 + off;
+      float val[1][kRows];
+#pragma unroll
+      for (int q = 0; q < kRows; ++q) val[0][q] = r0 + q < c.M ? outs[q * OQ + n * P.OS + off] : 0.f;
+      typename Epi::template Frag<kRows, 1, false> fr;
+      epi.template load<kRows, 1, false>(fr, lc, c.M, node_size);
+      epi.template apply<kRows, 1, false>(fr, lc, val, rs, c.M, node_size);
     }
   }
 
   if (c.partial) {
-    double tsum = 0.0;
 #pragma unroll
-    for (int q = 0; q < kEpiRows; ++q) tsum += rs[q];
-    for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
-    if (lane == 0) red[wave] = tsum;
+    for (int q = 0; q < kRows; ++q) {
+      double tsum = rs[q];
+      for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+      if (lane == 0) red[wave * kRows + q] = tsum;
+    }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < kRows && r0 + tid < c.M) {
       double sum = 0.0;
-      for (int w = 0; w < NW; ++w) sum += red[w];
-      c.partial[(size_t)(c.slot0 + band) * c.mp + r] = sum;
+      for (int w = 0; w < NW; ++w) sum += red[w * kRows + tid];
+      c.partial[(size_t)(c.slot0 + band) * c.mp + r0 + tid] = sum;
     }
   }
 }
@@ -379,7 +387,7 @@ template <typename T, int NW, int TN, bool TRANS, bool SIGN, class Epi>
 static hipError_t conv_go(const ConvArgs& c, const ConvPlan& P, const Epi& epi, hipStream_t st) {
   const int lds = conv_lds_bytes(P, (int)sizeof(T), NW);
   if (lds > kLdsLimit) return hipErrorInvalidValue;
-  const long grid = (long)c.M * P.n_bands;
+  const long grid = (long)((c.M + kRows - 1) / kRows) * P.n_bands;
   if (grid <= 0 || grid > 0x7fffffffL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((conv_slab_kernel<T, NW, TN, TRANS, SIGN, Epi>), dim3((unsigned)grid), dim3(NW * 64),
                      (unsigned)lds, st, c, P, epi);
