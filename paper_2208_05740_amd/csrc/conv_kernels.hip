@@ -34,6 +34,7 @@ namespace gcp {
 namespace {
 constexpr int kSlabBudget = 48 * 1024;   // bytes of fp32 slab + result bands a workgroup may use
 constexpr int kRows = 4;                 // batch rows per workgroup
+constexpr int kEpiN = 1;                 // neurons per lane in one epilogue step
 constexpr int kLdsLimit = 64 * 1024;
 __host__ __device__ inline int align16(int b) { return (b + 15) & ~15; }
 }  // namespace
@@ -335,8 +336,9 @@ __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan
   }
   __syncthreads();
 
-  // fused epilogue over the band's neurons in memory order, one neuron of the
-  // four batch rows per lane and step
+  // fused epilogue over the band's neurons in memory order: per step a lane
+  // takes kEpiN neurons (NT apart) of the four batch rows, so that the
+  // dependent load chains of several neurons are in flight together
   double rs[kRows];
 #pragma unroll
   for (int q = 0; q < kRows; ++q) rs[q] = 0.0;
@@ -345,20 +347,25 @@ __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan
     const int nel = P.Nch * per_ch;
     const int j0 = yb0 * P.We;
     const float inv_pc = 1.f / (float)per_ch;
-    LaneCoords<kRows, 1, false> lc;
+    LaneCoords<kRows, kEpiN, false> lc;
 #pragma unroll
     for (int q = 0; q < kRows; ++q) lc.r[q] = r0 + q;
-    for (int e = tid; e < nel; e += NT) {
-      // e = n * per_ch + off; the float quotient is within one of n
-      int n = (int)((float)e * inv_pc), off = e - n * per_ch;
-      if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
-      lc.j[0][0] = n * HWe + j0 + off;
-      float val[1][kRows];
+    for (int e0 = tid; e0 < nel; e0 += kEpiN * NT) {
+      float val[kEpiN][kRows];
 #pragma unroll
-      for (int q = 0; q < kRows; ++q) val[0][q] = r0 + q < c.M ? outs[q * OQ + n * P.OS + off] : 0.f;
-      typename Epi::template Frag<kRows, 1, false> fr;
-      epi.template load<kRows, 1, false>(fr, lc, c.M, node_size);
-      epi.template apply<kRows, 1, false>(fr, lc, val, rs, c.M, node_size);
+      for (int k = 0; k < kEpiN; ++k) {
+        const int e = e0 + k * NT;
+        // e = n * per_ch + off; the float quotient is within one of n
+        int n = (int)((float)e * inv_pc), off = e - n * per_ch;
+        if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
+        const bool ok = e < nel;
+        lc.j[k][0] = ok ? n * HWe + j0 + off : node_size;   // node_size marks no neuron
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) val[k][q] = ok && r0 + q < c.M ? outs[q * OQ + n * P.OS + off] : 0.f;
+      }
+      typename Epi::template Frag<kRows, kEpiN, false> fr;
+      epi.template load<kRows, kEpiN, false>(fr, lc, c.M, node_size);
+      epi.template apply<kRows, kEpiN, false>(fr, lc, val, rs, c.M, node_size);
     }
   }
 
