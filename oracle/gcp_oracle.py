@@ -133,6 +133,22 @@ def unstable_pi_h(a_hat, s, l, u):
     return pi, h
 
 
+def explicit_pi_h(a_hat, s, l, u, rho):
+    """pi and h of an unstable neuron when pi is a free variable instead of
+    Lemma A.1's maximiser (the remark closing the proof of Theorem 3.1 in
+    Appendix A: pi and the upper-relaxation multiplier can be optimised too).
+
+    The single-neuron problem of the proof maximises
+      h(pi) = l pi - [u (n - pi) + l pi - s]_+      over 0 <= pi <= n,
+    n = [-a_hat]_+ (the upper multiplier being n - pi).  Every feasible pi is
+    a valid dual point, so the bound stays sound; pi = rho * n with
+    rho in [0, 1] is the parametrisation used here."""
+    n = torch.relu(-a_hat)
+    pi = rho * n
+    h = l * pi - torch.relu(u * n - (u - l) * pi - s)
+    return pi, h
+
+
 def _cut_term(prob, gamma, node, kind, size):
     """(gamma^T X)_j for X in {H, G, Q} of one node: a sparse gather."""
     cu = prob.cuts
@@ -146,7 +162,7 @@ def _cut_term(prob, gamma, node, kind, size):
     return out.index_add(1, j, gamma[:, k] * c)
 
 
-def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False):
+def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False, rho=None):
     """Theorem 3.1 objective g for every (domain, spec row).
 
     alpha [M, n_I], beta [M, K], gamma [M, N] are float64 tensors over the
@@ -156,7 +172,9 @@ def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False)
     Returns g [M]; with ``with_scale`` also the sum of the magnitudes of
     every term added into g (the natural scale of its rounding error):
     sum|v_k x0_k| + eps*||v||_1 + sum|Lambda_j b_j| + sum|h_j| +
-    sum|s_j (active)| + sum|gamma_k d_k|."""
+    sum|s_j (active)| + sum|gamma_k d_k|.
+    ``rho`` [M, n_I] (optional, layout of alpha) replaces Lemma A.1's pi* of
+    every root-unstable neuron by pi = rho * [-a_hat]_+ (explicit_pi_h)."""
     prep = prep or Prepared(prob)
     net = prob.net
     S = prob.S
@@ -211,7 +229,13 @@ def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False)
         if cols.numel():
             a_full = a_full.index_copy(1, cols, alpha[:, torch.as_tensor(prep.alpha_pos[p])])
 
-        pi, h = unstable_pi_h(a_hat, s, l, u)
+        if rho is None:
+            pi, h = unstable_pi_h(a_hat, s, l, u)
+        else:
+            r_full = torch.zeros(M, d, dtype=torch.float64)
+            if cols.numel():
+                r_full = r_full.index_copy(1, cols, rho[:, torch.as_tensor(prep.alpha_pos[p])])
+            pi, h = explicit_pi_h(a_hat, s, l, u, r_full)
         lam_uns = a_full * torch.relu(a_hat) - pi + t
 
         lam = torch.where(act, a_hat + t, torch.where(ina, t, lam_uns)) + split_term
@@ -346,3 +370,82 @@ def error_scale(prob, alpha=None, beta=None, gamma=None, rows=None, prep=None, f
     with torch.no_grad():
         _, T = bound_rows(prob, a, b, c, prep, rows, with_scale=True)
     return T.numpy()
+
+
+# ---------------------------------------------------------------- explicit pi
+def full_rho(prob, prep=None):
+    """Starting rho [B, S, n_I]: u / (u - l), which is Lemma A.1's pi* / n
+    whenever the neuron's cut term s is 0 (no cut uses its z), so the first
+    bound equals the closed form's on cut-free neurons."""
+    prep = prep or Prepared(prob)
+    r = []
+    for k, p in enumerate(prep.relu):
+        l, u = prob.lu[k]
+        c = prep.unst_cols[p]
+        r.append(u[c] / (u[c] - l[c]))
+    vec = np.concatenate(r) if r else np.zeros(0)
+    return np.broadcast_to(vec, (prob.B, prob.S, vec.size)).copy()
+
+
+def _rho_param(prob, rho, rows, prep, flat):
+    if flat:
+        return _t(rho)
+    rho = full_rho(prob, prep) if rho is None else rho
+    r = _t(rho).reshape(prob.B * prob.S, -1)
+    if rows is not None:
+        r = r[torch.as_tensor(np.asarray(rows))]
+    return r
+
+
+def bound_pi(prob, alpha=None, beta=None, gamma=None, rho=None, rows=None, prep=None, flat=False):
+    """Bounds with explicit pi = rho * [-a_hat]_+ (explicit_pi_h)."""
+    prep = prep or Prepared(prob)
+    a, b, c = _params(prob, alpha, beta, gamma, rows, prep, flat)
+    r = _rho_param(prob, rho, rows, prep, flat)
+    with torch.no_grad():
+        g = bound_rows(prob, a, b, c, prep, rows, rho=r)
+    g = g.numpy()
+    return g if rows is not None else g.reshape(prob.B, prob.S)
+
+
+def bound_and_grad_pi(prob, alpha=None, beta=None, gamma=None, rho=None, rows=None, prep=None, flat=False):
+    """bound_pi and d(sum of bounds)/d(alpha, beta, gamma, rho) in float64
+    reverse mode (same kink conventions as bound_and_grad)."""
+    prep = prep or Prepared(prob)
+    a, b, c = _params(prob, alpha, beta, gamma, rows, prep, flat)
+    r = _rho_param(prob, rho, rows, prep, flat)
+    a, b, c, r = (x.clone().requires_grad_(True) for x in (a, b, c, r))
+    g = bound_rows(prob, a, b, c, prep, rows, rho=r)
+    g.sum().backward()
+    shp = (lambda x: x) if rows is not None else (lambda x: x.reshape(prob.B, prob.S, -1))
+    gv = g.detach().numpy()
+    return (gv if rows is not None else gv.reshape(prob.B, prob.S),
+            shp(_grad(a)), shp(_grad(b)), shp(_grad(c)), shp(_grad(r)))
+
+
+def optimize_pi(prob, iters=None, alpha=None, beta=None, gamma=None, rho=None, rows=None, opt=None, prep=None,
+                flat=False):
+    """optimize with rho as a fourth parameter: Adam ascent with alpha's
+    learning rate, projected onto [0, 1] like alpha.  Returns (bound [M],
+    alpha, beta, gamma, rho) over ``rows``."""
+    prep = prep or Prepared(prob)
+    o = dict(prob.opt)
+    o.update(opt or {})
+    iters = o["iters"] if iters is None else iters
+    rows = np.arange(prob.B * prob.S) if rows is None else np.asarray(rows)
+    a, b, c = (x.numpy().copy() for x in _params(prob, alpha, beta, gamma, rows, prep, flat))
+    r = _rho_param(prob, rho, rows, prep, flat).numpy().copy()
+    ma, va = np.zeros_like(a), np.zeros_like(a)
+    mb, vb = np.zeros_like(b), np.zeros_like(b)
+    mc, vc = np.zeros_like(c), np.zeros_like(c)
+    mr, vr = np.zeros_like(r), np.zeros_like(r)
+    b1, b2, ae = o["adam_b1"], o["adam_b2"], o["adam_eps"]
+    for it in range(iters):
+        _, ga, gb, gc, gr = bound_and_grad_pi(prob, a, b, c, r, rows=rows, prep=prep, flat=True)
+        dec = o["decay"] ** it
+        a, ma, va = adam_step(a, ga, ma, va, it + 1, o["lr_alpha"] * dec, b1, b2, ae, 0.0, 1.0)
+        b, mb, vb = adam_step(b, gb, mb, vb, it + 1, o["lr_mult"] * dec, b1, b2, ae, 0.0, np.inf)
+        c, mc, vc = adam_step(c, gc, mc, vc, it + 1, o["lr_mult"] * dec, b1, b2, ae, 0.0, np.inf)
+        r, mr, vr = adam_step(r, gr, mr, vr, it + 1, o["lr_alpha"] * dec, b1, b2, ae, 0.0, 1.0)
+    gfin = bound_pi(prob, a, b, c, r, rows=rows, prep=prep, flat=True)
+    return gfin, a, b, c, r

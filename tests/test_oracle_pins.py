@@ -445,3 +445,96 @@ def test_crown_intermediate_bounds_contain_sampled_preactivations(kind, seed):
     relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
     for (l, u), i in zip(lu, relu):
         assert (pre[i] >= l[None, :] - 1e-9).all() and (pre[i] <= u[None, :] + 1e-9).all()
+
+
+# ------------------------------- explicit pi (Appendix A, closing remark)
+
+def test_explicit_pi_h_is_the_lemma_objective():
+    # h(pi) of the free-pi form is the single-neuron objective of the proof:
+    # never above Lemma A.1's optimum (brute force), equal to it at
+    # pi = pi*, and its maximum over a fine rho grid reaches it.
+    rng = np.random.default_rng(11)
+    grid = torch.linspace(0.0, 1.0, 4001, dtype=torch.float64)
+    for _ in range(400):
+        l = -rng.exponential(1.0)
+        u = rng.exponential(1.0)
+        C = rng.exponential(1.0)
+        s = rng.normal() * 2.0
+        T = lambda x: torch.full_like(grid, x)
+        _, h = O.explicit_pi_h(T(-C), T(s), T(l), T(u), grid)
+        hb = _brute_h(l, u, C, s)
+        assert h.max().item() <= hb + 1e-9 * (1 + abs(hb))
+        assert hb - h.max().item() <= (u - l) * C / 4000 + 1e-12
+        pi_star, h_star = O.unstable_pi_h(torch.tensor([-C], dtype=torch.float64),
+                                          torch.tensor([s], dtype=torch.float64),
+                                          torch.tensor([l], dtype=torch.float64),
+                                          torch.tensor([u], dtype=torch.float64))
+        t1 = lambda x: torch.tensor([x], dtype=torch.float64)
+        _, h1 = O.explicit_pi_h(t1(-C), t1(s), t1(l), t1(u), t1(pi_star.item() / C))
+        assert abs(h1.item() - h_star.item()) <= 1e-9 * (1 + abs(hb))
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("cnn", 1), ("res", 2)])
+def test_explicit_pi_at_lemma_ratio_without_cut_terms_is_closed_form(kind, seed):
+    # With gamma = 0 every s_j is 0 and Lemma A.1's pi* is n u/(u - l):
+    # rho = u/(u - l) must reproduce the closed-form bound exactly.
+    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=5, input_terms=1)
+    rng = np.random.default_rng(seed)
+    a, b, c = _random_params(p, rng, scale=0.5)
+    c[:] = 0.0
+    g0 = O.bound(p, a, b, c)
+    g1 = O.bound_pi(p, a, b, c, O.full_rho(p))
+    assert np.allclose(g0, g1, rtol=1e-12, atol=1e-10)
+    # and a different rho gives a different (not larger) value somewhere
+    r = rng.random(O.full_rho(p).shape)
+    assert np.all(O.bound_pi(p, a, b, c, r) <= g0 + 1e-9)
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("mlp", 5), ("cnn", 1), ("res", 2)])
+def test_explicit_pi_bound_below_lp(kind, seed):
+    # any rho in [0, 1] is a feasible dual point: weak duality against the
+    # LP-cut optimum, for random multipliers of every scale
+    p = gen.make_tiny(kind, seed, B=3, splits=(1, 2), n_cuts=5, input_terms=1)
+    rng = np.random.default_rng(seed + 100)
+    lpv = np.array([[lp.lp_value(p, b, s) for s in range(p.S)] for b in range(p.B)])
+    for trial in range(12):
+        a, b, c = _random_params(p, rng, scale=[0.0, 0.1, 1.0, 5.0][trial % 4])
+        r = rng.random(a.shape)
+        g = O.bound_pi(p, a, b, c, r)
+        assert np.all(g <= lpv + 1e-8), (g, lpv)
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("cnn", 1), ("res", 2)])
+def test_explicit_pi_gradient_matches_finite_differences(kind, seed):
+    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=5, input_terms=1)
+    rng = np.random.default_rng(seed)
+    a, b, c = _random_params(p, rng, scale=0.5)
+    r = rng.random(a.shape)
+    _, ga, gb, gc, gr = O.bound_and_grad_pi(p, a, b, c, r)
+    h = 1e-6
+    checked = 0
+    args = [a, b, c, r]
+    for k, grad in enumerate((ga, gb, gc, gr)):
+        arr = args[k]
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(flat.size, 20), replace=False) if flat.size else []:
+            x = arr.copy().reshape(-1)
+            x[idx] += h
+            gp = O.bound_pi(p, *[x.reshape(arr.shape) if i == k else y for i, y in enumerate(args)])
+            x[idx] -= 2 * h
+            gm = O.bound_pi(p, *[x.reshape(arr.shape) if i == k else y for i, y in enumerate(args)])
+            fd = (gp - gm).sum() / (2 * h)
+            an = grad.reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-3 * max(1.0, abs(an)) + 1e-6, (k, idx, fd, an)
+            checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("cnn", 1)])
+def test_optimised_explicit_pi_is_sound_with_tight_cuts(kind, seed):
+    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=6, input_terms=1,
+                      gamma_dist="zero", beta_dist="zero")
+    p.cuts.d[:] = [lp.cut_max(p, k) for k in range(p.cuts.n)]
+    lpv = np.array([[lp.lp_value(p, b, s) for s in range(p.S)] for b in range(p.B)])
+    g, *_ = O.optimize_pi(p, iters=150, opt=dict(decay=0.99, lr_alpha=0.05, lr_mult=0.05))
+    assert np.all(g.reshape(p.B, p.S) <= lpv + 1e-7), (g, lpv)
