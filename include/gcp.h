@@ -214,6 +214,43 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  const gcp_opt* opt, int32_t mode,
                  double* bound, uint8_t* verified, void* stream);
 
+/* ------------------------------------------------------------ explicit pi */
+/* Variant of the unstable-neuron rule in which pi is a free variable
+ * instead of Lemma A.1's maximiser.  In the proof of Theorem 3.1
+ * (Appendix A) each unstable neuron's dual splits [-a_hat]_+ into pi and
+ * the upper multiplier [-a_hat]_+ - pi; every split with both parts >= 0 is
+ * a feasible dual point, and the closing remark of the proof notes that
+ * optimising them (rather than taking the per-neuron optimum) can tighten
+ * the bound.  Here pi = rho * [-a_hat]_+ with one rho in [0, 1] per
+ * (row, root-unstable neuron), so that
+ *   Lambda_j = alpha_j [a_hat]_+ - pi + t_j,
+ *   h_j      = l pi - [u ([-a_hat]_+ - pi) + l pi - s_j]_+ .
+ * rho = u / (u - l) gives Lemma A.1's pi* wherever s_j = 0.
+ *
+ * gcp_bound_pi: gcp_bound with rho (device fp32 [M][n_I], layout of
+ * alpha, in [0,1]) and its gradient d_rho (optional like the others; pass
+ * all four gradient outputs or none).  gcp_optimize_pi: gcp_optimize with
+ * rho updated in place by projected Adam with alpha's learning rate and
+ * clamp; adam_state holds 2*M*(n_I + K + N) + 2*M*n_I floats: the
+ * gcp_optimize layout followed by m_rho [M][n_I], v_rho [M][n_I].  The
+ * relaxation of every ReLU node then runs as an elementwise pass after its
+ * GEMMs (the fused GEMM epilogues implement pi* only), and grouped batch
+ * launches do not take this variant.  Errors: as gcp_bound / gcp_optimize;
+ * EINVAL for a null rho when n_I > 0; ERANGE (with GCP_FLAG_VALIDATE) for
+ * rho outside [0,1]. */
+int gcp_bound_pi(const gcp_net* net, const double* x0, double eps,
+                 const double* C, int32_t S,
+                 const gcp_splits* splits, const gcp_cuts* cuts,
+                 const float* alpha, const float* beta, const float* gamma, const float* rho,
+                 int32_t mode, double* bound, uint8_t* verified,
+                 float* d_alpha, float* d_beta, float* d_gamma, float* d_rho, void* stream);
+int gcp_optimize_pi(const gcp_net* net, const double* x0, double eps,
+                    const double* C, int32_t S,
+                    const gcp_splits* splits, const gcp_cuts* cuts,
+                    float* alpha, float* beta, float* gamma, float* rho, float* adam_state,
+                    const gcp_opt* opt, int32_t mode,
+                    double* bound, uint8_t* verified, void* stream);
+
 /* ------------------------------------------------------------ intermediate bounds */
 /* gcp_crown_bounds: pre-activation bounds l, u of every ReLU node of the
  * network `desc` (its lower/upper fields are ignored) over the L-inf box

@@ -363,12 +363,14 @@ def optimize(prob, iters=None, alpha=None, beta=None, gamma=None, rows=None, opt
     return out + (hist,) if history else out
 
 
-def error_scale(prob, alpha=None, beta=None, gamma=None, rows=None, prep=None, flat=False):
-    """Per-row sum of the magnitudes of all terms added into the bound."""
+def error_scale(prob, alpha=None, beta=None, gamma=None, rows=None, prep=None, flat=False, rho=None):
+    """Per-row sum of the magnitudes of all terms added into the bound (of
+    the explicit-pi bound when ``rho`` is given)."""
     prep = prep or Prepared(prob)
     a, b, c = _params(prob, alpha, beta, gamma, rows, prep, flat)
+    r = None if rho is None else _rho_param(prob, rho, rows, prep, flat)
     with torch.no_grad():
-        _, T = bound_rows(prob, a, b, c, prep, rows, with_scale=True)
+        _, T = bound_rows(prob, a, b, c, prep, rows, with_scale=True, rho=r)
     return T.numpy()
 
 

@@ -103,6 +103,9 @@ def lib():
     L.gcp_splits_destroy.argtypes = [vp]
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
+    L.gcp_bound_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gcp_optimize_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp,
+                                  vp]
     L.gcp_optimize_batch.argtypes = [i32, C.POINTER(BatchItem), C.POINTER(OptDesc), i32, vp]
     L.gcp_crown_bounds.argtypes = [C.POINTER(NetDesc), vp, dbl, C.POINTER(vp), C.POINTER(vp), i32, vp]
     L.gcp_net_get_unstable.argtypes = [vp, vp, vp, vp, vp]
@@ -313,6 +316,47 @@ def optimize(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cut
     return out, ver
 
 
+def bound_pi(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma, rho,
+             mode: int = GCP_MODE_FP32, grads: bool = False, verified: bool = False, validate: bool = False):
+    """gcp_bound_pi (explicit pi = rho * [-a_hat]_+); returns (bound[M],
+    verified or None, (d_alpha, d_beta, d_gamma, d_rho) or None)."""
+    import torch
+    dev = x0.device
+    S = Cspec.shape[0]
+    M = splits.B * S
+    out = torch.empty(M, dtype=torch.float64, device=dev)
+    ver = torch.empty(M, dtype=torch.uint8, device=dev) if verified else None
+    g = None
+    if grads:
+        g = (torch.empty_like(alpha), torch.empty_like(beta), torch.empty_like(gamma), torch.empty_like(rho))
+    md = mode | (GCP_FLAG_VALIDATE if validate else 0)
+    opt = lambda t: _ptr(t) if t.numel() else None
+    _check(lib().gcp_bound_pi(net.h, _ptr(x0), float(eps), _ptr(Cspec), S, splits.h, cuts.h if cuts else None,
+                              opt(alpha), opt(beta), opt(gamma), opt(rho), md, _ptr(out), _ptr(ver),
+                              *(opt(t) for t in g) if g else (None, None, None, None), _stream()))
+    return out, ver, g
+
+
+def optimize_pi(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma, rho,
+                adam_state, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.9, b2=0.999, adam_eps=1e-8,
+                mode: int = GCP_MODE_FP32, use_graph: bool = False):
+    """gcp_optimize_pi (alpha, beta, gamma, rho, adam_state updated in place;
+    adam_state of adam_state_size(..., explicit_pi=True) floats); returns
+    (bound[M] fp64 of the certifying pass, verified[M] uint8)."""
+    import torch
+    dev = x0.device
+    S = Cspec.shape[0]
+    M = splits.B * S
+    out = torch.empty(M, dtype=torch.float64, device=dev)
+    ver = torch.empty(M, dtype=torch.uint8, device=dev)
+    o = OptDesc(iters, lr_alpha, lr_mult, decay, b1, b2, adam_eps, int(use_graph))
+    opt = lambda t: _ptr(t) if t.numel() else None
+    _check(lib().gcp_optimize_pi(net.h, _ptr(x0), float(eps), _ptr(Cspec), S, splits.h, cuts.h if cuts else None,
+                                 opt(alpha), opt(beta), opt(gamma), opt(rho), _ptr(adam_state), C.byref(o), mode,
+                                 _ptr(out), _ptr(ver), _stream()))
+    return out, ver
+
+
 def optimize_batch(items, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.9, b2=0.999, adam_eps=1e-8,
                    mode: int = GCP_MODE_FP32, use_graph: bool = False):
     """gcp_optimize_batch over a list of dicts with keys P (a Problem),
@@ -331,8 +375,8 @@ def optimize_batch(items, iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9, b1=0.
     _check(lib().gcp_optimize_batch(len(items), arr, C.byref(o), mode, _stream()))
 
 
-def adam_state_size(M, n_I, K, N):
-    return 2 * M * (n_I + K + N)
+def adam_state_size(M, n_I, K, N, explicit_pi=False):
+    return 2 * M * (n_I + K + N) + (2 * M * n_I if explicit_pi else 0)
 
 
 class Problem:

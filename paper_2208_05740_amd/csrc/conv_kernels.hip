@@ -440,6 +440,7 @@ static hipError_t conv_typed(int cfg, EpiKind kind, const ConvArgs& c, const voi
 
 hipError_t launch_conv(int bf16_mode, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st) {
   if (c.M <= 0) return hipSuccess;
+  if (fused_explicit_pi(kind, epi)) return hipErrorInvalidValue;   // elementwise kernels only
   return bf16_mode ? conv_typed<bf16>(cfg, kind, c, epi, st) : conv_typed<float>(cfg, kind, c, epi, st);
 }
 

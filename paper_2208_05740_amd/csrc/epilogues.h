@@ -167,8 +167,10 @@ __device__ inline void split_class(const RowParams& rp, int rank, int cls, int r
 
 // ------------------------------------------------------------------ bound
 // Theorem 3.1 relaxation of one ReLU node: a_hat = GEMM + acc_in + gamma^T G,
-// Lambda and the row constant (bias, h, z-fixed Q terms).
-template <typename T>
+// Lambda and the row constant (bias, h, z-fixed Q terms).  PI: pi of an
+// unstable neuron is rho * [-a_hat]_+ with rho = rp.rho (Appendix A: any pi
+// in [0, [-a_hat]_+] is a feasible dual point) instead of Lemma A.1's pi*.
+template <typename T, bool PI = false>
 struct BoundEpi {
   BoundEpiArgs a;
   template <int R, int TN, bool PE> struct Frag {
@@ -179,6 +181,7 @@ struct BoundEpi {
     float tadd[TN][R];   // gamma^T H and the split term: added to Lambda
     float sQ[TN][R];     // gamma^T Q
     float al[TN][R];     // alpha (unstable) or 0
+    float rh[TN][PI ? R : 1];   // rho (PI only)
     int8_t c[TN][R];     // effective class
   };
   template <int R, int TN, bool PE>
@@ -219,6 +222,7 @@ struct BoundEpi {
         int c, slot;
         split_class<R>(rp, rk, kind_cls(kv[k][GCP_QC(q)]), f.rc[q], &c, &slot);
         f.al[k][q] = rk >= 0 ? rp.alpha[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
+        if constexpr (PI) f.rh[k][q] = rk >= 0 ? rp.rho[(size_t)f.rc[q] * rp.n_I + rk] : 0.f;
         const float bv = slot >= 0 ? rp.beta[(size_t)f.rc[q] * rp.K + slot] : 0.f;
         f.tadd[k][q] = c == ACTIVE ? -bv : (c == INACTIVE ? bv : 0.f);   // split term
         f.c[k][q] = (int8_t)c;
@@ -254,7 +258,11 @@ struct BoundEpi {
         } else {                                     // Lemma A.1, C = [-a_hat]_+, q = -s
           const float n = fmaxf(-ah, 0.f), p = fmaxf(ah, 0.f), sq = f.sQ[k][q];
           float pi, h;
-          if (sq >= f.uj[k][qc] * n) { pi = 0.f; h = 0.f; }
+          if constexpr (PI) {                        // h(pi) = l pi - [u (n - pi) + l pi - s]_+
+            const float uj = f.uj[k][qc], lj = f.lj[k][qc];
+            pi = f.rh[k][q] * n;
+            h = lj * pi - fmaxf(uj * n - (uj - lj) * pi - sq, 0.f);
+          } else if (sq >= f.uj[k][qc] * n) { pi = 0.f; h = 0.f; }
           else if (sq <= f.lj[k][qc] * n) { pi = n; h = sq; }
           else { pi = (f.uj[k][qc] * n - sq) * f.iul[k][qc]; h = f.lj[k][qc] * pi; }
           lam = f.al[k][q] * p - pi + f.tadd[k][q];
@@ -376,8 +384,9 @@ struct ConcEpi {
 // d bound / d Lambda arrives as the GEMM value; the relaxation's derivative
 // gives d bound / d a_hat (operand of the next adjoint GEMM), the gradient
 // pieces of the cuts, and d/d alpha, d/d beta -- applied by projected Adam in
-// place or written out.
-template <typename T>
+// place or written out.  PI: the explicit-pi relaxation of BoundEpi<T,
+// true>, with d/d rho applied to rho like alpha's.
+template <typename T, bool PI = false>
 struct AdjEpi {
   AdjEpiArgs a;
   template <int R, int TN, bool PE> struct Frag {
@@ -389,6 +398,7 @@ struct AdjEpi {
     float pre[TN][R];    // acc_in
     float sQ[TN][R];
     float al[TN][R], ma[TN][R], va[TN][R];
+    float rh[TN][PI ? R : 1], mr[TN][PI ? R : 1], vr[TN][PI ? R : 1];
     int8_t c[TN][R], slot[TN][R];
   };
   template <int R, int TN, bool PE>
@@ -436,6 +446,11 @@ struct AdjEpi {
         f.al[k][q] = rk >= 0 ? rp.alpha[ia] : 0.f;
         f.ma[k][q] = (rk >= 0 && adam) ? a.m_alpha[ia] : 0.f;
         f.va[k][q] = (rk >= 0 && adam) ? a.v_alpha[ia] : 0.f;
+        if constexpr (PI) {
+          f.rh[k][q] = rk >= 0 ? rp.rho[ia] : 0.f;
+          f.mr[k][q] = (rk >= 0 && adam) ? a.m_rho[ia] : 0.f;
+          f.vr[k][q] = (rk >= 0 && adam) ? a.v_rho[ia] : 0.f;
+        }
         f.c[k][q] = (int8_t)c;
         f.slot[k][q] = (int8_t)slot;
       }
@@ -461,7 +476,7 @@ struct AdjEpi {
       for (int q = 0; q < R; ++q) {
         const int qc = GCP_QC(q);
         const float dL = a.gemm_scale * val[k][q] + f.addj[k][qc] + f.pre[k][q];
-        float dA, dS, gA = 0.f;
+        float dA, dS, gA = 0.f, gR = 0.f;
         const int c = f.c[k][q];
         if (c == ACTIVE) {
           dA = dL; dS = 1.f;
@@ -472,7 +487,16 @@ struct AdjEpi {
           const float pos = x > 0.f ? 1.f : 0.f, neg = x < 0.f ? 1.f : 0.f;
           const float uj = f.uj[k][qc], lj = f.lj[k][qc], iul = f.iul[k][qc], al = f.al[k][q];
           float dLda, dhda, dLds, dhds;
-          if (sq >= uj * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
+          if constexpr (PI) {
+            // Lambda = alpha p - rho n + t,  h = l rho n - [w n - s]_+,  w = u - (u - l) rho
+            const float rho = f.rh[k][q], w = uj - (uj - lj) * rho;
+            const float ind = w * n - sq > 0.f ? 1.f : 0.f;
+            dLda = al * pos + rho * neg;
+            dhda = neg * (ind * w - lj * rho);
+            dLds = 0.f;
+            dhds = ind;
+            gR = n * (lj + ind * (uj - lj) - dL);
+          } else if (sq >= uj * n) { dLda = al * pos; dhda = 0.f; dLds = 0.f; dhds = 0.f; }
           else if (sq <= lj * n) { dLda = al * pos + neg; dhda = 0.f; dLds = 0.f; dhds = 1.f; }
           else {
             dLda = al * pos + uj * iul * neg;
@@ -505,8 +529,16 @@ struct AdjEpi {
             a.v_alpha[ia] = vv;
             const float stp = adam_step(lr_a, mm, vv, ibc1, ibc2, aeps);
             a.alpha_rw[ia] = fminf(fmaxf(f.al[k][q] + stp, 0.f), 1.f);
+            if constexpr (PI) {
+              const float mr = b1 * f.mr[k][q] + (1.f - b1) * gR;
+              const float vr = b2 * f.vr[k][q] + (1.f - b2) * gR * gR;
+              a.m_rho[ia] = mr;
+              a.v_rho[ia] = vr;
+              a.rho_rw[ia] = fminf(fmaxf(f.rh[k][q] + adam_step(lr_a, mr, vr, ibc1, ibc2, aeps), 0.f), 1.f);
+            }
           } else {
             a.d_alpha[ia] = gA;
+            if constexpr (PI) a.d_rho[ia] = gR;
           }
         }
         const int sl = f.slot[k][q];

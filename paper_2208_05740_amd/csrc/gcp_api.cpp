@@ -814,6 +814,22 @@ void ensure_ws(Call& c) {
   ws.partial.release();
 }
 
+// Explicit pi runs every ReLU node's relaxation (and its adjoint) as an
+// elementwise pass over the node's accumulated GEMM result, so every ReLU
+// node needs the accumulation buffer.
+void ensure_acc_all(Call& c) {
+  auto& ws = c.net->ws;
+  for (size_t i = 0; i < c.net->nodes.size(); ++i) {
+    const NodeH& n = c.net->nodes[i];
+    if (!n.relu) continue;
+    const size_t need = (size_t)ws.M * n.ld * 4;
+    if (ws.acc[i]->bytes < need) {
+      ws.acc[i]->alloc(need);
+      ws.gen = next_generation();
+    }
+  }
+}
+
 CutCol cut_col(const Call& c, int node) {
   if (!c.cuts) return CutCol{nullptr, nullptr, nullptr};
   int idx = node < 0 ? (int)c.net->nodes.size() : node;
@@ -901,6 +917,23 @@ struct BoundPass {
 
   void check(hipError_t e) { hip_check(e, "kernel launch (bound pass)"); }
 
+  // explicit pi: node p's relaxation over acc[p], which holds the complete
+  // GEMM sum (the last push stored into it instead of running fused)
+  void relax_elementwise(int p) {
+    auto& ws = c.net->ws;
+    BoundEpiArgs a = bound_args(p, true);
+    const int d = c.net->nodes[p].size;
+    const int nslot = slots_for_elementwise(d);
+    const double M = c.M, esz = bf16 ? 2 : 4;
+    const double bytes = M * d * (4 + esz + (keep_ahat ? 4 : 0)) + M * unst_of(c, p) * 8 +
+                         (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
+    if (!dry)
+      check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
+        return launch_bound_elementwise(bf16, nullptr, nullptr, a, ws.partial.as<double>(), slot, c.st);
+      }));
+    slot += nslot;
+  }
+
   void run() {
     gcp_net* net = c.net;
     const int nn = (int)net->nodes.size();
@@ -984,6 +1017,7 @@ struct BoundPass {
     const int d_src = E.d_src;
     const int ld_src = node_ld_of(net, p);
     float* accbuf = p < 0 ? ws.acc_in.as<float>() : ws.acc[p]->as<float>();
+    const bool unfused = c.rp.rho != nullptr && p >= 0;   // explicit pi: relaxation runs elementwise
 
     if (E.kind == GCP_EDGE_DENSE) {
       GemmArgs g{};
@@ -992,7 +1026,7 @@ struct BoundPass {
       g.Bt = wt_bound(E, bf16); g.ldb = dn.ld;
       g.a_is_sign = 0;
       g.mp = c.rp.mp;
-      if (!last) {
+      if (!last || unfused) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         g.partial = nullptr;
         if (!dry) {
@@ -1008,6 +1042,7 @@ struct BoundPass {
             check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         }
+        if (last) relax_elementwise(p);
         return;
       }
       int nslot = slots_for_gemm(d_src);
@@ -1064,7 +1099,7 @@ struct BoundPass {
       // every multiply-add of the forward conv appears once in its transpose
       const double flops = 2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw;
       const double wbytes = (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz;
-      if (!last) {
+      if (!last || unfused) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         if (!dry) {
           int cfg = choose_cfg("convT", EPI_STORE, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(), [&](int cf) {
@@ -1077,6 +1112,7 @@ struct BoundPass {
           check(timed(c.st, cls_name("convT_store", bf16, 0, -1), bytes, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         }
+        if (last) relax_elementwise(p);
         return;
       }
       const int nslot = conv_slots(cg, 1);
@@ -1145,6 +1181,8 @@ struct AdjPass {
   float* d_alpha; float* d_beta;
   float* alpha_rw; float* beta_rw;
   float *ma, *va, *mb, *vb;
+  float* d_rho = nullptr; float* rho_rw = nullptr;   // explicit pi (c.rp.rho set)
+  float* mr = nullptr; float* vr = nullptr;
 
   void check(hipError_t e) { hip_check(e, "kernel launch (adjoint)"); }
 
@@ -1227,7 +1265,9 @@ struct AdjPass {
     for (int eid : n.in_edges)
       if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
     float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
-    const bool fused_last = net->edges[order.back()]->kind != GCP_EDGE_IDENTITY;
+    // the node's adjoint epilogue runs fused with its last GEMM, or
+    // elementwise after all edges (identity last edge, explicit pi)
+    const bool fused_last = c.rp.rho == nullptr && net->edges[order.back()]->kind != GCP_EDGE_IDENTITY;
     const bool use_acc = order.size() > 1 || !fused_last;
     const double M = c.M, esz = bf16 ? 2 : 4, di = n.size;
     auto adj_bytes = [&](double a_bytes, double w_bytes) {
@@ -1251,7 +1291,7 @@ struct AdjPass {
         g.Bt = w_adj(E, bf16); g.ldb = lda;
         g.a_is_sign = sign;
         g.mp = c.rp.mp;
-        if (!last) {
+        if (!last || !fused_last) {
           StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
           int cfg = choose_cfg("gemm", EPI_STORE, bf16, sign, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
             StoreEpiArgs t = s;
@@ -1286,7 +1326,7 @@ struct AdjPass {
         const int HW = E.cg.ho * E.cg.wo;
         const double flops = 2.0 * M * HW * E.cg.co * E.cg.ci * E.cg.kh * E.cg.kw;
         const double wbytes = (double)E.cg.co * E.ldk_f * esz;
-        if (!last) {
+        if (!last || !fused_last) {
           StoreEpiArgs s{n.size, n.ld, scale, first ? nullptr : accbuf, accbuf};
           int cfg = choose_cfg("conv", EPI_STORE, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(), [&](int cf) {
             StoreEpiArgs t = s;
@@ -1312,12 +1352,12 @@ struct AdjPass {
         no_record(c, "identity");
         check(launch_identity_acc(bf16, c.M, n.size, A, lda, sign, scale, first ? nullptr : accbuf, accbuf, n.ld,
                                   c.st));
-        if (last) {
-          AdjEpiArgs a = epi(i, accbuf, 0.f);
-          check(timed(c.st, cls_name("adj_elem", bf16, 0, -1), adj_bytes(0, 0), 0.0,
-                      [&] { return launch_adj_elementwise(bf16, a, c.st); }));
-        }
       }
+    }
+    if (!fused_last) {
+      AdjEpiArgs a = epi(i, accbuf, 0.f);
+      check(timed(c.st, cls_name("adj_elem", bf16, 0, -1), adj_bytes(0, 0), 0.0,
+                  [&] { return launch_adj_elementwise(bf16, a, c.st); }));
     }
   }
 
@@ -1340,6 +1380,7 @@ struct AdjPass {
     a.m_alpha = ma; a.v_alpha = va; a.m_beta = mb; a.v_beta = vb;
     a.alpha_rw = alpha_rw; a.beta_rw = beta_rw;
     a.adam = adam;
+    a.d_rho = d_rho; a.rho_rw = rho_rw; a.m_rho = mr; a.v_rho = vr;
     return a;
   }
 };
@@ -1434,13 +1475,14 @@ void validate_params(Call& c, const float* alpha, const float* beta, const float
   hip_check(hipMemsetAsync(ws.flags.p, 0, 16, c.st), "hipMemsetAsync");
   int* f = ws.flags.as<int>();
   hip_check(launch_validate(alpha, (int64_t)c.M * c.rp.n_I, 0.f, 1.f, f, c.st), "validate");
+  if (c.rp.rho) hip_check(launch_validate(c.rp.rho, (int64_t)c.M * c.rp.n_I, 0.f, 1.f, f, c.st), "validate");
   hip_check(launch_validate(beta, (int64_t)c.M * c.rp.K, 0.f, INFINITY, f, c.st), "validate");
   hip_check(launch_validate(gamma, (int64_t)c.M * c.N, 0.f, INFINITY, f, c.st), "validate");
   int h = 0;
   hip_check(hipMemcpyAsync(&h, f, 4, hipMemcpyDeviceToHost, c.st), "hipMemcpyAsync");
   hip_check(hipStreamSynchronize(c.st), "hipStreamSynchronize");
   if (h & 1) fail(GCP_ENONFINITE, "non-finite alpha, beta or gamma");
-  if (h & 2) fail(GCP_ERANGE, "alpha outside [0,1] or a negative multiplier");
+  if (h & 2) fail(GCP_ERANGE, "alpha or rho outside [0,1] or a negative multiplier");
 }
 
 void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, uint8_t* verified) {
@@ -1457,22 +1499,23 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
             "reduce");
 }
 
-}  // namespace
-
-extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
-                         const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
-                         const float* gamma, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
-                         float* d_beta, float* d_gamma, void* stream) {
-  GCP_TRY
+// gcp_bound and gcp_bound_pi (rho non-null: explicit pi)
+void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
+                const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                const float* gamma, const float* rho, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
+                float* d_beta, float* d_gamma, float* d_rho, void* stream) {
   gcp_net* net = const_cast<gcp_net*>(net_c);
   Call c{};
   prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
+  c.rp.rho = rho;
+  if (rho) ensure_acc_all(c);
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   if (!bound) fail(GCP_EINVAL, "null bound output");
   const bool grads = d_alpha || d_beta || d_gamma;
   if (grads) {
-    if ((net->n_I > 0 && !d_alpha) || (splits->K > 0 && !d_beta) || (c.rp.N > 0 && !d_gamma))
+    if ((net->n_I > 0 && !d_alpha) || (splits->K > 0 && !d_beta) || (c.rp.N > 0 && !d_gamma) ||
+        (rho && net->n_I > 0 && !d_rho))
       fail(GCP_EINVAL, "pass all gradient outputs or none");
   }
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
@@ -1482,7 +1525,7 @@ extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, con
   if (grads) {
     if (splits->K > 0) hip_check(launch_fill_f32(d_beta, (int64_t)c.M * splits->K, 0.f, c.st), "fill");
     AdjPass ap{c, bf16, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, d_alpha, d_beta, nullptr, nullptr,
-               nullptr, nullptr, nullptr, nullptr};
+               nullptr, nullptr, nullptr, nullptr, rho ? d_rho : nullptr};
     ap.prepare();
     ap.run();
     if (c.rp.N > 0)
@@ -1493,19 +1536,19 @@ extern "C" int gcp_bound(const gcp_net* net_c, const double* x0, double eps, con
                 }),
                 "gamma gradient");
   }
-  g_err.clear();
-  return GCP_OK;
-  GCP_CATCH
 }
 
-extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
-                            const gcp_splits* splits, const gcp_cuts* cuts, float* alpha, float* beta,
-                            float* gamma, float* adam_state, const gcp_opt* opt, int32_t mode, double* bound,
-                            uint8_t* verified, void* stream) {
-  GCP_TRY
+// gcp_optimize and gcp_optimize_pi (rho non-null: explicit pi, its Adam
+// moments after gamma's in adam_state)
+void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
+                   const gcp_splits* splits, const gcp_cuts* cuts, float* alpha, float* beta, float* gamma,
+                   float* rho, float* adam_state, const gcp_opt* opt, int32_t mode, double* bound,
+                   uint8_t* verified, void* stream) {
   gcp_net* net = const_cast<gcp_net*>(net_c);
   Call c{};
   prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
+  c.rp.rho = rho;
+  if (rho) ensure_acc_all(c);
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   if (!opt || opt->iters < 0) fail(GCP_EINVAL, "bad optimiser settings");
@@ -1521,12 +1564,14 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
   float* vb = mb + M * K;
   float* mg = vb + M * K;
   float* vg = mg + M * N;
+  float* mr = rho ? vg + M * N : nullptr;
+  float* vr = rho ? mr + M * nI : nullptr;
   AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.consts.as<float>()};
   hip_check(launch_adam_prepare(ws.step.as<int>(), 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam reset");
   if (N > 0) hip_check(launch_transpose(gamma, c.M, (int)N, (int)N, ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
   size_partials(c, bf16, true, c.nnz > 0);
   {
-    AdjPass prep{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+    AdjPass prep{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
     prep.prepare();
   }
   auto iteration = [&](Call& cc) {
@@ -1535,7 +1580,7 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
               "adam prepare");
     BoundPass bp(cc, bf16, true, cc.nnz > 0, false);
     bp.run();
-    AdjPass ap{cc, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+    AdjPass ap{cc, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
     ap.run();
     if (N > 0)
       hip_check(timed(cc.st, "gamma_adam", (double)cc.M * (cc.nnz * 4.0 + N * 24.0), 0.0, [&] {
@@ -1552,7 +1597,8 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
   }
   if (opt->use_graph && opt->iters > 1) {
     std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits, (uintptr_t)cuts,
-                                  (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)adam_state,
+                                  (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)rho,
+                                  (uintptr_t)adam_state,
                                   (uintptr_t)S, (uintptr_t)bf16, (uintptr_t)c.M,
                                   (uintptr_t)std::hash<double>()(eps), (uintptr_t)ws.gen};
     for (uint8_t r : c.recompute) key.push_back(r);
@@ -1594,6 +1640,55 @@ extern "C" int gcp_optimize(const gcp_net* net_c, const double* x0, double eps, 
   if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   bound_pass(c, 0, false, false, bound, verified);
+}
+
+}  // namespace
+
+extern "C" int gcp_bound(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                         const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                         const float* gamma, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
+                         float* d_beta, float* d_gamma, void* stream) {
+  GCP_TRY
+  bound_impl(net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, nullptr, mode, bound, verified, d_alpha, d_beta,
+             d_gamma, nullptr, stream);
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_bound_pi(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                            const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                            const float* gamma, const float* rho, int32_t mode, double* bound, uint8_t* verified,
+                            float* d_alpha, float* d_beta, float* d_gamma, float* d_rho, void* stream) {
+  GCP_TRY
+  if (net && net->n_I > 0 && !rho) fail(GCP_EINVAL, "null rho");
+  bound_impl(net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, rho, mode, bound, verified, d_alpha, d_beta,
+             d_gamma, d_rho, stream);
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_optimize(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                            const gcp_splits* splits, const gcp_cuts* cuts, float* alpha, float* beta,
+                            float* gamma, float* adam_state, const gcp_opt* opt, int32_t mode, double* bound,
+                            uint8_t* verified, void* stream) {
+  GCP_TRY
+  optimize_impl(net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, nullptr, adam_state, opt, mode, bound,
+                verified, stream);
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
+extern "C" int gcp_optimize_pi(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                               const gcp_splits* splits, const gcp_cuts* cuts, float* alpha, float* beta,
+                               float* gamma, float* rho, float* adam_state, const gcp_opt* opt, int32_t mode,
+                               double* bound, uint8_t* verified, void* stream) {
+  GCP_TRY
+  if (net && net->n_I > 0 && !rho) fail(GCP_EINVAL, "null rho");
+  optimize_impl(net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, rho, adam_state, opt, mode, bound, verified,
+                stream);
   g_err.clear();
   return GCP_OK;
   GCP_CATCH

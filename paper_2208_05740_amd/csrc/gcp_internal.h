@@ -43,6 +43,8 @@ struct RowParams {
   const float* gammaT; int N;       // [N][mp]    (internal transposed copy)
   const int8_t* mask;               // [B][n_I]: 0, +(slot+1) x>=0, -(slot+1) x<=0
   double inv_S;                     // 1 / S (domain of a row without an integer division)
+  const float* rho;                 // [M][n_I] explicit pi / [-a_hat]_+, or null for Lemma A.1's pi*
+                                    // (read only by the elementwise relaxation kernels)
 };
 
 struct AdamArgs {
@@ -86,7 +88,15 @@ struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
   float* m_beta;  float* v_beta;
   float* alpha_rw; float* beta_rw;    // parameters updated in place
   AdamArgs adam;
+  float* d_rho; float* m_rho; float* v_rho; float* rho_rw;   // explicit pi (rp.rho set)
 };
+// The fused GEMM epilogues implement Lemma A.1's pi* only: explicit pi
+// (rp.rho set) must go through the elementwise relaxation kernels.
+inline bool fused_explicit_pi(EpiKind kind, const void* epi) {
+  if (kind == EPI_BOUND) return ((const BoundEpiArgs*)epi)->rp.rho != nullptr;
+  if (kind == EPI_ADJ) return ((const AdjEpiArgs*)epi)->rp.rho != nullptr;
+  return false;
+}
 struct StoreEpiArgs {       // raw accumulate into an fp32 buffer
   int size, ld;
   float scale;

@@ -312,6 +312,7 @@ static hipError_t launch_typed(int cfg, EpiKind kind, int sign, const GemmLaunch
 hipError_t launch_gemm(int bf16_mode, int cfg, EpiKind kind, const GemmArgs& g, const void* epi,
                        hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (fused_explicit_pi(kind, epi)) return hipErrorInvalidValue;   // elementwise kernels only
   GemmLaunch L{&g, epi, nullptr, nullptr, nullptr, 0, 0};
   return bf16_mode ? launch_typed<bf16>(cfg, kind, g.a_is_sign, L, st)
                    : launch_typed<float>(cfg, kind, g.a_is_sign, L, st);
@@ -327,14 +328,15 @@ hipError_t launch_gemm_grouped(int bf16_mode, int cfg, EpiKind kind, int sign, c
 // Elementwise relaxation (no GEMM: a_hat = bcast row + src): one block =
 // four consecutive rows x 256 columns, each thread one column of the four
 // rows, so a neuron's data is read once for them; one row partial per
-// (row, column block), summed over the block in a fixed order.
-template <typename T>
+// (row, column block), summed over the block in a fixed order.  PI selects
+// the explicit-pi relaxation (a.rp.rho set).
+template <typename T, bool PI>
 __device__ inline void bound_elem_rows(const float* bcast, const void* src, const BoundEpiArgs& a, double* partial,
                                        int slot0, int r0, int cb) {
   __shared__ double red[4][4];
   const int j = cb * 256 + threadIdx.x;
   const int M = a.rp.M;
-  BoundEpi<T> epi{a};
+  BoundEpi<T, PI> epi{a};
   LaneCoords<4, 1, false> lc;
 #pragma unroll
   for (int q = 0; q < 4; ++q) lc.r[q] = r0 + q;
@@ -351,7 +353,7 @@ __device__ inline void bound_elem_rows(const float* bcast, const void* src, cons
     val[0][q] = pre;
   }
   double rs[4] = {0.0, 0.0, 0.0, 0.0};
-  typename BoundEpi<T>::template Frag<4, 1, false> fr;
+  typename BoundEpi<T, PI>::template Frag<4, 1, false> fr;
   epi.template load<4, 1, false>(fr, lc, M, a.nd.size);
   epi.template apply<4, 1, false>(fr, lc, val, rs, M, a.nd.size);
 #pragma unroll
@@ -367,20 +369,25 @@ __device__ inline void bound_elem_rows(const float* bcast, const void* src, cons
   }
 }
 
-template <typename T>
+template <typename T, bool PI>
 __global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, const void* src, BoundEpiArgs a,
                                                          double* partial, int slot0) {
-  bound_elem_rows<T>(bcast, src, a, partial, slot0, 4 * blockIdx.x, blockIdx.y);
+  bound_elem_rows<T, PI>(bcast, src, a, partial, slot0, 4 * blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const void* src, const BoundEpiArgs& a,
                                     double* partial, int slot0, hipStream_t st) {
   if (a.rp.M <= 0) return hipSuccess;
   dim3 grid((a.rp.M + 3) / 4, (a.nd.size + 255) / 256);
-  if (bf16_mode)
-    hipLaunchKernelGGL(bound_elem_kernel<bf16>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
+  const bool pi = a.rp.rho != nullptr;
+  if (bf16_mode && pi)
+    hipLaunchKernelGGL((bound_elem_kernel<bf16, true>), grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
+  else if (bf16_mode)
+    hipLaunchKernelGGL((bound_elem_kernel<bf16, false>), grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
+  else if (pi)
+    hipLaunchKernelGGL((bound_elem_kernel<float, true>), grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   else
-    hipLaunchKernelGGL(bound_elem_kernel<float>, grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
+    hipLaunchKernelGGL((bound_elem_kernel<float, false>), grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
   return hipGetLastError();
 }
 
@@ -398,7 +405,7 @@ __global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __
   const ElemBoundJob& jb = jobs[lo];
   const int nb = (jb.a.nd.size + 255) / 256;
   const int b = t - prefix[lo];
-  bound_elem_rows<T>(jb.bcast, jb.src, jb.a, jb.partial, jb.slot0, 4 * (b / nb), b % nb);
+  bound_elem_rows<T, false>(jb.bcast, jb.src, jb.a, jb.partial, jb.slot0, 4 * (b / nb), b % nb);
 }
 
 hipError_t launch_bound_elementwise_grouped(int bf16_mode, const ElemBoundJob* d_jobs, const int* d_prefix, int np,
@@ -411,27 +418,32 @@ hipError_t launch_bound_elementwise_grouped(int bf16_mode, const ElemBoundJob* d
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool PI>
 __global__ void __launch_bounds__(256) adj_elem_kernel(AdjEpiArgs a) {
   const int r = blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
-  AdjEpi<T> epi{a};
+  AdjEpi<T, PI> epi{a};
   LaneCoords<1, 1, false> lc;
   lc.r[0] = r;
   lc.j[0][0] = j;
   float val[1][1] = {{0.f}};
   double rs[1] = {0.0};
-  typename AdjEpi<T>::template Frag<1, 1, false> fr;
+  typename AdjEpi<T, PI>::template Frag<1, 1, false> fr;
   epi.template load<1, 1, false>(fr, lc, a.rp.M, a.nd.size);
   epi.template apply<1, 1, false>(fr, lc, val, rs, a.rp.M, a.nd.size);
 }
 
 hipError_t launch_adj_elementwise(int bf16_mode, const AdjEpiArgs& a, hipStream_t st) {
   dim3 grid(a.rp.M, (a.nd.size + 255) / 256);
-  if (bf16_mode)
-    hipLaunchKernelGGL(adj_elem_kernel<bf16>, grid, dim3(256), 0, st, a);
+  const bool pi = a.rp.rho != nullptr;
+  if (bf16_mode && pi)
+    hipLaunchKernelGGL((adj_elem_kernel<bf16, true>), grid, dim3(256), 0, st, a);
+  else if (bf16_mode)
+    hipLaunchKernelGGL((adj_elem_kernel<bf16, false>), grid, dim3(256), 0, st, a);
+  else if (pi)
+    hipLaunchKernelGGL((adj_elem_kernel<float, true>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(adj_elem_kernel<float>, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((adj_elem_kernel<float, false>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
