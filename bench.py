@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
     ap.add_argument("--config", type=int, choices=[2, 3, 4, 5], default=2)
+    ap.add_argument("--explicit-pi", action="store_true",
+                    help="optimise pi of every unstable neuron too (gcp_optimize_pi) instead of Lemma A.1's pi*")
     a = ap.parse_args()
     if a.domains is None:
         a.domains = {2: 1024, 3: 2048, 5: 4096, 4: 0}[a.config]
@@ -89,21 +91,30 @@ def main():
     beta0 = torch.tensor(prob.beta.reshape(M, -1), dtype=torch.float32, device=dev)
     gamma0 = torch.zeros(M, P.N, dtype=torch.float32, device=dev)
     alpha, beta, gamma = alpha0.clone(), beta0.clone(), gamma0.clone()
-    state = torch.zeros(B.adam_state_size(M, P.n_I, P.K, P.N), dtype=torch.float32, device=dev)
+    pi = args.explicit_pi
+    state = torch.zeros(B.adam_state_size(M, P.n_I, P.K, P.N, explicit_pi=pi), dtype=torch.float32, device=dev)
     bound = torch.empty(M, dtype=torch.float64, device=dev)
     ver = torch.empty(M, dtype=torch.uint8, device=dev)
+    rho0 = torch.tensor(gen.rho_init(prob.lu), dtype=torch.float32, device=dev).expand(M, -1).contiguous()
+    rho = rho0.clone()
     o = prob.opt
     use_graph = [args.graph]
 
-    def step(mode):
+    def step(mode, explicit=pi):
         alpha.copy_(alpha0)
         beta.copy_(beta0)
         gamma.copy_(gamma0)
         state.zero_()
-        B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, state, iters=o["iters"],
-                   lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
-                   b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode, bound_out=bound, verified_out=ver,
-                   use_graph=use_graph[0])
+        kw = dict(iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
+                  b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode, use_graph=use_graph[0])
+        if explicit:
+            rho.copy_(rho0)
+            b, v = B.optimize_pi(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, rho, state, **kw)
+            bound.copy_(b)
+            ver.copy_(v)
+        else:
+            B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, state, bound_out=bound,
+                       verified_out=ver, **kw)
 
     def timed(mode, steps, warmup):
         for _ in range(warmup):
@@ -154,8 +165,19 @@ def main():
             "domains": args.domains, "spec_rows": prob.S, "rows": M, "n_unstable": P.n_I,
             "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
+            "relaxation": "explicit pi (rho optimised)" if pi else "Lemma A.1 pi*",
         },
     }
+    if pi:
+        # the same optimisation with Lemma A.1's pi*, for the bound it reaches
+        step(mode, explicit=False)
+        torch.cuda.synchronize()
+        closed = bound.cpu().numpy().copy()
+        out["config"]["final_bound_mean"] = float(bound_main.mean())
+        out["config"]["lemma_pi_final_bound_mean"] = float(closed.mean())
+        out["config"]["rows_tighter_than_lemma_pi"] = float(np.mean(bound_main > closed))
+        out["config"]["verified_rows"] = int((bound_main >= 0).sum())
+        out["config"]["lemma_pi_verified_rows"] = int((closed >= 0).sum())
     if kprof:
         out["roofline"] = roofline(kprof, args.mode)
         out["roofline"]["instrumented_ms_per_step"] = dt_prof * 1000.0 / args.steps

@@ -497,6 +497,16 @@ def crown_alpha_init(lu):
     return np.concatenate(out) if out else np.zeros(0)
 
 
+def rho_init(lu):
+    """Starting rho of the explicit-pi form per root-unstable neuron:
+    u / (u - l), the upper relaxation's slope (a starting point only)."""
+    out = []
+    for l, u in lu:
+        m = (l < 0) & (u > 0)
+        out.append(u[m] / (u[m] - l[m]))
+    return np.concatenate(out) if out else np.zeros(0)
+
+
 def _streams(seed):
     ss = np.random.SeedSequence(seed).spawn(5)
     return [np.random.default_rng(s) for s in ss]
