@@ -102,26 +102,39 @@ __device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ g
   if constexpr (!PE) {
     if (!jv[0]) return;
     const int2 rg = cc.rng[jq[0]];
-    for (int e = rg.x; e < rg.y; ++e) {
-      const float4 en = cc.ent[e];
-      const float ch = en.x, cg = en.y, cq = en.z;
-      const float* gk = gammaT + (size_t)__float_as_int(en.w) * mp;
-      float g[R];
-      if constexpr (R % 4 == 0) {
+    // kCutStep entries per step: their entry loads, then their gamma loads,
+    // are issued together (a neuron's list is walked in order, so the sums
+    // are the same as one entry at a time; a missing entry adds 0)
+    constexpr int kCutStep = 2;
+    for (int e0 = rg.x; e0 < rg.y; e0 += kCutStep) {
+      float4 en[kCutStep];
 #pragma unroll
-        for (int q = 0; q < R; q += 4) {
-          const float4 v = *(const float4*)(gk + rr[q]);
-          g[q] = v.x; g[q + 1] = v.y; g[q + 2] = v.z; g[q + 3] = v.w;
+      for (int t = 0; t < kCutStep; ++t) en[t] = cc.ent[e0 + t < rg.y ? e0 + t : e0];
+      float g[kCutStep][R];
+#pragma unroll
+      for (int t = 0; t < kCutStep; ++t) {
+        const float* gk = gammaT + (size_t)__float_as_int(en[t].w) * mp;
+        if constexpr (R % 4 == 0) {
+#pragma unroll
+          for (int q = 0; q < R; q += 4) {
+            const float4 v = *(const float4*)(gk + rr[q]);
+            g[t][q] = v.x; g[t][q + 1] = v.y; g[t][q + 2] = v.z; g[t][q + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < R; ++q) g[t][q] = gk[rr[q]];
         }
-      } else {
-#pragma unroll
-        for (int q = 0; q < R; ++q) g[q] = gk[rr[q]];
       }
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        sG[q] += g[q] * cg;
-        sH[q] += g[q] * ch;
-        sQ[q] += g[q] * cq;
+      for (int t = 0; t < kCutStep; ++t) {
+        const bool live = e0 + t < rg.y;
+        const float ch = live ? en[t].x : 0.f, cg = live ? en[t].y : 0.f, cq = live ? en[t].z : 0.f;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          sG[q] += g[t][q] * cg;
+          sH[q] += g[t][q] * ch;
+          sQ[q] += g[t][q] * cq;
+        }
       }
     }
   } else {
@@ -470,8 +483,12 @@ struct AdjEpi {
       lr_a = a.adam.consts[0]; lr_m = a.adam.consts[1]; ibc1 = a.adam.consts[2]; ibc2 = a.adam.consts[3];
     }
     const float b1 = a.adam.b1, b2 = a.adam.b2, aeps = a.adam.eps;
+    // dense lanes hold four consecutive rows per group: their cut-gradient
+    // pieces go out as one 16-byte store per entry after the row loop
+    constexpr bool kVecContrib = !PE && R % 4 == 0;
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
+      float cA[R], cL[R], cS[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int qc = GCP_QC(q);
@@ -508,11 +525,12 @@ struct AdjEpi {
           dS = dL * dLds + dhds;
           gA = dL * p;
         }
+        cA[q] = dA; cL[q] = dL; cS[q] = dS;
         if (!f.ev[k][q]) continue;
         const int j = lc.j[k][qc];
         const size_t ij = (size_t)f.rc[q] * nd.ld + j;
         if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
-        if (a.contrib && a.cc.rng) {
+        if (!kVecContrib && a.contrib && a.cc.rng) {
           const int2 rg = a.cc.rng[j];
           for (int e = rg.x; e < rg.y; ++e) {
             const float4 en = a.cc.ent[e];
@@ -554,6 +572,28 @@ struct AdjEpi {
             a.beta_rw[ib] = fmaxf(a.beta_rw[ib] + stp, 0.f);
           } else {
             a.d_beta[ib] = gB;
+          }
+        }
+      }
+      if constexpr (kVecContrib) {
+        // rows of a group are consecutive and the group lies below mp; rows
+        // in [M, mp) are padding of the contribution buffer, never read
+        const int j = lc.j[k][0];
+        if (a.contrib && a.cc.rng && j < N) {
+          const int2 rg = a.cc.rng[j];
+          for (int e = rg.x; e < rg.y; ++e) {
+            const float4 en = a.cc.ent[e];
+            float* dst = a.contrib + (size_t)a.cc.pos[e] * rp.mp;
+#pragma unroll
+            for (int q = 0; q < R; q += 4) {
+              if (lc.r[q] >= M) continue;
+              float4 v;
+              v.x = en.y * cA[q] + en.x * cL[q] + en.z * cS[q];
+              v.y = en.y * cA[q + 1] + en.x * cL[q + 1] + en.z * cS[q + 1];
+              v.z = en.y * cA[q + 2] + en.x * cL[q + 2] + en.z * cS[q + 2];
+              v.w = en.y * cA[q + 3] + en.x * cL[q + 3] + en.z * cS[q + 3];
+              *(float4*)(dst + lc.r[q]) = v;
+            }
           }
         }
       }
