@@ -73,6 +73,26 @@ struct LaneCoords {
 
 #define GCP_QC(q) (PE ? (q) : 0)
 
+// Per-column words of a dense lane fetched before the GEMM's K loop (the
+// neuron's kind word and its cut-entry range): the loads that the rank- and
+// cut-dependent loads of the epilogue wait on, issued early so their
+// latency hides under the K loop.  Columns >= N hold kind 0 and an empty
+// range.
+template <int TN>
+struct ColPre {
+  int kind[TN];
+  int2 rng[TN];
+};
+template <int TN>
+__device__ inline void col_prefetch(ColPre<TN>& p, const NodeDev& nd, const CutCol& cc, const int (&col)[TN], int N) {
+#pragma unroll
+  for (int k = 0; k < TN; ++k) {
+    const bool v = col[k] < N;
+    p.kind[k] = v ? nd.kind[col[k]] : 0;
+    p.rng[k] = (v && cc.rng) ? cc.rng[col[k]] : make_int2(0, 0);
+  }
+}
+
 // Row indices of a lane: rv = element row is real (< M); rc = row clamped
 // below M, for row-major [M][.] buffers; rr = row for the row-minor [.][mp]
 // buffers.  Dense lanes keep groups of 4 consecutive rows whole so 16-byte
@@ -95,13 +115,13 @@ __device__ inline void lane_rows(const int (&rows)[R], int M, int mp, int (&rr)[
 template <int R, bool PE>
 __device__ inline void gather_cuts(const CutCol& cc, const float* __restrict__ gammaT, int mp, const int (&jq)[R],
                                    const bool (&jv)[R], const int (&rr)[R], float (&sG)[R], float (&sH)[R],
-                                   float (&sQ)[R]) {
+                                   float (&sQ)[R], const int2* rg_pre = nullptr) {
 #pragma unroll
   for (int q = 0; q < R; ++q) sG[q] = sH[q] = sQ[q] = 0.f;
   if (!cc.rng) return;
   if constexpr (!PE) {
     if (!jv[0]) return;
-    const int2 rg = cc.rng[jq[0]];
+    const int2 rg = rg_pre ? *rg_pre : cc.rng[jq[0]];
     // kCutStep entries per step: their entry loads, then their gamma loads,
     // are issued together (a neuron's list is walked in order, so the sums
     // are the same as one entry at a time; a missing entry adds 0)
@@ -197,8 +217,12 @@ struct BoundEpi {
     float rh[TN][PI ? R : 1];   // rho (PI only)
     int8_t c[TN][R];     // effective class
   };
+  static constexpr bool kColPre = true;
+  __device__ inline const NodeDev& col_node() const { return a.nd; }
+  __device__ inline const CutCol& col_cuts() const { return a.cc; }
   template <int R, int TN, bool PE>
-  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N,
+                              const ColPre<TN>* pre = nullptr) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
     int rr[R];
@@ -221,7 +245,7 @@ struct BoundEpi {
         const int j = jq[k][q];
         const float4 nr = nd.rec[j];
         f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.bj[k][q] = nr.w;
-        kv[k][q] = nd.kind[j];
+        kv[k][q] = (!PE && pre) ? pre->kind[k] : nd.kind[j];
       }
 #pragma unroll
       for (int q = 0; q < R; ++q)
@@ -243,7 +267,7 @@ struct BoundEpi {
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
       float sG[R], sH[R];
-      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], rr, sG, sH, f.sQ[k]);
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], rr, sG, sH, f.sQ[k], pre ? &pre->rng[k] : nullptr);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         f.aoff[k][q] = f.aoff[k][q] + sG[q];     // acc_in + gamma^T G
@@ -298,6 +322,7 @@ struct BoundEpi {
 // a.ahat_out; nothing else is read or written.
 struct AhatEpi {
   BoundEpiArgs a;
+  static constexpr bool kColPre = false;
   template <int R, int TN, bool PE> struct Frag {
     int rc[R];
     bool ev[TN][R];
@@ -344,10 +369,12 @@ struct AhatEpi {
 // constant, sign(v) for the adjoint, input-cut gradient pieces.
 struct ConcEpi {
   ConcEpiArgs a;
+  static constexpr bool kColPre = false;
   template <int R, int TN, bool PE> struct Frag {
     int rr[R], rc[R];
     bool ev[TN][R];
     float sG[TN][R];
+    double xj[TN][PE ? R : 1];   // x0 of the element's input coordinate
   };
   template <int R, int TN, bool PE>
   __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
@@ -363,6 +390,10 @@ struct ConcEpi {
         jq[q] = jv[q] ? lc.j[k][GCP_QC(q)] : 0;
         f.ev[k][q] = jv[q] && rv[q];
       }
+      // x0 is read here, not next to the stores of apply: int8 stores may
+      // alias it, which would force one reload per element after each store
+#pragma unroll
+      for (int q = 0; q < (PE ? R : 1); ++q) f.xj[k][q] = a.x0[jq[q]];
       float sH[R], sQ[R];
       gather_cuts<R, PE>(a.cc, a.rp.gammaT, a.rp.mp, jq, jv, f.rr, f.sG[k], sH, sQ);
     }
@@ -376,7 +407,7 @@ struct ConcEpi {
       for (int q = 0; q < R; ++q) {
         if (!f.ev[k][q]) continue;
         const int j = lc.j[k][GCP_QC(q)];
-        const double xj = a.x0[j];
+        const double xj = f.xj[k][GCP_QC(q)];
         const float v = val[k][q] + f.sG[k][q];
         const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
         if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
@@ -412,10 +443,16 @@ struct AdjEpi {
     float sQ[TN][R];
     float al[TN][R], ma[TN][R], va[TN][R];
     float rh[TN][PI ? R : 1], mr[TN][PI ? R : 1], vr[TN][PI ? R : 1];
+    int2 rgc[TN];        // prefetched cut-entry range of the column (GEMM lanes)
+    bool has_rgc;        // rgc set; a compile-time constant after inlining
     int8_t c[TN][R], slot[TN][R];
   };
+  static constexpr bool kColPre = true;
+  __device__ inline const NodeDev& col_node() const { return a.nd; }
+  __device__ inline const CutCol& col_cuts() const { return a.cc; }
   template <int R, int TN, bool PE>
-  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N) const {
+  __device__ inline void load(Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc, int M, int N,
+                              const ColPre<TN>* pre = nullptr) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
     bool rv[R];
@@ -438,7 +475,7 @@ struct AdjEpi {
         const int j = jq[k][q];
         const float4 nr = nd.rec[j];
         f.lj[k][q] = nr.x; f.uj[k][q] = nr.y; f.iul[k][q] = nr.z; f.addj[k][q] = a.add_vec[j];
-        kv[k][q] = nd.kind[j];
+        kv[k][q] = (!PE && pre) ? pre->kind[k] : nd.kind[j];
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -470,7 +507,10 @@ struct AdjEpi {
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
       float sG[R], sH[R];
-      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], f.rr, sG, sH, f.sQ[k]);
+      f.has_rgc = !PE && pre != nullptr;
+      if (f.has_rgc) f.rgc[k] = pre->rng[k];
+      gather_cuts<R, PE>(a.cc, rp.gammaT, rp.mp, jq[k], jv[k], f.rr, sG, sH, f.sQ[k],
+                         f.has_rgc ? &f.rgc[k] : nullptr);
     }
   }
   template <int R, int TN, bool PE>
@@ -580,7 +620,7 @@ struct AdjEpi {
         // in [M, mp) are padding of the contribution buffer, never read
         const int j = lc.j[k][0];
         if (a.contrib && a.cc.rng && j < N) {
-          const int2 rg = a.cc.rng[j];
+          const int2 rg = f.has_rgc ? f.rgc[k] : a.cc.rng[j];
           for (int e = rg.x; e < rg.y; ++e) {
             const float4 en = a.cc.ent[e];
             float* dst = a.contrib + (size_t)a.cc.pos[e] * rp.mp;
@@ -605,6 +645,7 @@ struct AdjEpi {
 // out = scale * GEMM (+ acc_in): partial sums of a node with several edges
 struct StoreEpi {
   StoreEpiArgs a;
+  static constexpr bool kColPre = false;
   template <int R, int TN, bool PE> struct Frag {
     int rc[R];
     bool ev[TN][R];

@@ -155,6 +155,13 @@ __device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
 #pragma unroll
     for (int k = 0; k < TN; ++k) lc.j[k][0] = col0 + k * 16;
   }
+  ColPre<TN> pre;
+  if constexpr (Epi::kColPre) {
+    int col[TN];
+#pragma unroll
+    for (int k = 0; k < TN; ++k) col[k] = lc.j[k][0];
+    col_prefetch<TN>(pre, epi.col_node(), epi.col_cuts(), col, g.N);
+  }
   if (g.K > 0) load_stage(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
@@ -182,7 +189,8 @@ __device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
   // occupancy that buys back was worth more (measured: the adjoint kernel of
   // the 784-256x6 MLP at 1024 domains went from 41 to 36 us).
   typename Epi::template Frag<R, TN, false> fr;
-  epi.template load<R, TN, false>(fr, lc, g.M, g.N);
+  if constexpr (Epi::kColPre) epi.template load<R, TN, false>(fr, lc, g.M, g.N, &pre);
+  else epi.template load<R, TN, false>(fr, lc, g.M, g.N);
   {
     double rs[R];
 #pragma unroll
