@@ -766,6 +766,10 @@ struct Call {
   int nnz;
   int N;
   std::vector<uint8_t> recompute;   // per node: a_hat recomputed in the adjoint instead of stored
+  // the spec-row constants (C b_out, c-hat = C W_out or the materialised
+  // output Lambda) are already in the workspace for this C: later bound
+  // passes of one optimisation skip them
+  bool consts_done = false;
 };
 
 void ensure_ws(Call& c) {
@@ -946,7 +950,7 @@ struct BoundPass {
     if (net->out_general) {
       // Lambda^(out) = C on every row, pushed through the output's edges
       if (c.rec) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
-      if (!dry) {
+      if (!dry && !c.consts_done) {
         check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
         check(launch_spec_rows(bf16, c.C, c.S, on.size, c.M, ws.lam[net->out]->p, on.ld, c.st));
       }
@@ -955,7 +959,7 @@ struct BoundPass {
       for (int eid : on.in_edges)
         if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) push(eid);
     }
-    if (!net->out_general && !dry && !c.rec) {
+    if (!net->out_general && !dry && !c.rec && !c.consts_done) {
       check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st));
       for (int eid : on.in_edges) {
         const EdgeH& E = *net->edges[eid];
@@ -1594,6 +1598,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   if (opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
     iteration(c);
     done = 1;
+    c.consts_done = !net->out_general || !bf16;
   }
   if (opt->use_graph && opt->iters > 1) {
     std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits, (uintptr_t)cuts,
