@@ -421,7 +421,7 @@ static hipError_t conv_typed(int cfg, EpiKind kind, const ConvArgs& c, const voi
   if (c.trans) {
     switch (kind) {
       case EPI_BOUND: return conv_any<T, true, false>(cfg, c, BoundEpi<T>{*(const BoundEpiArgs*)epi}, st);
-      case EPI_AHAT: return conv_any<T, true, false>(cfg, c, AhatEpi{*(const BoundEpiArgs*)epi}, st);
+      case EPI_AHAT: return conv_any<T, true, false>(cfg, c, AhatEpi<T>{*(const BoundEpiArgs*)epi}, st);
       case EPI_CONC: return conv_any<T, true, false>(cfg, c, ConcEpi{*(const ConcEpiArgs*)epi}, st);
       case EPI_STORE: return conv_any<T, true, false>(cfg, c, StoreEpi{*(const StoreEpiArgs*)epi}, st);
       default: return hipErrorInvalidValue;

@@ -308,7 +308,7 @@ struct BoundEpi {
         if (f.ev[k][q]) {
           const size_t ij = (size_t)f.rc[q] * nd.ld + lc.j[k][qc];
           ((T*)a.lam_out)[ij] = to_t<T>(lam);
-          if (a.ahat_out) a.ahat_out[ij] = ah;
+          if (a.ahat_out) ((T*)a.ahat_out)[ij] = to_t<T>(ah);
           rs[q] += (double)lam * (double)f.bj[k][qc] + (double)konst;
         }
       }
@@ -319,7 +319,8 @@ struct BoundEpi {
 // ------------------------------------------------------------------ a_hat only
 // a_hat = GEMM + acc_in + gamma^T G recomputed for the adjoint instead of
 // stored by the bound pass: the same sum as BoundEpi forms, written to
-// a.ahat_out; nothing else is read or written.
+// a.ahat_out (operand type T); nothing else is read or written.
+template <typename T>
 struct AhatEpi {
   BoundEpiArgs a;
   static constexpr bool kColPre = false;
@@ -360,7 +361,8 @@ struct AhatEpi {
     for (int k = 0; k < TN; ++k)
 #pragma unroll
       for (int q = 0; q < R; ++q)
-        if (f.ev[k][q]) a.ahat_out[(size_t)f.rc[q] * a.nd.ld + lc.j[k][GCP_QC(q)]] = val[k][q] + f.aoff[k][q];
+        if (f.ev[k][q])
+          ((T*)a.ahat_out)[(size_t)f.rc[q] * a.nd.ld + lc.j[k][GCP_QC(q)]] = to_t<T>(val[k][q] + f.aoff[k][q]);
   }
 };
 
@@ -480,7 +482,7 @@ struct AdjEpi {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int j = jq[k][GCP_QC(q)];
-        f.ah[k][q] = a.ahat[(size_t)f.rc[q] * nd.ld + j];
+        f.ah[k][q] = from_t<T>(((const T*)a.ahat)[(size_t)f.rc[q] * nd.ld + j]);
         f.pre[k][q] = a.acc_in ? a.acc_in[(size_t)f.rc[q] * nd.ld + j] : 0.f;
       }
     }

@@ -915,7 +915,7 @@ struct BoundPass {
     a.acc_in = has_acc ? ws.acc[p]->as<float>() : nullptr;
     a.lam_out = ws.lam[p]->p;
     const bool rec = !c.recompute.empty() && c.recompute[p];
-    a.ahat_out = (keep_ahat && !rec) ? ws.ahat[p]->as<float>() : nullptr;
+    a.ahat_out = (keep_ahat && !rec) ? ws.ahat[p]->p : nullptr;
     return a;
   }
 
@@ -929,7 +929,7 @@ struct BoundPass {
     const int d = c.net->nodes[p].size;
     const int nslot = slots_for_elementwise(d);
     const double M = c.M, esz = bf16 ? 2 : 4;
-    const double bytes = M * d * (4 + esz + (keep_ahat ? 4 : 0)) + M * unst_of(c, p) * 8 +
+    const double bytes = M * d * (4 + esz + (keep_ahat ? esz : 0)) + M * unst_of(c, p) * 8 +
                          (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
     if (!dry)
       check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
@@ -976,7 +976,7 @@ struct BoundPass {
       BoundEpiArgs a = bound_args(p, false);
       int nslot = slots_for_elementwise(net->nodes[p].size);
       const double M = c.M, d = net->nodes[p].size, esz = bf16 ? 2 : 4;
-      const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * 4 : 0) + M * unst_of(c, p) * 4 +
+      const double bytes = c.S * d * 4 + M * d * esz + (keep_ahat ? M * d * esz : 0) + M * unst_of(c, p) * 4 +
                            (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
       if (!dry && c.rec) {
         Rec r{};
@@ -1059,7 +1059,7 @@ struct BoundPass {
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_BOUND, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
           const double M = g.M, esz = bf16 ? 2 : 4, dp = g.N;
-          const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * 4 : 0) +
+          const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * esz : 0) +
                                M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
           if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a, bytes))
@@ -1127,7 +1127,7 @@ struct BoundPass {
                                [&](int cf) { return launch_conv(bf16, cf, EPI_BOUND, ca, &a, c.st); });
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
-          const double bytes = M * dn.size * esz + wbytes + M * d_src * esz + (keep_ahat ? M * d_src * 4 : 0) +
+          const double bytes = M * dn.size * esz + wbytes + M * d_src * esz + (keep_ahat ? M * d_src * esz : 0) +
                                M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * d_src * 4 : 0) + M * nslot * 8;
           check(timed(c.st, cls_name("convT_bound", bf16, 0, -1), bytes, flops,
@@ -1228,7 +1228,7 @@ struct AdjPass {
     a.nd = n.dev();
     a.cc = cut_col(c, i);
     a.rp = c.rp;
-    a.ahat_out = ws.ahat_tmp.as<float>();
+    a.ahat_out = ws.ahat_tmp.p;
     const double M = c.M, esz = bf16 ? 2 : 4;
     if (E.kind == GCP_EDGE_DENSE) {
       GemmArgs g{};
@@ -1238,7 +1238,7 @@ struct AdjPass {
       g.mp = c.rp.mp;
       const int cfg = choose_cfg("gemm", EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
                                  [&](int cf) { return launch_gemm(bf16, cf, EPI_AHAT, g, &a, c.st); });
-      const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * g.N * 4 + M * nnz_of(c, i) * 4;
+      const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * g.N * esz + M * nnz_of(c, i) * 4;
       check(timed(c.st, cls_name("ahat", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
                   [&] { return launch_gemm(bf16, cfg, EPI_AHAT, g, &a, c.st); }));
     } else {
@@ -1251,7 +1251,7 @@ struct AdjPass {
       const int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, E.d_src, dn.size, c.st, conv_cands(),
                                  [&](int cf) { return launch_conv(bf16, cf, EPI_AHAT, ca, &a, c.st); });
       const double bytes = M * dn.size * esz + (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz +
-                           M * E.d_src * 4 + M * nnz_of(c, i) * 4;
+                           M * E.d_src * esz + M * nnz_of(c, i) * 4;
       check(timed(c.st, cls_name("convT_ahat", bf16, 0, -1), bytes,
                   2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw,
                   [&] { return launch_conv(bf16, cfg, EPI_AHAT, ca, &a, c.st); }));
@@ -1275,7 +1275,7 @@ struct AdjPass {
     const bool use_acc = order.size() > 1 || !fused_last;
     const double M = c.M, esz = bf16 ? 2 : 4, di = n.size;
     auto adj_bytes = [&](double a_bytes, double w_bytes) {
-      return a_bytes + w_bytes + M * di * 4 + M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
+      return a_bytes + w_bytes + M * di * esz + M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
              M * nnz_of(c, i) * 8 + M * di * esz + (use_acc ? M * di * 4 : 0);
     };
     for (size_t q = 0; q < order.size(); ++q) {
@@ -1376,7 +1376,7 @@ struct AdjPass {
     a.acc_in = acc_in;
     a.gemm_scale = scale;
     a.add_vec = ws.addv[i]->as<float>();
-    a.ahat = c.recompute.empty() || !c.recompute[i] ? ws.ahat[i]->as<float>() : ws.ahat_tmp.as<float>();
+    a.ahat = c.recompute.empty() || !c.recompute[i] ? ws.ahat[i]->p : ws.ahat_tmp.p;
     a.dahat_out = ws.dahat[i]->p;
     a.contrib = c.nnz ? ws.contrib.as<float>() : nullptr;
     a.nnz_e = c.nnz;

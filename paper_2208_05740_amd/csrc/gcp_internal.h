@@ -63,7 +63,7 @@ struct BoundEpiArgs {       // Theorem 3.1 relaxation of one ReLU node
   NodeDev nd; CutCol cc; RowParams rp;
   const float* acc_in;      // optional extra pre-activation [M][ld] (fp32)
   void* lam_out;            // [M][ld] in the GEMM operand type
-  float* ahat_out;          // optional [M][ld] fp32 (kept for the adjoint)
+  void* ahat_out;           // optional [M][ld] in the GEMM operand type (kept for the adjoint)
 };
 // EPI_AHAT (recomputing a_hat for the adjoint) takes BoundEpiArgs and writes
 // only ahat_out.
@@ -80,7 +80,7 @@ struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
   const float* acc_in;      // optional extra dLambda [M][ld]
   float gemm_scale;         // multiplies the GEMM result (-eps for the input edge)
   const float* add_vec;     // [size] added to dLambda (bias, or W x0 + b)
-  const float* ahat;        // [M][ld] stored pre-activation coefficients
+  const void* ahat;         // [M][ld] stored pre-activation coefficients (operand type)
   void* dahat_out;          // [M][ld] operand type, null if no consumer needs it
   float* contrib; int nnz_e;           // [nnz_e][mp]
   float* d_alpha; float* d_beta;      // raw gradient outputs (adam disabled)

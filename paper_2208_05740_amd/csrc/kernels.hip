@@ -305,7 +305,7 @@ template <typename T>
 static hipError_t launch_typed(int cfg, EpiKind kind, int sign, const GemmLaunch& L, hipStream_t st) {
   switch (kind) {
     case EPI_BOUND: return launch_any<T, false, BoundEpi<T>, BoundEpiArgs>(cfg, L, st);
-    case EPI_AHAT: return launch_any<T, false, AhatEpi, BoundEpiArgs>(cfg, L, st);
+    case EPI_AHAT: return launch_any<T, false, AhatEpi<T>, BoundEpiArgs>(cfg, L, st);
     case EPI_CONC: return launch_any<T, false, ConcEpi, ConcEpiArgs>(cfg, L, st);
     case EPI_STORE:
       if (sign) return launch_any<T, true, StoreEpi, StoreEpiArgs>(cfg, L, st);
