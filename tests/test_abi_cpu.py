@@ -40,3 +40,21 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.gcp_net_create(None, None) == -1
     assert lib.gcp_net_get_info(None, None) == -1
     assert lib.gcp_last_error()
+
+
+def test_shipped_tile_choices_are_well_formed():
+    # bench.py starts from these autotuner choices; each line is
+    # "<family>.k<epilogue>.b<bf16>.s<sign>.M<m>.N<n>.K<k> <config>" with a
+    # config index the family's launcher accepts (8 dense tiles, 6 conv shapes)
+    import re
+    path = os.path.join(os.path.dirname(LIB), "tuned_tiles_gfx950.txt")
+    pat = re.compile(r"^(gemm|conv|convT)\.k([0-4])\.b([01])\.s([01])\.M(\d+)\.N(\d+)\.K(\d+) (\d+)$")
+    n = 0
+    with open(path) as f:
+        for line in f:
+            m = pat.match(line.strip())
+            assert m, line
+            cfg = int(m.group(8))
+            assert 0 <= cfg < (8 if m.group(1) == "gemm" else 6), line
+            n += 1
+    assert n > 0
