@@ -982,7 +982,7 @@ struct BoundPass {
         Rec r{};
         r.type = 1; r.bf16 = bf16; r.cfg = -1; r.kind = EPI_BOUND; r.sign = 0;
         r.ej = ElemBoundJob{ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(), slot};
-        r.tiles = ((c.M + 3) / 4) * ((net->nodes[p].size + 255) / 256);
+        r.tiles = ((c.M + kElemRows - 1) / kElemRows) * ((net->nodes[p].size + 255) / 256);
         r.bytes = bytes;
         c.rec->push(r);
       } else if (!dry) {

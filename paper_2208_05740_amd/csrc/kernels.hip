@@ -334,24 +334,26 @@ hipError_t launch_gemm_grouped(int bf16_mode, int cfg, EpiKind kind, int sign, c
 
 // ------------------------------------------------------------------ elementwise
 // Elementwise relaxation (no GEMM: a_hat = bcast row + src): one block =
-// four consecutive rows x 256 columns, each thread one column of the four
-// rows, so a neuron's data is read once for them; one row partial per
-// (row, column block), summed over the block in a fixed order.  PI selects
-// the explicit-pi relaxation (a.rp.rho set).
+// kElemRows consecutive rows x 256 columns, each thread one column of those
+// rows, so a neuron's data is read once for them and their loads are in
+// flight together; one row partial per (row, column block), summed over the
+// block in a fixed order.  PI selects the explicit-pi relaxation (a.rp.rho
+// set).
 template <typename T, bool PI>
 __device__ inline void bound_elem_rows(const float* bcast, const void* src, const BoundEpiArgs& a, double* partial,
                                        int slot0, int r0, int cb) {
-  __shared__ double red[4][4];
+  constexpr int R = kElemRows;
+  __shared__ double red[R][4];
   const int j = cb * 256 + threadIdx.x;
   const int M = a.rp.M;
   BoundEpi<T, PI> epi{a};
-  LaneCoords<4, 1, false> lc;
+  LaneCoords<R, 1, false> lc;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) lc.r[q] = r0 + q;
+  for (int q = 0; q < R; ++q) lc.r[q] = r0 + q;
   lc.j[0][0] = j;
-  float val[1][4];
+  float val[1][R];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < R; ++q) {
     const int r = r0 + q;
     float pre = 0.f;
     if (j < a.nd.size && r < M) {
@@ -360,18 +362,20 @@ __device__ inline void bound_elem_rows(const float* bcast, const void* src, cons
     }
     val[0][q] = pre;
   }
-  double rs[4] = {0.0, 0.0, 0.0, 0.0};
-  typename BoundEpi<T, PI>::template Frag<4, 1, false> fr;
-  epi.template load<4, 1, false>(fr, lc, M, a.nd.size);
-  epi.template apply<4, 1, false>(fr, lc, val, rs, M, a.nd.size);
+  double rs[R];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < R; ++q) rs[q] = 0.0;
+  typename BoundEpi<T, PI>::template Frag<R, 1, false> fr;
+  epi.template load<R, 1, false>(fr, lc, M, a.nd.size);
+  epi.template apply<R, 1, false>(fr, lc, val, rs, M, a.nd.size);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
     double t = rs[q];
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = t;
   }
   __syncthreads();
-  if (threadIdx.x < 4 && partial) {
+  if (threadIdx.x < R && partial) {
     const int q = threadIdx.x, r = r0 + q;
     if (r < M) partial[(size_t)(slot0 + cb) * a.rp.mp + r] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
   }
@@ -380,13 +384,13 @@ __device__ inline void bound_elem_rows(const float* bcast, const void* src, cons
 template <typename T, bool PI>
 __global__ void __launch_bounds__(256) bound_elem_kernel(const float* bcast, const void* src, BoundEpiArgs a,
                                                          double* partial, int slot0) {
-  bound_elem_rows<T, PI>(bcast, src, a, partial, slot0, 4 * blockIdx.x, blockIdx.y);
+  bound_elem_rows<T, PI>(bcast, src, a, partial, slot0, kElemRows * blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const void* src, const BoundEpiArgs& a,
                                     double* partial, int slot0, hipStream_t st) {
   if (a.rp.M <= 0) return hipSuccess;
-  dim3 grid((a.rp.M + 3) / 4, (a.nd.size + 255) / 256);
+  dim3 grid((a.rp.M + kElemRows - 1) / kElemRows, (a.nd.size + 255) / 256);
   const bool pi = a.rp.rho != nullptr;
   if (bf16_mode && pi)
     hipLaunchKernelGGL((bound_elem_kernel<bf16, true>), grid, dim3(256), 0, st, bcast, src, a, partial, slot0);
@@ -399,8 +403,9 @@ hipError_t launch_bound_elementwise(int bf16_mode, const float* bcast, const voi
   return hipGetLastError();
 }
 
-// Grouped elementwise relaxation: block b of job p covers rows 4 * (b / nb)
-// .. + 3 and columns 256 * (b % nb) .. of that job, nb = ceil(size / 256).
+// Grouped elementwise relaxation: block b of job p covers rows
+// kElemRows * (b / nb) .. and columns 256 * (b % nb) .. of that job,
+// nb = ceil(size / 256).
 template <typename T>
 __global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __restrict__ jobs,
                                                           const int* __restrict__ prefix, int np) {
@@ -413,7 +418,7 @@ __global__ void __launch_bounds__(256) bound_elem_grouped(const ElemBoundJob* __
   const ElemBoundJob& jb = jobs[lo];
   const int nb = (jb.a.nd.size + 255) / 256;
   const int b = t - prefix[lo];
-  bound_elem_rows<T, false>(jb.bcast, jb.src, jb.a, jb.partial, jb.slot0, 4 * (b / nb), b % nb);
+  bound_elem_rows<T, false>(jb.bcast, jb.src, jb.a, jb.partial, jb.slot0, kElemRows * (b / nb), b % nb);
 }
 
 hipError_t launch_bound_elementwise_grouped(int bf16_mode, const ElemBoundJob* d_jobs, const int* d_prefix, int np,

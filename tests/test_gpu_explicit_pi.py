@@ -152,3 +152,35 @@ def test_explicit_pi_invalid_inputs():
         B.bound_pi(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, r[:, :0])
     assert ei.value.code == -1
     torch.cuda.synchronize()
+
+
+def _opt_pi(p, P, mode, use_graph=False):
+    import torch
+    from paper_2208_05740_amd import binding as B
+    a, b, c, r = (_t(x, P.M) for x in (O.full_alpha(p), p.beta, p.gamma, O.full_rho(p)))
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N, explicit_pi=True), dtype=torch.float32,
+                     device=_dev())
+    out, _ = B.optimize_pi(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, r, st, mode=mode,
+                           use_graph=use_graph)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), r.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_optimize_pi_graph_replay_equals_eager(mode):
+    p = gen.make_tiny("mlp", 4, B=3, splits=(1, 2), n_cuts=5, gamma_dist="zero")
+    P = _upload(p)
+    g0, r0 = _opt_pi(p, P, mode)
+    for _ in range(2):   # a fresh capture, then a cached replay
+        g1, r1 = _opt_pi(p, P, mode, use_graph=True)
+        assert np.array_equal(g0, g1) and np.array_equal(r0, r1)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn16"])
+def test_optimize_pi_recomputed_ahat_equals_stored(kind):
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny(kind, 5, B=2, splits=(1, 2), n_cuts=5, gamma_dist="zero")
+    P = _upload(p)
+    gs, rs = _opt_pi(p, P, B.GCP_MODE_BF16 | B.GCP_FLAG_STORE_AHAT)
+    gr, rr = _opt_pi(p, P, B.GCP_MODE_BF16 | B.GCP_FLAG_RECOMPUTE)
+    assert np.array_equal(gs, gr) and np.array_equal(rs, rr)
