@@ -206,6 +206,7 @@ struct gcp_net {
     int M = 0, S = 0, nnz = 0, N = 0;
     std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
     DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in, gammaT;
+    DBuf adam_tab;   // Adam constants of every iteration of a gcp_optimize call, [iters][4]
     DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
     DBuf ahat_tmp;      // a_hat of the node being differentiated, when recomputed
     // captured Adam iteration of gcp_optimize (valid for one argument set)
@@ -1571,32 +1572,41 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   float* mr = rho ? vg + M * N : nullptr;
   float* vr = rho ? mr + M * nI : nullptr;
   AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.consts.as<float>()};
-  hip_check(launch_adam_prepare(ws.step.as<int>(), 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam reset");
+  // eager iterations read their constants from a table made once per call;
+  // replayed graph iterations make them from the step counter (same bits)
+  ws.adam_tab.ensure((size_t)std::max(opt->iters, 1) * 16);
+  hip_check(launch_adam_table(ws.adam_tab.as<float>(), opt->iters, opt->lr_alpha, opt->lr_mult, opt->decay,
+                              opt->adam_b1, opt->adam_b2, c.st),
+            "adam table");
   if (N > 0) hip_check(launch_transpose(gamma, c.M, (int)N, (int)N, ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
   size_partials(c, bf16, true, c.nnz > 0);
   {
     AdjPass prep{c, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
     prep.prepare();
   }
-  auto iteration = [&](Call& cc) {
-    hip_check(launch_adam_prepare(ws.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
-                                  opt->adam_b2, ws.consts.as<float>(), cc.st),
-              "adam prepare");
+  auto iteration = [&](Call& cc, int t) {   // t < 0: the step counter gives t (graph replay)
+    AdamArgs ad = adam;
+    if (t < 0)
+      hip_check(launch_adam_prepare(ws.step.as<int>(), 0, opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1,
+                                    opt->adam_b2, ws.consts.as<float>(), cc.st),
+                "adam prepare");
+    else
+      ad.consts = ws.adam_tab.as<float>() + 4 * t;
     BoundPass bp(cc, bf16, true, cc.nnz > 0, false);
     bp.run();
-    AdjPass ap{cc, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
+    AdjPass ap{cc, bf16, ad, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
     ap.run();
     if (N > 0)
       hip_check(timed(cc.st, "gamma_adam", (double)cc.M * (cc.nnz * 4.0 + N * 24.0), 0.0, [&] {
                   return launch_gamma_update(cc.M, cc.rp.mp, (int)N, cc.cuts->row_ptr.as<int32_t>(),
                                              ws.contrib.as<float>(), cc.cuts->d.as<double>(), ws.gammaT.as<float>(),
-                                             nullptr, mg, vg, adam, cc.st);
+                                             nullptr, mg, vg, ad, cc.st);
                 }),
                 "gamma update");
   };
   int done = 0;
   if (opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
-    iteration(c);
+    iteration(c, 0);
     done = 1;
     c.consts_done = !net->out_general || !bf16;
   }
@@ -1613,6 +1623,8 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
       key.push_back(b);
     }
     if (!ws.gstream) hip_check(hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking), "hipStreamCreate");
+    // the replays continue the count from the eager iterations done so far
+    hip_check(launch_adam_prepare(ws.step.as<int>(), done + 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam step");
     hipEvent_t ev;
     hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
     hip_check(hipEventRecord(ev, c.st), "hipEventRecord");
@@ -1624,7 +1636,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
       hipGraph_t graph;
       hip_check(hipStreamBeginCapture(ws.gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       try {
-        iteration(cg);
+        iteration(cg, -1);
       } catch (...) {
         hipGraph_t g2;
         (void)hipStreamEndCapture(ws.gstream, &g2);
@@ -1641,7 +1653,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
     hip_check(hipStreamWaitEvent(c.st, ev, 0), "hipStreamWaitEvent");
     (void)hipEventDestroy(ev);
   }
-  for (; done < opt->iters; ++done) iteration(c);
+  for (; done < opt->iters; ++done) iteration(c, done);
   if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   bound_pass(c, 0, false, false, bound, verified);

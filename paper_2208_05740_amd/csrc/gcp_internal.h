@@ -212,8 +212,14 @@ hipError_t launch_gamma_update(int M, int mp, int N, const int32_t* row_ptr, con
 // [rows][cols] (pitch ld_in) -> [cols][ld_out]
 hipError_t launch_transpose(const float* in, int rows, int cols, int ld_in, float* out, int ld_out,
                             hipStream_t st);
+// reset = 0: write the constants of iteration *step to consts and advance
+// *step; reset > 0: set *step = reset - 1 only
 hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                float b2, float* consts, hipStream_t st);
+// the constants of iterations 0 .. iters-1 into tab[4 * t ..] (same values
+// as launch_adam_prepare at step t)
+hipError_t launch_adam_table(float* tab, int iters, float lr_alpha, float lr_mult, float decay, float b1, float b2,
+                             hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* flags,
                            hipStream_t st);

@@ -702,20 +702,39 @@ hipError_t launch_transpose(const float* in, int rows, int cols, int ld_in, floa
 
 // Per-iteration Adam constants from the device step counter t, then t += 1;
 // with reset the counter is only set to 0.  consts = {lr_a decay^t, lr_m decay^t, 1-b1^(t+1), 1-b2^(t+1)}.
+// Adam constants of iteration t: learning rates lr * decay^t and the
+// reciprocal bias corrections 1/(1 - b^(t+1)).  One function for the
+// per-call table and the per-iteration kernel, so both give the same bits.
+__device__ inline void adam_consts(int t, float lr_alpha, float lr_mult, float decay, float b1, float b2,
+                                   float* out) {
+  double dec = pow((double)decay, (double)t);
+  out[0] = (float)(lr_alpha * dec);
+  out[1] = (float)(lr_mult * dec);
+  out[2] = (float)(1.0 / (1.0 - pow((double)b1, (double)(t + 1))));
+  out[3] = (float)(1.0 / (1.0 - pow((double)b2, (double)(t + 1))));
+}
 __global__ void adam_prepare_kernel(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                     float b2, float* consts) {
   if (threadIdx.x != 0) return;
-  if (reset) {            // start of an optimisation: t = 0, no constants written
-    *step = 0;
+  if (reset) {            // set the step counter to reset - 1, no constants written
+    *step = reset - 1;
     return;
   }
   int t = *step;
-  double dec = pow((double)decay, (double)t);
-  consts[0] = (float)(lr_alpha * dec);
-  consts[1] = (float)(lr_mult * dec);
-  consts[2] = (float)(1.0 / (1.0 - pow((double)b1, (double)(t + 1))));
-  consts[3] = (float)(1.0 / (1.0 - pow((double)b2, (double)(t + 1))));
+  adam_consts(t, lr_alpha, lr_mult, decay, b1, b2, consts);
   *step = t + 1;
+}
+__global__ void adam_table_kernel(float* tab, int iters, float lr_alpha, float lr_mult, float decay, float b1,
+                                  float b2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < iters) adam_consts(t, lr_alpha, lr_mult, decay, b1, b2, tab + 4 * t);
+}
+hipError_t launch_adam_table(float* tab, int iters, float lr_alpha, float lr_mult, float decay, float b1, float b2,
+                             hipStream_t st) {
+  if (iters <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adam_table_kernel, dim3((iters + 63) / 64), dim3(64), 0, st, tab, iters, lr_alpha, lr_mult,
+                     decay, b1, b2);
+  return hipGetLastError();
 }
 hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mult, float decay, float b1,
                                float b2, float* consts, hipStream_t st) {
