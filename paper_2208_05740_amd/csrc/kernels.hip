@@ -608,27 +608,54 @@ hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n
 // cut k are contiguous in the cut-major order); then the Adam ascent step on
 // gammaT (gamma >= 0, moments [N][M]) or the raw gradient into d_gamma[M][N].
 // Thread per (k, r), rows fastest.
+// One (cut k, row r) of the gamma update.  The Adam state is read before the
+// sum and the cut's entry pieces four at a time, so the loads are in flight
+// together; the pieces are still added one by one in entry order.
+__device__ inline void gamma_one(int k, int r, int M, int mp, int N, const int32_t* row_ptr, const float* contrib,
+                                 const double* d, float* gammaT, float* d_gamma, float* m, float* v,
+                                 const AdamArgs& adam) {
+  const int e0 = row_ptr[k], e1 = row_ptr[k + 1];
+  const size_t im = (size_t)k * M + r;
+  float m0 = 0.f, v0 = 0.f, x0 = 0.f;
+  float* gp = adam.enabled ? gammaT + (size_t)k * mp + r : nullptr;
+  if (adam.enabled) {
+    m0 = m[im];
+    v0 = v[im];
+    x0 = *gp;
+  }
+  double g = -d[k];
+  for (int e = e0; e < e1; e += 4) {
+    float c[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) c[t] = e + t < e1 ? contrib[(size_t)(e + t) * mp + r] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (e + t < e1) g += (double)c[t];
+  }
+  if (adam.enabled) {
+    const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
+    const float gf = (float)g;
+    const float mm = adam.b1 * m0 + (1.f - adam.b1) * gf;
+    const float vv = adam.b2 * v0 + (1.f - adam.b2) * gf * gf;
+    m[im] = mm;
+    v[im] = vv;
+    *gp = fmaxf(x0 + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
+  } else {
+    d_gamma[(size_t)r * N + k] = (float)g;
+  }
+}
+
+// d bound / d gamma[r][k] = -d_k + sum of the cut's entry pieces (entries of
+// cut k are contiguous in the cut-major order); then the Adam ascent step on
+// gammaT (gamma >= 0, moments [N][M]) or the raw gradient into d_gamma[M][N].
+// Thread per (k, r), rows fastest.
 __global__ void __launch_bounds__(256) gamma_kernel(int M, int mp, int N, const int32_t* row_ptr,
                                                     const float* contrib, const double* d, float* gammaT,
                                                     float* d_gamma, float* m, float* v, AdamArgs adam) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (r >= M) return;
-  double g = -d[k];
-  for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e) g += (double)contrib[(size_t)e * mp + r];
-  if (adam.enabled) {
-    const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
-    const float gf = (float)g;
-    const size_t im = (size_t)k * M + r;
-    const float mm = adam.b1 * m[im] + (1.f - adam.b1) * gf;
-    const float vv = adam.b2 * v[im] + (1.f - adam.b2) * gf * gf;
-    m[im] = mm;
-    v[im] = vv;
-    float* gp = gammaT + (size_t)k * mp + r;
-    *gp = fmaxf(*gp + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
-  } else {
-    d_gamma[(size_t)r * N + k] = (float)g;
-  }
+  gamma_one(k, r, M, mp, N, row_ptr, contrib, d, gammaT, d_gamma, m, v, adam);
 }
 
 // Grouped gamma update: block b of job p covers rows 256 * (b % nr) .. of cut
@@ -647,17 +674,7 @@ __global__ void __launch_bounds__(256) gamma_grouped(const GammaJob* __restrict_
   const int k = b / nr;
   const int r = (b % nr) * 256 + threadIdx.x;
   if (r >= jb.M) return;
-  double g = -jb.d[k];
-  for (int e = jb.row_ptr[k]; e < jb.row_ptr[k + 1]; ++e) g += (double)jb.contrib[(size_t)e * jb.mp + r];
-  const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
-  const float gf = (float)g;
-  const size_t im = (size_t)k * jb.M + r;
-  const float mm = adam.b1 * jb.m[im] + (1.f - adam.b1) * gf;
-  const float vv = adam.b2 * jb.v[im] + (1.f - adam.b2) * gf * gf;
-  jb.m[im] = mm;
-  jb.v[im] = vv;
-  float* gp = jb.gammaT + (size_t)k * jb.mp + r;
-  *gp = fmaxf(*gp + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
+  gamma_one(k, r, jb.M, jb.mp, jb.N, jb.row_ptr, jb.contrib, jb.d, jb.gammaT, nullptr, jb.m, jb.v, adam);
 }
 
 hipError_t launch_gamma_grouped(const GammaJob* d_jobs, const int* d_prefix, int np, int total_blocks, AdamArgs adam,
