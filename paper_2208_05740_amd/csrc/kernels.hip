@@ -580,34 +580,44 @@ hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, i
   return hipGetLastError();
 }
 
-// bound[r] = sum_slots partial[slot][r] + c_s.b_out - gamma_r.d, fixed
-// summation order (thread per row, coalesced over rows).
+// bound[r] = sum_slots partial[slot][r] + c_s.b_out - gamma_r.d.  A block
+// takes kRedRows rows; each row's slots and cuts are split over kRedParts
+// threads (every kRedParts-th one, coalesced over rows) whose sums are
+// combined in a fixed order, so the result is deterministic.
+constexpr int kRedRows = 32, kRedParts = 8;
 __global__ void __launch_bounds__(256) reduce_rows_kernel(int M, int mp, int S, const double* partial, int n_slots,
                                                           const double* cb, const float* gammaT, int N,
                                                           const double* d, double* bound, uint8_t* verified) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= M) return;
+  __shared__ double sh[kRedParts][kRedRows];
+  const int rl = threadIdx.x % kRedRows, part = threadIdx.x / kRedRows;
+  const int r = blockIdx.x * kRedRows + rl;
   double s = 0.0;
-  for (int k = 0; k < n_slots; ++k) s += partial[(size_t)k * mp + r];
-  double gd = 0.0;
-  for (int k = 0; k < N; ++k) gd += (double)gammaT[(size_t)k * mp + r] * d[k];
-  const double b = s + cb[r % S] - gd;
-  bound[r] = b;
-  if (verified) verified[r] = (b >= 0.0) ? 1 : 0;
+  if (r < M) {
+    for (int k = part; k < n_slots; k += kRedParts) s += partial[(size_t)k * mp + r];
+    for (int k = part; k < N; k += kRedParts) s -= (double)gammaT[(size_t)k * mp + r] * d[k];
+  }
+  sh[part][rl] = s;
+  __syncthreads();
+  if (part == 0 && r < M) {
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < kRedParts; ++p) t += sh[p][rl];
+    const double b = t + cb[r % S];
+    bound[r] = b;
+    if (verified) verified[r] = (b >= 0.0) ? 1 : 0;
+  }
 }
 
 hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n_slots, const double* cb,
                               const float* gammaT, int N, const double* d, double* bound, uint8_t* verified,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3((M + 255) / 256), dim3(256), 0, st, M, mp, S, partial, n_slots, cb,
-                     gammaT, N, d, bound, verified);
+  static_assert(kRedRows * kRedParts == 256, "one 256-thread block");
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((M + kRedRows - 1) / kRedRows), dim3(256), 0, st, M, mp, S, partial,
+                     n_slots, cb, gammaT, N, d, bound, verified);
   return hipGetLastError();
 }
 
-// d bound / d gamma[r][k] = -d_k + sum of the cut's entry pieces (entries of
-// cut k are contiguous in the cut-major order); then the Adam ascent step on
-// gammaT (gamma >= 0, moments [N][M]) or the raw gradient into d_gamma[M][N].
-// Thread per (k, r), rows fastest.
 // One (cut k, row r) of the gamma update.  The Adam state is read before the
 // sum and the cut's entry pieces four at a time, so the loads are in flight
 // together; the pieces are still added one by one in entry order.
