@@ -17,9 +17,14 @@ import numpy as np
 from .lp import edge_matrix
 
 
-def crown_bound(net, lu, x0, eps, c, alpha_per_node):
+def crown_bound(net, lu, x0, eps, c, alpha_per_node, fixed=None):
     """Lower bound of c^T f(x) over the box.  alpha_per_node[k] is the lower
-    slope of every neuron of the k-th ReLU node (used where unstable)."""
+    slope of every neuron of the k-th ReLU node (used where unstable).
+    fixed[(node, neuron)] = +1 / -1 replaces the ReLU of that neuron by its
+    active (x_hat = x) / inactive (x_hat = 0) piece: the network of a BaB
+    domain with those splits, whose bound over the box also bounds it over
+    the domain (Sec. 3.1, splits; no split multipliers here)."""
+    fixed = fixed or {}
     relu = [i for i, n in enumerate(net.nodes) if n.relu]
     pos = {p: k for k, p in enumerate(relu)}
     coef = {}          # coefficient row on each post-activation
@@ -38,9 +43,10 @@ def crown_bound(net, lu, x0, eps, c, alpha_per_node):
         l, u = lu[pos[p]]
         lam = np.zeros(node.size)
         for j in range(node.size):
-            if l[j] >= 0:
+            fx = fixed.get((p, j), 0)
+            if fx > 0 or (fx == 0 and l[j] >= 0):
                 lam[j] = lam_hat[j]
-            elif u[j] <= 0:
+            elif fx < 0 or u[j] <= 0:
                 lam[j] = 0.0
             elif lam_hat[j] >= 0:
                 lam[j] = alpha_per_node[pos[p]][j] * lam_hat[j]
@@ -54,7 +60,7 @@ def crown_bound(net, lu, x0, eps, c, alpha_per_node):
     return float(w @ x0 - eps * np.abs(w).sum() + const)
 
 
-def crown_intermediate_bounds(net, x0, eps, lu_given=None):
+def crown_intermediate_bounds(net, x0, eps, lu_given=None, splits=None):
     """Layer-by-layer CROWN bounds on every ReLU node's pre-activation
     (intermediate bounds of Sec. 2, computed as in CROWN: the bounds of node k
     are the CROWN bounds of the prefix network that ends at node k's
@@ -64,22 +70,41 @@ def crown_intermediate_bounds(net, x0, eps, lu_given=None):
 
     With lu_given, node k uses lu_given[:k] for the earlier nodes instead of
     its own results (to compare one layer at a time with another
-    implementation)."""
+    implementation).
+
+    splits: optional [(node, neuron, sign)] of one BaB domain (sign +1 for
+    x >= 0, -1 for x <= 0): the bounds over that domain instead of the whole
+    box.  A split neuron of an earlier node takes its linear piece (as in
+    crown_bound's fixed), and its own bounds are clamped at 0 (l = max(l, 0)
+    for x >= 0, u = min(u, 0) for x <= 0); a split that contradicts the
+    bounds (the domain is empty, up to rounding) leaves the neuron at
+    exactly 0."""
     import dataclasses
 
     relu = [i for i, n in enumerate(net.nodes) if n.relu]
+    fixed_all = {(int(n), int(j)): int(sg) for n, j, sg in (splits or [])}
     lu = []
     for pos, k in enumerate(relu):
         node = net.nodes[k]
         prev = list(lu_given[:pos]) if lu_given is not None else list(lu)
         prefix = type(net)(net.in_shape, list(net.nodes[:k]) + [dataclasses.replace(node, relu=False)])
         apn = [np.where(u >= -l, 1.0, 0.0) for l, u in prev]
+        fixed = {key: sg for key, sg in fixed_all.items() if key[0] < k}
         lo = np.empty(node.size)
         hi = np.empty(node.size)
         for j in range(node.size):
             e = np.zeros(node.size)
             e[j] = 1.0
-            lo[j] = crown_bound(prefix, prev, x0, eps, e, apn)
-            hi[j] = -crown_bound(prefix, prev, x0, eps, -e, apn)
+            lo[j] = crown_bound(prefix, prev, x0, eps, e, apn, fixed)
+            hi[j] = -crown_bound(prefix, prev, x0, eps, -e, apn, fixed)
+        for (n, j), sg in fixed_all.items():
+            if n != k:
+                continue
+            if sg > 0:
+                lo[j] = max(lo[j], 0.0)
+                hi[j] = max(hi[j], lo[j])
+            else:
+                hi[j] = min(hi[j], 0.0)
+                lo[j] = min(lo[j], hi[j])
         lu.append((lo, hi))
     return lu

@@ -538,3 +538,60 @@ def test_optimised_explicit_pi_is_sound_with_tight_cuts(kind, seed):
     lpv = np.array([[lp.lp_value(p, b, s) for s in range(p.S)] for b in range(p.B)])
     g, *_ = O.optimize_pi(p, iters=150, opt=dict(decay=0.99, lr_alpha=0.05, lr_mult=0.05))
     assert np.all(g.reshape(p.B, p.S) <= lpv + 1e-7), (g, lpv)
+
+
+# ------------------------------- intermediate bounds of one BaB domain
+
+def _domain_splits(p, rng, n_split, x_ref):
+    # split root-unstable neurons of the ReLU nodes with the signs their
+    # pre-activations take at x_ref, so x_ref lies in the domain
+    root = crown.crown_intermediate_bounds(p.net, p.x0, p.eps)
+    _, pre = lp.plain_forward(p.net, x_ref[None, :], return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    cand = [(k, j) for (l, u), k in zip(root, relu) for j in np.nonzero((l < 0) & (u > 0))[0]]
+    pick = rng.choice(len(cand), size=min(n_split, len(cand)), replace=False)
+    return [(k, int(j), 1 if pre[k][0][j] >= 0 else -1) for k, j in (cand[t] for t in pick)]
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 2), ("cnn", 3), ("res", 4)])
+def test_domain_intermediate_bounds_contain_the_domain_samples(kind, seed):
+    p = gen.make_tiny(kind, seed, eps=0.2)
+    rng = np.random.default_rng(seed)
+    x_ref = p.x0 + p.eps * rng.uniform(-1, 1, size=p.x0.size)
+    sp = _domain_splits(p, rng, 4, x_ref)
+    lu = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, splits=sp)
+    xs = p.x0[None, :] + p.eps * rng.uniform(-1, 1, size=(20000, p.x0.size))
+    xs[0] = x_ref
+    _, pre = lp.plain_forward(p.net, xs, return_pre=True)
+    keep = np.ones(xs.shape[0], bool)
+    for k, j, sg in sp:
+        keep &= sg * pre[k][:, j] >= 0
+    assert keep.sum() >= 1
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    for (l, u), i in zip(lu, relu):
+        assert (pre[i][keep] >= l[None, :] - 1e-9).all() and (pre[i][keep] <= u[None, :] + 1e-9).all()
+    for k, j, sg in sp:   # each split neuron's own bound is clamped at 0
+        l, u = lu[relu.index(k)]
+        assert (l[j] >= 0.0) if sg > 0 else (u[j] <= 0.0)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn", "res"])
+def test_domain_intermediate_bounds_exact_at_zero_radius(kind):
+    # eps = 0 with splits that x0 satisfies: every neuron takes the piece it
+    # takes at x0, so every bound is x0's pre-activation
+    p = gen.make_tiny(kind, 0, eps=0.2)
+    rng = np.random.default_rng(5)
+    sp = _domain_splits(p, rng, 3, p.x0)
+    lu = crown.crown_intermediate_bounds(p.net, p.x0, 0.0, splits=sp)
+    _, pre = lp.plain_forward(p.net, p.x0[None, :], return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    for (l, u), i in zip(lu, relu):
+        assert np.allclose(l, pre[i][0], atol=1e-9) and np.allclose(u, pre[i][0], atol=1e-9)
+
+
+def test_domain_intermediate_bounds_without_splits_are_the_root_bounds():
+    p = gen.make_tiny("res", 1, eps=0.2)
+    a = crown.crown_intermediate_bounds(p.net, p.x0, p.eps)
+    b = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, splits=[])
+    for (l0, u0), (l1, u1) in zip(a, b):
+        assert np.array_equal(l0, l1) and np.array_equal(u0, u1)
