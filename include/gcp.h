@@ -269,6 +269,24 @@ int gcp_optimize_pi(const gcp_net* net, const double* x0, double eps,
 int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, double eps, double* const* lower,
                      double* const* upper, int32_t mode, void* stream);
 
+/* gcp_crown_bounds_domain: the same bounds over one BaB domain, the box
+ * restricted by n_split (<= 127) split constraints: neuron split_neuron[s]
+ * of ReLU node split_node[s] with split_sign[s] = +1 (x >= 0) or -1
+ * (x <= 0) (host arrays; each neuron at most once).  Layer by layer as in
+ * gcp_crown_bounds, with two changes (Sec. 3.1 on splits, without split
+ * multipliers): a split neuron of an earlier node that is unstable under
+ * the bounds found so far takes its linear piece (x_hat = x for x >= 0,
+ * x_hat = 0 for x <= 0) instead of its relaxation, and a split neuron's own
+ * bounds are clamped at 0 (l = max(l, 0), resp. u = min(u, 0)).  A split
+ * that contradicts its neuron's bounds (the domain is empty, up to
+ * rounding) leaves that neuron at exactly [0, 0], so l <= u always holds
+ * and the result can be passed to gcp_net_create as the domain's root
+ * bounds.  n_split = 0 is gcp_crown_bounds.  Errors: as gcp_crown_bounds;
+ * EINVAL for a bad split. */
+int gcp_crown_bounds_domain(const gcp_net_desc* desc, const double* x0, double eps, int32_t n_split,
+                            const int32_t* split_node, const int32_t* split_neuron, const int8_t* split_sign,
+                            double* const* lower, double* const* upper, int32_t mode, void* stream);
+
 /* ------------------------------------------------------------ branch and bound */
 /* gcp_bab: branch and bound on one property c^T f(x) >= 0 over the box
  * (Appendix B's procedure, easiest domains first as in Sec. 3.3), with

@@ -108,6 +108,8 @@ def lib():
                                   vp]
     L.gcp_optimize_batch.argtypes = [i32, C.POINTER(BatchItem), C.POINTER(OptDesc), i32, vp]
     L.gcp_crown_bounds.argtypes = [C.POINTER(NetDesc), vp, dbl, C.POINTER(vp), C.POINTER(vp), i32, vp]
+    L.gcp_crown_bounds_domain.argtypes = [C.POINTER(NetDesc), vp, dbl, i32, vp, vp, vp, C.POINTER(vp), C.POINTER(vp),
+                                          i32, vp]
     L.gcp_net_get_unstable.argtypes = [vp, vp, vp, vp, vp]
     L.gcp_cuts_info.argtypes = [vp, C.POINTER(i32)]
     L.gcp_bab.argtypes = [vp, vp, dbl, vp, vp, C.POINTER(BabOpt), C.POINTER(BabResult), vp]
@@ -206,17 +208,26 @@ class Net:
             self.h = None
 
 
-def crown_bounds(net, x0, eps: float, mode: int = GCP_MODE_FP32):
+def crown_bounds(net, x0, eps: float, mode: int = GCP_MODE_FP32, splits=None):
     """gcp_crown_bounds: CROWN pre-activation bounds of every ReLU node of a
     workloads.Net over the box around x0 (a device fp64 tensor), computed on
-    the device; returns [(l, u)] as host fp64 arrays, one pair per ReLU node."""
+    the device; returns [(l, u)] as host fp64 arrays, one pair per ReLU node.
+    splits: optional [(node, neuron, sign)] of one BaB domain
+    (gcp_crown_bounds_domain: the bounds over that domain)."""
     desc, keep = _net_desc(net, None)
     relu = [n for n in net.nodes if n.relu]
     lo = [np.empty(n.size, np.float64) for n in relu]
     hi = [np.empty(n.size, np.float64) for n in relu]
     lp = (C.c_void_p * len(relu))(*[a.ctypes.data for a in lo])
     up = (C.c_void_p * len(relu))(*[a.ctypes.data for a in hi])
-    _check(lib().gcp_crown_bounds(C.byref(desc), _ptr(x0), float(eps), lp, up, mode, _stream()))
+    if splits:
+        sn = np.ascontiguousarray([s[0] for s in splits], np.int32)
+        sj = np.ascontiguousarray([s[1] for s in splits], np.int32)
+        sg = np.ascontiguousarray([s[2] for s in splits], np.int8)
+        _check(lib().gcp_crown_bounds_domain(C.byref(desc), _ptr(x0), float(eps), len(splits), sn.ctypes.data,
+                                             sj.ctypes.data, sg.ctypes.data, lp, up, mode, _stream()))
+    else:
+        _check(lib().gcp_crown_bounds(C.byref(desc), _ptr(x0), float(eps), lp, up, mode, _stream()))
     return list(zip(lo, hi))
 
 

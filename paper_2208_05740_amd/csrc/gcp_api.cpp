@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -2126,6 +2127,13 @@ struct SplitsGuard { gcp_splits* p = nullptr; ~SplitsGuard() { if (p) gcp_splits
 
 extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, double eps, double* const* lower,
                                 double* const* upper, int32_t mode, void* stream) {
+  return gcp_crown_bounds_domain(desc, x0, eps, 0, nullptr, nullptr, nullptr, lower, upper, mode, stream);
+}
+
+extern "C" int gcp_crown_bounds_domain(const gcp_net_desc* desc, const double* x0, double eps, int32_t n_split,
+                                       const int32_t* split_node, const int32_t* split_neuron,
+                                       const int8_t* split_sign, double* const* lower, double* const* upper,
+                                       int32_t mode, void* stream) {
   GCP_TRY
   if (!desc || !desc->nodes || desc->n_nodes < 2) fail(GCP_EINVAL, "bad network description");
   if (!x0) fail(GCP_EINVAL, "null x0");
@@ -2133,6 +2141,19 @@ extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, doub
   if ((mode & 0xff) != GCP_MODE_FP32 && (mode & 0xff) != GCP_MODE_BF16) fail(GCP_EINVAL, "unknown mode");
   const int out = desc->n_nodes - 1;
   hipStream_t st = (hipStream_t)stream;
+  // the domain's splits, checked: node of a ReLU layer, neuron in range, sign
+  // +-1, no neuron twice
+  if (n_split < 0 || n_split > 127) fail(GCP_EINVAL, "need 0 <= n_split <= 127");
+  if (n_split > 0 && (!split_node || !split_neuron || !split_sign)) fail(GCP_EINVAL, "null split arrays");
+  std::set<std::pair<int, int>> seen;
+  for (int s = 0; s < n_split; ++s) {
+    const int k = split_node[s];
+    if (k < 0 || k >= out) fail(GCP_EINVAL, "split on a node that is not a ReLU layer");
+    const gcp_node_desc& nk = desc->nodes[k];
+    if (split_neuron[s] < 0 || split_neuron[s] >= nk.c * nk.h * nk.w) fail(GCP_EINVAL, "split neuron out of range");
+    if (split_sign[s] != 1 && split_sign[s] != -1) fail(GCP_EINVAL, "split sign must be +1 or -1");
+    if (!seen.insert({k, split_neuron[s]}).second) fail(GCP_EINVAL, "neuron split twice");
+  }
   std::vector<std::vector<double>> L(out), U(out);
   std::vector<gcp_node_desc> nodes(desc->nodes, desc->nodes + desc->n_nodes);
   constexpr int kRowsPerCall = 4096;
@@ -2162,16 +2183,30 @@ extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, doub
       for (size_t j = 0; j < L[i].size(); ++j)
         if (L[i][j] < 0.0 && U[i][j] > 0.0) arow.push_back(U[i][j] >= -L[i][j] ? 1.f : 0.f);
     const size_t nI = arow.size();
+    // splits of earlier nodes whose neuron is unstable under the bounds found
+    // so far (a stable one already takes the piece its bounds allow)
+    std::vector<int32_t> sn, sj;
+    std::vector<int8_t> ss;
+    for (int s = 0; s < n_split; ++s) {
+      const int i = split_node[s], j = split_neuron[s];
+      if (i < k && L[i][j] < 0.0 && U[i][j] > 0.0) {
+        sn.push_back(i);
+        sj.push_back(j);
+        ss.push_back(split_sign[s]);
+      }
+    }
+    const int K = (int)sn.size();
     SplitsGuard spl;
     {
-      const int rc = gcp_splits_create(net.p, 1, 0, nullptr, nullptr, nullptr, &spl.p);
+      const int rc = gcp_splits_create(net.p, 1, K, sn.data(), sj.data(), ss.data(), &spl.p);
       if (rc != GCP_OK) return rc;
     }
     // spec rows: +e_j (lower bound of x_j) then -e_j (minus the upper bound)
     const int S_all = 2 * d;
     const int rows = std::min(kRowsPerCall, S_all);
-    DBuf Cd, Ad, Bd;
+    DBuf Cd, Ad, Bd, Zd;   // Zd: the split multipliers, all 0
     Cd.alloc((size_t)rows * d * 8);
+    if (K) Zd.alloc((size_t)rows * K * 4);
     Ad.alloc(std::max<size_t>((size_t)rows * nI * 4, 4));
     Bd.alloc((size_t)rows * 8);
     std::vector<float> arows((size_t)rows * nI);
@@ -2188,8 +2223,8 @@ extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, doub
       }
       hip_check(hipMemcpyAsync(Cd.p, Ch.data(), (size_t)S * d * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
       const int rc = gcp_bound(net.p, x0, eps, Cd.as<double>(), S, spl.p, nullptr, nI ? Ad.as<float>() : nullptr,
-                               nullptr, nullptr, mode & 0xff, Bd.as<double>(), nullptr, nullptr, nullptr, nullptr,
-                               stream);
+                               K ? Zd.as<float>() : nullptr, nullptr, mode & 0xff, Bd.as<double>(), nullptr, nullptr,
+                               nullptr, nullptr, stream);
       if (rc != GCP_OK) return rc;
       hip_check(hipMemcpyAsync(bh.data(), Bd.p, (size_t)S * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
       hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -2205,6 +2240,20 @@ extern "C" int gcp_crown_bounds(const gcp_net_desc* desc, const double* x0, doub
       // an exactly determined pre-activation (l = u in exact arithmetic) can
       // come out a rounding error apart in the two directions
       if (lo[j] > hi[j]) std::swap(lo[j], hi[j]);
+    }
+    // a split neuron of this node: its bounds over the domain are clamped at
+    // 0; a split that contradicts them (empty domain, up to rounding) leaves
+    // the neuron at exactly 0
+    for (int s = 0; s < n_split; ++s) {
+      if (split_node[s] != k) continue;
+      const int j = split_neuron[s];
+      if (split_sign[s] > 0) {
+        lo[j] = std::max(lo[j], 0.0);
+        hi[j] = std::max(hi[j], lo[j]);
+      } else {
+        hi[j] = std::min(hi[j], 0.0);
+        lo[j] = std::min(lo[j], hi[j]);
+      }
     }
     L[k] = std::move(lo);
     U[k] = std::move(hi);

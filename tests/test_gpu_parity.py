@@ -430,6 +430,44 @@ def test_crown_intermediate_bounds_match_oracle(kind, seed):
         assert (pre[i] >= l[None, :] - 1e-6).all() and (pre[i] <= u[None, :] + 1e-6).all()
 
 
+@pytest.mark.parametrize("kind,seed", [("mlp", 5), ("cnn", 6), ("res", 7), ("res16", 8)])
+def test_domain_intermediate_bounds_match_oracle(kind, seed):
+    # one BaB domain (splits that a reference point satisfies): layer by layer
+    # against the oracle given the device's earlier bounds, and sound on the
+    # sampled points of the domain
+    import torch
+    from paper_2208_05740_amd import binding as B
+    from oracle import crown
+    p = gen.make_tiny(kind, seed, eps=0.1)
+    rng = np.random.default_rng(seed)
+    x_ref = p.x0 + p.eps * rng.uniform(-1, 1, size=p.x0.size)
+    root = crown.crown_intermediate_bounds(p.net, p.x0, p.eps)
+    _, pre_ref = lp.plain_forward(p.net, x_ref[None, :], return_pre=True)
+    relu = [i for i, n in enumerate(p.net.nodes) if n.relu]
+    cand = [(k, int(j)) for (l, u), k in zip(root, relu) for j in np.nonzero((l < 0) & (u > 0))[0]]
+    pick = rng.choice(len(cand), size=min(5, len(cand)), replace=False)
+    sp = [(k, j, 1 if pre_ref[k][0][j] >= 0 else -1) for k, j in (cand[t] for t in pick)]
+    x0 = torch.tensor(p.x0, dtype=torch.float64, device=_dev())
+    got = B.crown_bounds(p.net, x0, p.eps, splits=sp)
+    want = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, lu_given=got, splits=sp)
+    for (gl, gu), (wl, wu) in zip(got, want):
+        scale = np.abs(wl) + np.abs(wu) + 1.0
+        assert (np.abs(gl - wl) / scale).max() <= 1e-5
+        assert (np.abs(gu - wu) / scale).max() <= 1e-5
+        assert (gl <= gu).all()
+    xs = p.x0[None, :] + p.eps * rng.uniform(-1, 1, size=(20000, p.x0.size))
+    xs[0] = x_ref
+    _, pre = lp.plain_forward(p.net, xs, return_pre=True)
+    keep = np.ones(xs.shape[0], bool)
+    for k, j, sg in sp:
+        keep &= sg * pre[k][:, j] >= 0
+    for (l, u), i in zip(got, relu):
+        assert (pre[i][keep] >= l[None, :] - 1e-6).all() and (pre[i][keep] <= u[None, :] + 1e-6).all()
+    # the domain's bounds are valid root bounds of a net for that domain
+    net = B.Net(p.net, got)
+    del net
+
+
 def test_crown_intermediate_bounds_as_root_bounds_mlp784():
     # CROWN bounds of a 784-256x3-10 MLP computed on the device: tighter than
     # interval bounds on the deeper layers, and usable as root bounds
