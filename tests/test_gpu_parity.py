@@ -108,6 +108,15 @@ def test_single_row():
     check_bound(p)
 
 
+@pytest.mark.parametrize("kind", ["cnn16", "res16"])
+@pytest.mark.parametrize("B,S", [(1, 1), (1, 2), (5, 1)])
+def test_conv_row_counts_off_the_four_row_groups(kind, B, S):
+    # conv workgroups take four batch rows: 1, 2 and 5 rows leave 3, 2 and 3
+    # of them empty
+    p = gen.make_tiny(kind, 6, B=B, splits=(1, 2), n_cuts=4, S=S, input_terms=1)
+    check_bound(p)
+
+
 def test_invalid_inputs_raise():
     import torch
     from paper_2208_05740_amd import binding as B
