@@ -40,6 +40,15 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.gcp_net_create(None, None) == -1
     assert lib.gcp_net_get_info(None, None) == -1
     assert lib.gcp_last_error()
+    # the variant and intermediate-bound entry points check their handles first
+    vp = ctypes.c_void_p
+    lib.gcp_bound_pi.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_int32] + [vp] * 6 + [ctypes.c_int32] + \
+        [vp] * 7
+    assert lib.gcp_bound_pi(None, None, 0.0, None, 1, *([None] * 6), 0, *([None] * 7)) == -1
+    lib.gcp_crown_bounds_domain.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                            ctypes.c_int32, vp]
+    assert lib.gcp_crown_bounds_domain(None, None, 0.1, 0, None, None, None, None, None, 0, None) == -1
+    assert b"network" in lib.gcp_last_error()
 
 
 def test_shipped_tile_choices_are_well_formed():
