@@ -621,6 +621,48 @@ def test_certified_bounds_never_exceed_sampled_minimum(k):
         assert (g[dom] <= smin + 1e-9).all(), (dom, g[dom], smin)
 
 
+@pytest.mark.parametrize("k,B_,n", [(3, 4, 2000), (5, 2, 100)])
+def test_conv_certified_bounds_never_exceed_points_of_their_domains(k, B_, n):
+    # CNN and ResNet workloads: every domain keeps its split neurons but takes
+    # their signs from a reference point, so the reference point and the
+    # sampled points around it that meet the splits are points of the domain;
+    # the certified bound may not exceed c^T f at any of them
+    import dataclasses
+
+    import torch
+    from paper_2208_05740_amd import binding as B
+    prob = gen.make_config(k, 0, B=B_)
+    rng = np.random.default_rng(k)
+    x_ref = prob.x0 + prob.eps * rng.uniform(-1, 1, size=prob.x0.size)
+    _, pre_ref = lp.plain_forward(prob.net, x_ref[None, :], return_pre=True)
+    sp = prob.splits
+    sign = sp.sign.copy()
+    for b_ in range(sp.B):
+        for s_ in range(sp.K):
+            if sp.node[b_, s_] >= 0:
+                sign[b_, s_] = 1 if pre_ref[int(sp.node[b_, s_])][0][int(sp.neuron[b_, s_])] >= 0 else -1
+    prob = dataclasses.replace(prob, splits=gen.Splits(sp.node, sp.neuron, sign))
+    P = upload(prob)
+    a, b, c, *_ = params(prob, P)
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+    out, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=20, mode=B.GCP_MODE_BF16)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().reshape(prob.B, prob.S)
+    X = np.clip(x_ref[None, :] + 0.05 * prob.eps * rng.uniform(-1, 1, size=(n, x_ref.size)),
+                prob.x0 - prob.eps, prob.x0 + prob.eps)
+    X[0] = x_ref
+    fx, pre = lp.plain_forward(prob.net, X, return_pre=True)
+    for dom in range(prob.B):
+        ok = np.ones(X.shape[0], bool)
+        for s_ in range(sp.K):
+            if sp.node[dom, s_] >= 0:
+                v = pre[int(sp.node[dom, s_])][:, int(sp.neuron[dom, s_])]
+                ok &= (v >= 0) if sign[dom, s_] > 0 else (v <= 0)
+        assert ok[0]
+        vmin = (fx[ok] @ prob.C.T).min(0)
+        assert (g[dom] <= vmin + 1e-9).all(), (dom, g[dom], vmin)
+
+
 @pytest.mark.parametrize("kind,B_", [("res16", 2), ("cfg5", 1)])
 def test_adjoint_gradient_matches_central_differences(kind, B_):
     # d bound / d alpha and d gamma from the device adjoint against central
