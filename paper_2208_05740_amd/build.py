@@ -38,6 +38,13 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    # a command-line example that uses the C ABI alone (no Python)
+    ex = os.path.join(HERE, "examples", "gcp_bound_mlp")
+    cmd = ["hipcc", "-O2", "-std=c++17", os.path.join(HERE, "examples", "gcp_bound_mlp.cpp"), "-L" + HERE, "-lgcp",
+           "-Wl,-rpath,$ORIGIN/..", "-o", ex]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stderr}")
     if verbose:
         print("built", OUT)
     return OUT

@@ -715,3 +715,48 @@ def test_adjoint_gradient_matches_central_differences(kind, B_):
             assert abs(got - fd) <= 1e-3 * max(abs(fd), abs(got)) + noise, (which, idx, got, fd, noise)
             checked += 1
     assert checked >= 6
+
+
+def test_c_abi_example_program_matches_oracle(tmp_path):
+    # the command-line example drives gcp_net_create / gcp_splits_create /
+    # gcp_cuts_create / gcp_bound from C++ with the HIP runtime alone
+    import os
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2208_05740_amd",
+                       "examples", "gcp_bound_mlp")
+    assert os.path.exists(exe), "example not built"
+    p = gen.make_tiny("mlp", 3, B=3, splits=(1, 2), n_cuts=5, input_terms=1)
+    rng = np.random.default_rng(3)
+    prep = O.Prepared(p)
+    f32 = lambda x: np.asarray(x, np.float32).astype(np.float64)  # noqa: E731
+    a = f32(rng.random((p.B, p.S, prep.n_I)))
+    b = f32(rng.random((p.B, p.S, p.splits.K)) * 0.5 * (p.splits.node >= 0)[:, None, :])
+    c = f32(rng.random((p.B, p.S, p.cuts.n)) * 0.5)
+    net = p.net
+    dims = [net.in_size] + [n.size for n in net.nodes]
+    out = [f"{len(net.nodes)} " + " ".join(map(str, dims))]
+    for n in net.nodes:
+        out.append(" ".join(repr(float(v)) for v in np.asarray(n.edges[0].W, np.float32).ravel()))
+        out.append(" ".join(repr(float(v)) for v in np.asarray(n.bias, np.float32)))
+    for l, u in p.lu:
+        out.append(" ".join(repr(float(v)) for v in l))
+        out.append(" ".join(repr(float(v)) for v in u))
+    out.append(" ".join(repr(float(v)) for v in p.x0) + f" {p.eps!r}")
+    out.append(f"{p.S} " + " ".join(repr(float(v)) for v in p.C.ravel()))
+    sp = p.splits
+    out.append(f"{sp.B} {sp.K} " + " ".join(map(str, sp.node.ravel())) + " " + " ".join(map(str, sp.neuron.ravel()))
+               + " " + " ".join(map(str, sp.sign.ravel())))
+    cu = p.cuts
+    ents = " ".join(f"{cu.cut[e]} {cu.node[e]} {cu.neuron[e]} {cu.kind[e]} {float(cu.coef[e])!r}"
+                    for e in range(cu.cut.size))
+    out.append(f"{cu.n} {cu.cut.size} {ents} " + " ".join(repr(float(v)) for v in cu.d))
+    out.append(f"{prep.n_I} " + " ".join(repr(float(v)) for x in (a, b, c) for v in x.ravel()))
+    path = tmp_path / "problem.txt"
+    path.write_text("\n".join(out) + "\n")
+    r = subprocess.run([exe, str(path), "fp32"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = np.array([float(t) for t in r.stdout.split()])
+    ref = O.bound(p, a, b, c).reshape(-1)
+    T = O.error_scale(p, a, b, c).reshape(-1)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref, T).max() <= 1e-5, (got, ref)
