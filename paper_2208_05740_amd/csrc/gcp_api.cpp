@@ -1418,7 +1418,8 @@ void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const dou
   c.N = N;
   ensure_ws(c);
   c.rp = RowParams{c.M, S, round_up(c.M, 16), alpha, net->n_I, beta, splits->K, net->ws.gammaT.as<float>(), N,
-                   splits->K > 0 ? splits->mask.as<int8_t>() : nullptr, 1.0 / S};
+                   splits->K > 0 ? splits->mask.as<int8_t>() : nullptr, 1.0 / S,
+                   nullptr /* rho: set by the explicit-pi entry points */};
 }
 
 // Which nodes recompute a_hat in the adjoint (Theorem 3.1 needs a_hat of
