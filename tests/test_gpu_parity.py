@@ -145,6 +145,58 @@ def test_invalid_inputs_raise():
     torch.cuda.synchronize()
 
 
+def test_bad_splits_cuts_and_call_arguments_are_rejected_before_any_launch():
+    """Host-side validation of the handles and call arguments (include/gcp.h):
+    every case returns GCP_EINVAL and leaves nothing launched."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    p = gen.make_tiny("mlp", 0, B=2, splits=(1, 2), n_cuts=3)
+    P = upload(p)
+    prep = O.Prepared(p)
+    q = prep.relu[0]
+    unst = [int(j) for j in np.nonzero(prep.cls[q] == 2)[0]]
+    out_node = len(p.net.nodes) - 1
+
+    def splits(node, neuron, sign):
+        a = lambda x, t: np.asarray(x, t).reshape(len(x), -1)  # noqa: E731
+        return gen.Splits(a(node, np.int32), a(neuron, np.int32), a(sign, np.int8))
+
+    def rejected(make):
+        with pytest.raises(B.GcpError) as ei:
+            make()
+        assert ei.value.code == -1, ei.value
+
+    z = np.zeros((0, 1))
+    rejected(lambda: B.Splits(P.net, gen.Splits(z.astype(np.int32), z.astype(np.int32), z.astype(np.int8))))
+    rejected(lambda: B.Splits(P.net, splits([[-1] * 128], [[0] * 128], [[1] * 128])))        # K > 127
+    rejected(lambda: B.Splits(P.net, splits([[q]], [[unst[0]]], [[0]])))                     # sign 0
+    rejected(lambda: B.Splits(P.net, splits([[q, q]], [[unst[0], unst[0]]], [[1, -1]])))     # split twice
+    rejected(lambda: B.Splits(P.net, splits([[out_node]], [[0]], [[1]])))                    # not a ReLU node
+    rejected(lambda: B.Splits(P.net, splits([[q]], [[8]], [[1]])))                           # neuron out of range
+
+    def cuts(cut, node, neuron, kind, n=1):
+        e = len(cut)
+        return gen.Cuts(n, np.asarray(cut, np.int32), np.asarray(node, np.int32), np.asarray(neuron, np.int32),
+                        np.asarray(kind, np.int8), np.ones(e), np.zeros(n))
+    rejected(lambda: B.Cuts(P.net, cuts([1], [q], [0], [0])))                   # cut index >= N
+    rejected(lambda: B.Cuts(P.net, cuts([0], [q], [0], [3])))                   # unknown coefficient kind
+    rejected(lambda: B.Cuts(P.net, cuts([0], [-1], [0], [0])))                  # input entry of kind H
+    rejected(lambda: B.Cuts(P.net, cuts([0], [q], [8], [0])))                   # neuron out of range
+    rejected(lambda: B.Cuts(P.net, cuts([0], [out_node], [0], [0])))            # output node
+
+    a, b, c, *_ = params(p, P)
+    rejected(lambda: B.bound(P.net, P.x0, P.eps, P.C[:0], P.splits, P.cuts, a, b, c))          # S = 0
+    rejected(lambda: B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, mode=7))      # unknown mode
+    other = upload(gen.make_tiny("mlp", 0, B=2, splits=(1, 2), n_cuts=3))
+    rejected(lambda: B.bound(P.net, P.x0, P.eps, P.C, other.splits, P.cuts, a, b, c))         # foreign splits
+    rejected(lambda: B.bound(P.net, P.x0, P.eps, P.C, P.splits, other.cuts, a, b, c))         # foreign cuts
+    torch.cuda.synchronize()
+    # the handles still work after the rejected calls
+    out, _, _ = B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c)
+    ref = O.bound(p, O.full_alpha(p), p.beta, p.gamma).reshape(-1)
+    assert np.allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
 def test_autograd_function_matches_adjoint():
     import torch
     from paper_2208_05740_amd import binding as B
