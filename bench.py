@@ -91,9 +91,8 @@ def main():
     if not args.retune:
         use_tuned_tiles()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the bound pass shards BaB domains across GPUs by design but that path is not built.",
-              file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); sharding the BaB domains "
+              "of a call across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
