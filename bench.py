@@ -1,6 +1,6 @@
 """Benchmark: GCP-CROWN domains bounded per second on one MI355X.
 
-Default workload (--config 2): MLP 784-256x6-10, weights N(0, 2/fan_in),
+Default workload (--workload mlp784): MLP 784-256x6-10, weights N(0, 2/fan_in),
 x0 ~ U[0,1]^784, eps = 0.015, 9 margin spec rows, 1024 BaB domains with 1-8
 splits each, 200 LP-implied cuts over 2-6 neurons of >= 2 layers.  One step
 bounds one batch: it resets alpha/beta/gamma and the Adam state to their
@@ -8,11 +8,12 @@ starting values, runs 20 projected Adam iterations (bound pass + adjoint +
 update, all on the device) and the certifying pass (fp32 GEMMs, fp64
 reductions, margin check).  value = domains per second over the timed steps.
 
-Other workloads: --config 3 (CNN-A shape, 2048 domains, 500 cuts),
---config 5 (ResNet, 4096 domains, 1000 cuts), --config 4 (64 uneven MLP
-instances in grouped launches, compared with one gcp_optimize per instance).
+Other workloads: --workload cnn (CNN-A shape, 2048 domains, 500 cuts),
+--workload resnet (ResNet, 4096 domains, 1000 cuts), --workload batch (64
+uneven MLP instances in grouped launches, compared with one gcp_optimize per
+instance).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode bf16|fp32] [--config 2|3|4|5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode bf16|fp32] [--workload mlp784|cnn|resnet|batch]
 """
 import argparse
 import json
@@ -45,25 +46,25 @@ def parse():
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
-    ap.add_argument("--config", type=int, choices=[2, 3, 4, 5], default=2)
+    ap.add_argument("--workload", choices=["mlp784", "cnn", "resnet", "batch"], default="mlp784")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every GEMM/conv tile afresh instead of starting from the shipped MI355X choices")
     ap.add_argument("--explicit-pi", action="store_true",
                     help="optimise pi of every unstable neuron too (gcp_optimize_pi) instead of Lemma A.1's pi*")
     a = ap.parse_args()
     if a.domains is None:
-        a.domains = {2: 1024, 3: 2048, 5: 4096, 4: 0}[a.config]
+        a.domains = {"mlp784": 1024, "cnn": 2048, "resnet": 4096, "batch": 0}[a.workload]
     if a.cpu_domains is None:
-        a.cpu_domains = {2: 1024, 3: 256, 5: 16, 4: 0}[a.config]
+        a.cpu_domains = {"mlp784": 1024, "cnn": 256, "resnet": 16, "batch": 0}[a.workload]
     return a
 
 
 WORKLOADS = {
-    2: "GCP-CROWN bound optimisation, MLP 784-256x6-10, {B} BaB domains x 9 spec rows, 200 cuts, "
+    "mlp784": "GCP-CROWN bound optimisation, MLP 784-256x6-10, {B} BaB domains x 9 spec rows, 200 cuts, "
        "1-8 splits/domain, 20 Adam iterations + fp32/fp64 certifying pass",
-    3: "GCP-CROWN bound optimisation, CNN Conv(3,16,4,s2)-Conv(16,32,4,s2)-2048-100-10 on 3x32x32, {B} BaB "
+    "cnn": "GCP-CROWN bound optimisation, CNN Conv(3,16,4,s2)-Conv(16,32,4,s2)-2048-100-10 on 3x32x32, {B} BaB "
        "domains x 9 spec rows, 500 cuts, 1-8 splits/domain, 20 Adam iterations + certifying pass",
-    5: "GCP-CROWN bound optimisation, ResNet stem16-blocks16/32/64-linear10 on 3x32x32, {B} BaB domains x 9 "
+    "resnet": "GCP-CROWN bound optimisation, ResNet stem16-blocks16/32/64-linear10 on 3x32x32, {B} BaB domains x 9 "
        "spec rows, 1000 cuts, 1-8 splits/domain, 20 Adam iterations + certifying pass",
 }
 
@@ -101,9 +102,9 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
-    if args.config == 4:
+    if args.workload == "batch":
         return bench_batch(args)
-    prob = gen.make_config(args.config, 0, B=args.domains)
+    prob = gen.make_workload(args.workload, 0, B=args.domains)
     P = B.Problem(prob, device=dev)
     M = P.M
     # starting point: CROWN-adaptive alpha, beta ~ U[0,1] on used split slots, gamma = 0
@@ -182,7 +183,7 @@ def main():
         "dtype": args.mode,
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.config].format(B=args.domains),
+            "workload": WORKLOADS[args.workload].format(B=args.domains),
             "domains": args.domains, "spec_rows": prob.S, "rows": M, "n_unstable": P.n_I,
             "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
@@ -328,7 +329,7 @@ def bench_batch(args):
     from paper_2208_05740_amd import binding as B
     from workloads import gen
     dev = torch.device("cuda:0")
-    probs = gen.make_batch_config(seed=0)
+    probs = gen.make_batch(seed=0)
     Ps = [B.Problem(p, device=dev) for p in probs]
     o = probs[0].opt
     mode = B.GCP_MODE_BF16 if args.mode == "bf16" else B.GCP_MODE_FP32

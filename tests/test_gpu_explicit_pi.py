@@ -77,9 +77,9 @@ def test_bound_pi_and_gradients_match_oracle(kind, seed):
     _check(p, *_random_params(p, rng, 0.5))
 
 
-def test_bound_pi_config2_rows_fp32_and_bf16():
+def test_bound_pi_mlp784_rows_fp32_and_bf16():
     # 784-256x6-10 with 200 cuts: several tiles and ragged 256-column blocks
-    p = gen.make_config(2, 0, B=2)
+    p = gen.make_workload("mlp784", 0, B=2)
     rng = np.random.default_rng(4)
     a, b, c, r = _random_params(p, rng, 0.05)
     _check(p, a, b, c, r)

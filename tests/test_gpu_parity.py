@@ -72,8 +72,8 @@ def check_bound(prob, mode=0, tol=1e-5, alpha=None, beta=None, gamma=None, grads
     return gb, ref, T
 
 
-def test_config1_fp32_bound_and_gradients_match_oracle():
-    check_bound(gen.make_config(1, 0))
+def test_mlp8_fp32_bound_and_gradients_match_oracle():
+    check_bound(gen.make_workload("mlp8", 0))
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -82,10 +82,10 @@ def test_tiny_mlp_with_splits_and_cuts(seed):
     check_bound(p)
 
 
-def test_config2_small_batch_fp32():
+def test_mlp784_small_batch_fp32():
     # 784-256x6-10 with 200 cuts, 1-8 splits per domain: several column tiles
     # per layer and a ragged last row tile (M = 5 * 9 = 45).
-    p = gen.make_config(2, 0, B=5)
+    p = gen.make_workload("mlp784", 0, B=5)
     rng = np.random.default_rng(0)
     prep = O.Prepared(p)
     alpha = rng.random((p.B, p.S, prep.n_I)).astype(np.float32)
@@ -93,8 +93,8 @@ def test_config2_small_batch_fp32():
     check_bound(p, alpha=alpha, gamma=gamma)
 
 
-def test_config2_small_batch_bf16_close_to_oracle():
-    p = gen.make_config(2, 0, B=3)
+def test_mlp784_small_batch_bf16_close_to_oracle():
+    p = gen.make_workload("mlp784", 0, B=3)
     check_bound(p, mode=1, tol=2e-2, grads=False)
 
 
@@ -238,10 +238,10 @@ def test_optimize_zero_iterations_is_the_certified_bound(kind, seed):
     assert rel_err(g, ref, T).max() <= 1e-5
 
 
-@pytest.mark.parametrize("cfg", ["tiny", "cfg2"])
-def test_optimize_fp32_matches_oracle_optimisation(cfg):
-    p = gen.make_tiny("mlp", 1, B=4, splits=(1, 2), n_cuts=6, gamma_dist="zero") if cfg == "tiny" \
-        else gen.make_config(2, 0, B=2)
+@pytest.mark.parametrize("which", ["tiny", "mlp784"])
+def test_optimize_fp32_matches_oracle_optimisation(which):
+    p = gen.make_tiny("mlp", 1, B=4, splits=(1, 2), n_cuts=6, gamma_dist="zero") if which == "tiny" \
+        else gen.make_workload("mlp784", 0, B=2)
     P = upload(p)
     g, a, b, c = _optimize(p, P, 0)
     # certifying pass = the oracle's bound at the device's final parameters
@@ -260,7 +260,7 @@ def test_optimize_fp32_matches_oracle_optimisation(cfg):
 
 
 def test_optimize_bf16_final_bound_close_to_fp32():
-    p = gen.make_config(2, 0, B=4)
+    p = gen.make_workload("mlp784", 0, B=4)
     P = upload(p)
     g32, *_ = _optimize(p, P, 0)
     g16, a, b, c = _optimize(p, P, 1)
@@ -286,9 +286,9 @@ def test_conv_bf16_close_to_oracle():
     check_bound(p, mode=1, tol=2e-2, grads=False)
 
 
-def test_config3_cnn_small_batch_fp32():
+def test_cnn_small_batch_fp32():
     # Conv(3,16,4,s2,p1) - Conv(16,32,4,s2,p1) - 2048-100-10 with 500 cuts
-    p = gen.make_config(3, 0, B=2)
+    p = gen.make_workload("cnn", 0, B=2)
     rng = np.random.default_rng(1)
     prep = O.Prepared(p)
     alpha = rng.random((p.B, p.S, prep.n_I)).astype(np.float32)
@@ -296,8 +296,8 @@ def test_config3_cnn_small_batch_fp32():
     check_bound(p, alpha=alpha, gamma=gamma)
 
 
-def test_config5_resnet_single_domain_fp32():
-    p = gen.make_config(5, 0, B=1)
+def test_resnet_single_domain_fp32():
+    p = gen.make_workload("resnet", 0, B=1)
     rng = np.random.default_rng(2)
     gamma = (rng.random((p.B, p.S, p.cuts.n)) * 0.05).astype(np.float32)
     check_bound(p, gamma=gamma)
@@ -322,7 +322,7 @@ def test_graph_replayed_optimisation_equals_eager():
     # eager work in between.
     import torch
     from paper_2208_05740_amd import binding as B
-    p = gen.make_config(2, 1, B=3)
+    p = gen.make_workload("mlp784", 1, B=3)
     P = upload(p)
     a0, b0, c0, *_ = params(p, P)
     o = p.opt
@@ -367,7 +367,7 @@ def test_batched_optimisation_equals_per_instance(mode):
     # grouped launches must give exactly the per-instance results
     import torch
     from paper_2208_05740_amd import binding as B
-    probs = gen.make_batch_config(seed=3, n_inst=5, bmax=24)
+    probs = gen.make_batch(seed=3, n_inst=5, bmax=24)
     Ps = [upload(p) for p in probs]
     o = probs[0].opt
     # an fp32 certifying pass first, so the buffers shared by both
@@ -418,7 +418,7 @@ def test_batched_optimisation_mixed_alone_and_grouped(monkeypatch):
     # grouped; either way the results equal per-instance gcp_optimize
     import torch
     from paper_2208_05740_amd import binding as B
-    probs = gen.make_batch_config(seed=6, n_inst=6, bmax=48)
+    probs = gen.make_batch(seed=6, n_inst=6, bmax=48)
     work = sorted(p.B * p.S * max((n.size + 15) // 16 * 16 for n in p.net.nodes) for p in probs)
     thr = (work[2] + work[3]) // 2
     assert work[0] < thr <= work[-1]
@@ -444,7 +444,7 @@ def test_batched_optimisation_mixed_alone_and_grouped(monkeypatch):
 def test_batched_optimisation_certified_bound_matches_oracle():
     import torch
     from paper_2208_05740_amd import binding as B
-    probs = gen.make_batch_config(seed=5, n_inst=3, bmax=16)
+    probs = gen.make_batch(seed=5, n_inst=3, bmax=16)
     Ps = [upload(p) for p in probs]
     items = _batch_items(probs, Ps)
     B.optimize_batch(items, iters=5)
@@ -600,13 +600,13 @@ def test_bab_with_cuts_verifies_and_never_verifies_a_false_property():
 
 
 # ------------------------------------------------------------ full sizes, sampled rows
-def _full_size_check(k, B, n_rows, seed=0):
+def _full_size_check(name, B, n_rows, seed=0):
     # the workload at the size the bench times: bf16-optimised, fp32/fp64
     # certified bounds of every row on the device; a random sample of rows
     # recomputed by the oracle at the device's final parameters (fp64)
     import torch
     from paper_2208_05740_amd import binding as B_
-    prob = gen.make_config(k, 0, B=B)
+    prob = gen.make_workload(name, 0, B=B)
     P = upload(prob)
     M = P.M
     a = torch.tensor(gen.crown_alpha_init(prob.lu), dtype=torch.float32, device=_dev()).expand(M, -1).contiguous()
@@ -627,16 +627,16 @@ def _full_size_check(k, B, n_rows, seed=0):
     assert rel_err(g[rows], ref, T).max() <= 1e-5
 
 
-def test_config2_full_size_sampled_rows():
-    _full_size_check(2, 1024, 48)
+def test_mlp784_full_size_sampled_rows():
+    _full_size_check("mlp784", 1024, 48)
 
 
-def test_config3_full_size_sampled_rows():
-    _full_size_check(3, 2048, 12)
+def test_cnn_full_size_sampled_rows():
+    _full_size_check("cnn", 2048, 12)
 
 
-def test_config5_full_size_sampled_rows():
-    _full_size_check(5, 4096, 3)
+def test_resnet_full_size_sampled_rows():
+    _full_size_check("resnet", 4096, 3)
 
 
 @pytest.mark.parametrize("kind", ["mlp", "cnn16", "res16"])
@@ -655,13 +655,13 @@ def test_zero_radius_bound_is_the_network_output(kind):
 
 
 # ------------------------------------------------------------ soundness and finite differences
-@pytest.mark.parametrize("k", [1, 2])
-def test_certified_bounds_never_exceed_sampled_minimum(k):
+@pytest.mark.parametrize("name", ["mlp8", "mlp784"])
+def test_certified_bounds_never_exceed_sampled_minimum(name):
     # after the bf16-optimised ascent and the fp32/fp64 certifying pass, no
     # bound is above the minimum of c^T f over sampled points of its domain
     import torch
     from paper_2208_05740_amd import binding as B
-    prob = gen.make_config(k, 0, B=None if k == 1 else 16)
+    prob = gen.make_workload(name, 0, B=None if name == "mlp8" else 16)
     P = upload(prob)
     a, b, c, *_ = params(prob, P)
     st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
@@ -669,12 +669,12 @@ def test_certified_bounds_never_exceed_sampled_minimum(k):
     torch.cuda.synchronize()
     g = out.cpu().numpy().reshape(prob.B, prob.S)
     for dom in range(prob.B):
-        smin = lp.sampled_min(prob, b=dom, n=20000 if k == 2 else 100000, seed=dom)
+        smin = lp.sampled_min(prob, b=dom, n=20000 if name == "mlp784" else 100000, seed=dom)
         assert (g[dom] <= smin + 1e-9).all(), (dom, g[dom], smin)
 
 
-@pytest.mark.parametrize("k,B_,n", [(3, 4, 2000), (5, 2, 100)])
-def test_conv_certified_bounds_never_exceed_points_of_their_domains(k, B_, n):
+@pytest.mark.parametrize("name,seed,B_,n", [("cnn", 3, 4, 2000), ("resnet", 5, 2, 100)])
+def test_conv_certified_bounds_never_exceed_points_of_their_domains(name, seed, B_, n):
     # CNN and ResNet workloads: every domain keeps its split neurons but takes
     # their signs from a reference point, so the reference point and the
     # sampled points around it that meet the splits are points of the domain;
@@ -683,8 +683,8 @@ def test_conv_certified_bounds_never_exceed_points_of_their_domains(k, B_, n):
 
     import torch
     from paper_2208_05740_amd import binding as B
-    prob = gen.make_config(k, 0, B=B_)
-    rng = np.random.default_rng(k)
+    prob = gen.make_workload(name, 0, B=B_)
+    rng = np.random.default_rng(seed)
     x_ref = prob.x0 + prob.eps * rng.uniform(-1, 1, size=prob.x0.size)
     _, pre_ref = lp.plain_forward(prob.net, x_ref[None, :], return_pre=True)
     sp = prob.splits
@@ -715,7 +715,7 @@ def test_conv_certified_bounds_never_exceed_points_of_their_domains(k, B_, n):
         assert (g[dom] <= vmin + 1e-9).all(), (dom, g[dom], vmin)
 
 
-@pytest.mark.parametrize("kind,B_", [("res16", 2), ("cfg5", 1)])
+@pytest.mark.parametrize("kind,B_", [("res16", 2), ("resnet", 1)])
 def test_adjoint_gradient_matches_central_differences(kind, B_):
     # d bound / d alpha and d gamma from the device adjoint against central
     # differences of the device bound (fp32 GEMMs, fp64 sums); the bound is
@@ -723,8 +723,8 @@ def test_adjoint_gradient_matches_central_differences(kind, B_):
     # slopes disagree (a kink within the step) are skipped
     import torch
     from paper_2208_05740_amd import binding as B
-    if kind == "cfg5":
-        prob = gen.make_config(5, 0, B=B_)
+    if kind == "resnet":
+        prob = gen.make_workload("resnet", 0, B=B_)
     else:
         prob = gen.make_tiny(kind, 4, B=B_, splits=(1, 2), n_cuts=5)
     P = upload(prob)

@@ -99,8 +99,8 @@ def test_zero_multipliers_equal_textbook_crown(kind, seed):
         assert abs(g[0, s] - ref) <= 1e-10 * (1 + abs(ref))
 
 
-def test_config1_zero_gamma_equals_crown():
-    p = gen.make_config(1, 0)
+def test_mlp8_zero_gamma_equals_crown():
+    p = gen.make_workload("mlp8", 0)
     prep = O.Prepared(p)
     a = O.full_alpha(p, prep)
     g = O.bound(p, a, p.beta, np.zeros_like(p.gamma), prep=prep)
@@ -138,8 +138,8 @@ def test_bound_below_lp_mip_and_samples(kind, seed):
         assert np.all(g <= lpv + 1e-8), (g, lpv)
 
 
-def test_config1_tight_cuts_bound_below_lp_and_enumerated_mip():
-    p = gen.make_config(1, 0)
+def test_mlp8_tight_cuts_bound_below_lp_and_enumerated_mip():
+    p = gen.make_workload("mlp8", 0)
     # tighten every cut to the MIP maximum of its left side (still valid)
     p.cuts.d[:] = [lp.cut_max(p, k) for k in range(p.cuts.n)]
     rng = np.random.default_rng(7)
@@ -296,13 +296,13 @@ def test_ibp_bounds_and_cuts_hold_on_samples(kind):
     assert np.all(lhs <= cu.d + 1e-9)
 
 
-def test_config_shapes():
-    p = gen.make_config(2, 0, B=3)
+def test_workload_shapes():
+    p = gen.make_workload("mlp784", 0, B=3)
     assert p.net.in_size == 784 and [n.size for n in p.net.nodes] == [256] * 6 + [10]
     assert p.S == 9 and p.cuts.n == 200 and p.splits.K == 8
-    p3 = gen.make_config(3, 0, B=2)
+    p3 = gen.make_workload("cnn", 0, B=2)
     assert [n.size for n in p3.net.nodes] == [4096, 2048, 100, 10]
-    p5 = gen.make_config(5, 0, B=1)
+    p5 = gen.make_workload("resnet", 0, B=1)
     assert sum(n.size for n in p5.net.nodes if n.relu) == 73728
 
 
@@ -396,12 +396,12 @@ def test_cut_on_pre_activation_of_first_layer_neuron_has_lagrangian_slope():
         assert abs(slope[0, s_] - (H * cj - d)) < 1e-5 * (1 + abs(cj)), (slope, cj)
 
 
-def test_config1_golden_values():
+def test_mlp8_golden_values():
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "cfg1_oracle.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", "mlp8_oracle.json")
     ref = json.load(open(path))
-    p = gen.make_config(1, 0)
+    p = gen.make_workload("mlp8", 0)
     g, ga, gb, gc = O.bound_and_grad(p)
     assert np.allclose(g, ref["bound"], rtol=1e-12, atol=1e-12)
     assert np.allclose(ga, ref["d_alpha"], rtol=1e-12, atol=1e-12)

@@ -8,6 +8,7 @@ implements that independently.
 """
 from .gen import (  # noqa: F401
     Edge, Node, Net, Splits, Cuts, Problem,
-    make_config, make_problem, make_tiny, mlp_net, cnn_net, cnn_wide_net, resnet_net, crown_alpha_init,
+    make_workload, WORKLOAD_NAMES, make_problem, make_tiny, mlp_net, cnn_net, cnn_wide_net, resnet_net,
+    crown_alpha_init,
     forward, ibp_bounds, unstable_index, num_relu_neurons,
 )

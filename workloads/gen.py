@@ -512,38 +512,49 @@ def _streams(seed):
     return [np.random.default_rng(s) for s in ss]
 
 
-def make_config(k: int, seed: int = 0, B: Optional[int] = None, **kw) -> Problem:
-    """Workload k in 1..5 (k = 4 returns a list of instance Problems)."""
+WORKLOAD_NAMES = ("mlp8", "mlp784", "cnn", "batch", "resnet")
+
+
+def make_workload(name: str, seed: int = 0, B: Optional[int] = None, **kw):
+    """The named synthetic workloads (B overrides the number of domains):
+      mlp8    MLP 8-16-16-3, one domain, S = 2, 8 cuts (small enough for exact
+              LP / MIP checks);
+      mlp784  MLP 784-256x6-10, 1024 domains, S = 9, 200 cuts;
+      cnn     Conv(3,16,4,s2)-Conv(16,32,4,s2)-2048-100-10 on 3x32x32, 2048
+              domains, 500 cuts;
+      resnet  stem 16, residual blocks 16/32/64, linear 10 on 3x32x32, 4096
+              domains, 1000 cuts;
+      batch   64 uneven MLP instances (returns a list of Problems)."""
     r_w, r_x, r_cut, r_split, r_par = _streams(seed)
-    if k == 1:
-        # MLP 8-16-16-3, W ~ N(0, 1/fan_in), b ~ N(0, 0.1); eps = 0.05; S = 2;
-        # one domain, no splits; 8 cuts over 2-4 neurons; alpha, gamma ~ U[0,1].
+    if name == "mlp8":
+        # W ~ N(0, 1/fan_in), b ~ N(0, 0.1); eps = 0.05; S = 2; one domain, no
+        # splits; 8 cuts over 2-4 neurons; alpha, gamma ~ U[0,1]
         net = mlp_net(r_w, [8, 16, 16, 3], w_var_num=1.0)
         x0 = r_x.random(8)
-        return make_problem("cfg1-mlp8-16-16-3", net, x0, 0.05, 2, B or 1, 0, 0, 8, 2, 4,
+        return make_problem("mlp8-16-16-3", net, x0, 0.05, 2, B or 1, 0, 0, 8, 2, 4,
                             (r_cut, r_split, r_par), alpha_init="given",
                             beta_dist="zero", gamma_dist="uniform", **kw)
-    if k == 2:
+    if name == "mlp784":
         net = mlp_net(r_w, [784] + [256] * 6 + [10])
         x0 = r_x.random(784)
-        return make_problem("cfg2-mlp784-256x6-10", net, x0, 0.015, 9, B or 1024, 1, 8, 200, 2, 6,
+        return make_problem("mlp784-256x6-10", net, x0, 0.015, 9, B or 1024, 1, 8, 200, 2, 6,
                             (r_cut, r_split, r_par), **kw)
-    if k == 3:
+    if name == "cnn":
         net = cnn_wide_net(r_w)
         x0 = r_x.random(3 * 32 * 32)
-        return make_problem("cfg3-cnn-wide", net, x0, 2.0 / 255.0, 9, B or 2048, 1, 8, 500, 2, 6,
-                            (r_cut, r_split, r_par), **kw)
-    if k == 5:
+        return make_problem("cnn-3x32x32-c16-c32-2048-100-10", net, x0, 2.0 / 255.0, 9, B or 2048, 1, 8, 500,
+                            2, 6, (r_cut, r_split, r_par), **kw)
+    if name == "resnet":
         net = resnet_net(r_w)
         x0 = r_x.random(3 * 32 * 32)
-        return make_problem("cfg5-resnet", net, x0, 2.0 / 255.0, 9, B or 4096, 1, 8, 1000, 2, 6,
+        return make_problem("resnet-3x32x32-16-32-64", net, x0, 2.0 / 255.0, 9, B or 4096, 1, 8, 1000, 2, 6,
                             (r_cut, r_split, r_par), **kw)
-    if k == 4:
-        return make_batch_config(seed, **kw)
-    raise ValueError(k)
+    if name == "batch":
+        return make_batch(seed, **kw)
+    raise ValueError(f"unknown workload {name!r}; one of {WORKLOAD_NAMES}")
 
 
-def make_batch_config(seed: int = 0, n_inst: int = 64, bmax: int = 4096,
+def make_batch(seed: int = 0, n_inst: int = 64, bmax: int = 4096,
                       bscale: float = 1.0) -> List[Problem]:
     """Uneven instances: MLP depth U{3..9} linear layers, hidden width
     U[64, 1024], input 784 (eps 0.015) or 3072 (eps 2/255), domains
@@ -561,7 +572,7 @@ def make_batch_config(seed: int = 0, n_inst: int = 64, bmax: int = 4096,
         r_w, r_x, r_cut, r_split, r_par = _streams([seed, 4, i])
         net = mlp_net(r_w, [d0] + [width] * (depth - 1) + [10])
         x0 = r_x.random(d0)
-        out.append(make_problem(f"cfg4-inst{i}", net, x0, eps, 9, B, 1, 8, n_cuts, 2, 6,
+        out.append(make_problem(f"batch-mlp-inst{i}", net, x0, eps, 9, B, 1, 8, n_cuts, 2, 6,
                                 (r_cut, r_split, r_par)))
     return out
 
