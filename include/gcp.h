@@ -232,10 +232,10 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
  * all four gradient outputs or none).  gcp_optimize_pi: gcp_optimize with
  * rho updated in place by projected Adam with alpha's learning rate and
  * clamp; adam_state holds 2*M*(n_I + K + N) + 2*M*n_I floats: the
- * gcp_optimize layout followed by m_rho [M][n_I], v_rho [M][n_I].  The
- * relaxation of every ReLU node then runs as an elementwise pass after its
- * GEMMs (the fused GEMM epilogues implement pi* only), and grouped batch
- * launches do not take this variant.  Errors: as gcp_bound / gcp_optimize;
+ * gcp_optimize layout followed by m_rho [M][n_I], v_rho [M][n_I].  Dense
+ * GEMMs run the relaxation fused in their epilogues; a node reached through a
+ * conv or identity edge relaxes in an elementwise pass after its GEMMs, and
+ * gcp_optimize_batch does not take this variant.  Errors: as gcp_bound / gcp_optimize;
  * EINVAL for a null rho when n_I > 0; ERANGE (with GCP_FLAG_VALIDATE) for
  * rho outside [0,1]. */
 int gcp_bound_pi(const gcp_net* net, const double* x0, double eps,

@@ -24,6 +24,7 @@
 #include <stdexcept>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 using namespace gcp;
@@ -115,6 +116,10 @@ std::string cls_name(const char* kind, int bf16, int sign, int cfg) {
   if (cfg >= 0) n += ".t" + std::to_string(bm) + "x" + std::to_string(bn);
   return n;
 }
+
+// Tile configuration an explicit-pi bound/adjoint GEMM runs with (the
+// launcher instantiates those epilogues for the small tiles only).
+int pi_cfg(int cfg) { return (cfg == 6 || cfg == 7) ? cfg : 5; }
 
 // Owned device allocation (zero-filled at allocation).
 struct DBuf {
@@ -872,6 +877,8 @@ float* tune_beta(Call& c) {
 template <class A>
 bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a, double bytes) {
   if (!c.rec) return false;
+  if constexpr (std::is_same_v<A, BoundEpiArgs> || std::is_same_v<A, AdjEpiArgs>)
+    if (a.rp.rho) fail(GCP_EUNSUPPORTED, "batched optimisation takes Lemma A.1's pi* only");
   Rec r{};
   r.type = 0; r.bf16 = bf16; r.cfg = cfg; r.kind = kind; r.sign = g.a_is_sign;
   r.g = g;
@@ -1023,7 +1030,10 @@ struct BoundPass {
     const int d_src = E.d_src;
     const int ld_src = node_ld_of(net, p);
     float* accbuf = p < 0 ? ws.acc_in.as<float>() : ws.acc[p]->as<float>();
-    const bool unfused = c.rp.rho != nullptr && p >= 0;   // explicit pi: relaxation runs elementwise
+    // explicit pi through a conv edge: the relaxation runs elementwise (the
+    // dense GEMM epilogues take rho themselves)
+    const bool pi = c.rp.rho != nullptr;
+    const bool unfused = pi && p >= 0 && E.kind != GCP_EDGE_DENSE;
 
     if (E.kind == GCP_EDGE_DENSE) {
       GemmArgs g{};
@@ -1062,11 +1072,11 @@ struct BoundPass {
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
           const double M = g.M, esz = bf16 ? 2 : 4, dp = g.N;
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * esz : 0) +
-                               M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
+                               M * unst_of(c, p) * (pi ? 8 : 4) + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
           if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a, bytes))
-            check(timed(c.st, cls_name("bound", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
-                        [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
+            check(timed(c.st, pi ? cls_name("bound_pi", bf16, 0, pi_cfg(cfg)) : cls_name("bound", bf16, 0, cfg), bytes,
+                        2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
         }
       } else {
         if (has_acc) fail(GCP_EUNSUPPORTED, "several consumers of the input");
@@ -1272,13 +1282,16 @@ struct AdjPass {
       if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
     float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
     // the node's adjoint epilogue runs fused with its last GEMM, or
-    // elementwise after all edges (identity last edge, explicit pi)
-    const bool fused_last = c.rp.rho == nullptr && net->edges[order.back()]->kind != GCP_EDGE_IDENTITY;
+    // elementwise after all edges (identity last edge; explicit pi unless
+    // the last edge is dense)
+    const bool pi = c.rp.rho != nullptr;
+    const int last_kind = net->edges[order.back()]->kind;
+    const bool fused_last = last_kind != GCP_EDGE_IDENTITY && (!pi || last_kind == GCP_EDGE_DENSE);
     const bool use_acc = order.size() > 1 || !fused_last;
     const double M = c.M, esz = bf16 ? 2 : 4, di = n.size;
     auto adj_bytes = [&](double a_bytes, double w_bytes) {
-      return a_bytes + w_bytes + M * di * esz + M * unst_of(c, i) * (adam.enabled ? 24 : 8) + (double)c.B * unst_of(c, i) +
-             M * nnz_of(c, i) * 8 + M * di * esz + (use_acc ? M * di * 4 : 0);
+      return a_bytes + w_bytes + M * di * esz + M * unst_of(c, i) * (adam.enabled ? 24 : 8) * (pi ? 2 : 1) +
+             (double)c.B * unst_of(c, i) + M * nnz_of(c, i) * 8 + M * di * esz + (use_acc ? M * di * 4 : 0);
     };
     for (size_t q = 0; q < order.size(); ++q) {
       const EdgeH& E = *net->edges[order[q]];
@@ -1316,11 +1329,13 @@ struct AdjPass {
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);
             t.d_beta = tune_beta(c);
+            if (pi) t.d_rho = t.d_alpha;   // same [M][n_I] shape, each element written by one thread
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
           const double bytes = adj_bytes(a_bytes, (double)g.N * g.K * esz);
           if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a, bytes))
-            check(timed(c.st, cls_name("adj", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
+            check(timed(c.st, pi ? cls_name("adj_pi", bf16, sign, pi_cfg(cfg)) : cls_name("adj", bf16, sign, cfg), bytes,
+                        2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
       } else if (E.kind == GCP_EDGE_CONV) {
         no_record(c, "conv");

@@ -317,15 +317,38 @@ static hipError_t launch_typed(int cfg, EpiKind kind, int sign, const GemmLaunch
   return hipErrorInvalidValue;
 }
 
+// Explicit-pi epilogues (rho set): instantiated for the small tiles only
+// (their fragments carry rho and its moments); a large-tile choice runs as
+// 32x32.
+template <typename T, bool SIGN, class Epi, class Args>
+static hipError_t launch_small(int cfg, const GemmLaunch& L, hipStream_t st) {
+  switch (cfg) {
+    case 6: return launch_cfg<T, 16, 64, 1, 4, SIGN, Epi, Args>(L, st);
+    case 7: return launch_cfg<T, 16, 32, 1, 2, SIGN, Epi, Args>(L, st);
+    default: return launch_cfg<T, 32, 32, 2, 2, SIGN, Epi, Args>(L, st);
+  }
+}
+
+template <typename T>
+static hipError_t launch_pi(int cfg, EpiKind kind, int sign, const GemmLaunch& L, hipStream_t st) {
+  if (kind == EPI_BOUND) return launch_small<T, false, BoundEpi<T, true>, BoundEpiArgs>(cfg, L, st);
+  if (kind != EPI_ADJ) return hipErrorInvalidValue;
+  if (sign) return launch_small<T, true, AdjEpi<T, true>, AdjEpiArgs>(cfg, L, st);
+  return launch_small<T, false, AdjEpi<T, true>, AdjEpiArgs>(cfg, L, st);
+}
+
 hipError_t launch_gemm(int bf16_mode, int cfg, EpiKind kind, const GemmArgs& g, const void* epi,
                        hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  if (fused_explicit_pi(kind, epi)) return hipErrorInvalidValue;   // elementwise kernels only
+  if (cfg < 0 || cfg >= gemm_num_configs()) return hipErrorInvalidValue;
   GemmLaunch L{&g, epi, nullptr, nullptr, nullptr, 0, 0};
+  if (fused_explicit_pi(kind, epi))
+    return bf16_mode ? launch_pi<bf16>(cfg, kind, g.a_is_sign, L, st) : launch_pi<float>(cfg, kind, g.a_is_sign, L, st);
   return bf16_mode ? launch_typed<bf16>(cfg, kind, g.a_is_sign, L, st)
                    : launch_typed<float>(cfg, kind, g.a_is_sign, L, st);
 }
 
+// Grouped problems carry Lemma A.1's pi* epilogues only (no rho).
 hipError_t launch_gemm_grouped(int bf16_mode, int cfg, EpiKind kind, int sign, const GemmArgs* d_gs,
                                const void* d_epis, const int* d_prefix, int np, int total_tiles, hipStream_t st) {
   GemmLaunch L{nullptr, nullptr, d_gs, d_epis, d_prefix, np, total_tiles};
