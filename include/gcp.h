@@ -233,9 +233,9 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
  * rho updated in place by projected Adam with alpha's learning rate and
  * clamp; adam_state holds 2*M*(n_I + K + N) + 2*M*n_I floats: the
  * gcp_optimize layout followed by m_rho [M][n_I], v_rho [M][n_I].  Dense
- * GEMMs run the relaxation fused in their epilogues; a node reached through a
- * conv or identity edge relaxes in an elementwise pass after its GEMMs, and
- * gcp_optimize_batch does not take this variant.  Errors: as gcp_bound / gcp_optimize;
+ * and conv edges run the relaxation fused in their epilogues; a node whose
+ * last edge is an identity relaxes in an elementwise pass after its GEMMs,
+ * and gcp_optimize_batch does not take this variant.  Errors: as gcp_bound / gcp_optimize;
  * EINVAL for a null rho when n_I > 0; ERANGE (with GCP_FLAG_VALIDATE) for
  * rho outside [0,1]. */
 int gcp_bound_pi(const gcp_net* net, const double* x0, double eps,

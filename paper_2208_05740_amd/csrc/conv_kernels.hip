@@ -438,9 +438,31 @@ static hipError_t conv_typed(int cfg, EpiKind kind, const ConvArgs& c, const voi
   }
 }
 
+// Explicit-pi epilogues (rho set): instantiated for one column tile per
+// wave only, 4 or 8 waves; the other shapes run as 8 waves.
+template <typename T, bool TRANS, bool SIGN, class Epi>
+static hipError_t conv_pi_any(int cfg, const ConvArgs& c, const Epi& epi, hipStream_t st) {
+  const ConvPlan P = conv_plan(c.cg, TRANS ? 1 : 0);
+  if (c.ldb < P.KP || c.ldb % 32 != 0) return hipErrorInvalidValue;
+  if (cfg == 0) return conv_go<T, 4, 1, TRANS, SIGN>(c, P, epi, st);
+  return conv_go<T, 8, 1, TRANS, SIGN>(c, P, epi, st);
+}
+
+template <typename T>
+static hipError_t conv_typed_pi(int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st) {
+  if (c.trans)
+    return kind == EPI_BOUND ? conv_pi_any<T, true, false>(cfg, c, BoundEpi<T, true>{*(const BoundEpiArgs*)epi}, st)
+                             : hipErrorInvalidValue;
+  if (kind != EPI_ADJ) return hipErrorInvalidValue;
+  if (c.x_is_sign) return conv_pi_any<T, false, true>(cfg, c, AdjEpi<T, true>{*(const AdjEpiArgs*)epi}, st);
+  return conv_pi_any<T, false, false>(cfg, c, AdjEpi<T, true>{*(const AdjEpiArgs*)epi}, st);
+}
+
 hipError_t launch_conv(int bf16_mode, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st) {
   if (c.M <= 0) return hipSuccess;
-  if (fused_explicit_pi(kind, epi)) return hipErrorInvalidValue;   // elementwise kernels only
+  if (cfg < 0 || cfg >= conv_num_configs()) return hipErrorInvalidValue;
+  if (fused_explicit_pi(kind, epi))
+    return bf16_mode ? conv_typed_pi<bf16>(cfg, kind, c, epi, st) : conv_typed_pi<float>(cfg, kind, c, epi, st);
   return bf16_mode ? conv_typed<bf16>(cfg, kind, c, epi, st) : conv_typed<float>(cfg, kind, c, epi, st);
 }
 

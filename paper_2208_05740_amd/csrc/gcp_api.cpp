@@ -1030,10 +1030,7 @@ struct BoundPass {
     const int d_src = E.d_src;
     const int ld_src = node_ld_of(net, p);
     float* accbuf = p < 0 ? ws.acc_in.as<float>() : ws.acc[p]->as<float>();
-    // explicit pi through a conv edge: the relaxation runs elementwise (the
-    // dense GEMM epilogues take rho themselves)
-    const bool pi = c.rp.rho != nullptr;
-    const bool unfused = pi && p >= 0 && E.kind != GCP_EDGE_DENSE;
+    const bool pi = c.rp.rho != nullptr;   // explicit pi: the pi-switched epilogues
 
     if (E.kind == GCP_EDGE_DENSE) {
       GemmArgs g{};
@@ -1042,7 +1039,7 @@ struct BoundPass {
       g.Bt = wt_bound(E, bf16); g.ldb = dn.ld;
       g.a_is_sign = 0;
       g.mp = c.rp.mp;
-      if (!last || unfused) {
+      if (!last) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         g.partial = nullptr;
         if (!dry) {
@@ -1115,7 +1112,7 @@ struct BoundPass {
       // every multiply-add of the forward conv appears once in its transpose
       const double flops = 2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw;
       const double wbytes = (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz;
-      if (!last || unfused) {
+      if (!last) {
         StoreEpiArgs s{d_src, ld_src, 1.f, first ? nullptr : accbuf, accbuf};
         if (!dry) {
           int cfg = choose_cfg("convT", EPI_STORE, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(), [&](int cf) {
@@ -1140,9 +1137,9 @@ struct BoundPass {
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
           const double bytes = M * dn.size * esz + wbytes + M * d_src * esz + (keep_ahat ? M * d_src * esz : 0) +
-                               M * unst_of(c, p) * 4 + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
+                               M * unst_of(c, p) * (pi ? 8 : 4) + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * d_src * 4 : 0) + M * nslot * 8;
-          check(timed(c.st, cls_name("convT_bound", bf16, 0, -1), bytes, flops,
+          check(timed(c.st, cls_name(pi ? "convT_bound_pi" : "convT_bound", bf16, 0, -1), bytes, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_BOUND, cr, &a, c.st); }));
         }
       } else {
@@ -1282,11 +1279,9 @@ struct AdjPass {
       if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
     float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
     // the node's adjoint epilogue runs fused with its last GEMM, or
-    // elementwise after all edges (identity last edge; explicit pi unless
-    // the last edge is dense)
+    // elementwise after all edges when the last edge is an identity
     const bool pi = c.rp.rho != nullptr;
-    const int last_kind = net->edges[order.back()]->kind;
-    const bool fused_last = last_kind != GCP_EDGE_IDENTITY && (!pi || last_kind == GCP_EDGE_DENSE);
+    const bool fused_last = net->edges[order.back()]->kind != GCP_EDGE_IDENTITY;
     const bool use_acc = order.size() > 1 || !fused_last;
     const double M = c.M, esz = bf16 ? 2 : 4, di = n.size;
     auto adj_bytes = [&](double a_bytes, double w_bytes) {
@@ -1364,9 +1359,10 @@ struct AdjPass {
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);
             t.d_beta = tune_beta(c);
+            if (pi) t.d_rho = t.d_alpha;   // same [M][n_I] shape, each element written by one thread
             return launch_conv(bf16, cf, EPI_ADJ, ca, &t, c.st);
           });
-          check(timed(c.st, cls_name("conv_adj", bf16, sign, -1), adj_bytes(a_bytes, wbytes), flops,
+          check(timed(c.st, cls_name(pi ? "conv_adj_pi" : "conv_adj", bf16, sign, -1), adj_bytes(a_bytes, wbytes), flops,
                       [&] { return launch_conv(bf16, cfg, EPI_ADJ, ca, &a, c.st); }));
         }
       } else {   // identity: accumulate; the node's relaxation runs after the last edge

@@ -90,9 +90,8 @@ struct AdjEpiArgs {         // adjoint of one ReLU node's relaxation
   AdamArgs adam;
   float* d_rho; float* m_rho; float* v_rho; float* rho_rw;   // explicit pi (rp.rho set)
 };
-// Explicit pi (rp.rho set) in a bound or adjoint epilogue: the dense GEMM
-// launcher runs the pi-switched epilogues; the conv launcher refuses it (conv
-// nodes relax through the elementwise kernels).
+// Explicit pi (rp.rho set) in a bound or adjoint epilogue: the GEMM and conv
+// launchers run the pi-switched epilogue instantiations.
 inline bool fused_explicit_pi(EpiKind kind, const void* epi) {
   if (kind == EPI_BOUND) return ((const BoundEpiArgs*)epi)->rp.rho != nullptr;
   if (kind == EPI_ADJ) return ((const AdjEpiArgs*)epi)->rp.rho != nullptr;
