@@ -498,6 +498,11 @@ Cands conv_cands() {
   for (int i = 0; i < conv_num_configs(); ++i) c.list.push_back(i);
   return c;
 }
+// Explicit-pi launches: the shapes their epilogues are instantiated for, and
+// tile-cache keys of their own (epilogue kind + kPiKey).
+constexpr int kPiKey = 16;
+Cands pi_dense_cands(int M, int N) { return Cands{{5, 6, 7}, pi_cfg(heuristic_cfg(M, N))}; }
+Cands pi_conv_cands() { return Cands{{0, 2}, 2}; }
 
 template <class Trial>
 int choose_cfg(const char* fam, int kind, int bf16, int sign, int M, int N, int K, hipStream_t st,
@@ -1064,7 +1069,8 @@ struct BoundPass {
         if (!dry) {
           GemmArgs gt = g;
           gt.partial = nullptr;
-          int cfg = choose_cfg("gemm", EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
+          int cfg = choose_cfg("gemm", pi ? EPI_BOUND + kPiKey : EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st,
+                               pi ? pi_dense_cands(g.M, g.N) : dense_cands(g.M, g.N),
                                [&](int cf) { return launch_gemm(bf16, cf, EPI_BOUND, gt, &a, c.st); });
           g.partial = ws.partial.as<double>(); g.slot0 = slot;
           const double M = g.M, esz = bf16 ? 2 : 4, dp = g.N;
@@ -1132,7 +1138,8 @@ struct BoundPass {
       if (p >= 0) {
         BoundEpiArgs a = bound_args(p, has_acc);
         if (!dry) {
-          int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(),
+          int cfg = choose_cfg("convT", pi ? EPI_BOUND + kPiKey : EPI_BOUND, bf16, 0, c.M, d_src, dn.size, c.st,
+                               pi ? pi_conv_cands() : conv_cands(),
                                [&](int cf) { return launch_conv(bf16, cf, EPI_BOUND, ca, &a, c.st); });
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
@@ -1319,7 +1326,8 @@ struct AdjPass {
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
-          int cfg = choose_cfg("gemm", EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N), [&](int cf) {
+          int cfg = choose_cfg("gemm", pi ? EPI_ADJ + kPiKey : EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st,
+                               pi ? pi_dense_cands(g.M, g.N) : dense_cands(g.M, g.N), [&](int cf) {
             AdjEpiArgs t = a;     // gradient-only trial into scratch: no parameter moves
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);
@@ -1354,7 +1362,8 @@ struct AdjPass {
                       flops, [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
-          int cfg = choose_cfg("conv", EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st, conv_cands(), [&](int cf) {
+          int cfg = choose_cfg("conv", pi ? EPI_ADJ + kPiKey : EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st,
+                               pi ? pi_conv_cands() : conv_cands(), [&](int cf) {
             AdjEpiArgs t = a;
             t.adam.enabled = 0;
             t.d_alpha = tune_alpha(c);
