@@ -29,9 +29,18 @@ EPI = {"bound": "BoundEpi", "conc": "ConcEpi", "adj": "AdjEpi", "store": "StoreE
 CONV_EPI = {"BoundEpi": "bound", "ConcEpi": "conc", "StoreEpi": "store", "AdjEpi": "adj", "AhatEpi": "ahat"}
 
 
+def _explicit_pi(symbol, epi):
+    """True for the explicit-pi instantiation of a bound or adjoint epilogue
+    (its second template argument, PI, set)."""
+    if epi not in ("BoundEpi", "AdjEpi"):
+        return False
+    return bool(re.search(epi + r"I(DF16b|f)Lb1E", symbol) or re.search(epi + r"<(float|__bf16), true>", symbol))
+
+
 def conv_class_of(symbol):
     """Kernel-class name ('convT_bound.bf16.w4x1', 'conv_adj.bf16.sign.w4x1',
-    ...) of a conv_slab instantiation (waves x column tiles), or None."""
+    'conv_adj_pi.bf16.w8x1', ...) of a conv_slab instantiation (waves x
+    column tiles), or None."""
     m = re.search(r"conv_slab_kernelI(DF16b|f)Li(\d+)ELi(\d+)ELb([01])ELb([01])ENS_\d+(\w+?Epi)", symbol)
     if m:
         dt, nw, tn, tr, sg, epi = m.groups()
@@ -45,6 +54,8 @@ def conv_class_of(symbol):
     kind = CONV_EPI.get(epi)
     if kind is None:
         return None
+    if _explicit_pi(symbol, epi):
+        kind += "_pi"
     name = ("convT_" if tr == "1" else "conv_") + kind + (".bf16" if dt in ("DF16b", "__bf16") else ".fp32")
     return name + (".sign" if sg == "1" else "") + f".w{nw}x{tn}"
 
@@ -68,6 +79,8 @@ def class_of(symbol):
     kind = {v: k for k, v in EPI.items()}.get(epi)
     if kind is None:
         return None
+    if _explicit_pi(symbol, epi):
+        kind += "_pi"
     name = f"{kind}.{'bf16' if dt in ('DF16b', '__bf16') else 'fp32'}"
     if sg == "1":
         name += ".sign"
