@@ -1,7 +1,8 @@
 """Kernel-class names the rocprofv3 summaries use, from mangled and demangled
-kernel symbols: they must be the names the library's own event profiler
-reports (gcp_profile_read), or the traffic record and the bench roofline
-would not line up."""
+kernel symbols.  Dense classes must be the names the library's own event
+profiler reports (gcp_profile_read), or the traffic record and the bench
+roofline would not line up; conv classes add the launch shape
+(.w<waves>x<column tiles>), which the library's names leave out."""
 import pytest
 
 from paper_2208_05740_amd.profiling import class_of
