@@ -124,7 +124,12 @@ typedef struct gcp_cuts gcp_cuts;
  * (eq. cuts).  node = -1 (input) allows only GCP_CUT_G.  Repeated
  * (cut, node, neuron, kind) entries are summed.  A Q term on a neuron that
  * is active in a domain uses z = 1 there, on an inactive one z = 0.
- * Coefficients are stored in fp32, d in fp64.  n_cuts = 0 is allowed
+ * Coefficients are stored in fp32, d in fp64; where rounding a merged
+ * coefficient c to fp32 changes it, d is widened by |fp32(c) - c| times the
+ * largest magnitude the variable takes under the root bounds (|x| <=
+ * max(|l|, |u|), 0 <= x_hat <= max(u, 0), 0 <= z <= 1), so the stored cut
+ * still holds wherever the given one does.  Input-variable (node -1)
+ * coefficients must be fp32 values (EINVAL otherwise).  n_cuts = 0 is allowed
  * (gamma rows then have length 0 and the bound is beta-CROWN's).
  * Errors: EINVAL (index out of range, bad kind), ENONFINITE. */
 int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz,
@@ -366,16 +371,23 @@ int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* op
 /* Kernel timing for roofline reports.  While enabled, every kernel the
  * library launches is bracketed by HIP events on the stream it runs on and
  * attributed to a class (one class per kernel instantiation: epilogue kind,
- * operand type, sign input, tile shape); each launch also records its
- * algorithmic HBM bytes (operands read once, results written once) and
- * FLOPs.  gcp_profile_enable(1) resets the records, (0) stops recording.
+ * operand type, sign input, tile shape); each launch also records its FLOPs
+ * and its HBM bytes under two models: `bytes` = every operand read once and
+ * every result written once; `alg_bytes` = the optimiser-state traffic the
+ * method needs (Appendix C.1's Adam on alpha, beta, gamma: 4 bytes of alpha
+ * read per (row, unstable neuron) in the bound pass, 24 bytes of alpha and
+ * its two moments read and written in the adjoint, 28 bytes per (row,
+ * multiplier) counted with the multiplier update, 1 byte of split mask per
+ * (domain, unstable neuron) and launch), 0 for launches without such state.
+ * gcp_profile_enable(1) resets the records, (0) stops recording.
  * gcp_profile_read synchronises the recorded events and returns class idx
  * (0-based, GCP_EINVAL past the last class): its name (NUL-terminated,
- * truncated to name_len), launches, total milliseconds, bytes and FLOPs.
+ * truncated to name_len), launches, total milliseconds, both byte figures
+ * and FLOPs (summed over the launches; any output may be NULL).
  * Autotuner trial launches are never recorded. */
 int gcp_profile_enable(int32_t on);
 int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64_t* launches,
-                     double* total_ms, double* bytes, double* flops);
+                     double* total_ms, double* bytes, double* alg_bytes, double* flops);
 
 /* Last error message of this thread ("" if none). */
 const char* gcp_last_error(void);

@@ -17,14 +17,20 @@ import numpy as np
 from .lp import edge_matrix
 
 
-def crown_bound(net, lu, x0, eps, c, alpha_per_node, fixed=None):
+def crown_bound(net, lu, x0, eps, c, alpha_per_node, fixed=None, with_scale=False):
     """Lower bound of c^T f(x) over the box.  alpha_per_node[k] is the lower
     slope of every neuron of the k-th ReLU node (used where unstable).
     fixed[(node, neuron)] = +1 / -1 replaces the ReLU of that neuron by its
     active (x_hat = x) / inactive (x_hat = 0) piece: the network of a BaB
     domain with those splits, whose bound over the box also bounds it over
-    the domain (Sec. 3.1, splits; no split multipliers here)."""
+    the domain (Sec. 3.1, splits; no split multipliers here).
+
+    with_scale: also return the sum of the magnitudes of the individual
+    terms the bound adds up (each bias term lam_j b_j, each chord intercept,
+    each input term w_k x0_k and eps |w_k|), counted term by term here in
+    the primal form."""
     fixed = fixed or {}
+    scale = 0.0
     relu = [i for i, n in enumerate(net.nodes) if n.relu]
     pos = {p: k for k, p in enumerate(relu)}
     coef = {}          # coefficient row on each post-activation
@@ -37,6 +43,7 @@ def crown_bound(net, lu, x0, eps, c, alpha_per_node, fixed=None):
             coef[e.src] = coef.get(e.src, 0.0) + lam @ A
 
     spread(out, np.asarray(c, np.float64))
+    scale += float(np.abs(np.asarray(c, np.float64) * out.bias).sum())
     for p in reversed(relu):
         node = net.nodes[p]
         lam_hat = np.asarray(coef.get(p, np.zeros(node.size)), np.float64)
@@ -54,10 +61,15 @@ def crown_bound(net, lu, x0, eps, c, alpha_per_node, fixed=None):
                 slope = u[j] / (u[j] - l[j])
                 lam[j] = lam_hat[j] * slope
                 const += lam_hat[j] * (-slope * l[j])
+                scale += abs(lam_hat[j] * slope * l[j])
         const += float(lam @ node.bias)
+        scale += float(np.abs(lam * node.bias).sum())
         spread(node, lam)
     w = coef.get(-1, np.zeros(net.in_size))
-    return float(w @ x0 - eps * np.abs(w).sum() + const)
+    val = float(w @ x0 - eps * np.abs(w).sum() + const)
+    if with_scale:
+        return val, scale + float(np.abs(w * x0).sum() + eps * np.abs(w).sum())
+    return val
 
 
 def crown_intermediate_bounds(net, x0, eps, lu_given=None, splits=None):

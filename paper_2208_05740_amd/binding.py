@@ -115,7 +115,7 @@ def lib():
     L.gcp_bab.argtypes = [vp, vp, dbl, vp, vp, C.POINTER(BabOpt), C.POINTER(BabResult), vp]
     L.gcp_profile_enable.argtypes = [i32]
     L.gcp_profile_read.argtypes = [i32, C.c_char_p, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.gcp_last_error.restype = C.c_char_p
     L.gcp_version.restype = C.c_char_p
     for f in ("gcp_net_create", "gcp_net_destroy", "gcp_net_get_info", "gcp_cuts_create", "gcp_cuts_destroy",
@@ -450,15 +450,17 @@ def profile_enable(on: bool = True):
 
 
 def profile_read():
-    """Per kernel class: {name: dict(launches, ms, bytes, flops)}."""
+    """Per kernel class: {name: dict(launches, ms, bytes, alg_bytes, flops)} (bytes: every operand
+    once; alg_bytes: optimiser-state traffic only)."""
     out = {}
     i = 0
     buf = C.create_string_buffer(256)
     while True:
-        n, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
-        rc = lib().gcp_profile_read(i, buf, 256, C.byref(n), C.byref(ms), C.byref(by), C.byref(fl))
+        n, ms, by, al, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        rc = lib().gcp_profile_read(i, buf, 256, C.byref(n), C.byref(ms), C.byref(by), C.byref(al), C.byref(fl))
         if rc != 0:
             break
-        out[buf.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+        out[buf.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value, alg_bytes=al.value,
+                                       flops=fl.value)
         i += 1
     return out

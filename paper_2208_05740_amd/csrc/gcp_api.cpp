@@ -61,12 +61,12 @@ uint64_t next_generation() {
 struct Profiler {
   std::mutex mu;
   bool on = false;
-  struct Rec { int cls; hipEvent_t e0, e1; double bytes, flops; };
+  struct Rec { int cls; hipEvent_t e0, e1; double bytes, alg, flops; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   std::vector<std::string> names;
   std::map<std::string, int> ids;
-  struct Agg { int64_t n = 0; double ms = 0, bytes = 0, flops = 0; };
+  struct Agg { int64_t n = 0; double ms = 0, bytes = 0, alg = 0, flops = 0; };
   std::vector<Agg> agg;
   hipEvent_t get() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -80,7 +80,8 @@ struct Profiler {
       float ms = 0.f;
       hip_check(hipEventElapsedTime(&ms, r.e0, r.e1), "hipEventElapsedTime");
       if ((int)agg.size() <= r.cls) agg.resize(r.cls + 1);
-      agg[r.cls].n++; agg[r.cls].ms += ms; agg[r.cls].bytes += r.bytes; agg[r.cls].flops += r.flops;
+      agg[r.cls].n++; agg[r.cls].ms += ms; agg[r.cls].bytes += r.bytes; agg[r.cls].alg += r.alg;
+      agg[r.cls].flops += r.flops;
       pool.push_back(r.e0); pool.push_back(r.e1);
     }
     recs.clear();
@@ -88,9 +89,17 @@ struct Profiler {
 };
 Profiler& prof() { static Profiler p; return p; }
 
+// HBM bytes of one launch under two models: `all` = every operand read once
+// and every result written once (what a launch must move when nothing stays
+// on chip between launches); `alg` = the optimiser-state traffic the method
+// itself needs (alpha / rho read in the bound pass, alpha / rho and their Adam
+// moments read and written in the adjoint, multipliers and their moments in
+// the multiplier update, the split mask), 0 for launches that carry none.
+struct Bytes { double all, alg; };
+
 // Launch `f` on `st`; while profiling, bracket it with events under `name`.
 template <class F>
-hipError_t timed(hipStream_t st, const std::string& name, double bytes, double flops, F f) {
+hipError_t timed(hipStream_t st, const std::string& name, Bytes bytes, double flops, F f) {
   Profiler& P = prof();
   if (!P.on) return f();
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -105,7 +114,7 @@ hipError_t timed(hipStream_t st, const std::string& name, double bytes, double f
   int cls;
   if (it == P.ids.end()) { cls = (int)P.names.size(); P.ids[name] = cls; P.names.push_back(name); }
   else cls = it->second;
-  P.recs.push_back(Profiler::Rec{cls, e0, e1, bytes, flops});
+  P.recs.push_back(Profiler::Rec{cls, e0, e1, bytes.all, bytes.alg, flops});
   return err;
 }
 
@@ -226,6 +235,9 @@ struct gcp_net {
 };
 
 struct gcp_cuts {
+  // process-unique: cached launch tables and graphs key on it, so a handle
+  // created at the address of a destroyed one never matches their entries
+  uint64_t id = next_generation();
   int N = 0;
   int nnz_e = 0;
   DBuf row_ptr;     // [N + 1] over merged entries in cut-major order
@@ -244,6 +256,7 @@ struct gcp_cuts {
 };
 
 struct gcp_splits {
+  uint64_t id = next_generation();   // process-unique (see gcp_cuts::id)
   int B = 0, K = 0;
   DBuf mask;        // int8 [B][n_I]
   const gcp_net* net = nullptr;
@@ -453,17 +466,23 @@ int heuristic_cfg(int M, int N) {
 }
 
 // Process-wide tile cache.  With GCP_TILE_CACHE=<file> decisions are read
-// from the file at first use and every new decision is appended, so a later
-// process (for example a profiler run) launches exactly the same tiles.
+// from the file at first use (and again whenever the variable names another
+// file) and every new decision is appended, so a later process (for example
+// a profiler run) launches exactly the same tiles.
 struct TileCache {
   std::mutex mu;
   bool loaded = false;
+  std::string loaded_path;    // the file the decisions came from ("" = none)
   std::map<std::string, int> m;
   const char* path() { return std::getenv("GCP_TILE_CACHE"); }
+  // (re)load when first used or when GCP_TILE_CACHE names another file
   void load() {
-    if (loaded) return;
-    loaded = true;
     const char* p = path();
+    const std::string ps = p ? p : "";
+    if (loaded && ps == loaded_path) return;
+    loaded = true;
+    loaded_path = ps;
+    m.clear();
     if (!p) return;
     FILE* f = std::fopen(p, "r");
     if (!f) return;
@@ -640,6 +659,26 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   }
   for (int k = 0; k < n_cuts; ++k)
     if (!std::isfinite(d[k])) fail(GCP_ENONFINITE, "non-finite cut offset");
+  // Coefficients are stored in fp32.  Where rounding changes one, the cut the
+  // kernels see is  sum c' var <= d'  with d' = d + sum |c' - c| max|var|,
+  // which every point satisfying the given cut satisfies too (var ranges:
+  // x in [l, u] and x_hat in [0, max(u, 0)] from the root bounds, z in
+  // [0, 1]), so the bound stays sound.  Input-variable coefficients have no
+  // range before the call (x0, eps) and must be fp32 values.
+  std::vector<double> slack(n_cuts, 0.0);
+  for (auto& kv : m) {
+    const int k = std::get<0>(kv.first), nd = std::get<1>(kv.first), j = std::get<2>(kv.first);
+    for (int kd = 0; kd < 3; ++kd) {
+      const double c = kv.second[kd];
+      const double err = std::fabs((double)(float)c - c);
+      if (err == 0.0) continue;
+      if (nd < 0) fail(GCP_EINVAL, "input-variable cut coefficients must be fp32 values");
+      const NodeH& n = net->nodes[nd];
+      const double range = kd == GCP_CUT_H ? std::max(std::fabs(n.l_h[j]), std::fabs(n.u_h[j]))
+                         : kd == GCP_CUT_G ? std::max(n.u_h[j], 0.0) : 1.0;
+      slack[k] += err * range;
+    }
+  }
   auto C = std::make_unique<gcp_cuts>();
   C->N = n_cuts;
   C->net = net;
@@ -658,6 +697,8 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   for (int k = 0; k < n_cuts; ++k) row_ptr[k + 1] += row_ptr[k];
   C->row_ptr.upload(row_ptr);
   std::vector<double> dv(d ? d : (const double*)nullptr, d ? d + n_cuts : (const double*)nullptr);
+  for (int k = 0; k < n_cuts; ++k)
+    if (slack[k] > 0.0) dv[k] = std::nextafter(dv[k] + slack[k], INFINITY);
   C->d.upload(dv);
   C->cols.resize(n_nodes + 1);
   C->nnz_node.assign(n_nodes + 1, 0);
@@ -755,7 +796,7 @@ struct Rec {
   alignas(16) unsigned char epi[sizeof(AdjEpiArgs) > sizeof(BoundEpiArgs) ? sizeof(AdjEpiArgs) : sizeof(BoundEpiArgs)];
   ElemBoundJob ej;
   int tiles;           // workgroups of this problem
-  double bytes, flops; // algorithmic HBM bytes and FLOPs of this launch
+  double bytes, alg, flops; // HBM bytes (both models, see Bytes) and FLOPs of this launch
 };
 static_assert(sizeof(ConcEpiArgs) <= sizeof(Rec::epi) && sizeof(StoreEpiArgs) <= sizeof(Rec::epi), "epi blob");
 struct Recorder {
@@ -830,22 +871,6 @@ void ensure_ws(Call& c) {
   ws.partial.release();
 }
 
-// Explicit pi runs every ReLU node's relaxation (and its adjoint) as an
-// elementwise pass over the node's accumulated GEMM result, so every ReLU
-// node needs the accumulation buffer.
-void ensure_acc_all(Call& c) {
-  auto& ws = c.net->ws;
-  for (size_t i = 0; i < c.net->nodes.size(); ++i) {
-    const NodeH& n = c.net->nodes[i];
-    if (!n.relu) continue;
-    const size_t need = (size_t)ws.M * n.ld * 4;
-    if (ws.acc[i]->bytes < need) {
-      ws.acc[i]->alloc(need);
-      ws.gen = next_generation();
-    }
-  }
-}
-
 CutCol cut_col(const Call& c, int node) {
   if (!c.cuts) return CutCol{nullptr, nullptr, nullptr};
   int idx = node < 0 ? (int)c.net->nodes.size() : node;
@@ -857,6 +882,18 @@ double nnz_of(const Call& c, int node) {
   return (double)c.cuts->nnz_node[node < 0 ? (int)c.net->nodes.size() : node];
 }
 double unst_of(const Call& c, int node) { return node < 0 ? 0.0 : (double)c.net->nodes[node].n_unst; }
+// optimiser-state bytes (Bytes::alg) of a bound-pass and of an adjoint launch on node p
+double alg_bound(const Call& c, int p) {
+  const double nu = unst_of(c, p);
+  return (double)c.M * nu * (c.rp.rho ? 8.0 : 4.0) + (double)c.B * nu;
+}
+// multipliers: gamma read once by the bound pass, gamma and beta with their
+// Adam moments read and written by the update (counted with the gamma update)
+double alg_mult(const Call& c) { return (double)c.M * (c.N + c.rp.K) * 28.0; }
+double alg_adj(const Call& c, int p, bool adam) {
+  const double nu = unst_of(c, p);
+  return (double)c.M * nu * (adam ? 24.0 : 8.0) * (c.rp.rho ? 2.0 : 1.0) + (double)c.B * nu;
+}
 
 float* tune_store(Call& c) {
   auto& ws = c.net->ws;
@@ -880,14 +917,15 @@ float* tune_beta(Call& c) {
 
 // In recording mode a GEMM launch is stored instead of issued.
 template <class A>
-bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a, double bytes) {
+bool record_gemm(Call& c, int bf16, int cfg, EpiKind kind, const GemmArgs& g, const A& a, Bytes bytes) {
   if (!c.rec) return false;
   if constexpr (std::is_same_v<A, BoundEpiArgs> || std::is_same_v<A, AdjEpiArgs>)
     if (a.rp.rho) fail(GCP_EUNSUPPORTED, "batched optimisation takes Lemma A.1's pi* only");
   Rec r{};
   r.type = 0; r.bf16 = bf16; r.cfg = cfg; r.kind = kind; r.sign = g.a_is_sign;
   r.g = g;
-  r.bytes = bytes;
+  r.bytes = bytes.all;
+  r.alg = bytes.alg;
   r.flops = 2.0 * g.M * g.N * g.K;
   std::memcpy(r.epi, &a, sizeof(A));
   int bm, bn;
@@ -935,23 +973,6 @@ struct BoundPass {
 
   void check(hipError_t e) { hip_check(e, "kernel launch (bound pass)"); }
 
-  // explicit pi: node p's relaxation over acc[p], which holds the complete
-  // GEMM sum (the last push stored into it instead of running fused)
-  void relax_elementwise(int p) {
-    auto& ws = c.net->ws;
-    BoundEpiArgs a = bound_args(p, true);
-    const int d = c.net->nodes[p].size;
-    const int nslot = slots_for_elementwise(d);
-    const double M = c.M, esz = bf16 ? 2 : 4;
-    const double bytes = M * d * (4 + esz + (keep_ahat ? esz : 0)) + M * unst_of(c, p) * 8 +
-                         (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 + M * nslot * 8;
-    if (!dry)
-      check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
-        return launch_bound_elementwise(bf16, nullptr, nullptr, a, ws.partial.as<double>(), slot, c.st);
-      }));
-    slot += nslot;
-  }
-
   void run() {
     gcp_net* net = c.net;
     const int nn = (int)net->nodes.size();
@@ -998,9 +1019,10 @@ struct BoundPass {
         r.ej = ElemBoundJob{ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(), slot};
         r.tiles = ((c.M + kElemRows - 1) / kElemRows) * ((net->nodes[p].size + 255) / 256);
         r.bytes = bytes;
+        r.alg = alg_bound(c, p);
         c.rec->push(r);
       } else if (!dry) {
-        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), bytes, 0.0, [&] {
+        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), Bytes{bytes, alg_bound(c, p)}, 0.0, [&] {
           return launch_bound_elementwise(bf16, ws.chat.as<float>() + ws.chat_off[p], nullptr, a, ws.partial.as<double>(),
                                           slot, c.st);
         }));
@@ -1056,11 +1078,10 @@ struct BoundPass {
           });
           const double esz = bf16 ? 2 : 4;
           const double bytes = (double)g.M * g.K * esz + (double)g.N * g.K * esz + (double)g.M * g.N * 4 * (first ? 1 : 2);
-          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, bytes))
-            check(timed(c.st, cls_name("store", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, Bytes{bytes, 0.0}))
+            check(timed(c.st, cls_name("store", bf16, 0, cfg), Bytes{bytes, 0.0}, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         }
-        if (last) relax_elementwise(p);
         return;
       }
       int nslot = slots_for_gemm(d_src);
@@ -1077,8 +1098,9 @@ struct BoundPass {
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * dp * esz + (keep_ahat ? M * dp * esz : 0) +
                                M * unst_of(c, p) * (pi ? 8 : 4) + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * dp * 4 : 0) + M * nslot * 8;
-          if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a, bytes))
-            check(timed(c.st, pi ? cls_name("bound_pi", bf16, 0, pi_cfg(cfg)) : cls_name("bound", bf16, 0, cfg), bytes,
+          if (!record_gemm(c, bf16, cfg, EPI_BOUND, g, a, Bytes{bytes, alg_bound(c, p)}))
+            check(timed(c.st, pi ? cls_name("bound_pi", bf16, 0, pi_cfg(cfg)) : cls_name("bound", bf16, 0, cfg),
+                        Bytes{bytes, alg_bound(c, p)},
                         2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_BOUND, g, &a, c.st); }));
         }
       } else {
@@ -1098,8 +1120,8 @@ struct BoundPass {
           const double M = g.M, esz = bf16 ? 2 : 4;
           const double bytes = M * g.K * esz + (double)g.N * g.K * esz + (keep_ahat ? M * g.N : 0) +
                                M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
-          if (!record_gemm(c, bf16, cfg, EPI_CONC, g, a, bytes))
-            check(timed(c.st, cls_name("conc", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+          if (!record_gemm(c, bf16, cfg, EPI_CONC, g, a, Bytes{bytes, 0.0}))
+            check(timed(c.st, cls_name("conc", bf16, 0, cfg), Bytes{bytes, 0.0}, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_CONC, g, &a, c.st); }));
         }
       }
@@ -1128,10 +1150,9 @@ struct BoundPass {
             return launch_conv(bf16, cf, EPI_STORE, ca, &t, c.st);
           });
           const double bytes = M * dn.size * esz + wbytes + M * d_src * 4 * (first ? 1 : 2);
-          check(timed(c.st, cls_name("convT_store", bf16, 0, -1), bytes, flops,
+          check(timed(c.st, cls_name("convT_store", bf16, 0, -1), Bytes{bytes, 0.0}, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         }
-        if (last) relax_elementwise(p);
         return;
       }
       const int nslot = conv_slots(cg, 1);
@@ -1146,7 +1167,8 @@ struct BoundPass {
           const double bytes = M * dn.size * esz + wbytes + M * d_src * esz + (keep_ahat ? M * d_src * esz : 0) +
                                M * unst_of(c, p) * (pi ? 8 : 4) + (double)c.B * unst_of(c, p) + M * nnz_of(c, p) * 4 +
                                (has_acc ? M * d_src * 4 : 0) + M * nslot * 8;
-          check(timed(c.st, cls_name(pi ? "convT_bound_pi" : "convT_bound", bf16, 0, -1), bytes, flops,
+          check(timed(c.st, cls_name(pi ? "convT_bound_pi" : "convT_bound", bf16, 0, -1), Bytes{bytes, alg_bound(c, p)},
+                      flops,
                       [&] { return launch_conv(bf16, cfg, EPI_BOUND, cr, &a, c.st); }));
         }
       } else {
@@ -1164,7 +1186,7 @@ struct BoundPass {
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
           const double bytes = M * dn.size * esz + wbytes + (keep_ahat ? M * d_src : 0) +
                                M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
-          check(timed(c.st, cls_name("convT_conc", bf16, 0, -1), bytes, flops,
+          check(timed(c.st, cls_name("convT_conc", bf16, 0, -1), Bytes{bytes, 0.0}, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_CONC, cr, &a, c.st); }));
         }
       }
@@ -1183,7 +1205,7 @@ struct BoundPass {
       BoundEpiArgs a = bound_args(p, has_acc);
       const int nslot = slots_for_elementwise(d_src);
       if (!dry)
-        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), (double)c.M * d_src * 16, 0.0, [&] {
+        check(timed(c.st, cls_name("bound_elem", bf16, 0, -1), Bytes{(double)c.M * d_src * 16, alg_bound(c, p)}, 0.0, [&] {
           return launch_bound_elementwise(bf16, nullptr, ws.lam[E.dst]->p, a, ws.partial.as<double>(), slot, c.st);
         }));
       slot += nslot;
@@ -1255,7 +1277,7 @@ struct AdjPass {
       const int cfg = choose_cfg("gemm", EPI_BOUND, bf16, 0, g.M, g.N, g.K, c.st, dense_cands(g.M, g.N),
                                  [&](int cf) { return launch_gemm(bf16, cf, EPI_AHAT, g, &a, c.st); });
       const double bytes = M * g.K * esz + (double)g.N * g.K * esz + M * g.N * esz + M * nnz_of(c, i) * 4;
-      check(timed(c.st, cls_name("ahat", bf16, 0, cfg), bytes, 2.0 * g.M * g.N * g.K,
+      check(timed(c.st, cls_name("ahat", bf16, 0, cfg), Bytes{bytes, 0.0}, 2.0 * g.M * g.N * g.K,
                   [&] { return launch_gemm(bf16, cfg, EPI_AHAT, g, &a, c.st); }));
     } else {
       ConvArgs ca{};
@@ -1268,7 +1290,7 @@ struct AdjPass {
                                  [&](int cf) { return launch_conv(bf16, cf, EPI_AHAT, ca, &a, c.st); });
       const double bytes = M * dn.size * esz + (double)cg.stride * cg.stride * cg.ci * E.ldk_t * esz +
                            M * E.d_src * esz + M * nnz_of(c, i) * 4;
-      check(timed(c.st, cls_name("convT_ahat", bf16, 0, -1), bytes,
+      check(timed(c.st, cls_name("convT_ahat", bf16, 0, -1), Bytes{bytes, 0.0},
                   2.0 * M * cg.ho * cg.wo * cg.ci * cg.co * cg.kh * cg.kw,
                   [&] { return launch_conv(bf16, cfg, EPI_AHAT, ca, &a, c.st); }));
     }
@@ -1321,8 +1343,8 @@ struct AdjPass {
             return launch_gemm(bf16, cf, EPI_STORE, g, &t, c.st);
           });
           const double bytes = a_bytes + (double)g.N * g.K * esz + M * di * 4 * (first ? 1 : 2);
-          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, bytes))
-            check(timed(c.st, cls_name("store", bf16, sign, cfg), bytes, 2.0 * g.M * g.N * g.K,
+          if (!record_gemm(c, bf16, cfg, EPI_STORE, g, s, Bytes{bytes, 0.0}))
+            check(timed(c.st, cls_name("store", bf16, sign, cfg), Bytes{bytes, 0.0}, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
@@ -1336,8 +1358,9 @@ struct AdjPass {
             return launch_gemm(bf16, cf, EPI_ADJ, g, &t, c.st);
           });
           const double bytes = adj_bytes(a_bytes, (double)g.N * g.K * esz);
-          if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a, bytes))
-            check(timed(c.st, pi ? cls_name("adj_pi", bf16, sign, pi_cfg(cfg)) : cls_name("adj", bf16, sign, cfg), bytes,
+          if (!record_gemm(c, bf16, cfg, EPI_ADJ, g, a, Bytes{bytes, alg_adj(c, i, adam.enabled)}))
+            check(timed(c.st, pi ? cls_name("adj_pi", bf16, sign, pi_cfg(cfg)) : cls_name("adj", bf16, sign, cfg),
+                        Bytes{bytes, alg_adj(c, i, adam.enabled)},
                         2.0 * g.M * g.N * g.K, [&] { return launch_gemm(bf16, cfg, EPI_ADJ, g, &a, c.st); }));
         }
       } else if (E.kind == GCP_EDGE_CONV) {
@@ -1358,7 +1381,7 @@ struct AdjPass {
             t.out = tune_store(c);
             return launch_conv(bf16, cf, EPI_STORE, ca, &t, c.st);
           });
-          check(timed(c.st, cls_name("conv_store", bf16, sign, -1), a_bytes + wbytes + M * di * 4 * (first ? 1 : 2),
+          check(timed(c.st, cls_name("conv_store", bf16, sign, -1), Bytes{a_bytes + wbytes + M * di * 4 * (first ? 1 : 2), 0.0},
                       flops, [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         } else {
           AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
@@ -1371,7 +1394,8 @@ struct AdjPass {
             if (pi) t.d_rho = t.d_alpha;   // same [M][n_I] shape, each element written by one thread
             return launch_conv(bf16, cf, EPI_ADJ, ca, &t, c.st);
           });
-          check(timed(c.st, cls_name(pi ? "conv_adj_pi" : "conv_adj", bf16, sign, -1), adj_bytes(a_bytes, wbytes), flops,
+          check(timed(c.st, cls_name(pi ? "conv_adj_pi" : "conv_adj", bf16, sign, -1),
+                      Bytes{adj_bytes(a_bytes, wbytes), alg_adj(c, i, adam.enabled)}, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_ADJ, ca, &a, c.st); }));
         }
       } else {   // identity: accumulate; the node's relaxation runs after the last edge
@@ -1382,7 +1406,7 @@ struct AdjPass {
     }
     if (!fused_last) {
       AdjEpiArgs a = epi(i, accbuf, 0.f);
-      check(timed(c.st, cls_name("adj_elem", bf16, 0, -1), adj_bytes(0, 0), 0.0,
+      check(timed(c.st, cls_name("adj_elem", bf16, 0, -1), Bytes{adj_bytes(0, 0), alg_adj(c, i, adam.enabled)}, 0.0,
                   [&] { return launch_adj_elementwise(bf16, a, c.st); }));
     }
   }
@@ -1518,7 +1542,7 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
   bp.run();
   auto& ws = c.net->ws;
   const double rb = (double)c.M * (ws.n_slots * 8.0 + c.rp.N * 4.0 + 8.0 + (verified ? 1 : 0));
-  hip_check(timed(c.st, "reduce_rows", rb, 0.0, [&] {
+  hip_check(timed(c.st, "reduce_rows", Bytes{rb, 0.0}, 0.0, [&] {
               return launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
                                         c.rp.gammaT, c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound,
                                         verified, c.st);
@@ -1535,7 +1559,6 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
   Call c{};
   prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
   c.rp.rho = rho;
-  if (rho) ensure_acc_all(c);
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   if (!bound) fail(GCP_EINVAL, "null bound output");
@@ -1556,7 +1579,8 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
     ap.prepare();
     ap.run();
     if (c.rp.N > 0)
-      hip_check(timed(c.st, "gamma_grad", (double)c.M * (c.nnz * 4.0 + c.rp.N * 4.0), 0.0, [&] {
+      hip_check(timed(c.st, "gamma_grad", Bytes{(double)c.M * (c.nnz * 4.0 + c.rp.N * 4.0), (double)c.M * c.rp.N * 8.0},
+                      0.0, [&] {
                   return launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(),
                                              net->ws.contrib.as<float>(), c.cuts->d.as<double>(), nullptr, d_gamma,
                                              nullptr, nullptr, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st);
@@ -1575,7 +1599,6 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   Call c{};
   prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
   c.rp.rho = rho;
-  if (rho) ensure_acc_all(c);
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   if (!opt || opt->iters < 0) fail(GCP_EINVAL, "bad optimiser settings");
@@ -1619,7 +1642,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
     AdjPass ap{cc, bf16, ad, nullptr, nullptr, alpha, beta, ma, va, mb, vb, nullptr, rho, mr, vr};
     ap.run();
     if (N > 0)
-      hip_check(timed(cc.st, "gamma_adam", (double)cc.M * (cc.nnz * 4.0 + N * 24.0), 0.0, [&] {
+      hip_check(timed(cc.st, "gamma_adam", Bytes{(double)cc.M * (cc.nnz * 4.0 + N * 24.0), alg_mult(cc)}, 0.0, [&] {
                   return launch_gamma_update(cc.M, cc.rp.mp, (int)N, cc.cuts->row_ptr.as<int32_t>(),
                                              ws.contrib.as<float>(), cc.cuts->d.as<double>(), ws.gammaT.as<float>(),
                                              nullptr, mg, vg, ad, cc.st);
@@ -1633,7 +1656,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
     c.consts_done = !net->out_general || !bf16;
   }
   if (opt->use_graph && opt->iters > 1) {
-    std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits, (uintptr_t)cuts,
+    std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits->id, (uintptr_t)(c.cuts ? c.cuts->id : 0),
                                   (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)rho,
                                   (uintptr_t)adam_state,
                                   (uintptr_t)S, (uintptr_t)bf16, (uintptr_t)c.M,
@@ -1747,7 +1770,7 @@ extern "C" int gcp_profile_enable(int32_t on) {
 }
 
 extern "C" int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64_t* launches, double* total_ms,
-                                double* bytes, double* flops) {
+                                double* bytes, double* alg_bytes, double* flops) {
   GCP_TRY
   Profiler& P = prof();
   std::lock_guard<std::mutex> lk(P.mu);
@@ -1760,6 +1783,7 @@ extern "C" int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64
   if (launches) *launches = a.n;
   if (total_ms) *total_ms = a.ms;
   if (bytes) *bytes = a.bytes;
+  if (alg_bytes) *alg_bytes = a.alg;
   if (flops) *flops = a.flops;
   return GCP_OK;
   GCP_CATCH
@@ -1788,7 +1812,7 @@ void launch_constants(Call& c) {
 struct Group {
   int type, bf16, cfg, kind, sign;
   int np, total;
-  double bytes, flops;                    // summed over the group's problems
+  double bytes, alg, flops;               // summed over the group's problems
   size_t off_args, off_epi, off_prefix;   // byte offsets into the plan buffer
 };
 struct BatchPlan {
@@ -1797,7 +1821,7 @@ struct BatchPlan {
   std::vector<Group> groups;              // in launch order
   size_t off_gjobs = 0, off_gprefix = 0;
   int g_np = 0, g_total = 0;
-  double g_bytes = 0.0;                   // algorithmic bytes of the grouped gamma update
+  double g_bytes = 0.0, g_alg = 0.0;      // bytes (both models) of the grouped gamma update
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
   ~BatchPlan() {
@@ -1846,6 +1870,7 @@ void build_plan(BatchPlan& plan, std::vector<Recorder>& recs, std::vector<GammaJ
       for (const Rec* r : v) {
         prefix.push_back(prefix.back() + r->tiles);
         G.bytes += r->bytes;
+        G.alg += r->alg;
         G.flops += r->flops;
       }
       G.total = prefix.back();
@@ -1889,21 +1914,21 @@ void run_grouped_iteration(BatchPlan& plan, int* step, float* consts, const gcp_
   static const char* grp_names[] = {"store_grp", "bound_grp", "conc_grp", "adj_grp"};   // by EpiKind
   for (const Group& G : plan.groups) {
     if (G.type == 0)
-      hip_check(timed(st, cls_name(grp_names[G.kind], G.bf16, G.sign, G.cfg), G.bytes, G.flops, [&] {
+      hip_check(timed(st, cls_name(grp_names[G.kind], G.bf16, G.sign, G.cfg), Bytes{G.bytes, G.alg}, G.flops, [&] {
                   return launch_gemm_grouped(G.bf16, G.cfg, (EpiKind)G.kind, G.sign,
                                              (const GemmArgs*)(b + G.off_args), b + G.off_epi,
                                              (const int*)(b + G.off_prefix), G.np, G.total, st);
                 }),
                 "grouped gemm");
     else
-      hip_check(timed(st, cls_name("bound_elem_grp", G.bf16, 0, -1), G.bytes, 0.0, [&] {
+      hip_check(timed(st, cls_name("bound_elem_grp", G.bf16, 0, -1), Bytes{G.bytes, G.alg}, 0.0, [&] {
                   return launch_bound_elementwise_grouped(G.bf16, (const ElemBoundJob*)(b + G.off_args),
                                                           (const int*)(b + G.off_prefix), G.np, G.total, st);
                 }),
                 "grouped elementwise");
   }
   if (plan.g_np)
-    hip_check(timed(st, "gamma_adam_grp", plan.g_bytes, 0.0, [&] {
+    hip_check(timed(st, "gamma_adam_grp", Bytes{plan.g_bytes, plan.g_alg}, 0.0, [&] {
                 return launch_gamma_grouped((const GammaJob*)(b + plan.off_gjobs), (const int*)(b + plan.off_gprefix),
                                             plan.g_np, plan.g_total, adam, st);
               }),
@@ -2030,6 +2055,12 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   struct Moments { float *ma, *va, *mb, *vb, *mg, *vg; };
   std::vector<Moments> mom(n);
   std::vector<uintptr_t> key = {(uintptr_t)n, (uintptr_t)bf16};
+  // the captured graph and the recorded epilogue arguments hold these
+  for (float v : {opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, opt->adam_eps}) {
+    uint32_t b;
+    std::memcpy(&b, &v, 4);
+    key.push_back(b);
+  }
   for (int i = 0; i < n; ++i) {
     Call& c = calls[i];
     const gcp_batch_item& it = items[i];
@@ -2044,7 +2075,8 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     AdjPass prep{c, bf16, adam, nullptr, nullptr, it.alpha, it.beta, m.ma, m.va, m.mb, m.vb};
     prep.prepare();
     for (uintptr_t v : {(uintptr_t)it.net, (uintptr_t)it.x0, (uintptr_t)it.C, (uintptr_t)it.S,
-                        (uintptr_t)it.splits, (uintptr_t)it.cuts, (uintptr_t)it.alpha, (uintptr_t)it.beta,
+                        (uintptr_t)it.splits->id, (uintptr_t)(c.cuts ? c.cuts->id : 0), (uintptr_t)it.alpha,
+                        (uintptr_t)it.beta,
                         (uintptr_t)it.gamma, (uintptr_t)it.adam_state, (uintptr_t)std::hash<double>()(it.eps),
                         (uintptr_t)c.net->ws.gen})
       key.push_back(v);
@@ -2088,6 +2120,7 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
       ap.run();
       if (c.rp.N > 0) {
         plan->g_bytes += (double)c.M * (c.nnz * 4.0 + c.rp.N * 24.0);
+        plan->g_alg += alg_mult(c);
         gj.push_back(GammaJob{c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), c.net->ws.contrib.as<float>(),
                               c.cuts->d.as<double>(), c.net->ws.gammaT.as<float>(), mom[i].mg, mom[i].vg});
       }

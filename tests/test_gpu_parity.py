@@ -265,7 +265,7 @@ def test_optimize_bf16_final_bound_close_to_fp32():
     g32, *_ = _optimize(p, P, 0)
     g16, a, b, c = _optimize(p, P, 1)
     rel = np.abs(g16 - g32) / np.abs(g32)
-    assert np.median(rel) <= 1e-3, (np.median(rel), rel.max())
+    assert rel.max() <= 1e-3, (np.median(rel), rel.max())
     # the bf16-optimised parameters are certified exactly (fp32/fp64 pass)
     a64, b64, c64 = (x.cpu().numpy().astype(np.float64).reshape(p.B, p.S, -1) for x in (a, b, c))
     ref = O.bound(p, a64, b64, c64).reshape(-1)

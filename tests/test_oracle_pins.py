@@ -306,6 +306,31 @@ def test_workload_shapes():
     assert sum(n.size for n in p5.net.nodes if n.relu) == 73728
 
 
+@pytest.mark.parametrize("kind,seed", [("mlp", 0), ("mlp", 3), ("cnn", 1), ("res", 2)])
+def test_error_scale_equals_textbook_crown_term_sum(kind, seed):
+    # The scale T that every parity tolerance divides by, pinned from above
+    # and below: with beta = gamma = 0 it must equal the sum of the term
+    # magnitudes that the independent primal-form CROWN adds up (bias terms,
+    # chord intercepts, input terms), so a term counted twice or dropped in
+    # T fails here.
+    p = gen.make_tiny(kind, seed, B=2, splits=(0, 0), n_cuts=3)
+    prep = O.Prepared(p)
+    a = np.random.default_rng(seed).random((p.B, p.S, prep.n_I))
+    zb, zc = np.zeros_like(p.beta), np.zeros_like(p.gamma)
+    T = O.error_scale(p, a, zb, zc, prep=prep).reshape(p.B, p.S)
+    g = O.bound(p, a, zb, zc, prep=prep)
+    for b in range(p.B):
+        for s in range(p.S):
+            apn = []
+            for q in prep.relu:
+                full = np.zeros(p.net.nodes[q].size)
+                full[prep.unst_cols[q]] = a[b, s, prep.alpha_pos[q]]
+                apn.append(full)
+            val, scale = crown.crown_bound(p.net, p.lu, p.x0, p.eps, p.C[s], apn, with_scale=True)
+            assert abs(g[b, s] - val) <= 1e-10 * (1 + abs(val))
+            assert abs(T[b, s] - scale) <= 1e-10 * scale, (T[b, s], scale)
+
+
 def test_error_scale_dominates_bound():
     p = gen.make_tiny("cnn", 0, B=2, splits=(1, 2), n_cuts=4)
     g = O.bound(p)

@@ -438,14 +438,31 @@ def make_cuts(rng, lu, relu_nodes, n_cuts, kmin, kmax, multi_layer=True,
                 add(k, -1, q, KIND_G, w); d[k] += w * (x0[q] + eps)
             else:
                 add(k, -1, q, KIND_G, -w); d[k] += w * (-x0[q] + eps)
-    keys = sorted(k for k, v in acc.items() if v != 0.0)
+    # Coefficients are rounded to fp32 values (the device stores fp32) and each
+    # cut's offset is widened by |rounded - exact| times the largest magnitude
+    # the variable takes (|x| <= max(|l|, |u|), 0 <= x_hat <= max(u, 0),
+    # 0 <= z <= 1, inputs within the box), so the rounded cut is still valid
+    # and both sides of every comparison see the same numbers.
+    pos = {nd: p for p, nd in enumerate(relu_nodes)}
+    keys = sorted(k for k, v in acc.items() if np.float32(v) != 0.0)
+    coef = np.array([acc[k] for k in keys], np.float64)
+    c32 = _f32(coef)
+    for (k, node, j, kind), c, c_r in zip(keys, coef, c32):
+        if c == c_r:
+            continue
+        if node < 0:
+            rng_ = max(abs(x0[j] - eps), abs(x0[j] + eps))
+        else:
+            l, u = lu[pos[node]][0][j], lu[pos[node]][1][j]
+            rng_ = max(abs(l), abs(u)) if kind == KIND_H else (max(u, 0.0) if kind == KIND_G else 1.0)
+        d[k] += abs(c_r - c) * rng_
     return Cuts(
         n_cuts,
         np.array([k[0] for k in keys], np.int32),
         np.array([k[1] for k in keys], np.int32),
         np.array([k[2] for k in keys], np.int32),
         np.array([k[3] for k in keys], np.int8),
-        np.array([acc[k] for k in keys], np.float64),
+        c32,
         d,
     )
 
