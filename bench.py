@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--mode", choices=["bf16", "fp32"], default="fp32",
+                    help="GEMM precision of the 20 ascent iterations (the certifying pass is fp32/fp64 either way)")
     ap.add_argument("--domains", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp32-mode comparison run")
@@ -55,7 +56,7 @@ def parse():
     if a.domains is None:
         a.domains = {"mlp784": 1024, "cnn": 2048, "resnet": 4096, "batch": 0}[a.workload]
     if a.cpu_domains is None:
-        a.cpu_domains = {"mlp784": 1024, "cnn": 256, "resnet": 16, "batch": 0}[a.workload]
+        a.cpu_domains = {"mlp784": 384, "cnn": 96, "resnet": 16, "batch": 0}[a.workload]
     return a
 
 
@@ -154,20 +155,31 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    def measure(mode, steps, warmup):
+        """Timed steps, then (unless --no-profile) the same steps again with
+        every library launch bracketed by HIP events on its stream (the
+        markers slow the run, so the timed value comes from the first
+        region); returns the time, the kernel classes, the final bounds and
+        the final parameters of the last step."""
+        dt = timed(mode, steps, warmup)
+        kp, dtp = None, None
+        if not args.no_profile:
+            B.profile_enable(True)
+            use_graph[0] = False     # per-kernel events need eager launches
+            dtp = timed(mode, steps, 0)
+            use_graph[0] = args.graph
+            B.profile_enable(False)
+            kp = B.profile_read()
+        torch.cuda.synchronize()
+        par = tuple(t.cpu().numpy().astype(np.float64) for t in (alpha, beta, gamma))
+        return dt, kp, dtp, bound.cpu().numpy().copy(), par
+
+    def kernel_table(kp):
+        return {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
+                for k, v in sorted(kp.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+
     mode = B.GCP_MODE_BF16 if args.mode == "bf16" else B.GCP_MODE_FP32
-    dt = timed(mode, args.steps, args.warmup)
-    kprof = None
-    if not args.no_profile:
-        # the same K steps again with every library launch bracketed by HIP
-        # events on its stream (the markers slow the run, so `value` comes
-        # from the uninstrumented region above)
-        B.profile_enable(True)
-        use_graph[0] = False     # per-kernel events need eager launches
-        dt_prof = timed(mode, args.steps, 0)
-        use_graph[0] = args.graph
-        B.profile_enable(False)
-        kprof = B.profile_read()
-    bound_main = bound.cpu().numpy().copy()
+    dt, kprof, dt_prof, bound_main, par_main = measure(mode, args.steps, args.warmup)
     value = args.domains * args.steps / dt
     out = {
         "metric": "BaB domains bounded/sec (fwd+adjoint iter) at fixed bound accuracy; % MFMA/HBM peak",
@@ -188,6 +200,8 @@ def main():
             "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
             "relaxation": "explicit pi (rho optimised)" if pi else "Lemma A.1 pi*",
+            "final_bound_mean": float(bound_main.mean()),
+            "verified_rows": int((bound_main >= 0).sum()),
         },
     }
     if pi:
@@ -195,32 +209,80 @@ def main():
         step(mode, explicit=False)
         torch.cuda.synchronize()
         closed = bound.cpu().numpy().copy()
-        out["config"]["final_bound_mean"] = float(bound_main.mean())
         out["config"]["lemma_pi_final_bound_mean"] = float(closed.mean())
         out["config"]["rows_tighter_than_lemma_pi"] = float(np.mean(bound_main > closed))
-        out["config"]["verified_rows"] = int((bound_main >= 0).sum())
         out["config"]["lemma_pi_verified_rows"] = int((closed >= 0).sum())
+    copy_bw = None
     if kprof:
         out["roofline"] = roofline(kprof, args.mode)
         out["roofline"]["instrumented_ms_per_step"] = dt_prof * 1000.0 / args.steps
-        if out["roofline"]["bound"] == "hbm":
-            out["roofline"]["achievable_copy_GBps"] = copy_bandwidth()
-        out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
-                                    for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+        copy_bw = copy_bandwidth()
+        out["roofline"]["achievable_copy_GBps"] = copy_bw
+        out["config"]["kernels"] = kernel_table(kprof)
+    if not pi:
+        out["oracle_error"] = oracle_error(prob, bound_main, par_main, 0)
     if not args.no_compare:
         other = B.GCP_MODE_FP32 if mode == B.GCP_MODE_BF16 else B.GCP_MODE_BF16
-        dt2 = timed(other, max(1, args.steps // 2), 1)
-        bound_other = bound.cpu().numpy().copy()
+        osteps = max(1, args.steps // 2)
+        dt2, kprof2, dt_prof2, bound_other, par_other = measure(other, osteps, 1)
         rel = np.abs(bound_main - bound_other) / np.maximum(np.abs(bound_other), 1e-30)
-        out["config"]["other_mode"] = {
+        om = {
             "dtype": "fp32" if other == B.GCP_MODE_FP32 else "bf16",
-            "value": args.domains * max(1, args.steps // 2) / dt2,
+            "value": args.domains * osteps / dt2,
             "final_bound_rel_diff_max": float(rel.max()),
             "final_bound_rel_diff_median": float(np.median(rel)),
+            "final_bound_mean": float(bound_other.mean()),
         }
+        if kprof2:
+            om["roofline"] = roofline(kprof2, om["dtype"])
+            om["roofline"]["instrumented_ms_per_step"] = dt_prof2 * 1000.0 / osteps
+            om["roofline"]["achievable_copy_GBps"] = copy_bw
+            om["kernels"] = kernel_table(kprof2)
+        if not pi:
+            om["oracle_error"] = oracle_error(prob, bound_other, par_other, 0)
+        out["config"]["other_mode"] = om
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline([prob], args.cpu_domains)
+        cb, g_oracle, rows = cpu_baseline([prob], args.cpu_domains)
+        out["cpu_baseline"] = cb
+        if not pi:
+            out["oracle_opt_gap"] = opt_gap(prob, bound_main, g_oracle, rows)
+            if not args.no_compare:
+                out["config"]["other_mode"]["oracle_opt_gap"] = opt_gap(prob, bound_other, g_oracle, rows)
     print(json.dumps(out))
+
+
+def oracle_error(prob, bound, par, seed, n=64):
+    """Error of the device's certified bounds against the FP64 oracle at the
+    device's final parameters, on a sample of rows (n random rows and the
+    last 8): max |d| / max(|g|, T) (T = sum of the magnitudes of every term
+    of the bound) and max |d| / |g|."""
+    import numpy as np
+
+    from oracle import gcp_oracle as O
+    M = bound.size
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([rng.choice(M - 8, size=min(n, M - 8), replace=False), np.arange(M - 8, M)]))
+    a, b, c = (x[rows] for x in par)
+    ref = O.bound(prob, a, b, c, rows=rows, flat=True)
+    T = O.error_scale(prob, a, b, c, rows=rows, flat=True)
+    d = np.abs(bound[rows] - ref)
+    return {"rows_sampled": int(rows.size), "max_rel_err_T": float((d / np.maximum(np.abs(ref), T)).max()),
+            "max_rel_err": float((d / np.abs(ref)).max()),
+            "sample": f"{rows.size} rows ({min(n, M - 8)} seeded random + the last 8), oracle bound (fp64) at the "
+                      "device's final alpha, beta, gamma"}
+
+
+def opt_gap(prob, bound, g_oracle, rows):
+    """Final certified bound of the device run against the oracle's own
+    20-iteration fp64 optimisation from the same start, on the rows the CPU
+    baseline optimised: (device - oracle) / max(|oracle|, T)."""
+    import numpy as np
+
+    from oracle import gcp_oracle as O
+    del O
+    rel = (bound[rows] - g_oracle) / np.maximum(np.abs(g_oracle), 1e-30)
+    return {"rows": int(rows.size), "max_abs_rel_gap": float(np.abs(rel).max()), "mean_rel_gap": float(rel.mean()),
+            "note": "(device final bound - oracle 20-step optimum) / |oracle|, same start and Adam settings"}
 
 
 def copy_bandwidth(mib=2048, reps=5):
@@ -244,21 +306,29 @@ def copy_bandwidth(mib=2048, reps=5):
 
 
 def roofline(kprof, dtype):
-    """Dominant kernel class (largest total time in the timed region): its
-    algorithmic bytes or FLOPs per launch over its average event-timed
-    duration, against the published MI355X peak for the bound its
-    arithmetic intensity implies."""
+    """Dominant kernel class (largest total time in the timed region) against
+    the published MI355X peak of the resource its arithmetic intensity binds
+    it to.  Algorithmic work per launch: its FLOPs (the GEMMs' 2 M N K) and
+    its optimiser-state bytes (alpha read in the bound pass, alpha and its
+    Adam moments read and written in the adjoint, multipliers with their
+    moments in their update, the split mask); intensity = FLOPs / those
+    bytes, compared with the ridge of the kernel's operand type.  `achieved`
+    = the bound resource's algorithmic amount per launch over the launch's
+    average event-timed duration.  The every-operand-once byte figure is
+    reported beside it."""
     name, k = max(kprof.items(), key=lambda kv: kv[1]["ms"])
     secs = k["ms"] * 1e-3
     mf_peak = PEAKS["bf16_TFLOPs"] if ".bf16" in name else PEAKS["fp32_TFLOPs"]
     ridge = mf_peak * 1e12 / (PEAKS["hbm_GBps"] * 1e9)
-    ai = k["flops"] / k["bytes"] if k["bytes"] else float("inf")
-    per_launch_bytes = k["bytes"] / k["launches"]
-    r = {"kernel": name, "launches": k["launches"], "avg_us": 1e6 * secs / k["launches"],
-         "algorithmic_bytes_per_launch": per_launch_bytes, "flops_per_launch": k["flops"] / k["launches"],
-         "arith_intensity": ai}
+    alg = k.get("alg_bytes", 0.0)
+    ai = k["flops"] / alg if alg else float("inf")
+    n = k["launches"]
+    r = {"kernel": name, "launches": n, "avg_us": 1e6 * secs / n,
+         "algorithmic_bytes_per_launch": alg / n, "flops_per_launch": k["flops"] / n,
+         "operand_bytes_per_launch": k["bytes"] / n, "operand_GBps": k["bytes"] / secs / 1e9,
+         "arith_intensity": ai, "ridge": ridge}
     if ai < ridge:
-        ach = k["bytes"] / secs / 1e9
+        ach = alg / secs / 1e9
         r.update(bound="hbm", achieved=ach, peak=PEAKS["hbm_GBps"], unit="GB/s", frac=ach / PEAKS["hbm_GBps"])
     else:
         ach = k["flops"] / secs / 1e12
@@ -297,26 +367,39 @@ def oracle_start(prob, rows):
     return a, b, c
 
 
-def cpu_baseline(probs, nd):
+def cpu_baseline(probs, nd, runs=3):
     """The FP64 oracle (as it stands) on the first `nd` domains of each given
-    problem, the same 20-iteration optimisation + final bound, host cores."""
+    problem, the same 20-iteration optimisation + final bound, on the host
+    cores this process may run on (torch and BLAS threads set to that
+    count); the median of `runs` runs.  Returns the record, the oracle's
+    final bounds of the first problem's rows, and those rows."""
     import numpy as np
     import torch
+    from threadpoolctl import threadpool_limits
 
     from oracle import gcp_oracle as O
-    t0 = time.perf_counter()
-    total = 0
-    for prob in probs:
-        k = min(nd, prob.B)
-        rows = np.arange(k * prob.S)
-        a, b, c = oracle_start(prob, rows)
-        O.optimize(prob, alpha=a, beta=b, gamma=c, rows=rows, flat=True)
-        total += k
-    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    times, g_first, rows_first = [], None, None
+    with threadpool_limits(limits=cores):
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            total = 0
+            for i, prob in enumerate(probs):
+                k = min(nd, prob.B)
+                rows = np.arange(k * prob.S)
+                a, b, c = oracle_start(prob, rows)
+                g, *_ = O.optimize(prob, alpha=a, beta=b, gamma=c, rows=rows, flat=True)
+                if i == 0:
+                    g_first, rows_first = g, rows
+                total += k
+            times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     what = probs[0].name if len(probs) == 1 else f"{len(probs)} instances"
-    return {"value": total / dt, "unit": "domains/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"first {nd} domains of {what} ({total} domains), same 20-iteration optimisation "
-                      f"+ final bound in float64, {dt:.1f} s"}
+    rec = {"value": total / dt, "unit": "domains/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {nd} domains of {what} ({total} domains), same 20-iteration optimisation + final "
+                     f"bound in float64; median of {runs} runs: {dt:.1f} s ({', '.join(f'{t:.1f}' for t in times)})"}
+    return rec, g_first, rows_first
 
 
 def bench_batch(args):
@@ -421,7 +504,7 @@ def bench_batch(args):
         out["config"]["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
                                     for k, v in sorted(kprof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(probs[:8], 16)
+        out["cpu_baseline"] = cpu_baseline(probs[:8], 16)[0]
     print(json.dumps(out))
 
 
