@@ -192,6 +192,29 @@ int gcp_bound(const gcp_net* net, const double* x0, double eps,
               int32_t mode, double* bound, uint8_t* verified,
               float* d_alpha, float* d_beta, float* d_gamma, void* stream);
 
+/* gcp_bound_noalloc: gcp_bound for callers that cannot allocate device
+ * memory -- code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, results and errors as
+ * gcp_bound, but the call allocates nothing: its workspace (Lambda, a_hat
+ * and d a_hat of every layer, row partial sums, the transposed gamma, cut
+ * gradient pieces) lies in a static device array of 64 MiB per device that
+ * the library holds until the process ends, tile shapes come from the tile
+ * cache (GCP_TILE_CACHE) or a fixed rule (no timing trials), and no profiler
+ * events are recorded.  Limit: a call whose workspace exceeds 64 MiB fails
+ * with GCP_ENOMEM (for the 784-256x6-10 MLP with 200 cuts, about 2500 rows
+ * with gradients, 6500 without); GCP_FLAG_VALIDATE (which waits for the
+ * device) is rejected with GCP_EINVAL.  Every call on one device shares that
+ * device's array, so calls that overlap on one device -- on different streams
+ * or from several threads -- race and must be serialised by the caller; the
+ * array holds the last call's intermediate values, which no later call reads
+ * before writing. */
+int gcp_bound_noalloc(const gcp_net* net, const double* x0, double eps,
+                      const double* C, int32_t S,
+                      const gcp_splits* splits, const gcp_cuts* cuts,
+                      const float* alpha, const float* beta, const float* gamma,
+                      int32_t mode, double* bound, uint8_t* verified,
+                      float* d_alpha, float* d_beta, float* d_gamma, void* stream);
+
 /* Optimiser settings (Appendix C.1 defaults: iters 20, lr_alpha 0.1,
  * lr_mult 0.02, decay 0.9, Adam 0.9/0.999/1e-8). */
 typedef struct {

@@ -102,6 +102,8 @@ def lib():
     L.gcp_splits_create.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(vp)]
     L.gcp_splits_destroy.argtypes = [vp]
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    L.gcp_bound_noalloc.argtypes = L.gcp_bound.argtypes
+    L.gcp_bound_noalloc.restype = C.c_int
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
     L.gcp_bound_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp,
@@ -306,6 +308,21 @@ def bound(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts],
                            *((_ptr(t) if t.numel() else None) for t in g) if g else (None, None, None),
                            _stream()))
     return out, ver, g
+
+
+def bound_noalloc(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma,
+                  out, verified=None, grads=None, mode: int = GCP_MODE_FP32):
+    """gcp_bound_noalloc (no device allocation inside the call; workspace in
+    the library's static array) into caller-allocated outputs: out [M] fp64,
+    verified [M] uint8 or None, grads = (d_alpha, d_beta, d_gamma) or None."""
+    S = Cspec.shape[0]
+    _check(lib().gcp_bound_noalloc(net.h, _ptr(x0), float(eps), _ptr(Cspec), S, splits.h, cuts.h if cuts else None,
+                                   _ptr(alpha) if alpha.numel() else None, _ptr(beta) if beta.numel() else None,
+                                   _ptr(gamma) if gamma.numel() else None, mode, _ptr(out),
+                                   _ptr(verified) if verified is not None else None,
+                                   *((_ptr(t) if t.numel() else None) for t in grads) if grads else (None, None, None),
+                                   _stream()))
+    return out
 
 
 def optimize(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma,

@@ -32,6 +32,14 @@ using namespace gcp;
 namespace {
 
 thread_local std::string g_err;
+// Set while this thread runs an entry point that must not allocate: no
+// autotuning trials (they need scratch outputs and a host wait) and no
+// profiler events.
+thread_local bool g_no_alloc = false;
+struct NoAllocScope {
+  NoAllocScope() { g_no_alloc = true; }
+  ~NoAllocScope() { g_no_alloc = false; }
+};
 
 struct Err {
   int code;
@@ -101,7 +109,7 @@ struct Bytes { double all, alg; };
 template <class F>
 hipError_t timed(hipStream_t st, const std::string& name, Bytes bytes, double flops, F f) {
   Profiler& P = prof();
-  if (!P.on) return f();
+  if (!P.on || g_no_alloc) return f();
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(st, &cs);
   if (cs != hipStreamCaptureStatusNone) return f();   // graph replays are not timed per kernel
@@ -130,27 +138,36 @@ std::string cls_name(const char* kind, int bf16, int sign, int cfg) {
 // launcher instantiates those epilogues for the small tiles only).
 int pi_cfg(int cfg) { return (cfg == 6 || cfg == 7) ? cfg : 5; }
 
-// Owned device allocation (zero-filled at allocation).
+// Owned device allocation (zero-filled at allocation), or a borrowed view of
+// memory owned elsewhere (never freed here).
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes;
+      p = o.p; bytes = o.bytes; owned = o.owned;
       o.p = nullptr; o.bytes = 0;
     }
     return *this;
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
+  }
+  void borrow(void* q, size_t n) {
+    release();
+    p = q;
+    bytes = n;
+    owned = false;
   }
   void alloc(size_t n) {
     release();
@@ -537,6 +554,7 @@ int choose_cfg(const char* fam, int kind, int bf16, int sign, int M, int N, int 
     if (it != TC.m.end()) return it->second;
   }
   int best = cands.fallback;
+  if (g_no_alloc) return best;   // no trials, nothing recorded
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(st, &cs);
   if (autotune_enabled() && cs == hipStreamCaptureStatusNone && cands.list.size() > 1) {
@@ -808,6 +826,8 @@ struct Recorder {
 struct Call {
   Recorder* rec = nullptr;
   gcp_net* net;
+  gcp_net::WS* ws = nullptr;   // the workspace of this call: the net's own, or a view of the static scratch
+  bool no_alloc = false;       // no device allocation, autotuning trial or profiler event in this call
   const gcp_cuts* cuts;
   const gcp_splits* splits;
   const double* x0;
@@ -896,20 +916,20 @@ double alg_adj(const Call& c, int p, bool adam) {
 }
 
 float* tune_store(Call& c) {
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   size_t need = 0;
   for (auto& n : c.net->nodes) need = std::max(need, (size_t)c.M * n.ld * 4);
   if (ws.tune_store.bytes < need) ws.tune_store.alloc(need);
   return ws.tune_store.as<float>();
 }
 float* tune_alpha(Call& c) {
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   size_t need = (size_t)c.M * std::max(c.rp.n_I, 1) * 4;
   if (ws.tune_alpha.bytes < need) ws.tune_alpha.alloc(need);
   return ws.tune_alpha.as<float>();
 }
 float* tune_beta(Call& c) {
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   size_t need = (size_t)c.M * std::max(c.rp.K, 1) * 4;
   if (ws.tune_beta.bytes < need) ws.tune_beta.alloc(need);
   return ws.tune_beta.as<float>();
@@ -959,7 +979,7 @@ struct BoundPass {
   int esz() const { return bf16 ? 2 : 4; }
 
   BoundEpiArgs bound_args(int p, bool has_acc) {
-    auto& ws = c.net->ws;
+    auto& ws = *c.ws;
     BoundEpiArgs a{};
     a.nd = c.net->nodes[p].dev();
     a.cc = cut_col(c, p);
@@ -976,7 +996,7 @@ struct BoundPass {
   void run() {
     gcp_net* net = c.net;
     const int nn = (int)net->nodes.size();
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     pushes_left.assign(nn + 1, 0);
     for (int i = 0; i < nn; ++i) pushes_left[i] = (int)net->nodes[i].consumers.size();
     pushes_left[nn] = (int)net->in_consumers.size();
@@ -1044,7 +1064,7 @@ struct BoundPass {
   // Lambda^(dst) pushed through edge E into target src.
   void push(int eid) {
     gcp_net* net = c.net;
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     const EdgeH& E = *net->edges[eid];
     const int nn = (int)net->nodes.size();
     const int p = E.src;
@@ -1231,7 +1251,7 @@ struct AdjPass {
   // add vectors: bias (+ A x0 for edges from the input); once per call
   void prepare() {
     gcp_net* net = c.net;
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     for (int i = 0; i < net->out; ++i) {
       const NodeH& n = net->nodes[i];
       bool seeded = false;
@@ -1257,7 +1277,7 @@ struct AdjPass {
   // (same operands, same tile configuration) with only the a_hat epilogue
   void recompute_ahat(int i) {
     gcp_net* net = c.net;
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     if (c.rec) fail(GCP_EUNSUPPORTED, "a_hat recomputation in grouped launches");
     const NodeH& n = net->nodes[i];
     const EdgeH& E = *net->edges[n.consumers[0]];
@@ -1298,7 +1318,7 @@ struct AdjPass {
 
   void node(int i) {
     gcp_net* net = c.net;
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     const NodeH& n = net->nodes[i];
     if (!c.recompute.empty() && c.recompute[i]) recompute_ahat(i);
     std::vector<int> order;   // identity edges first: they can only accumulate
@@ -1413,7 +1433,7 @@ struct AdjPass {
 
   AdjEpiArgs epi(int i, float* acc_in, float scale) {
     gcp_net* net = c.net;
-    auto& ws = net->ws;
+    auto& ws = *c.ws;
     const NodeH& n = net->nodes[i];
     AdjEpiArgs a{};
     a.nd = n.dev();
@@ -1460,8 +1480,12 @@ void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const dou
   c.nnz = c.cuts ? c.cuts->nnz_e : 0;
   c.st = (hipStream_t)stream;
   c.N = N;
-  ensure_ws(c);
-  c.rp = RowParams{c.M, S, round_up(c.M, 16), alpha, net->n_I, beta, splits->K, net->ws.gammaT.as<float>(), N,
+  if (!c.no_alloc) {
+    ensure_ws(c);
+    c.ws = &net->ws;
+  }
+  c.rp = RowParams{c.M, S, round_up(c.M, 16), alpha, net->n_I, beta, splits->K,
+                   c.ws ? c.ws->gammaT.as<float>() : nullptr, N,
                    splits->K > 0 ? splits->mask.as<int8_t>() : nullptr, 1.0 / S,
                    nullptr /* rho: set by the explicit-pi entry points */};
 }
@@ -1481,7 +1505,7 @@ bool ahat_recomputable(const gcp_net* net, int i) {
 }
 void plan_ahat(Call& c, int32_t mode) {
   gcp_net* net = c.net;
-  auto& ws = net->ws;
+  auto& ws = *c.ws;
   const int nn = (int)net->nodes.size();
   size_t stored = 0;
   for (int i = 0; i < nn; ++i)
@@ -1512,7 +1536,7 @@ void plan_ahat(Call& c, int32_t mode) {
 void size_partials(Call& c, int bf16, bool keep, bool contrib) {
   BoundPass dry(c, bf16, keep, contrib, true);
   dry.run();
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   const size_t need = (size_t)round_up(ws.M, 16) * std::max(dry.slot, 1) * 8;
   if (need > ws.partial.bytes) {
     ws.partial.alloc(need);
@@ -1522,7 +1546,7 @@ void size_partials(Call& c, int bf16, bool keep, bool contrib) {
 }
 
 void validate_params(Call& c, const float* alpha, const float* beta, const float* gamma) {
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   hip_check(hipMemsetAsync(ws.flags.p, 0, 16, c.st), "hipMemsetAsync");
   int* f = ws.flags.as<int>();
   hip_check(launch_validate(alpha, (int64_t)c.M * c.rp.n_I, 0.f, 1.f, f, c.st), "validate");
@@ -1540,7 +1564,7 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
   size_partials(c, bf16, keep_ahat, contrib);
   BoundPass bp(c, bf16, keep_ahat, contrib, false);
   bp.run();
-  auto& ws = c.net->ws;
+  auto& ws = *c.ws;
   const double rb = (double)c.M * (ws.n_slots * 8.0 + c.rp.N * 4.0 + 8.0 + (verified ? 1 : 0));
   hip_check(timed(c.st, "reduce_rows", Bytes{rb, 0.0}, 0.0, [&] {
               return launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
@@ -1550,13 +1574,88 @@ void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, 
             "reduce");
 }
 
-// gcp_bound and gcp_bound_pi (rho non-null: explicit pi)
+// The workspace of a bound call (with gradients when `grads`) laid out in the
+// static scratch region instead of the net's own buffers: every buffer the
+// call reads it also writes first, so nothing needs clearing; a_hat of every
+// layer is stored (no recomputation).  Fails with ENOMEM when the call needs
+// more than the region holds.
+void carve_static(Call& c, gcp_net::WS& sws, int bf16, bool grads) {
+  gcp_net* net = c.net;
+  const int nn = (int)net->nodes.size();
+  for (int i = 0; i < nn; ++i) {
+    sws.lam.push_back(std::make_unique<DBuf>());
+    sws.ahat.push_back(std::make_unique<DBuf>());
+    sws.dahat.push_back(std::make_unique<DBuf>());
+    sws.acc.push_back(std::make_unique<DBuf>());
+    sws.addv.push_back(std::make_unique<DBuf>());
+  }
+  sws.chat_off.assign(nn, -1);
+  size_t chat_floats = 0;
+  if (!net->out_general)
+    for (int eid : net->nodes[net->out].in_edges) {
+      const int p = net->edges[eid]->src;
+      sws.chat_off[p] = (int)chat_floats;
+      chat_floats += (size_t)c.S * net->nodes[p].ld;
+    }
+  c.ws = &sws;
+  c.recompute.assign(nn, 0);
+  BoundPass dry(c, bf16, grads, grads && c.nnz > 0, true);
+  dry.run();
+  void* base = nullptr;
+  size_t cap = 0;
+  hip_check(scratch_region(&base, &cap), "static workspace");
+  const size_t M = c.M, mp = c.rp.mp;
+  size_t off = 0;
+  auto take = [&](DBuf& b, size_t n) {
+    off = (off + 255) / 256 * 256;
+    b.borrow(n && off + n <= cap ? (char*)base + off : nullptr, n);
+    off += n;
+  };
+  for (int i = 0; i < nn; ++i) {
+    const NodeH& n = net->nodes[i];
+    const size_t elems = (n.relu || (i == net->out && net->out_general)) ? M * n.ld : 0;
+    bool ident = false;
+    for (int eid : n.in_edges) ident |= net->edges[eid]->kind == GCP_EDGE_IDENTITY;
+    for (int eid : n.consumers) ident |= net->edges[eid]->kind == GCP_EDGE_IDENTITY;
+    const bool multi = n.relu && (n.consumers.size() > 1 || n.in_edges.size() > 1 || ident);
+    take(*sws.lam[i], elems * 4);
+    take(*sws.acc[i], multi ? elems * 4 : 0);
+    if (grads) {
+      take(*sws.ahat[i], n.relu ? elems * 4 : 0);
+      take(*sws.dahat[i], elems * 4);
+      take(*sws.addv[i], n.relu ? (size_t)n.ld * 4 : 0);
+    }
+  }
+  if (grads) take(sws.sign, M * net->in_ld);
+  if (grads && c.nnz) take(sws.contrib, mp * c.nnz * 4);
+  if (c.N) take(sws.gammaT, mp * c.N * 4);
+  take(sws.chat, std::max<size_t>(chat_floats, 1) * 4);
+  take(sws.cb, (size_t)c.S * 8);
+  take(sws.consts, 16);
+  take(sws.step, 16);
+  take(sws.flags, 16);
+  take(sws.partial, mp * std::max(dry.slot, 1) * 8);
+  if (off > cap) {
+    char m[200];
+    std::snprintf(m, sizeof m, "the call needs %.1f MiB of workspace; the static workspace holds %.0f MiB",
+                  off / 1048576.0, cap / 1048576.0);
+    fail(GCP_ENOMEM, m);
+  }
+  sws.M = c.M; sws.S = c.S; sws.nnz = c.nnz; sws.N = c.N;
+  sws.n_slots = 0;
+  c.rp.gammaT = sws.gammaT.as<float>();
+}
+
+// gcp_bound and gcp_bound_pi (rho non-null: explicit pi); no_alloc: the
+// workspace is the static scratch region (gcp_bound_noalloc)
 void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
                 const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
                 const float* gamma, const float* rho, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
-                float* d_beta, float* d_gamma, float* d_rho, void* stream) {
+                float* d_beta, float* d_gamma, float* d_rho, void* stream, bool no_alloc = false) {
   gcp_net* net = const_cast<gcp_net*>(net_c);
   Call c{};
+  c.no_alloc = no_alloc;
+  gcp_net::WS sws;
   prepare_call(c, net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, stream);
   c.rp.rho = rho;
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
@@ -1568,9 +1667,13 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
         (rho && net->n_I > 0 && !d_rho))
       fail(GCP_EINVAL, "pass all gradient outputs or none");
   }
+  if (no_alloc) {
+    if (mode & GCP_FLAG_VALIDATE) fail(GCP_EINVAL, "GCP_FLAG_VALIDATE waits for the device; not available here");
+    carve_static(c, sws, bf16, grads);
+  }
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
-  if (c.N > 0) hip_check(launch_transpose(gamma, c.M, c.N, c.N, net->ws.gammaT.as<float>(), c.rp.mp, c.st), "transpose");
-  if (grads) plan_ahat(c, mode);
+  if (c.N > 0) hip_check(launch_transpose(gamma, c.M, c.N, c.N, c.ws->gammaT.as<float>(), c.rp.mp, c.st), "transpose");
+  if (grads && !no_alloc) plan_ahat(c, mode);
   bound_pass(c, bf16, grads, grads && c.nnz > 0, bound, verified);
   if (grads) {
     if (splits->K > 0) hip_check(launch_fill_f32(d_beta, (int64_t)c.M * splits->K, 0.f, c.st), "fill");
@@ -1582,7 +1685,7 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
       hip_check(timed(c.st, "gamma_grad", Bytes{(double)c.M * (c.nnz * 4.0 + c.rp.N * 4.0), (double)c.M * c.rp.N * 8.0},
                       0.0, [&] {
                   return launch_gamma_update(c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(),
-                                             net->ws.contrib.as<float>(), c.cuts->d.as<double>(), nullptr, d_gamma,
+                                             c.ws->contrib.as<float>(), c.cuts->d.as<double>(), nullptr, d_gamma,
                                              nullptr, nullptr, AdamArgs{0, 0.f, 0.f, 0.f, nullptr}, c.st);
                 }),
                 "gamma gradient");
@@ -1606,7 +1709,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   if (!bound) fail(GCP_EINVAL, "null bound output");
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
   plan_ahat(c, mode);
-  auto& ws = net->ws;
+  auto& ws = *c.ws;
   const size_t M = c.M, nI = c.rp.n_I, K = c.rp.K, N = c.rp.N;
   float* ma = adam_state;
   float* va = ma + M * nI;
@@ -1718,6 +1821,19 @@ extern "C" int gcp_bound(const gcp_net* net, const double* x0, double eps, const
   GCP_CATCH
 }
 
+extern "C" int gcp_bound_noalloc(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
+                                 const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
+                                 const float* gamma, int32_t mode, double* bound, uint8_t* verified, float* d_alpha,
+                                 float* d_beta, float* d_gamma, void* stream) {
+  GCP_TRY
+  NoAllocScope scope;
+  bound_impl(net, x0, eps, C, S, splits, cuts, alpha, beta, gamma, nullptr, mode, bound, verified, d_alpha, d_beta,
+             d_gamma, nullptr, stream, true);
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
 extern "C" int gcp_bound_pi(const gcp_net* net, const double* x0, double eps, const double* C, int32_t S,
                             const gcp_splits* splits, const gcp_cuts* cuts, const float* alpha, const float* beta,
                             const float* gamma, const float* rho, int32_t mode, double* bound, uint8_t* verified,
@@ -1796,7 +1912,7 @@ namespace {
 // constants of the output layer for one call (c-hat = C W, C b_out)
 void launch_constants(Call& c) {
   gcp_net* net = c.net;
-  auto& ws = net->ws;
+  auto& ws = *c.ws;
   if (net->out_general) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
   const NodeH& on = net->nodes[net->out];
   hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");

@@ -225,4 +225,9 @@ hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* f
                            hipStream_t st);
 hipError_t launch_fill_bf16_from_f32(const float* src, bf16* dst, int64_t n, hipStream_t st);
 
+// Static workspace (scratch.hip): the device address and size of the calling
+// thread's current device's copy, looked up on its first use on that device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_region(void** ptr, size_t* bytes);
+
 }  // namespace gcp
