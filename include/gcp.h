@@ -234,7 +234,10 @@ typedef struct {
  * (caller-owned so optimisation can resume; zero for a fresh start).
  * Finally the bound at the final parameters is recomputed
  * with fp32 GEMMs and fp64 reductions (the certifying pass) into
- * bound/verified. */
+ * bound/verified.  With the environment variable GCP_FUSED=1, a network whose
+ * ReLU layers form a chain of dense layers runs all iterations in one launch
+ * instead of one launch per layer (the same results bit for bit; slower on
+ * MI355X at the sizes measured, kept for study). */
 int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  const double* C, int32_t S,
                  const gcp_splits* splits, const gcp_cuts* cuts,

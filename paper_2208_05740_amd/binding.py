@@ -477,7 +477,8 @@ def profile_read():
         rc = lib().gcp_profile_read(i, buf, 256, C.byref(n), C.byref(ms), C.byref(by), C.byref(al), C.byref(fl))
         if rc != 0:
             break
-        out[buf.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value, alg_bytes=al.value,
-                                       flops=fl.value)
+        if n.value:   # classes registered by earlier runs but not launched since the reset are left out
+            out[buf.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value, alg_bytes=al.value,
+                                           flops=fl.value)
         i += 1
     return out

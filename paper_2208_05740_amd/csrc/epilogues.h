@@ -55,6 +55,40 @@ template <typename T> __device__ inline float from_t(T x);
 template <> __device__ inline float from_t<float>(float x) { return x; }
 template <> __device__ inline float from_t<bf16>(bf16 x) { return (float)x; }
 
+// Keep the first `keep` elements of a 16-byte operand vector, zero the rest:
+// columns >= K of a row are padding whose bytes may hold data of the other
+// operand precision (buffers are shared by the bf16 and fp32 passes), so the
+// K tail is masked explicitly instead of relying on zero padding.
+template <typename T>
+__device__ inline uint4 mask_tail(uint4 v, int keep) {
+  T e[16 / sizeof(T)];
+  *(uint4*)e = v;
+#pragma unroll
+  for (int q = 0; q < (int)(16 / sizeof(T)); ++q)
+    if (q >= keep) e[q] = to_t<T>(0.f);
+  return *(const uint4*)e;
+}
+
+// ------------------------------------------------------------------ output sinks
+// Where an epilogue puts the per-row activation it produces (Lambda in the
+// bound pass, d a_hat in the adjoint, sign(v) in the concretisation): the
+// [M][ld] global buffer of a per-layer launch, or a row-major buffer in the
+// workgroup's dynamic LDS (rows row0 .. of the tile, pitch ld elements,
+// starting `off` bytes in) in the fused chain kernel.
+extern __shared__ __attribute__((aligned(16))) unsigned char gcp_smem[];
+template <typename T>
+struct GlobalSink {
+  T* base;
+  __device__ inline void operator()(size_t ij, int, int, T v) const { base[ij] = v; }
+};
+template <typename T>
+struct LdsSink {
+  int off, row0, ld;
+  __device__ inline void operator()(size_t, int row, int j, T v) const {
+    *(T*)(gcp_smem + off + ((row - row0) * ld + j) * (int)sizeof(T)) = v;
+  }
+};
+
 // ------------------------------------------------------------------ helpers
 __device__ inline double wave_sum16(double v) {
   // sum over the 16 lanes that share lane/16 (lane bits 0..3)
@@ -278,6 +312,12 @@ struct BoundEpi {
   template <int R, int TN, bool PE>
   __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
                                const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+    apply_to<R, TN, PE>(f, lc, val, rs, M, N, GlobalSink<T>{(T*)a.lam_out});
+  }
+  // Lambda goes to `lam`; a_hat (if kept) to a.ahat_out
+  template <int R, int TN, bool PE, class Sink>
+  __device__ inline void apply_to(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                                  const float (&val)[TN][R], double (&rs)[R], int M, int N, const Sink& lam_sink) const {
     const NodeDev& nd = a.nd;
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
@@ -307,7 +347,7 @@ struct BoundEpi {
         }
         if (f.ev[k][q]) {
           const size_t ij = (size_t)f.rc[q] * nd.ld + lc.j[k][qc];
-          ((T*)a.lam_out)[ij] = to_t<T>(lam);
+          lam_sink(ij, f.rc[q], lc.j[k][qc], to_t<T>(lam));
           if (a.ahat_out) ((T*)a.ahat_out)[ij] = to_t<T>(ah);
           rs[q] += (double)lam * (double)f.bj[k][qc] + (double)konst;
         }
@@ -403,6 +443,12 @@ struct ConcEpi {
   template <int R, int TN, bool PE>
   __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
                                const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+    apply_to<R, TN, PE>(f, lc, val, rs, M, N, GlobalSink<int8_t>{a.sign_out});
+  }
+  // sign(v) goes to `sign_sink` (when a.sign_out is set)
+  template <int R, int TN, bool PE, class Sink>
+  __device__ inline void apply_to(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                                  const float (&val)[TN][R], double (&rs)[R], int M, int N, const Sink& sign_sink) const {
 #pragma unroll
     for (int k = 0; k < TN; ++k) {
 #pragma unroll
@@ -412,7 +458,7 @@ struct ConcEpi {
         const double xj = f.xj[k][GCP_QC(q)];
         const float v = val[k][q] + f.sG[k][q];
         const float sg = (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f);
-        if (a.sign_out) a.sign_out[(size_t)f.rc[q] * a.ld + j] = (int8_t)sg;
+        if (a.sign_out) sign_sink((size_t)f.rc[q] * a.ld + j, f.rc[q], j, (int8_t)sg);
         if (a.contrib && a.cc.rng) {
           const float dv = (float)(xj - a.eps * (double)sg);
           const int2 rg = a.cc.rng[j];
@@ -518,6 +564,12 @@ struct AdjEpi {
   template <int R, int TN, bool PE>
   __device__ inline void apply(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
                                const float (&val)[TN][R], double (&rs)[R], int M, int N) const {
+    apply_to<R, TN, PE>(f, lc, val, rs, M, N, GlobalSink<T>{(T*)a.dahat_out});
+  }
+  // d a_hat goes to `da_sink` (when a.dahat_out is set)
+  template <int R, int TN, bool PE, class Sink>
+  __device__ inline void apply_to(const Frag<R, TN, PE>& f, const LaneCoords<R, TN, PE>& lc,
+                                  const float (&val)[TN][R], double (&rs)[R], int M, int N, const Sink& da_sink) const {
     const NodeDev& nd = a.nd;
     const RowParams& rp = a.rp;
     float lr_a = 0.f, lr_m = 0.f, ibc1 = 1.f, ibc2 = 1.f;
@@ -571,7 +623,7 @@ struct AdjEpi {
         if (!f.ev[k][q]) continue;
         const int j = lc.j[k][qc];
         const size_t ij = (size_t)f.rc[q] * nd.ld + j;
-        if (a.dahat_out) ((T*)a.dahat_out)[ij] = to_t<T>(dA);
+        if (a.dahat_out) da_sink(ij, f.rc[q], j, to_t<T>(dA));
         if (!kVecContrib && a.contrib && a.cc.rng) {
           const int2 rg = a.cc.rng[j];
           for (int e = rg.x; e < rg.y; ++e) {
@@ -675,5 +727,43 @@ struct StoreEpi {
         if (f.ev[k][q]) a.out[(size_t)f.rc[q] * a.ld + lc.j[k][GCP_QC(q)]] = a.scale * val[k][q] + f.pre[k][q];
   }
 };
+
+// ------------------------------------------------------------------ multipliers
+// One (cut k, row r) of the gamma update.  The Adam state is read before the
+// sum and the cut's entry pieces four at a time, so the loads are in flight
+// together; the pieces are still added one by one in entry order.
+__device__ inline void gamma_one(int k, int r, int M, int mp, int N, const int32_t* row_ptr, const float* contrib,
+                                 const double* d, float* gammaT, float* d_gamma, float* m, float* v,
+                                 const AdamArgs& adam) {
+  const int e0 = row_ptr[k], e1 = row_ptr[k + 1];
+  const size_t im = (size_t)k * M + r;
+  float m0 = 0.f, v0 = 0.f, x0 = 0.f;
+  float* gp = adam.enabled ? gammaT + (size_t)k * mp + r : nullptr;
+  if (adam.enabled) {
+    m0 = m[im];
+    v0 = v[im];
+    x0 = *gp;
+  }
+  double g = -d[k];
+  for (int e = e0; e < e1; e += 4) {
+    float c[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) c[t] = e + t < e1 ? contrib[(size_t)(e + t) * mp + r] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (e + t < e1) g += (double)c[t];
+  }
+  if (adam.enabled) {
+    const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
+    const float gf = (float)g;
+    const float mm = adam.b1 * m0 + (1.f - adam.b1) * gf;
+    const float vv = adam.b2 * v0 + (1.f - adam.b2) * gf * gf;
+    m[im] = mm;
+    v[im] = vv;
+    *gp = fmaxf(x0 + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
+  } else {
+    d_gamma[(size_t)r * N + k] = (float)g;
+  }
+}
 
 }  // namespace gcp

@@ -239,6 +239,8 @@ struct gcp_net {
     std::vector<std::unique_ptr<DBuf>> lam, ahat, dahat, acc, addv;
     DBuf sign, partial, contrib, chat, cb, consts, step, flags, acc_in, gammaT;
     DBuf adam_tab;   // Adam constants of every iteration of a gcp_optimize call, [iters][4]
+    DBuf chain_tab;  // per-node tables of the fused chain launch (ChainNode [L])
+    std::vector<ChainNode> chain_host;
     DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
     DBuf ahat_tmp;      // a_hat of the node being differentiated, when recomputed
     // captured Adam iteration of gcp_optimize (valid for one argument set)
@@ -1692,6 +1694,122 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
   }
 }
 
+// ---------------------------------------------------------------- fused dense chains
+// Whether the whole optimisation can run in the fused chain kernel: ReLU
+// nodes 0..L-1 each fed by one dense edge from the node before (node 0 by
+// the input), each feeding only the next, the output fed by node L-1 through
+// the c-hat form, Lemma A.1's pi*, a_hat stored, and the workgroup's LDS
+// (two activation buffers of kChainRows rows plus the signs of v) within
+// 160 KB.  Opt-in (GCP_FUSED=1): on MI355X it measured slower than the
+// per-layer launches (one workgroup per 16 rows walks the layers in order, so
+// far fewer tiles are in flight per layer, and the weights it streams are
+// spread over all layers at once instead of one layer's at a time).
+struct ChainPlan {
+  bool ok = false;
+  int P = 0, sign_ld = 0;
+  size_t lds = 0;
+};
+ChainPlan chain_plan(const Call& c, int bf16) {
+  ChainPlan pl;
+  const char* e = std::getenv("GCP_FUSED");
+  if (!e || e[0] != '1') return pl;
+  const gcp_net* net = c.net;
+  if (net->out_general || c.rp.rho || c.rec || c.M <= 0) return pl;
+  const int out = net->out;
+  if (out < 1 || net->in_consumers.size() != 1) return pl;
+  int ldmax = 0;
+  for (int i = 0; i <= out; ++i) {
+    const NodeH& n = net->nodes[i];
+    if (n.in_edges.size() != 1) return pl;
+    const EdgeH& E = *net->edges[n.in_edges[0]];
+    if (E.kind != GCP_EDGE_DENSE || E.src != i - 1) return pl;
+    if (i < out && (n.consumers.size() != 1 || !n.relu)) return pl;
+    if (i < out) ldmax = std::max(ldmax, n.ld);
+  }
+  if (!c.recompute.empty())
+    for (uint8_t rc : c.recompute)
+      if (rc) return pl;
+  const int esz = bf16 ? 2 : 4;
+  pl.P = ldmax + 16 / esz;                               // row pitch: an odd number of 16-byte units apart
+  pl.sign_ld = (net->in_ld + 255) / 256 * 256 + 16;      // signs: rows 16 bytes apart modulo 256
+  const size_t buf = (size_t)kChainRows * pl.P * esz;
+  pl.lds = 2 * buf + (size_t)kChainRows * pl.sign_ld;
+  pl.ok = pl.lds <= 160 * 1024;
+  return pl;
+}
+
+// All `iters` Adam iterations of an eligible chain in one launch.
+void run_chain(Call& c, int bf16, const ChainPlan& pl, float* alpha, float* beta, float* ma, float* va, float* mb,
+               float* vb, float* mg, float* vg, const gcp_opt* opt) {
+  gcp_net* net = c.net;
+  auto& ws = *c.ws;
+  const int L = net->out;
+  if (!c.consts_done) {
+    const NodeH& on = net->nodes[net->out];
+    hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");
+    const EdgeH& E = *net->edges[on.in_edges[0]];
+    hip_check(launch_chat(c.C, c.S, on.size, E.Wraw.as<float>(), E.d_src, 0, ws.chat.as<float>() + ws.chat_off[E.src],
+                          net->nodes[E.src].ld, c.st),
+              "c-hat");
+    c.consts_done = true;
+  }
+  ws.chain_host.resize(L);
+  double flops = 0.0, elems = 0.0;
+  for (int i = 0; i < L; ++i) {
+    const NodeH& n = net->nodes[i];
+    const EdgeH& E = *net->edges[n.in_edges[0]];
+    ChainNode& cn = ws.chain_host[i];
+    cn.nd = n.dev();
+    cn.cc = cut_col(c, i);
+    cn.WT = wt_bound(E, bf16);
+    cn.ldWT = n.ld;
+    cn.W = w_adj(E, bf16);
+    cn.ldW = node_ld_of(net, i - 1);
+    cn.addv = ws.addv[i]->as<float>();
+    cn.ahat = ws.ahat[i]->p;
+    cn.dahat = ws.dahat[i]->p;
+    flops += 4.0 * c.M * E.d_src * E.d_dst;   // the bound-pass and adjoint GEMM of the in-edge
+    elems += n.size;
+  }
+  ws.chain_tab.ensure(sizeof(ChainNode) * L);
+  hip_check(hipMemcpyAsync(ws.chain_tab.p, ws.chain_host.data(), sizeof(ChainNode) * L, hipMemcpyHostToDevice, c.st),
+            "hipMemcpyAsync");
+  ChainArgs a{};
+  a.L = L;
+  a.nodes = ws.chain_tab.as<ChainNode>();
+  a.in_size = net->in_size;
+  a.in_ld = net->in_ld;
+  a.x0 = c.x0;
+  a.eps = c.eps;
+  a.cc_in = cut_col(c, -1);
+  a.sign = ws.sign.as<int8_t>();
+  a.chat = ws.chat.as<float>() + ws.chat_off[L - 1];
+  a.chat_ld = net->nodes[L - 1].ld;
+  a.rp = c.rp;
+  a.gammaT = ws.gammaT.as<float>();
+  a.contrib = ws.contrib.as<float>();
+  a.nnz_e = c.nnz;
+  a.row_ptr = c.cuts ? c.cuts->row_ptr.as<int32_t>() : nullptr;
+  a.cut_d = c.cuts ? c.cuts->d.as<double>() : nullptr;
+  a.m_alpha = ma; a.v_alpha = va; a.m_beta = mb; a.v_beta = vb; a.m_gamma = mg; a.v_gamma = vg;
+  a.alpha_rw = alpha; a.beta_rw = beta;
+  a.adam = AdamArgs{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.adam_tab.as<float>()};
+  a.iters = opt->iters;
+  a.P = pl.P;
+  const int esz = bf16 ? 2 : 4;
+  a.off_buf0 = 0;
+  a.off_buf1 = kChainRows * pl.P * esz;
+  a.off_sign = 2 * kChainRows * pl.P * esz;
+  a.sign_ld = pl.sign_ld;
+  const double M = c.M, it = opt->iters, nI = c.rp.n_I, N = c.rp.N, K = c.rp.K, nnz = c.nnz;
+  const double alg = it * (28.0 * M * (nI + N + K) + 2.0 * c.B * nI);
+  const double all = it * (M * (nI * 28.0 + elems * 2.0 * esz + nnz * 12.0 + N * 24.0 + K * 28.0) + 2.0 * c.B * nI);
+  const int tiles = (c.M + kChainRows - 1) / kChainRows;
+  hip_check(timed(c.st, std::string("chain.") + (bf16 ? "bf16" : "fp32"), Bytes{all, alg}, it * flops,
+                  [&] { return launch_chain_opt(bf16, a, tiles, pl.lds, c.st); }),
+            "fused chain");
+}
+
 // gcp_optimize and gcp_optimize_pi (rho non-null: explicit pi, its Adam
 // moments after gamma's in adam_state)
 void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
@@ -1709,6 +1827,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   if (!bound) fail(GCP_EINVAL, "null bound output");
   if (mode & GCP_FLAG_VALIDATE) validate_params(c, alpha, beta, gamma);
   plan_ahat(c, mode);
+  const ChainPlan chain = chain_plan(c, bf16);
   auto& ws = *c.ws;
   const size_t M = c.M, nI = c.rp.n_I, K = c.rp.K, N = c.rp.N;
   float* ma = adam_state;
@@ -1753,12 +1872,16 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
                 "gamma update");
   };
   int done = 0;
-  if (opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
+  if (chain.ok && opt->iters > 0) {   // every iteration in one launch
+    run_chain(c, bf16, chain, alpha, beta, ma, va, mb, vb, mg, vg, opt);
+    done = opt->iters;
+  }
+  if (done == 0 && opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
     iteration(c, 0);
     done = 1;
     c.consts_done = !net->out_general || !bf16;
   }
-  if (opt->use_graph && opt->iters > 1) {
+  if (opt->use_graph && opt->iters > 1 && done < opt->iters) {
     std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits->id, (uintptr_t)(c.cuts ? c.cuts->id : 0),
                                   (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)rho,
                                   (uintptr_t)adam_state,
@@ -2246,7 +2369,7 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     g_batch = plan.release();
   }
   BatchPlan& plan = *g_batch;
-  if (opt->use_graph && opt->iters - done > 1) {
+  if (opt->use_graph && opt->iters > 1 && done < opt->iters) {
     if (!plan.gstream) hip_check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "hipStreamCreate");
     hipEvent_t ev;
     hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");

@@ -225,6 +225,44 @@ hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* f
                            hipStream_t st);
 hipError_t launch_fill_bf16_from_f32(const float* src, bf16* dst, int64_t n, hipStream_t st);
 
+// ---------------------------------------------------------------- fused dense chains
+// A network whose ReLU nodes 0..L-1 form a chain of dense layers (node i's
+// only input is node i-1, node 0's the network input; the output's only
+// input is node L-1) runs its whole projected-Adam optimisation in one
+// launch (chain_kernels.hip): one workgroup per kChainRows rows performs
+// every iteration's bound pass, concretisation, adjoint and multiplier
+// update for its rows, holding Lambda / d a_hat in LDS between layers.
+constexpr int kChainRows = 16;
+struct ChainNode {            // ReLU node i with its in-edge from node i-1 (the input for i = 0)
+  NodeDev nd; CutCol cc;
+  const void* WT; int ldWT;   // in-edge, bound direction Bt [n_{i-1}][ldWT] (operand type)
+  const void* W; int ldW;     // in-edge, adjoint direction Bt [n_i][ldW]
+  const float* addv;          // added to d Lambda^(i): b_i (node 0: b_0 + W_0 x0)
+  void* ahat;                 // [M][ld_i] a_hat^(i), operand type (bound pass -> adjoint)
+  void* dahat;                // [M][ld_i] (the per-layer path's buffer; unused by the fused kernel)
+};
+struct ChainArgs {
+  int L;                      // ReLU nodes
+  const ChainNode* nodes;     // device [L]
+  int in_size, in_ld;
+  const double* x0; double eps;
+  CutCol cc_in;               // input-variable cuts
+  int8_t* sign;               // [M][in_ld] (the per-layer path's buffer; unused by the fused kernel)
+  const float* chat; int chat_ld;     // [S][chat_ld]: C W_out per spec row (fp32)
+  RowParams rp;
+  float* gammaT;              // writable view of rp.gammaT
+  float* contrib; int nnz_e;  // [nnz_e][mp] gamma-gradient pieces
+  const int32_t* row_ptr; const double* cut_d;
+  float *m_alpha, *v_alpha, *m_beta, *v_beta, *m_gamma, *v_gamma;
+  float *alpha_rw, *beta_rw;
+  AdamArgs adam;              // consts: table of every iteration, [iters][4]
+  int iters;
+  int P;                      // LDS pitch (elements) of the two activation buffers
+  int off_buf0, off_buf1, off_sign, sign_ld;   // byte offsets into the dynamic LDS; sign pitch (bytes)
+};
+// lds_bytes: 2 kChainRows P esz + kChainRows sign_ld
+hipError_t launch_chain_opt(int bf16, const ChainArgs& a, int n_tiles, size_t lds_bytes, hipStream_t st);
+
 // Static workspace (scratch.hip): the device address and size of the calling
 // thread's current device's copy, looked up on its first use on that device.
 constexpr size_t kScratchBytes = size_t(64) << 20;

@@ -29,20 +29,6 @@ __device__ inline int xcd_tile(int id, int total) {
   return xcd * per + (xcd < rem ? xcd : rem) + kx;
 }
 
-// Keep the first `keep` elements of a 16-byte operand vector, zero the rest:
-// columns >= K of a row are padding whose bytes may hold data of the other
-// operand precision (buffers are shared by the bf16 and fp32 passes), so the
-// K tail is masked explicitly instead of relying on zero padding.
-template <typename T>
-__device__ inline uint4 mask_tail(uint4 v, int keep) {
-  T e[16 / sizeof(T)];
-  *(uint4*)e = v;
-#pragma unroll
-  for (int q = 0; q < (int)(16 / sizeof(T)); ++q)
-    if (q >= keep) e[q] = to_t<T>(0.f);
-  return *(const uint4*)e;
-}
-
 // One output tile (linear index vt, row panel major) of one GEMM problem.
 template <typename T, int BM, int BN, int WM, int WN, int BK, bool SIGN, class Epi>
 __device__ inline void gemm_tile(const GemmArgs& g, const Epi& epi, int vt) {
@@ -639,43 +625,6 @@ hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n
   hipLaunchKernelGGL(reduce_rows_kernel, dim3((M + kRedRows - 1) / kRedRows), dim3(256), 0, st, M, mp, S, partial,
                      n_slots, cb, gammaT, N, d, bound, verified);
   return hipGetLastError();
-}
-
-// One (cut k, row r) of the gamma update.  The Adam state is read before the
-// sum and the cut's entry pieces four at a time, so the loads are in flight
-// together; the pieces are still added one by one in entry order.
-__device__ inline void gamma_one(int k, int r, int M, int mp, int N, const int32_t* row_ptr, const float* contrib,
-                                 const double* d, float* gammaT, float* d_gamma, float* m, float* v,
-                                 const AdamArgs& adam) {
-  const int e0 = row_ptr[k], e1 = row_ptr[k + 1];
-  const size_t im = (size_t)k * M + r;
-  float m0 = 0.f, v0 = 0.f, x0 = 0.f;
-  float* gp = adam.enabled ? gammaT + (size_t)k * mp + r : nullptr;
-  if (adam.enabled) {
-    m0 = m[im];
-    v0 = v[im];
-    x0 = *gp;
-  }
-  double g = -d[k];
-  for (int e = e0; e < e1; e += 4) {
-    float c[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) c[t] = e + t < e1 ? contrib[(size_t)(e + t) * mp + r] : 0.f;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (e + t < e1) g += (double)c[t];
-  }
-  if (adam.enabled) {
-    const float lr = adam.consts[1], ibc1 = adam.consts[2], ibc2 = adam.consts[3];
-    const float gf = (float)g;
-    const float mm = adam.b1 * m0 + (1.f - adam.b1) * gf;
-    const float vv = adam.b2 * v0 + (1.f - adam.b2) * gf * gf;
-    m[im] = mm;
-    v[im] = vv;
-    *gp = fmaxf(x0 + adam_step(lr, mm, vv, ibc1, ibc2, adam.eps), 0.f);
-  } else {
-    d_gamma[(size_t)r * N + k] = (float)g;
-  }
 }
 
 // d bound / d gamma[r][k] = -d_k + sum of the cut's entry pieces (entries of
