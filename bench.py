@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
     ap.add_argument("--workload", choices=["mlp784", "cnn", "resnet", "batch"], default="mlp784")
+    ap.add_argument("--roots", choices=["crown", "ibp"], default="crown",
+                    help="root pre-activation bounds of the workload: the stored fp64 CROWN bounds or interval bounds")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every GEMM/conv tile afresh instead of starting from the shipped MI355X choices")
     ap.add_argument("--explicit-pi", action="store_true",
@@ -105,7 +107,7 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch":
         return bench_batch(args)
-    prob = gen.make_workload(args.workload, 0, B=args.domains)
+    prob = gen.make_workload(args.workload, 0, B=args.domains, roots=args.roots)
     P = B.Problem(prob, device=dev)
     M = P.M
     # starting point: CROWN-adaptive alpha, beta ~ U[0,1] on used split slots, gamma = 0
@@ -197,6 +199,7 @@ def main():
         "config": {
             "workload": WORKLOADS[args.workload].format(B=args.domains),
             "domains": args.domains, "spec_rows": prob.S, "rows": M, "n_unstable": P.n_I,
+            "root_bounds": "fp64 CROWN (stored)" if args.roots == "crown" else "interval arithmetic",
             "cuts": P.N, "split_slots": P.K, "iters": o["iters"], "graph_replay": args.graph,
             "domain_iters_per_s": value * o["iters"],
             "relaxation": "explicit pi (rho optimised)" if pi else "Lemma A.1 pi*",
@@ -233,6 +236,11 @@ def main():
             "final_bound_rel_diff_median": float(np.median(rel)),
             "final_bound_mean": float(bound_other.mean()),
         }
+        if not pi:
+            if args.mode == "fp32":
+                om.update(scaled_diff(prob, bound_main, bound_other, par_main))
+            else:
+                om.update(scaled_diff(prob, bound_other, bound_main, par_other))
         if kprof2:
             om["roofline"] = roofline(kprof2, om["dtype"])
             om["roofline"]["instrumented_ms_per_step"] = dt_prof2 * 1000.0 / osteps
@@ -270,6 +278,22 @@ def oracle_error(prob, bound, par, seed, n=64):
             "max_rel_err": float((d / np.abs(ref)).max()),
             "sample": f"{rows.size} rows ({min(n, M - 8)} seeded random + the last 8), oracle bound (fp64) at the "
                       "device's final alpha, beta, gamma"}
+
+
+def scaled_diff(prob, b32, b16, par32, max_rows=20000):
+    """bf16 against fp32 final bounds relative to max(|g|, T), T = the sum of
+    the magnitudes of every term of the fp32 run's bound (the oracle's error
+    scale at its final parameters), over every row (or a seeded sample of
+    max_rows rows)."""
+    import numpy as np
+
+    from oracle import gcp_oracle as O
+    M = b32.size
+    rows = np.arange(M) if M <= max_rows else np.sort(np.random.default_rng(1).choice(M, max_rows, replace=False))
+    a, b, c = (x[rows] for x in par32)
+    T = O.error_scale(prob, a, b, c, rows=rows, flat=True)
+    d = np.abs(b16[rows] - b32[rows]) / np.maximum(np.abs(b32[rows]), T)
+    return {"final_bound_diff_max_over_T": float(d.max()), "final_bound_diff_rows": int(rows.size)}
 
 
 def opt_gap(prob, bound, g_oracle, rows):

@@ -245,6 +245,23 @@ int gcp_optimize(const gcp_net* net, const double* x0, double eps,
                  const gcp_opt* opt, int32_t mode,
                  double* bound, uint8_t* verified, void* stream);
 
+/* gcp_prepare: allocate and tune once, ahead of the bounding calls (the
+ * problem statement's bound calls, Sec. 2, issued many times on one net).
+ * Sizes the net's workspace for M = B*S rows (B of `splits`, the cut count
+ * and entries of `cuts`, may be NULL) and runs the autotuner for every GEMM
+ * and convolution shape that gcp_bound (with and without gradients, in `mode`
+ * and in fp32) and gcp_optimize (in `mode`, with its fp32 certifying pass, up
+ * to `iters` iterations) launch for these shapes; `mode` may carry
+ * GCP_FLAG_RECOMPUTE / GCP_FLAG_STORE_AHAT.  Allocates device memory and
+ * synchronises `stream`.  Afterwards, gcp_bound and gcp_optimize on this net
+ * with the same S, number of domains, cuts and mode (and iters <= the
+ * prepared count, use_graph = 0) allocate no device memory and never wait for
+ * the device, so they can be issued inside a HIP stream capture.  Other
+ * shapes tune (and may allocate) on first use as usual.  Errors: EINVAL,
+ * ENOMEM, EDEVICE. */
+int gcp_prepare(const gcp_net* net, int32_t S, const gcp_splits* splits, const gcp_cuts* cuts,
+                int32_t iters, int32_t mode, void* stream);
+
 /* ------------------------------------------------------------ explicit pi */
 /* Variant of the unstable-neuron rule in which pi is a free variable
  * instead of Lemma A.1's maximiser.  In the proof of Theorem 3.1

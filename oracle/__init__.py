@@ -14,4 +14,8 @@ Modules
               sampled minimum, and a plain forward pass.
   crown       Textbook CROWN / alpha-CROWN in primal form (an independent
               derivation used to pin the beta = gamma = 0 special case).
+  root_bounds Layer-by-layer CROWN root bounds of the benchmark workloads
+              (the Theorem 3.1 bound at beta = gamma = 0 on each prefix
+              network); as a script it writes the stored bounds that the
+              input generator reads.
 """

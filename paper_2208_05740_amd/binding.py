@@ -104,6 +104,8 @@ def lib():
     L.gcp_bound.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.gcp_bound_noalloc.argtypes = L.gcp_bound.argtypes
     L.gcp_bound_noalloc.restype = C.c_int
+    L.gcp_prepare.argtypes = [vp, i32, vp, vp, i32, i32, vp]
+    L.gcp_prepare.restype = C.c_int
     L.gcp_optimize.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp, vp]
     L.gcp_bound_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gcp_optimize_pi.argtypes = [vp, vp, dbl, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(OptDesc), i32, vp, vp,
@@ -308,6 +310,13 @@ def bound(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts],
                            *((_ptr(t) if t.numel() else None) for t in g) if g else (None, None, None),
                            _stream()))
     return out, ver, g
+
+
+def prepare(net: Net, S: int, splits: Splits, cuts: Optional[Cuts], iters: int = 20, mode: int = GCP_MODE_FP32):
+    """gcp_prepare: size the workspace and tune every tile shape for these
+    shapes, so later bound / optimize calls of them allocate and wait for
+    nothing."""
+    _check(lib().gcp_prepare(net.h, S, splits.h, cuts.h if cuts else None, iters, mode, _stream()))
 
 
 def bound_noalloc(net: Net, x0, eps: float, Cspec, splits: Splits, cuts: Optional[Cuts], alpha, beta, gamma,

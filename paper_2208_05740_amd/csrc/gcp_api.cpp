@@ -1995,6 +1995,46 @@ extern "C" int gcp_optimize_pi(const gcp_net* net, const double* x0, double eps,
   GCP_CATCH
 }
 
+// gcp_prepare: one gradient bound pass in `mode`, one fp32 bound pass and
+// an optimisation of `iters` iterations on zero inputs of the given shapes
+// size every workspace buffer and tune every tile shape the calls of these
+// shapes launch; the scratch inputs are freed at the end.
+extern "C" int gcp_prepare(const gcp_net* net, int32_t S, const gcp_splits* splits, const gcp_cuts* cuts,
+                           int32_t iters, int32_t mode, void* stream) {
+  GCP_TRY
+  if (!net || !splits) fail(GCP_EINVAL, "null net or splits");
+  if (S <= 0 || iters < 0) fail(GCP_EINVAL, "need S >= 1 and iters >= 0");
+  if (mode & GCP_FLAG_VALIDATE) fail(GCP_EINVAL, "GCP_FLAG_VALIDATE is a per-call check");
+  const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
+  if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t M = (size_t)splits->B * S, nI = net->n_I, K = splits->K, N = cuts ? cuts->N : 0;
+  DBuf x0, C, a, b, g, da, db, dg, state, bound, ver;
+  x0.alloc((size_t)std::max(net->in_size, 1) * 8);
+  C.alloc((size_t)S * net->nodes[net->out].size * 8);
+  a.alloc(std::max<size_t>(M * nI, 1) * 4);
+  b.alloc(std::max<size_t>(M * K, 1) * 4);
+  g.alloc(std::max<size_t>(M * N, 1) * 4);
+  da.alloc(std::max<size_t>(M * nI, 1) * 4);
+  db.alloc(std::max<size_t>(M * K, 1) * 4);
+  dg.alloc(std::max<size_t>(M * N, 1) * 4);
+  state.alloc(std::max<size_t>(2 * M * (nI + K + N), 1) * 4);
+  bound.alloc(M * 8);
+  ver.alloc(M);
+  float* pa = a.as<float>(); float* pb = K ? b.as<float>() : nullptr; float* pg = N ? g.as<float>() : nullptr;
+  bound_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, mode, bound.as<double>(),
+             ver.as<uint8_t>(), da.as<float>(), K ? db.as<float>() : nullptr, N ? dg.as<float>() : nullptr, nullptr, st);
+  bound_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, GCP_MODE_FP32,
+             bound.as<double>(), ver.as<uint8_t>(), nullptr, nullptr, nullptr, nullptr, st);
+  gcp_opt o{std::max(iters, 1), 0.1f, 0.02f, 0.9f, 0.9f, 0.999f, 1e-8f, 0};
+  optimize_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, state.as<float>(), &o,
+                mode, bound.as<double>(), ver.as<uint8_t>(), st);
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+
 extern "C" int gcp_profile_enable(int32_t on) {
   GCP_TRY
   Profiler& P = prof();

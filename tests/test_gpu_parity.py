@@ -322,7 +322,7 @@ def test_graph_replayed_optimisation_equals_eager():
     # eager work in between.
     import torch
     from paper_2208_05740_amd import binding as B
-    p = gen.make_workload("mlp784", 1, B=3)
+    p = gen.make_workload("mlp784", 1, B=3, roots="ibp")
     P = upload(p)
     a0, b0, c0, *_ = params(p, P)
     o = p.opt

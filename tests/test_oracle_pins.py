@@ -620,3 +620,39 @@ def test_domain_intermediate_bounds_without_splits_are_the_root_bounds():
     b = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, splits=[])
     for (l0, u0), (l1, u1) in zip(a, b):
         assert np.array_equal(l0, l1) and np.array_equal(u0, u1)
+
+
+# ------------------------------- stored CROWN root bounds of the benchmark workloads
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 1), ("cnn", 2), ("res", 3)])
+def test_root_bounds_equal_textbook_crown_layer_by_layer(kind, seed):
+    # the batched root-bound computation (Theorem 3.1 at beta = gamma = 0 on
+    # each prefix network, rows +e_j / -e_j) against the primal-form textbook
+    # CROWN given the same earlier bounds, node by node; the stored values are
+    # rounded outward to fp32, so within one fp32 ulp and on the outer side
+    from oracle import root_bounds
+    p = gen.make_tiny(kind, seed, eps=0.1)
+    ours = root_bounds.crown_root_bounds(p.net, p.x0, p.eps, chunk=7)
+    ref = crown.crown_intermediate_bounds(p.net, p.x0, p.eps, lu_given=ours)
+    for (l, u), (lr, ur) in zip(ours, ref):
+        assert np.all(l <= lr + 1e-12) and np.all(u >= ur - 1e-12)
+        assert np.all(lr - l <= 2.0 ** -23 * np.abs(lr) + 1e-300)
+        assert np.all(u - ur <= 2.0 ** -23 * np.abs(ur) + 1e-300)
+        assert np.all(l.astype(np.float32).astype(np.float64) == l)
+
+
+@pytest.mark.parametrize("name", ["mlp784", "cnn", "resnet"])
+def test_stored_root_bounds_contain_sampled_preactivations(name):
+    # the workloads' stored bounds are valid over the box: sampled points and
+    # box vertices stay inside, and they are no looser than interval bounds
+    net, x0, eps = gen.workload_net(name, 0)
+    lu = gen.load_root_bounds(name, 0, net, x0, eps)
+    ibp = gen.ibp_bounds(net, x0, eps)
+    rng = np.random.default_rng(5)
+    n = 64 if name == "resnet" else 512
+    xs = x0[None, :] + eps * rng.uniform(-1, 1, size=(n, x0.size))
+    xs[: n // 8] = x0[None, :] + eps * np.sign(rng.uniform(-1, 1, size=(n // 8, x0.size)))
+    _, pre = lp.plain_forward(net, xs, return_pre=True)
+    for (l, u), (li, ui), i in zip(lu, ibp, net.relu_nodes):
+        assert (pre[i] >= l[None, :]).all() and (pre[i] <= u[None, :]).all()
+        assert np.all(l >= li) and np.all(u <= ui)

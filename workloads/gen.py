@@ -18,7 +18,9 @@ on its own.  Nothing in this module evaluates the GCP-CROWN bound.
 """
 from __future__ import annotations
 
+import hashlib
 import math
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Tuple
 
@@ -477,10 +479,13 @@ OPT_DEFAULT = dict(iters=20, lr_alpha=0.1, lr_mult=0.02, decay=0.9,
 
 def make_problem(name, net, x0, eps, S, B, kmin_split, kmax_split, n_cuts,
                  cut_kmin, cut_kmax, streams, alpha_init="crown",
-                 beta_dist="uniform", gamma_dist="zero", input_terms=0) -> Problem:
+                 beta_dist="uniform", gamma_dist="zero", input_terms=0, lu=None) -> Problem:
+    """A problem on `net` around x0; root bounds `lu` as given, else by
+    interval arithmetic."""
     r_cut, r_split, r_par = streams
     x0 = _f32(x0)
-    lu = ibp_bounds(net, x0, eps)
+    if lu is None:
+        lu = ibp_bounds(net, x0, eps)
     rel = net.relu_nodes
     C = margin_spec(net, x0, S)
     splits = make_splits(r_split, lu, rel, B, kmin_split, kmax_split)
@@ -530,9 +535,57 @@ def _streams(seed):
 
 
 WORKLOAD_NAMES = ("mlp8", "mlp784", "cnn", "batch", "resnet")
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
 
-def make_workload(name: str, seed: int = 0, B: Optional[int] = None, **kw):
+def workload_net(name: str, seed: int = 0):
+    """The network, centre x0 (fp32 values) and radius of a named workload."""
+    r_w, r_x = _streams(seed)[:2]
+    if name == "mlp784":
+        return mlp_net(r_w, [784] + [256] * 6 + [10]), _f32(r_x.random(784)), 0.015
+    if name == "cnn":
+        return cnn_wide_net(r_w), _f32(r_x.random(3 * 32 * 32)), 2.0 / 255.0
+    if name == "resnet":
+        return resnet_net(r_w), _f32(r_x.random(3 * 32 * 32)), 2.0 / 255.0
+    raise ValueError(f"no stored root bounds for workload {name!r}")
+
+
+def inputs_digest(net: Net, x0, eps) -> str:
+    """Fingerprint of what root bounds depend on (weights, biases, x0, eps),
+    stored beside them so a changed generator cannot pick up stale bounds."""
+    h = hashlib.sha256()
+    for n in net.nodes:
+        h.update(np.ascontiguousarray(n.bias, np.float64).tobytes())
+        for e in n.edges:
+            h.update(f"{e.src}:{e.kind}:{e.stride}:{e.pad}".encode())
+            if e.W is not None:
+                h.update(np.ascontiguousarray(e.W, np.float64).tobytes())
+    h.update(np.ascontiguousarray(x0, np.float64).tobytes())
+    h.update(repr(float(eps)).encode())
+    return h.hexdigest()
+
+
+def root_bounds_path(name: str, seed: int = 0) -> str:
+    return os.path.join(DATA, f"{name}_s{seed}_crown_roots.npz")
+
+
+def load_root_bounds(name: str, seed: int, net: Net, x0, eps):
+    """Stored CROWN root bounds of a workload (written by oracle/root_bounds.py
+    from the float64 oracle; fp32 values rounded outward), checked against the
+    network they were computed for."""
+    path = root_bounds_path(name, seed)
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: run `python -m oracle.root_bounds {name}`")
+    with np.load(path, allow_pickle=False) as z:
+        if str(z["digest"]) != inputs_digest(net, x0, eps):
+            raise ValueError(f"{path} was computed for another network or input")
+        lu = []
+        for i in range(len(net.relu_nodes)):
+            lu.append((z[f"l{i}"].astype(np.float64), z[f"u{i}"].astype(np.float64)))
+    return lu
+
+
+def make_workload(name: str, seed: int = 0, B: Optional[int] = None, roots: str = "crown", **kw):
     """The named synthetic workloads (B overrides the number of domains):
       mlp8    MLP 8-16-16-3, one domain, S = 2, 8 cuts (small enough for exact
               LP / MIP checks);
@@ -541,8 +594,16 @@ def make_workload(name: str, seed: int = 0, B: Optional[int] = None, **kw):
               domains, 500 cuts;
       resnet  stem 16, residual blocks 16/32/64, linear 10 on 3x32x32, 4096
               domains, 1000 cuts;
-      batch   64 uneven MLP instances (returns a list of Problems)."""
+      batch   64 uneven MLP instances (returns a list of Problems).
+    roots: root bounds of mlp784, cnn and resnet -- "crown" (the stored
+    float64 CROWN bounds, Sec. 2's intermediate bounds) or "ibp" (interval
+    arithmetic); mlp8 and batch use interval arithmetic."""
     r_w, r_x, r_cut, r_split, r_par = _streams(seed)
+    if name in ("mlp784", "cnn", "resnet") and roots == "crown":
+        net, x0, eps = workload_net(name, seed)
+        kw["lu"] = load_root_bounds(name, seed, net, x0, eps)
+    elif roots not in ("crown", "ibp"):
+        raise ValueError(f"roots must be 'crown' or 'ibp', not {roots!r}")
     if name == "mlp8":
         # W ~ N(0, 1/fan_in), b ~ N(0, 0.1); eps = 0.05; S = 2; one domain, no
         # splits; 8 cuts over 2-4 neurons; alpha, gamma ~ U[0,1]
