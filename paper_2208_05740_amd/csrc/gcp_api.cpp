@@ -1238,6 +1238,16 @@ struct BoundPass {
 };
 
 // ---------------------------------------------------------------- adjoint
+// What the adjoint adds to d Lambda^(i) (the derivative of the Lambda.b and
+// input terms): the bias, plus W x0 for a node fed by the network input (made
+// per call by AdjPass::prepare into the workspace).
+const float* add_vec_of(const Call& c, int i) {
+  const NodeH& n = c.net->nodes[i];
+  for (int eid : n.in_edges)
+    if (c.net->edges[eid]->src < 0) return c.ws->addv[i]->as<float>();
+  return n.bias.as<float>();
+}
+
 struct AdjPass {
   Call& c;
   int bf16;
@@ -1250,7 +1260,8 @@ struct AdjPass {
 
   void check(hipError_t e) { hip_check(e, "kernel launch (adjoint)"); }
 
-  // add vectors: bias (+ A x0 for edges from the input); once per call
+  // add vectors of the nodes fed by the input: bias + A x0, once per call
+  // (the other nodes add their bias, read in place: add_vec_of)
   void prepare() {
     gcp_net* net = c.net;
     auto& ws = *c.ws;
@@ -1265,9 +1276,6 @@ struct AdjPass {
                          seeded ? nullptr : n.bias.as<float>(), ws.addv[i]->as<float>(), c.st));
         seeded = true;
       }
-      if (!seeded)
-        hip_check(hipMemcpyAsync(ws.addv[i]->p, n.bias.p, n.size * 4, hipMemcpyDeviceToDevice, c.st),
-                  "hipMemcpyAsync");
     }
   }
 
@@ -1443,7 +1451,7 @@ struct AdjPass {
     a.rp = c.rp;
     a.acc_in = acc_in;
     a.gemm_scale = scale;
-    a.add_vec = ws.addv[i]->as<float>();
+    a.add_vec = add_vec_of(c, i);
     a.ahat = c.recompute.empty() || !c.recompute[i] ? ws.ahat[i]->p : ws.ahat_tmp.p;
     a.dahat_out = ws.dahat[i]->p;
     a.contrib = c.nnz ? ws.contrib.as<float>() : nullptr;
@@ -1765,7 +1773,7 @@ void run_chain(Call& c, int bf16, const ChainPlan& pl, float* alpha, float* beta
     cn.ldWT = n.ld;
     cn.W = w_adj(E, bf16);
     cn.ldW = node_ld_of(net, i - 1);
-    cn.addv = ws.addv[i]->as<float>();
+    cn.addv = add_vec_of(c, i);
     cn.ahat = ws.ahat[i]->p;
     cn.dahat = ws.dahat[i]->p;
     flops += 4.0 * c.M * E.d_src * E.d_dst;   // the bound-pass and adjoint GEMM of the in-edge
