@@ -169,6 +169,26 @@ int gcp_splits_destroy(gcp_splits* splits);
  * Results are identical either way.  The flags force one policy. */
 #define GCP_FLAG_RECOMPUTE   0x200  /* recompute a_hat wherever possible      */
 #define GCP_FLAG_STORE_AHAT  0x400  /* store a_hat of every layer             */
+/* Outward rounding (the bound is sound in exact arithmetic, Theorem 3.1; its
+ * floating-point value can exceed the exact one by rounding).  With
+ * GCP_FLAG_OUTWARD the bound pass subtracts from every row a bound on that
+ * excess, so the returned value is at most the exact Theorem 3.1 value of
+ * the multipliers the pass used (each node's stored Lambda, beta, gamma and
+ * the spec row: a valid dual point) and hence a lower bound on c.f(x) over
+ * the box.  The slack is sum over nodes of |Lambda| w with per-neuron
+ * weights w from |W| times the root-bound magnitudes and the accumulation
+ * bound K u / (1 - K u) of each fp32 sum (u = 2^-23, twice the unit
+ * roundoff, so that any rounding of the matrix cores' internal steps is
+ * covered), plus the operand rounding of bf16 mode (2^-8 of |Lambda||W|),
+ * the relaxation's fp32 operations, the |beta| and |gamma| terms and the
+ * fp64 row sums.  It does not cover root bounds that are themselves wrong.
+ * A net whose output Lambda is materialised (out_general) needs spec rows
+ * exactly representable in the operand type, else the row's bound is -inf.
+ * Applies to gcp_bound, gcp_bound_noalloc, gcp_bound_pi, the certifying
+ * pass of gcp_optimize, gcp_optimize_pi and gcp_optimize_batch, and the
+ * bounds of gcp_crown_bounds / gcp_crown_bounds_domain; gradients are those
+ * of the bound without the slack.  Costs one extra read of every Lambda. */
+#define GCP_FLAG_OUTWARD     0x800
 /* In every mode the row reductions (concretisation v.x0 - eps*|v|_1, bias,
  * h and cut-offset sums, gamma.d) accumulate in fp64; the bound is fp64. */
 

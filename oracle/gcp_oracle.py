@@ -162,7 +162,7 @@ def _cut_term(prob, gamma, node, kind, size):
     return out.index_add(1, j, gamma[:, k] * c)
 
 
-def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False, rho=None):
+def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False, rho=None, lams=None):
     """Theorem 3.1 objective g for every (domain, spec row).
 
     alpha [M, n_I], beta [M, K], gamma [M, N] are float64 tensors over the
@@ -174,7 +174,9 @@ def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False,
     sum|v_k x0_k| + eps*||v||_1 + sum|Lambda_j b_j| + sum|h_j| +
     sum|s_j (active)| + sum|gamma_k d_k|.
     ``rho`` [M, n_I] (optional, layout of alpha) replaces Lemma A.1's pi* of
-    every root-unstable neuron by pi = rho * [-a_hat]_+ (explicit_pi_h)."""
+    every root-unstable neuron by pi = rho * [-a_hat]_+ (explicit_pi_h).
+    ``lams`` (optional dict) receives Lambda [M, size] of every ReLU node,
+    keyed by node index (read-only view of the recursion, for tests)."""
     prep = prep or Prepared(prob)
     net = prob.net
     S = prob.S
@@ -242,6 +244,8 @@ def bound_rows(prob, alpha, beta, gamma, prep=None, rows=None, with_scale=False,
         K = K + lam @ _t(node.bias) + (h * uns).sum(1) + (s * act).sum(1)
         if with_scale:
             T = T + (lam * _t(node.bias)).abs().sum(1) + (h * uns).abs().sum(1) + (s * act).abs().sum(1)
+        if lams is not None:
+            lams[p] = lam.detach().clone()
         push(p, lam)
 
     v = acc.get(-1, torch.zeros(M, net.in_size, dtype=torch.float64)) + \
@@ -361,6 +365,17 @@ def optimize(prob, iters=None, alpha=None, beta=None, gamma=None, rows=None, opt
     gfin = bound(prob, a, b, c, rows=rows, prep=prep, flat=True)
     out = (gfin, a, b, c)
     return out + (hist,) if history else out
+
+
+def node_lambdas(prob, alpha=None, beta=None, gamma=None, rows=None, prep=None, flat=False):
+    """Lambda [rows, size] of every ReLU node at the given parameters (the
+    multipliers of the Theorem 3.1 recursion), keyed by node index."""
+    prep = prep or Prepared(prob)
+    a, b, c = _params(prob, alpha, beta, gamma, rows, prep, flat)
+    lams = {}
+    with torch.no_grad():
+        bound_rows(prob, a, b, c, prep, rows, lams=lams)
+    return {k: v.numpy() for k, v in lams.items()}
 
 
 def error_scale(prob, alpha=None, beta=None, gamma=None, rows=None, prep=None, flat=False, rho=None):

@@ -207,6 +207,11 @@ struct NodeH {
   DBuf bias, rec, kind;
   std::vector<int32_t> rank_h;    // host copy of rank
   std::vector<double> l_h, u_h;   // host copies of the root bounds (as given)
+  // outward rounding: Z = max(|l|, |u|) and Y = the largest |x_hat| the
+  // relaxation faces (0 inactive, u active, max(-l, u) unstable), both from
+  // the fp32 bounds the device holds
+  std::vector<double> z_h, y_h;
+  DBuf slack_w;                   // fp64 [5][ld]: the node's outward-rounding weights
   int n_unst = 0, rank0 = 0;
   NodeDev dev() const { return NodeDev{size, ld, rec.as<float4>(), kind.as<int32_t>()}; }
 };
@@ -243,6 +248,7 @@ struct gcp_net {
     std::vector<ChainNode> chain_host;
     DBuf tune_store, tune_alpha, tune_beta;   // autotuner trial outputs (lazy)
     DBuf ahat_tmp;      // a_hat of the node being differentiated, when recomputed
+    DBuf slackw;        // outward rounding: combined weights of every node, then X_in
     // captured Adam iteration of gcp_optimize (valid for one argument set)
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -271,6 +277,11 @@ struct gcp_cuts {
   };
   std::vector<Col> cols;   // per node; index n_nodes is the network input
   std::vector<int> nnz_node;   // merged entries per node (same indexing)
+  // outward rounding: fp64 [3][N] = sum |coef| range over a cut's node
+  // entries (range Z for H and G, 2 for Q), sum |coef| over its input
+  // entries (times X_in per call), |d|; and the most entries of one column
+  DBuf kap;
+  int col_max = 0;
   const gcp_net* net = nullptr;
 };
 
@@ -278,6 +289,7 @@ struct gcp_splits {
   uint64_t id = next_generation();   // process-unique (see gcp_cuts::id)
   int B = 0, K = 0;
   DBuf mask;        // int8 [B][n_I]
+  DBuf zsplit;      // fp64 [B][K]: max(|l|, |u|) of slot k's neuron (0: unused slot), for outward rounding
   const gcp_net* net = nullptr;
 };
 
@@ -319,6 +331,52 @@ int node_ld_of(const gcp_net* net, int src) { return src < 0 ? net->in_ld : net-
 
 // ------------------------------------------------------------------ net create
 
+// Accumulation bound of a K-term fp32 sum, K u / (1 - K u), with u = 2^-23:
+// twice the unit roundoff of round-to-nearest, so that the bound also holds
+// if the matrix cores round their internal steps another way.
+double acc_bound(double K) {
+  const double u = 0x1p-23;
+  return K * u / (1.0 - K * u);
+}
+
+// The five outward-rounding weight vectors of every node (w0..w4 of
+// SlackArgs).  Column j of a source p collects the terms of all of p's
+// consumer edges, plus one addition per edge and the cut and relaxation
+// terms: K_p = sum of the edges' terms + edges + 4.
+void build_slack_weights(gcp_net* net, const std::vector<std::vector<double>>& e_wy,
+                         const std::vector<double>& e_terms) {
+  const int nn = (int)net->nodes.size();
+  std::vector<double> kp(nn + 1, 4.0);   // index nn: the input
+  for (size_t e = 0; e < net->edges.size(); ++e) {
+    const int p = net->edges[e]->src;
+    kp[p < 0 ? nn : p] += e_terms[e] + 1.0;
+  }
+  const double margin = 1.0 + 0x1p-30;   // covers the rounding of these host sums
+  for (int i = 0; i < nn; ++i) {
+    NodeH& n = net->nodes[i];
+    std::vector<double> w((size_t)5 * n.ld, 0.0);
+    for (int eid : n.in_edges) {
+      const int p = net->edges[eid]->src;
+      const double g = acc_bound(kp[p < 0 ? nn : p]);
+      const std::vector<double>& wy = e_wy[eid];
+      for (int k = 0; k < n.size; ++k) {
+        if (p >= 0) {
+          w[k] += g * wy[k];
+          w[(size_t)n.ld + k] += wy[k];
+        } else {
+          w[(size_t)3 * n.ld + k] += g * wy[k];
+          w[(size_t)4 * n.ld + k] += wy[k];
+        }
+      }
+    }
+    std::vector<float> b(n.size);
+    hip_check(hipMemcpy(b.data(), n.bias.p, (size_t)n.size * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    for (int k = 0; k < n.size; ++k) w[(size_t)2 * n.ld + k] = (n.relu ? n.z_h[k] : 0.0) + std::fabs((double)b[k]);
+    for (double& v : w) v *= margin;
+    n.slack_w.upload(w);
+  }
+}
+
 void build_net(const gcp_net_desc* d, gcp_net* net) {
   if (!d || !d->nodes) fail(GCP_EINVAL, "null network description");
   if (d->n_nodes < 1) fail(GCP_EINVAL, "a network needs an output node");
@@ -330,6 +388,10 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
   net->nodes.resize(d->n_nodes);
   net->out = d->n_nodes - 1;
   int rank0 = 0;
+  // outward rounding, per edge: |W| Y_src (|W| 1 from the input) and the
+  // number of terms one source column accumulates through the edge
+  std::vector<std::vector<double>> e_wy;
+  std::vector<double> e_terms;
   for (int i = 0; i < d->n_nodes; ++i) {
     const gcp_node_desc& nd = d->nodes[i];
     NodeH& n = net->nodes[i];
@@ -374,6 +436,13 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
       n.rank_h = rank;
       n.l_h.assign(nd.lower, nd.lower + n.size);
       n.u_h.assign(nd.upper, nd.upper + n.size);
+      n.z_h.resize(n.size);
+      n.y_h.resize(n.size);
+      for (int j = 0; j < n.size; ++j) {
+        const double lo = l[j], hi = u[j];
+        n.z_h[j] = std::max(std::fabs(lo), std::fabs(hi));
+        n.y_h[j] = cls[j] == INACTIVE ? 0.0 : (cls[j] == ACTIVE ? hi : std::max(-lo, hi));
+      }
       net->n_relu += n.size;
     }
     n.rec.upload(rec);
@@ -402,6 +471,12 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         E->Wraw.upload(raw);
         E->W32.upload(fw); E->W16.upload(to_bf16(fw));
         E->WT32.upload(ft); E->WT16.upload(to_bf16(ft));
+        std::vector<double> wy(E->d_dst, 0.0);
+        for (int o = 0; o < E->d_dst; ++o)
+          for (int k = 0; k < E->d_src; ++k)
+            wy[o] += std::fabs((double)raw[(size_t)o * E->d_src + k]) * (ed.src < 0 ? 1.0 : net->nodes[ed.src].y_h[k]);
+        e_wy.push_back(std::move(wy));
+        e_terms.push_back(E->d_dst);
       } else if (ed.kind == GCP_EDGE_CONV) {
         if (!ed.W) fail(GCP_EINVAL, "null conv weight");
         int ci, hi, wi;
@@ -430,8 +505,29 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         E->ldk_t = kt;
         E->W32.upload(fw); E->W16.upload(to_bf16(fw));
         E->WT32.upload(ft); E->WT16.upload(to_bf16(ft));
+        std::vector<double> wy(E->d_dst, 0.0);
+        for (int o = 0; o < n.c; ++o)
+          for (int y = 0; y < ho; ++y)
+            for (int x = 0; x < wo; ++x) {
+              double t = 0.0;
+              for (int cc = 0; cc < ci; ++cc)
+                for (int ky = 0; ky < ed.kh; ++ky)
+                  for (int kx = 0; kx < ed.kw; ++kx) {
+                    const int iy = y * ed.stride - ed.pad + ky, ix = x * ed.stride - ed.pad + kx;
+                    if (iy < 0 || iy >= hi || ix < 0 || ix >= wi) continue;
+                    const size_t src_j = ((size_t)cc * hi + iy) * wi + ix;
+                    t += std::fabs((double)raw[(((size_t)o * ci + cc) * ed.kh + ky) * ed.kw + kx]) *
+                         (ed.src < 0 ? 1.0 : net->nodes[ed.src].y_h[src_j]);
+                  }
+              wy[((size_t)o * ho + y) * wo + x] = t;
+            }
+        e_wy.push_back(std::move(wy));
+        e_terms.push_back((double)n.c * ed.kh * ed.kw);
       } else if (ed.kind == GCP_EDGE_IDENTITY) {
         if (E->d_src != E->d_dst) fail(GCP_EINVAL, "identity edge between different sizes");
+        if (ed.src < 0) e_wy.emplace_back(E->d_dst, 1.0);
+        else e_wy.push_back(net->nodes[ed.src].y_h);
+        e_terms.push_back(1.0);
       } else {
         fail(GCP_EINVAL, "unknown edge kind");
       }
@@ -445,6 +541,7 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
   net->n_I = rank0;
   for (int i = 0; i < net->out; ++i)
     if (net->nodes[i].consumers.empty()) fail(GCP_EUNSUPPORTED, "ReLU node without consumers");
+  build_slack_weights(net, e_wy, e_terms);
   if (net->in_consumers.empty()) fail(GCP_EINVAL, "network input is unused");
   const char* og = std::getenv("GCP_OUT_GENERAL");
   net->out_general = og && *og && std::atoi(og) != 0;
@@ -707,6 +804,14 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   struct Ent { int k, nd, j, pos; float h, g, q; };
   std::vector<Ent> ents;
   ents.reserve(m.size());
+  std::vector<double> kap((size_t)3 * n_cuts, 0.0);
+  for (auto& kv : m) {
+    const int k = std::get<0>(kv.first), nd = std::get<1>(kv.first), j = std::get<2>(kv.first);
+    const double h = std::fabs((double)(float)kv.second[0]), g = std::fabs((double)(float)kv.second[1]),
+                 q = std::fabs((double)(float)kv.second[2]);
+    if (nd < 0) kap[(size_t)n_cuts + k] += g;
+    else kap[k] += (h + g) * net->nodes[nd].z_h[j] + 2.0 * q;
+  }
   int pos = 0;
   for (auto& kv : m) {   // std::map order = (cut, node, neuron): cut-major
     int k = std::get<0>(kv.first);
@@ -720,6 +825,9 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
   for (int k = 0; k < n_cuts; ++k)
     if (slack[k] > 0.0) dv[k] = std::nextafter(dv[k] + slack[k], INFINITY);
   C->d.upload(dv);
+  for (int k = 0; k < n_cuts; ++k) kap[(size_t)2 * n_cuts + k] = std::fabs(dv[k]);
+  for (double& v : kap) v *= 1.0 + 0x1p-30;
+  if (n_cuts > 0) C->kap.upload(kap);
   C->cols.resize(n_nodes + 1);
   C->nnz_node.assign(n_nodes + 1, 0);
   for (auto& e : ents) C->nnz_node[e.nd < 0 ? n_nodes : e.nd]++;
@@ -741,6 +849,7 @@ extern "C" int gcp_cuts_create(const gcp_net* net, int32_t n_cuts, int64_t nnz, 
       std::memcpy(&kb, &e.k, 4);
       en.push_back(make_float4(e.h, e.g, e.q, kb));
     }
+    for (int j = 0; j < sz; ++j) C->col_max = std::max(C->col_max, cp[j + 1]);
     for (int j = 0; j < sz; ++j) cp[j + 1] += cp[j];
     std::vector<int2> rg(sz);
     for (int j = 0; j < sz; ++j) rg[j] = make_int2(cp[j], cp[j + 1]);
@@ -773,6 +882,7 @@ extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const
   if (B <= 0 || K < 0 || K > 127) fail(GCP_EINVAL, "need B >= 1 and 0 <= K <= 127");
   if (K > 0 && (!node || !neuron || !sign)) fail(GCP_EINVAL, "null split array");
   std::vector<int8_t> mask((size_t)B * net->n_I, 0);
+  std::vector<double> zs((size_t)B * K, 0.0);
   for (int b = 0; b < B; ++b)
     for (int k = 0; k < K; ++k) {
       size_t i = (size_t)b * K + k;
@@ -788,10 +898,12 @@ extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const
       int8_t& mm = mask[(size_t)b * net->n_I + rk];
       if (mm != 0) fail(GCP_EINVAL, "neuron split twice in one domain");
       mm = (int8_t)(sign[i] > 0 ? (k + 1) : -(k + 1));
+      zs[i] = n.z_h[j];
     }
   auto S = std::make_unique<gcp_splits>();
   S->B = B; S->K = K; S->net = net;
   S->mask.upload(mask);
+  if (K > 0) S->zsplit.upload(zs);
   *out = S.release();
   g_err.clear();
   return GCP_OK;
@@ -845,6 +957,8 @@ struct Call {
   // output Lambda) are already in the workspace for this C: later bound
   // passes of one optimisation skip them
   bool consts_done = false;
+  // the bound pass subtracts its rounding slack (GCP_FLAG_OUTWARD)
+  bool outward = false;
 };
 
 void ensure_ws(Call& c) {
@@ -1547,7 +1661,7 @@ void size_partials(Call& c, int bf16, bool keep, bool contrib) {
   BoundPass dry(c, bf16, keep, contrib, true);
   dry.run();
   auto& ws = *c.ws;
-  const size_t need = (size_t)round_up(ws.M, 16) * std::max(dry.slot, 1) * 8;
+  const size_t need = (size_t)round_up(ws.M, 16) * (dry.slot + 1) * 8;   // + the outward-rounding slot
   if (need > ws.partial.bytes) {
     ws.partial.alloc(need);
     ws.gen = next_generation();
@@ -1570,14 +1684,71 @@ void validate_params(Call& c, const float* alpha, const float* beta, const float
   if (h & 2) fail(GCP_ERANGE, "alpha or rho outside [0,1] or a negative multiplier");
 }
 
+// fp64 words of the combined outward-rounding weights (every node's ld, then X_in)
+size_t slack_words(const gcp_net* net) {
+  size_t w = 1;
+  for (const NodeH& n : net->nodes) w += n.ld;
+  return w;
+}
+
+// GCP_FLAG_OUTWARD: minus each row's rounding slack into partial slot `slot`
+// (bounds and the derivation at SlackArgs; the constants below follow it).
+void launch_outward(Call& c, int bf16, int slot) {
+  gcp_net* net = c.net;
+  auto& ws = *c.ws;
+  const int nn = (int)net->nodes.size();
+  if (nn > kSlackMaxNodes) fail(GCP_EUNSUPPORTED, "outward rounding handles nets of at most 64 nodes");
+  SlackArgs a{};
+  a.n_nodes = nn;
+  int off = 0;
+  for (int i = 0; i < nn; ++i) {
+    const NodeH& n = net->nodes[i];
+    const bool has_lam = n.relu || net->out_general;
+    a.nodes[i] = SlackNode{n.slack_w.as<double>(), n.ld, n.size, off, has_lam ? ws.lam[i]->p : nullptr};
+    off += n.ld;
+  }
+  const size_t words = slack_words(net);
+  if (!c.no_alloc && ws.slackw.bytes < words * 8) ws.slackw.alloc(words * 8);
+  if (ws.slackw.bytes < words * 8) fail(GCP_ENOMEM, "no room for the outward-rounding weights");
+  a.total = off;
+  a.wcomb = ws.slackw.as<double>();
+  a.M = c.M; a.S = c.S; a.mp = c.rp.mp; a.bf16 = bf16;
+  // u_op: operand rounding (bf16 weights and stored Lambda), e_r: the few
+  // fp32 operations of a relaxation, e_st: Lambda stored vs the value its
+  // row constant used, e64: the fp64 sums of a row
+  const double u_op = bf16 ? 0x1p-8 : 0.0, e_r = 0x1p-20, e_st = bf16 ? 0x1p-8 : 0x1p-22;
+  const double n64 = (double)net->n_relu + net->nodes[net->out].size + net->in_size + c.rp.N + slot + 64;
+  const double e64 = n64 * 0x1p-52;
+  a.c_sum = u_op + e_r + e64;
+  a.c_zb = e_st + e64;
+  a.c_in = u_op + e64;
+  a.x0 = c.x0; a.d_in = net->in_size; a.eps = c.eps;
+  a.C = c.C; a.d_out = net->nodes[net->out].size;
+  a.out_off = off - net->nodes[net->out].ld;
+  a.out_chat = net->out_general ? 0 : 1;
+  a.beta = c.rp.beta; a.K = c.rp.K;
+  a.zsplit = c.rp.K > 0 ? c.splits->zsplit.as<double>() : nullptr;
+  a.c_beta = e_r + e_st + e64;
+  a.gammaT = c.rp.gammaT; a.N = c.rp.N;
+  a.kap = c.rp.N > 0 ? c.cuts->kap.as<double>() : nullptr;
+  a.c_cut = acc_bound((c.cuts ? c.cuts->col_max : 0) + 4.0) + e_r + e_st + e64;
+  a.c_d = e64;
+  a.out = ws.partial.as<double>() + (size_t)slot * c.rp.mp;
+  hip_check(timed(c.st, "outward_slack", Bytes{(double)c.M * (off * (bf16 ? 2.0 : 4.0) + 8.0), 0.0}, 0.0,
+                  [&] { return launch_slack(a, c.st); }),
+            "outward slack");
+}
+
 void bound_pass(Call& c, int bf16, bool keep_ahat, bool contrib, double* bound, uint8_t* verified) {
   size_partials(c, bf16, keep_ahat, contrib);
   BoundPass bp(c, bf16, keep_ahat, contrib, false);
   bp.run();
   auto& ws = *c.ws;
-  const double rb = (double)c.M * (ws.n_slots * 8.0 + c.rp.N * 4.0 + 8.0 + (verified ? 1 : 0));
+  const int n_slots = ws.n_slots + (c.outward ? 1 : 0);
+  if (c.outward) launch_outward(c, bf16, ws.n_slots);
+  const double rb = (double)c.M * (n_slots * 8.0 + c.rp.N * 4.0 + 8.0 + (verified ? 1 : 0));
   hip_check(timed(c.st, "reduce_rows", Bytes{rb, 0.0}, 0.0, [&] {
-              return launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), ws.n_slots, ws.cb.as<double>(),
+              return launch_reduce_rows(c.M, c.rp.mp, c.S, ws.partial.as<double>(), n_slots, ws.cb.as<double>(),
                                         c.rp.gammaT, c.rp.N, c.cuts ? c.cuts->d.as<double>() : nullptr, bound,
                                         verified, c.st);
             }),
@@ -1644,7 +1815,8 @@ void carve_static(Call& c, gcp_net::WS& sws, int bf16, bool grads) {
   take(sws.consts, 16);
   take(sws.step, 16);
   take(sws.flags, 16);
-  take(sws.partial, mp * std::max(dry.slot, 1) * 8);
+  take(sws.partial, mp * (dry.slot + 1) * 8);   // + the outward-rounding slot
+  if (c.outward) take(sws.slackw, slack_words(net) * 8);
   if (off > cap) {
     char m[200];
     std::snprintf(m, sizeof m, "the call needs %.1f MiB of workspace; the static workspace holds %.0f MiB",
@@ -1672,6 +1844,7 @@ void bound_impl(const gcp_net* net_c, const double* x0, double eps, const double
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   if (!bound) fail(GCP_EINVAL, "null bound output");
   const bool grads = d_alpha || d_beta || d_gamma;
+  c.outward = (mode & GCP_FLAG_OUTWARD) != 0;
   if (grads) {
     if ((net->n_I > 0 && !d_alpha) || (splits->K > 0 && !d_beta) || (c.rp.N > 0 && !d_gamma) ||
         (rho && net->n_I > 0 && !d_rho))
@@ -1935,6 +2108,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   for (; done < opt->iters; ++done) iteration(c, done);
   if (N > 0) hip_check(launch_transpose(ws.gammaT.as<float>(), (int)N, c.M, c.rp.mp, gamma, (int)N, c.st), "transpose");
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
+  c.outward = (mode & GCP_FLAG_OUTWARD) != 0;
   bound_pass(c, 0, false, false, bound, verified);
 }
 
@@ -2032,8 +2206,9 @@ extern "C" int gcp_prepare(const gcp_net* net, int32_t S, const gcp_splits* spli
   float* pa = a.as<float>(); float* pb = K ? b.as<float>() : nullptr; float* pg = N ? g.as<float>() : nullptr;
   bound_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, mode, bound.as<double>(),
              ver.as<uint8_t>(), da.as<float>(), K ? db.as<float>() : nullptr, N ? dg.as<float>() : nullptr, nullptr, st);
-  bound_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, GCP_MODE_FP32,
-             bound.as<double>(), ver.as<uint8_t>(), nullptr, nullptr, nullptr, nullptr, st);
+  bound_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr,
+             GCP_MODE_FP32 | GCP_FLAG_OUTWARD, bound.as<double>(), ver.as<uint8_t>(), nullptr, nullptr, nullptr, nullptr,
+             st);   // sizes the outward-rounding weights too
   gcp_opt o{std::max(iters, 1), 0.1f, 0.02f, 0.9f, 0.9f, 0.999f, 1e-8f, 0};
   optimize_impl(net, x0.as<double>(), 0.0, C.as<double>(), S, splits, cuts, pa, pb, pg, nullptr, state.as<float>(), &o,
                 mode, bound.as<double>(), ver.as<uint8_t>(), st);
@@ -2448,6 +2623,7 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   // certifying pass per instance, then gamma back to the caller's layout
   for (int i = 0; i < n; ++i) {
     Call& c = calls[i];
+    c.outward = (mode & GCP_FLAG_OUTWARD) != 0;
     bound_pass(c, 0, false, false, items[i].bound, items[i].verified);
     if (c.rp.N > 0)
       hip_check(launch_transpose(c.net->ws.gammaT.as<float>(), c.rp.N, c.M, c.rp.mp, items[i].gamma, c.rp.N, st),
@@ -2564,7 +2740,8 @@ extern "C" int gcp_crown_bounds_domain(const gcp_net_desc* desc, const double* x
       }
       hip_check(hipMemcpyAsync(Cd.p, Ch.data(), (size_t)S * d * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
       const int rc = gcp_bound(net.p, x0, eps, Cd.as<double>(), S, spl.p, nullptr, nI ? Ad.as<float>() : nullptr,
-                               K ? Zd.as<float>() : nullptr, nullptr, mode & 0xff, Bd.as<double>(), nullptr, nullptr,
+                               K ? Zd.as<float>() : nullptr, nullptr, mode & (0xff | GCP_FLAG_OUTWARD),
+                               Bd.as<double>(), nullptr, nullptr,
                                nullptr, nullptr, stream);
       if (rc != GCP_OK) return rc;
       hip_check(hipMemcpyAsync(bh.data(), Bd.p, (size_t)S * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");

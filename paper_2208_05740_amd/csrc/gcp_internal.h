@@ -204,6 +204,41 @@ hipError_t launch_wx0(const ConvGeom* cg, int kind, const float* W, int d_out, i
 hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n_slots,
                               const double* cb, const float* gammaT, int N, const double* d,
                               double* bound, uint8_t* verified, hipStream_t st);
+// ---------------------------------------------------------------- outward rounding
+// Rounding slack of the bound pass (GCP_FLAG_OUTWARD).  Every multiplier the
+// pass stores (Lambda of each node, the spec rows, beta, gamma) is one valid
+// dual point; the slack bounds how far the pass's floating-point value can
+// exceed the exact value of the bound at that point.  Per node the host holds
+// five weight vectors [5][ld] (fp64) that depend only on the net:
+//   w0 = sum over in-edges from nodes p: g(K_p) |W_e| Y_p,  w1 = sum |W_e| Y_p,
+//   w2 = Z + |b|,  w3 = g(K_in) |W_e| 1 (in-edges from the input),  w4 = |W_e| 1
+// (Y: the largest |x_hat| a neuron's relaxation can face, Z = max(|l|, |u|),
+// g(K): the accumulation bound of a K-term fp32 sum).  A call combines them
+// into one weight per neuron, w = w0 + c_sum w1 + c_zb w2 + X_in (w3 + c_in w4)
+// (X_in = max |x0| + eps), and a row's slack is sum |Lambda| w over its nodes
+// plus the beta, gamma and spec-row terms.
+constexpr int kSlackMaxNodes = 64;
+struct SlackNode {
+  const double* w;     // [5][ld]
+  int ld, size, off;   // off: position of this node's weights in the combined vector
+  const void* lam;     // [M][ld] in the operand type; null: the output in c-hat form
+};
+struct SlackArgs {
+  int n_nodes;
+  SlackNode nodes[kSlackMaxNodes];
+  int M, S, mp, bf16;
+  double c_sum, c_zb, c_in;          // per-call constants of the combined weights
+  const double* x0; int d_in; double eps;
+  double* wcomb;                     // [total + 1]: combined weights, then X_in
+  int total;
+  const double* C; int d_out;        // spec rows; out_off: the output's weights in wcomb
+  int out_off, out_chat;             // out_chat: output in c-hat form (C W precomputed)
+  const float* beta; int K; const double* zsplit; double c_beta;    // zsplit [B][K]
+  const float* gammaT; int N; const double* kap; double c_cut, c_d;  // kap [3][N]: kappa, kappa_in, |d|
+  double* out;                       // partial slot [mp]: minus the slack of each row
+};
+hipError_t launch_slack(const SlackArgs& a, hipStream_t st);
+
 // d bound/d gamma from the entry pieces; Adam on gammaT (moments m, v are
 // [N][M]) or the raw gradient into d_gamma [M][N].
 hipError_t launch_gamma_update(int M, int mp, int N, const int32_t* row_ptr, const float* contrib,

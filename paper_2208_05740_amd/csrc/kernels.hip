@@ -627,6 +627,95 @@ hipError_t launch_reduce_rows(int M, int mp, int S, const double* partial, int n
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ outward rounding
+// X_in = max_j |x0_j| + eps, by one block (fixed reduction order).
+__device__ inline double block_xin(const double* x0, int d_in, double eps, double* sh) {
+  double m = 0.0;
+  for (int j = threadIdx.x; j < d_in; j += blockDim.x) m = fmax(m, fabs(x0[j]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, sh[w]);
+  __syncthreads();
+  return t + eps;
+}
+
+// wcomb[off + k] = w0 + c_sum w1 + c_zb w2 + X_in (w3 + c_in w4) for the
+// node blockIdx.y (0 beyond its size), wcomb[total] = X_in.
+__global__ void __launch_bounds__(256) slack_weights_kernel(SlackArgs a) {
+  __shared__ double sh[4];
+  const double xin = block_xin(a.x0, a.d_in, a.eps, sh);
+  const SlackNode& n = a.nodes[blockIdx.y];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.wcomb[a.total] = xin;
+  if (k >= n.ld) return;
+  double w = 0.0;
+  if (k < n.size) {
+    const double* v = n.w;
+    w = v[k] + a.c_sum * v[n.ld + k] + a.c_zb * v[2 * n.ld + k] + xin * (v[3 * n.ld + k] + a.c_in * v[4 * n.ld + k]);
+  }
+  a.wcomb[n.off + k] = w;
+}
+
+template <typename T>
+__device__ inline double abs_dot(const T* lam, const double* w, int size, int lane) {
+  double s = 0.0;
+  for (int k = lane; k < size; k += 64) s += fabs((double)from_t<T>(lam[k])) * w[k];
+  return s;
+}
+
+// One wave per row: the row's slack (sum |Lambda| w over its nodes, the
+// spec-row term, |beta| and |gamma| terms), written negated into its
+// partial slot.  Lanes stride over the neurons; the wave's sum is combined
+// in a fixed order.
+__global__ void __launch_bounds__(256) slack_rows_kernel(SlackArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= a.M) return;
+  const double xin = a.wcomb[a.total];
+  const int s = r % a.S, b = r / a.S;
+  double acc = 0.0;
+  for (int i = 0; i < a.n_nodes; ++i) {
+    const SlackNode& n = a.nodes[i];
+    if (!n.lam) continue;
+    const double* w = a.wcomb + n.off;
+    if (a.bf16) acc += abs_dot((const bf16*)n.lam + (size_t)r * n.ld, w, n.size, lane);
+    else acc += abs_dot((const float*)n.lam + (size_t)r * n.ld, w, n.size, lane);
+  }
+  const double* Cs = a.C + (size_t)s * a.d_out;
+  bool bad = false;
+  for (int k = lane; k < a.d_out; k += 64) {
+    const double c = Cs[k];
+    if (a.out_chat) acc += fabs(c) * a.wcomb[a.out_off + k];
+    else {   // the materialised output Lambda must be C itself
+      const double held = a.bf16 ? (double)(float)to_t<bf16>((float)c) : (double)(float)c;
+      bad |= held != c;
+    }
+  }
+  for (int k = lane; k < a.K; k += 64)
+    acc += a.c_beta * fabs((double)a.beta[(size_t)r * a.K + k]) * a.zsplit[(size_t)b * a.K + k];
+  for (int c = lane; c < a.N; c += 64) {
+    const double g = fabs((double)a.gammaT[(size_t)c * a.mp + r]);
+    acc += g * (a.c_cut * (a.kap[c] + xin * a.kap[a.N + c]) + a.c_d * a.kap[2 * a.N + c]);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  bad = __any(bad);
+  if (lane == 0) a.out[r] = bad ? -INFINITY : -(acc * (1.0 + 0x1p-40));
+}
+
+hipError_t launch_slack(const SlackArgs& a, hipStream_t st) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.n_nodes <= 0 || a.n_nodes > kSlackMaxNodes) return hipErrorInvalidValue;
+  int ldmax = 1;
+  for (int i = 0; i < a.n_nodes; ++i) ldmax = ldmax > a.nodes[i].ld ? ldmax : a.nodes[i].ld;
+  hipLaunchKernelGGL(slack_weights_kernel, dim3((ldmax + 255) / 256, a.n_nodes), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(slack_rows_kernel, dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // d bound / d gamma[r][k] = -d_k + sum of the cut's entry pieces (entries of
 // cut k are contiguous in the cut-major order); then the Adam ascent step on
 // gammaT (gamma >= 0, moments [N][M]) or the raw gradient into d_gamma[M][N].

@@ -105,13 +105,11 @@ def test_bound_pi_at_lemma_ratio_equals_closed_form_kernels():
     assert _rel(g1.cpu().numpy(), g0.cpu().numpy(), T).max() <= 2e-6
 
 
-@pytest.mark.parametrize("kind,seed", [("mlp", 1), ("res16", 3)])
-def test_optimize_pi_matches_oracle_optimisation(kind, seed):
+def _optimize_pi(p, rho0):
     import torch
     from paper_2208_05740_amd import binding as B
-    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=5, gamma_dist="zero")
     P = _upload(p)
-    a, b, c, r = (_t(x, P.M) for x in (O.full_alpha(p), p.beta, p.gamma, O.full_rho(p)))
+    a, b, c, r = (_t(x, P.M) for x in (O.full_alpha(p), p.beta, p.gamma, rho0))
     st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N, explicit_pi=True), dtype=torch.float32,
                      device=_dev())
     o = p.opt
@@ -121,19 +119,40 @@ def test_optimize_pi_matches_oracle_optimisation(kind, seed):
     g = out.cpu().numpy()
     a64, b64, c64, r64 = (_f64(x, p) for x in (a, b, c, r))
     assert np.all(r64 >= 0) and np.all(r64 <= 1) and np.all(a64 >= 0) and np.all(a64 <= 1)
+    assert np.all(b64 >= 0) and np.all(c64 >= 0)
     # certifying pass = the oracle's bound at the device's final parameters
     ref = O.bound_pi(p, a64, b64, c64, r64).reshape(-1)
     T = O.error_scale(p, a64, b64, c64, rho=r64).reshape(-1)
     assert _rel(g, ref, T).max() <= 1e-5
-    # the same 20 Adam steps in fp64.  h of every unstable neuron has a kink
-    # where u n - (u - l) pi - s changes sign; Adam's normalised step turns
-    # rounding-level gradient differences there into full steps, so the
-    # fp32 and fp64 trajectories separate more than with Lemma A.1's pi*
-    # (measured 1.2e-3 of the error scale); 5e-3 bounds that, while the
-    # certified bound above is held to 1e-5.
-    go, *_ = O.optimize_pi(p)
-    To = O.error_scale(p, rho=O.full_rho(p)).reshape(-1)
-    assert _rel(g, go.reshape(-1), To).max() <= 5e-3
+    return g
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 1), ("res16", 3)])
+def test_optimize_pi_matches_oracle_optimisation(kind, seed):
+    # A generic start (rho drawn away from the kinks of h): the 20 Adam steps
+    # are determined by the mathematics, so the device follows the oracle's
+    # fp64 trajectory to the tolerance of the closed-form optimiser's test.
+    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=5, gamma_dist="zero")
+    rho0 = 0.1 + 0.8 * np.random.default_rng(seed).random(O.full_rho(p).shape)
+    g = _optimize_pi(p, rho0)
+    go, *_ = O.optimize_pi(p, rho=rho0)
+    To = O.error_scale(p, rho=rho0).reshape(-1)
+    assert _rel(g, go.reshape(-1), To).max() <= 1e-3
+
+
+@pytest.mark.parametrize("kind,seed", [("mlp", 1), ("res16", 3)])
+def test_optimize_pi_from_the_kink(kind, seed):
+    # rho = u / (u - l) with no cut term puts every unstable neuron exactly on
+    # the kink of h(pi) = l pi - [u (n - pi) + l pi - s]_+, where h has no
+    # derivative: whichever one-sided derivative rounding selects is a valid
+    # supergradient, and Adam's normalised first step turns either into a full
+    # step.  Several trajectories are therefore correct; what is unique is the
+    # bound at the parameters reached (checked above at 1e-5) and that the
+    # ascent does not end below its start.
+    p = gen.make_tiny(kind, seed, B=2, splits=(1, 2), n_cuts=5, gamma_dist="zero")
+    g = _optimize_pi(p, O.full_rho(p))
+    g0 = O.bound_pi(p).reshape(-1)
+    assert np.mean(g) > np.mean(g0)
 
 
 def test_explicit_pi_invalid_inputs():
