@@ -47,7 +47,7 @@ def parse():
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--graph", action="store_true", help="replay the Adam iteration as a captured hipGraph")
-    ap.add_argument("--workload", choices=["mlp784", "cnn", "resnet", "batch"], default="mlp784")
+    ap.add_argument("--workload", choices=["mlp784", "cnn", "resnet", "batch", "bab"], default="mlp784")
     ap.add_argument("--roots", choices=["crown", "ibp"], default="crown",
                     help="root pre-activation bounds of the workload: the stored fp64 CROWN bounds or interval bounds")
     ap.add_argument("--retune", action="store_true",
@@ -56,9 +56,9 @@ def parse():
                     help="optimise pi of every unstable neuron too (gcp_optimize_pi) instead of Lemma A.1's pi*")
     a = ap.parse_args()
     if a.domains is None:
-        a.domains = {"mlp784": 1024, "cnn": 2048, "resnet": 4096, "batch": 0}[a.workload]
+        a.domains = {"mlp784": 1024, "cnn": 2048, "resnet": 4096, "batch": 0, "bab": 1024}[a.workload]
     if a.cpu_domains is None:
-        a.cpu_domains = {"mlp784": 384, "cnn": 96, "resnet": 16, "batch": 0}[a.workload]
+        a.cpu_domains = {"mlp784": 384, "cnn": 96, "resnet": 16, "batch": 0, "bab": 0}[a.workload]
     return a
 
 
@@ -107,6 +107,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "bab":
+        return bench_bab(args)
     prob = gen.make_workload(args.workload, 0, B=args.domains, roots=args.roots)
     P = B.Problem(prob, device=dev)
     M = P.M
@@ -222,8 +224,11 @@ def main():
         copy_bw = copy_bandwidth()
         out["roofline"]["achievable_copy_GBps"] = copy_bw
         out["config"]["kernels"] = kernel_table(kprof)
+    flagged = None
+    if not pi and mode == B.GCP_MODE_FP32:
+        flagged, out["outward"] = outward(B, P, alpha, beta, gamma, bound_main)
     if not pi:
-        out["oracle_error"] = oracle_error(prob, bound_main, par_main, 0)
+        out["oracle_error"] = oracle_error(prob, bound_main, par_main, 0, flagged=flagged)
     if not args.no_compare:
         other = B.GCP_MODE_FP32 if mode == B.GCP_MODE_BF16 else B.GCP_MODE_BF16
         osteps = max(1, args.steps // 2)
@@ -259,11 +264,45 @@ def main():
     print(json.dumps(out))
 
 
-def oracle_error(prob, bound, par, seed, n=64):
+def outward(B, P, alpha, beta, gamma, certified, reps=5):
+    """The certifying pass at the final parameters with GCP_FLAG_OUTWARD
+    (every bound minus its rounding slack) beside the plain one: verified
+    rows and the time of each form (HIP events around `reps` calls)."""
+    import numpy as np
+    import torch
+
+    def run(mode):
+        return B.bound(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, mode=mode, verified=True)
+
+    times = {}
+    for name, mode in (("plain", B.GCP_MODE_FP32), ("outward", B.GCP_MODE_FP32 | B.GCP_FLAG_OUTWARD)):
+        run(mode)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g, v, _ = run(mode)
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / reps
+        if name == "plain":
+            plain = g.cpu().numpy()
+        else:
+            flagged, vf = g.cpu().numpy(), v.cpu().numpy()
+    return flagged, {
+        "certified_equals_plain_pass": bool(np.array_equal(plain, certified)),
+        "verified_rows": int(vf.sum()), "verified_rows_plain": int((certified >= 0).sum()),
+        "slack_rel_max": float(np.max((certified - flagged) / np.maximum(np.abs(certified), 1e-300))),
+        "slack_rel_median": float(np.median((certified - flagged) / np.maximum(np.abs(certified), 1e-300))),
+        "ms_certifying_pass": times["plain"], "ms_certifying_pass_outward": times["outward"]}
+
+
+def oracle_error(prob, bound, par, seed, n=64, flagged=None):
     """Error of the device's certified bounds against the FP64 oracle at the
     device's final parameters, on a sample of rows (n random rows and the
     last 8): max |d| / max(|g|, T) (T = sum of the magnitudes of every term
-    of the bound) and max |d| / |g|."""
+    of the bound) and max |d| / |g|.  With ``flagged`` (the GCP_FLAG_OUTWARD
+    bounds at the same parameters) also how far those lie below the exact
+    value and their slack, in units of T."""
     import numpy as np
 
     from oracle import gcp_oracle as O
@@ -274,10 +313,16 @@ def oracle_error(prob, bound, par, seed, n=64):
     ref = O.bound(prob, a, b, c, rows=rows, flat=True)
     T = O.error_scale(prob, a, b, c, rows=rows, flat=True)
     d = np.abs(bound[rows] - ref)
-    return {"rows_sampled": int(rows.size), "max_rel_err_T": float((d / np.maximum(np.abs(ref), T)).max()),
-            "max_rel_err": float((d / np.abs(ref)).max()),
-            "sample": f"{rows.size} rows ({min(n, M - 8)} seeded random + the last 8), oracle bound (fp64) at the "
-                      "device's final alpha, beta, gamma"}
+    res = {"rows_sampled": int(rows.size), "max_rel_err_T": float((d / np.maximum(np.abs(ref), T)).max()),
+           "max_rel_err": float((d / np.abs(ref)).max()),
+           "rows_above_exact": int((bound[rows] > ref).sum()),
+           "sample": f"{rows.size} rows ({min(n, M - 8)} seeded random + the last 8), oracle bound (fp64) at the "
+                     "device's final alpha, beta, gamma"}
+    if flagged is not None:
+        res["outward_rows_above_exact"] = int((flagged[rows] > ref).sum())
+        res["outward_max_minus_exact_T"] = float(((flagged[rows] - ref) / T).max())
+        res["outward_slack_T_max"] = float(((bound[rows] - flagged[rows]) / T).max())
+    return res
 
 
 def scaled_diff(prob, b32, b16, par32, max_rows=20000):
@@ -424,6 +469,83 @@ def cpu_baseline(probs, nd, runs=3):
            "sample": f"first {nd} domains of {what} ({total} domains), same 20-iteration optimisation + final "
                      f"bound in float64; median of {runs} runs: {dt:.1f} s ({', '.join(f'{t:.1f}' for t in times)})"}
     return rec, g_first, rows_first
+
+
+def bench_bab(args):
+    """gcp_bab on one property of the 784-256x6-10 MLP (the spec row with the
+    largest root bound, 200 cuts): `domains` domains per bounding call,
+    splits up to depth 16, a budget of `steps` full batches.  One untimed
+    run of the same search first (it tunes every batch shape the search
+    meets), then the timed one; beside it gcp_optimize alone on one full
+    batch of the same shape, the rate the search would reach without its
+    own work."""
+    import numpy as np
+    import torch
+
+    from paper_2208_05740_amd import binding as B
+    from workloads import gen
+
+    dev = torch.device("cuda:0")
+    mode = B.GCP_MODE_BF16 if args.mode == "bf16" else B.GCP_MODE_FP32
+    prob = gen.make_workload("mlp784", 0, B=1, roots=args.roots)
+    P = B.Problem(prob, device=dev)
+    a0 = torch.tensor(gen.crown_alpha_init(prob.lu), dtype=torch.float32, device=dev).expand(P.M, -1).contiguous()
+    z = lambda n: torch.zeros(P.M, n, dtype=torch.float32, device=dev)  # noqa: E731
+    sp0 = B.Splits(P.net, gen.Splits(np.full((1, 0), -1, np.int32), np.zeros((1, 0), np.int32),
+                                     np.zeros((1, 0), np.int8)))
+    root, _, _ = B.bound(P.net, P.x0, P.eps, P.C, sp0, P.cuts, a0, z(0), z(P.N), mode=B.GCP_MODE_FP32)
+    s = int(torch.argmax(root).item())
+    c_row = P.C[s].contiguous()
+    o = prob.opt
+    budget = args.domains * args.steps
+    kw = dict(cuts=P.cuts, batch=args.domains, max_depth=16, max_domains=budget, max_pool=1 << 22, retries=0,
+              iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], mode=mode)
+    for _ in range(max(args.warmup, 1)):
+        B.bab(P.net, P.x0, P.eps, c_row, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = B.bab(P.net, P.x0, P.eps, c_row, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the bounding call alone at the full batch shape (one spec row per domain)
+    sp = B.Splits(P.net, gen.Splits(np.full((args.domains, 16), -1, np.int32), np.zeros((args.domains, 16), np.int32),
+                                    np.ones((args.domains, 16), np.int8)))
+    al = torch.tensor(gen.crown_alpha_init(prob.lu), dtype=torch.float32, device=dev).expand(args.domains, -1)
+    al = al.contiguous()
+    be = torch.zeros(args.domains, 16, dtype=torch.float32, device=dev)
+    ga = torch.zeros(args.domains, P.N, dtype=torch.float32, device=dev)
+    st = torch.zeros(B.adam_state_size(args.domains, P.n_I, 16, P.N), dtype=torch.float32, device=dev)
+
+    def opt():
+        B.optimize(P.net, P.x0, P.eps, c_row.reshape(1, -1), sp, P.cuts, al.clone(), be.clone(), ga.clone(),
+                   st.zero_(), iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                   mode=mode)
+    opt()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        opt()
+    torch.cuda.synchronize()
+    opt_rate = 3 * args.domains / (time.perf_counter() - t1)
+    value = res["bounded"] / dt
+    out = {
+        "metric": "BaB domains bounded/sec (fwd+adjoint iter) at fixed bound accuracy; % MFMA/HBM peak",
+        "value": value, "unit": "domains/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1000.0 / max(res["rounds"], 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
+        "config": {
+            "workload": f"branch and bound (gcp_bab) on one property of the MLP 784-256x6-10 (spec row {s}, the "
+                        f"largest root bound), 200 cuts, {args.domains} domains per bounding call, depth <= 16, "
+                        f"budget {budget} domains, 20 Adam iterations + certifying pass per call",
+            "root_bound": float(root[s].item()), "result": res,
+            "ms_per_round": dt * 1000.0 / max(res["rounds"], 1),
+            "optimize_only_domains_per_s": opt_rate,
+            "search_efficiency": value / opt_rate,
+            "note": "one spec row per domain (the headline line counts 9 per domain); ms_per_step is per round; "
+                    "the ramp-up rounds (1, 2, 4, ... domains) are inside the timed search",
+        },
+    }
+    print(json.dumps(out))
 
 
 def bench_batch(args):

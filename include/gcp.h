@@ -370,7 +370,9 @@ int gcp_crown_bounds_domain(const gcp_net_desc* desc, const double* x0, double e
  * beta = gamma = 0; a child starts from its parent's optimised alpha, beta
  * (its new split's multiplier at 0) and gamma, with fresh Adam moments; cuts
  * apply to every domain.  c: device fp64 [d_out] (one spec row); x0 as gcp_bound.
- * Synchronises `stream` once per round. */
+ * The open domains' alpha, beta and gamma stay on the device (a pool of
+ * rows); a round sends the device its split lists and row indices and reads
+ * back the batch's bounds, synchronising `stream` twice. */
 typedef struct {
   int32_t batch;           /* domains per bounding call, >= 1                */
   int32_t max_depth;       /* splits per domain at most (K slots)            */

@@ -13,8 +13,16 @@
 // multiplier at 0) and gamma, so a deep domain has accumulated the Adam
 // steps of all its ancestors; a domain that cannot be split further is
 // bounded again from its own optimum up to `retries` times before it counts
-// as unresolved.  Built only on the library's public calls.
+// as unresolved.
+//
+// The open domains' parameters stay on the device: a pool of rows (alpha,
+// beta, gamma of each open domain) from which a round gathers its batch and
+// into which it scatters the children's warm starts (the new split's beta
+// column zeroed) after the bounding call, so a round moves only row indices
+// to the device and the bounds back.  Built on the library's public calls
+// plus the row-copy kernel and the in-place split-handle refill.
 #include "../../include/gcp.h"
+#include "gcp_internal.h"
 
 #include <hip/hip_runtime.h>
 
@@ -42,7 +50,7 @@ struct Domain {
   std::vector<int32_t> split;    // indices into the unstable list
   std::vector<int8_t> sign;      // +1: x >= 0, -1: x <= 0
   double parent;                 // bound of the parent domain (-inf at the root)
-  std::vector<float> a, b, g;    // warm start (empty: alpha CROWN-adaptive, beta = gamma = 0)
+  int slot = 0;                  // pool row of the warm start (row 0: alpha CROWN-adaptive, beta = gamma = 0)
   int retry = 0;
 };
 
@@ -79,6 +87,55 @@ struct SplitsHandle {
   }
 };
 
+// Rows of the parameter pool (alpha [nI], beta [K], gamma [N] per row); row 0
+// is the root start and never freed.  Grows by doubling (device copy of the
+// rows in use).
+struct Pool {
+  int nI, K, N;
+  int cap = 0;
+  DevMem a, b, g;
+  std::vector<int> free_rows;
+  void grow(int want, hipStream_t st) {
+    int nc = std::max(cap * 2, want);
+    DevMem na, nb, ng;
+    na.need(std::max<size_t>((size_t)nc * nI * 4, 4));
+    nb.need(std::max<size_t>((size_t)nc * K * 4, 4));
+    ng.need(std::max<size_t>((size_t)nc * N * 4, 4));
+    if (cap > 0) {
+      if (nI) hcheck(hipMemcpyAsync(na.p, a.p, (size_t)cap * nI * 4, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+      if (K) hcheck(hipMemcpyAsync(nb.p, b.p, (size_t)cap * K * 4, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+      if (N) hcheck(hipMemcpyAsync(ng.p, g.p, (size_t)cap * N * 4, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+      hcheck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+    std::swap(a.p, na.p); std::swap(a.n, na.n);
+    std::swap(b.p, nb.p); std::swap(b.n, nb.n);
+    std::swap(g.p, ng.p); std::swap(g.n, ng.n);
+    for (int r = nc - 1; r >= std::max(cap, 1); --r) free_rows.push_back(r);
+    cap = nc;
+  }
+  int take(hipStream_t st) {
+    if (free_rows.empty()) grow(cap + 1, st);
+    const int r = free_rows.back();
+    free_rows.pop_back();
+    return r;
+  }
+  void release(int r) {
+    if (r > 0) free_rows.push_back(r);
+  }
+};
+
+// dst[dst_row[i]] = src[src_row[i]] for the index lists on the device, in
+// launches of at most 65535 rows
+void copy_rows(float* dst, int64_t ld_dst, const int32_t* dst_row, const float* src, int64_t ld_src,
+               const int32_t* src_row, int n, int L, const int32_t* zero_col, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += 65535) {
+    const int c = std::min(65535, n - i0);
+    hcheck(gcp::launch_copy_rows(dst, ld_dst, dst_row + i0, src, ld_src, src_row + i0, c, L,
+                                 zero_col ? zero_col + i0 : nullptr, st),
+           "row copy");
+  }
+}
+
 }  // namespace
 
 extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const double* c, const gcp_cuts* cuts,
@@ -114,9 +171,24 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
     R.status = GCP_BAB_UNKNOWN;
     double min_leaf = std::numeric_limits<double>::infinity();     // smallest verified leaf bound
     double min_open = std::numeric_limits<double>::infinity();     // smallest bound left unresolved
-    DevMem alpha, beta, gamma, state, bound, verified;
+    const int Kc = std::max(K, 1);
+    Pool P{nI, K, (int)N};
+    P.grow(std::max(2, std::min<int>(4 * o->batch + 1, 1 << 16)), st);
+    // row 0: the root start (alpha CROWN-adaptive, beta = gamma = 0; the
+    // pool's fresh memory is zero)
+    if (nI) hcheck(hipMemcpyAsync(P.a.p, arow.data(), (size_t)nI * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    if (K) hcheck(hipMemsetAsync(P.b.p, 0, (size_t)K * 4, st), "hipMemsetAsync");
+    if (N) hcheck(hipMemsetAsync(P.g.p, 0, (size_t)N * 4, st), "hipMemsetAsync");
+    DevMem alpha, beta, gamma, state, bound, verified, idx;
+    SplitsHandle sp;
     std::vector<double> hb;
+    // row-index lists of a round, staged on the host until the round's sync:
+    // [0, Bp) gather rows, then (dst, src, zero column) of the scatter
+    std::vector<int32_t> hidx;
     while (true) {
+      // the previous round's scatter is done before its host lists and
+      // device buffers are reused or regrown
+      hcheck(hipStreamSynchronize(st), "hipStreamSynchronize");
       if (pool.empty()) {
         if (R.unresolved == 0) R.status = GCP_BAB_VERIFIED;
         break;
@@ -127,14 +199,13 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
       if ((int)pool.size() > take)
         std::nth_element(pool.begin(), pool.begin() + take, pool.end(),
                          [](const Domain& a, const Domain& b) { return a.parent > b.parent; });
-      std::vector<Domain> sel(pool.begin(), pool.begin() + take);
+      std::vector<Domain> sel(std::make_move_iterator(pool.begin()), std::make_move_iterator(pool.begin() + take));
       pool.erase(pool.begin(), pool.begin() + take);
       // batch rows padded to a power of two (repeating the first domain) so
       // few distinct shapes are tuned
       int Bp = 1;
       while (Bp < take) Bp *= 2;
       Bp = std::min(Bp, std::max(o->batch, take));
-      const int Kc = std::max(K, 1);
       std::vector<int32_t> snode((size_t)Bp * Kc, -1), sneur((size_t)Bp * Kc, 0);
       std::vector<int8_t> ssign((size_t)Bp * Kc, 1);
       for (int b = 0; b < Bp; ++b) {
@@ -145,9 +216,8 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
           ssign[(size_t)b * Kc + k] = d.sign[k];
         }
       }
-      SplitsHandle sp;
-      check(gcp_splits_create(net, Bp, K, K ? snode.data() : nullptr, K ? sneur.data() : nullptr,
-                              K ? ssign.data() : nullptr, &sp.p));
+      check(gcp::splits_assign(net, &sp.p, Bp, K, K ? snode.data() : nullptr, K ? sneur.data() : nullptr,
+                               K ? ssign.data() : nullptr, st));
       const size_t M = (size_t)Bp;     // one spec row per domain
       alpha.need(std::max<size_t>(M * nI * 4, 4));
       beta.need(std::max<size_t>(M * K * 4, 4));
@@ -155,28 +225,47 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
       state.need(std::max<size_t>(2 * M * (nI + K + N) * 4, 4));
       bound.need(M * 8);
       verified.need(M);
-      std::vector<float> ha(M * nI), hbeta(M * K, 0.f), hg(M * N, 0.f);
+      // index lists: batch rows 0..Bp-1, their pool rows, then the scatter
+      // lists (destination pool row, source batch row, zeroed beta column;
+      // at most two entries per selected domain)
+      const size_t n_sc = 2 * (size_t)take;
+      hidx.assign(2 * M + 3 * n_sc, 0);
       for (size_t m = 0; m < M; ++m) {
-        const Domain& d = sel[m < (size_t)take ? m : 0];
-        std::copy(d.a.empty() ? arow.begin() : d.a.begin(), d.a.empty() ? arow.end() : d.a.end(), ha.begin() + m * nI);
-        std::copy(d.b.begin(), d.b.end(), hbeta.begin() + m * K);
-        if (!d.g.empty()) std::copy(d.g.begin(), d.g.end(), hg.begin() + m * N);
+        hidx[m] = (int32_t)m;
+        hidx[M + m] = sel[m < (size_t)take ? m : 0].slot;
       }
-      if (nI) hcheck(hipMemcpyAsync(alpha.p, ha.data(), ha.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
-      if (K) hcheck(hipMemcpyAsync(beta.p, hbeta.data(), hbeta.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
-      if (N) hcheck(hipMemcpyAsync(gamma.p, hg.data(), hg.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+      idx.need(hidx.size() * 4);
+      const int32_t* d_rows = (const int32_t*)idx.p;
+      const int32_t* d_slots = d_rows + M;
+      hcheck(hipMemcpyAsync(idx.p, hidx.data(), 2 * M * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+      copy_rows((float*)alpha.p, nI, d_rows, (const float*)P.a.p, nI, d_slots, (int)M, nI, nullptr, st);
+      copy_rows((float*)beta.p, K, d_rows, (const float*)P.b.p, K, d_slots, (int)M, K, nullptr, st);
+      copy_rows((float*)gamma.p, N, d_rows, (const float*)P.g.p, N, d_slots, (int)M, N, nullptr, st);
+      for (Domain& d : sel) {     // their rows are read before any later write on this stream
+        P.release(d.slot);
+        d.slot = 0;
+      }
       hcheck(hipMemsetAsync(state.p, 0, 2 * M * (nI + K + N) * 4, st), "hipMemsetAsync");
       check(gcp_optimize(net, x0, eps, c, 1, sp.p, cuts, nI ? (float*)alpha.p : nullptr, K ? (float*)beta.p : nullptr,
                          N ? (float*)gamma.p : nullptr, (float*)state.p, &o->opt, o->mode, (double*)bound.p,
                          (uint8_t*)verified.p, stream));
       hb.resize(M);
       hcheck(hipMemcpyAsync(hb.data(), bound.p, M * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-      if (nI) hcheck(hipMemcpyAsync(ha.data(), alpha.p, (size_t)take * nI * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-      if (K) hcheck(hipMemcpyAsync(hbeta.data(), beta.p, (size_t)take * K * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-      if (N) hcheck(hipMemcpyAsync(hg.data(), gamma.p, (size_t)take * N * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
       hcheck(hipStreamSynchronize(st), "hipStreamSynchronize");
       R.bounded += take;
       R.rounds += 1;
+      // children (and retried domains) take pool rows holding this round's
+      // optimum of their parent (the new split's beta column zeroed)
+      int32_t* dst = hidx.data() + 2 * M;
+      int32_t* src = dst + n_sc;
+      int32_t* zc = src + n_sc;
+      int n_copy = 0;
+      auto keep = [&](int b, int zero_col) {
+        const int r = P.take(st);
+        dst[n_copy] = r; src[n_copy] = b; zc[n_copy] = zero_col;
+        ++n_copy;
+        return r;
+      };
       for (int b = 0; b < take; ++b) {
         Domain& d = sel[b];
         const double g = hb[b];
@@ -185,10 +274,6 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
           min_leaf = std::min(min_leaf, g);
           continue;
         }
-        // optimised parameters of this domain: its children's start
-        d.a.assign(ha.begin() + (size_t)b * nI, ha.begin() + (size_t)(b + 1) * nI);
-        d.b.assign(hbeta.begin() + (size_t)b * K, hbeta.begin() + (size_t)b * K + d.split.size());
-        d.g.assign(hg.begin() + (size_t)b * N, hg.begin() + (size_t)(b + 1) * N);
         int next = -1;
         if ((int)d.split.size() < K)
           for (int r : order)
@@ -200,6 +285,7 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
           if (d.retry < o->retries) {
             d.retry += 1;
             d.parent = g;
+            d.slot = keep(b, -1);
             pool.push_back(std::move(d));
             continue;
           }
@@ -212,14 +298,20 @@ extern "C" int gcp_bab(const gcp_net* net, const double* x0, double eps, const d
           ch.split = d.split;
           ch.sign = d.sign;
           ch.parent = g;
-          ch.a = d.a;
-          ch.b = d.b;
-          ch.g = d.g;
+          ch.slot = keep(b, (int)d.split.size());
           ch.split.push_back(next);
           ch.sign.push_back(sg);
-          ch.b.push_back(0.f);
           pool.push_back(std::move(ch));
         }
+      }
+      if (n_copy > 0) {
+        int32_t* d_dst = (int32_t*)idx.p + 2 * M;
+        int32_t* d_src = d_dst + n_sc;
+        int32_t* d_zc = d_src + n_sc;
+        hcheck(hipMemcpyAsync(d_dst, dst, 3 * n_sc * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        copy_rows((float*)P.a.p, nI, d_dst, (const float*)alpha.p, nI, d_src, n_copy, nI, nullptr, st);
+        copy_rows((float*)P.b.p, K, d_dst, (const float*)beta.p, K, d_src, n_copy, K, d_zc, st);
+        copy_rows((float*)P.g.p, N, d_dst, (const float*)gamma.p, N, d_src, n_copy, N, nullptr, st);
       }
       R.max_open = std::max<int64_t>(R.max_open, (int64_t)pool.size());
     }

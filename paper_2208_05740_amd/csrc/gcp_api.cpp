@@ -290,6 +290,9 @@ struct gcp_splits {
   int B = 0, K = 0;
   DBuf mask;        // int8 [B][n_I]
   DBuf zsplit;      // fp64 [B][K]: max(|l|, |u|) of slot k's neuron (0: unused slot), for outward rounding
+  // host staging of splits_assign (kept until the handle is refilled again)
+  std::vector<int8_t> mask_h;
+  std::vector<double> zs_h;
   const gcp_net* net = nullptr;
 };
 
@@ -875,14 +878,16 @@ extern "C" int gcp_cuts_destroy(gcp_cuts* c) {
   return GCP_OK;
 }
 
-extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const int32_t* node,
-                                 const int32_t* neuron, const int8_t* sign, gcp_splits** out) {
-  GCP_TRY
-  if (!net || !out) fail(GCP_EINVAL, "null argument");
+namespace {
+// The device form of B domains' splits: mask [B][n_I] (0, +(slot+1) for
+// x >= 0, -(slot+1) for x <= 0) and zsplit [B][K]; validates as
+// gcp_splits_create documents.
+void split_arrays(const gcp_net* net, int32_t B, int32_t K, const int32_t* node, const int32_t* neuron,
+                  const int8_t* sign, std::vector<int8_t>& mask, std::vector<double>& zs) {
   if (B <= 0 || K < 0 || K > 127) fail(GCP_EINVAL, "need B >= 1 and 0 <= K <= 127");
   if (K > 0 && (!node || !neuron || !sign)) fail(GCP_EINVAL, "null split array");
-  std::vector<int8_t> mask((size_t)B * net->n_I, 0);
-  std::vector<double> zs((size_t)B * K, 0.0);
+  mask.assign((size_t)B * net->n_I, 0);
+  zs.assign((size_t)B * K, 0.0);
   for (int b = 0; b < B; ++b)
     for (int k = 0; k < K; ++k) {
       size_t i = (size_t)b * K + k;
@@ -900,6 +905,16 @@ extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const
       mm = (int8_t)(sign[i] > 0 ? (k + 1) : -(k + 1));
       zs[i] = n.z_h[j];
     }
+}
+}  // namespace
+
+extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const int32_t* node,
+                                 const int32_t* neuron, const int8_t* sign, gcp_splits** out) {
+  GCP_TRY
+  if (!net || !out) fail(GCP_EINVAL, "null argument");
+  std::vector<int8_t> mask;
+  std::vector<double> zs;
+  split_arrays(net, B, K, node, neuron, sign, mask, zs);
   auto S = std::make_unique<gcp_splits>();
   S->B = B; S->K = K; S->net = net;
   S->mask.upload(mask);
@@ -909,6 +924,33 @@ extern "C" int gcp_splits_create(const gcp_net* net, int32_t B, int32_t K, const
   return GCP_OK;
   GCP_CATCH
 }
+
+namespace gcp {
+int splits_assign(const gcp_net* net, gcp_splits** s, int32_t B, int32_t K, const int32_t* node,
+                  const int32_t* neuron, const int8_t* sign, hipStream_t st) {
+  GCP_TRY
+  if (!net || !s) fail(GCP_EINVAL, "null argument");
+  gcp_splits* h = *s;
+  if (h && h->net != net) fail(GCP_EINVAL, "splits were created for another net");
+  if (!h || h->mask.bytes < (size_t)B * net->n_I || h->zsplit.bytes < (size_t)B * K * 8) {
+    if (h) gcp_splits_destroy(h);
+    *s = nullptr;
+    return gcp_splits_create(net, B, K, node, neuron, sign, s);
+  }
+  split_arrays(net, B, K, node, neuron, sign, h->mask_h, h->zs_h);
+  if (!h->mask_h.empty())
+    hip_check(hipMemcpyAsync(h->mask.p, h->mask_h.data(), h->mask_h.size(), hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+  if (!h->zs_h.empty())
+    hip_check(hipMemcpyAsync(h->zsplit.p, h->zs_h.data(), h->zs_h.size() * 8, hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+  h->B = B; h->K = K;
+  h->id = next_generation();   // new contents: cached plans keyed on the handle do not match it
+  g_err.clear();
+  return GCP_OK;
+  GCP_CATCH
+}
+}  // namespace gcp
 
 extern "C" int gcp_splits_destroy(gcp_splits* s) {
   delete s;

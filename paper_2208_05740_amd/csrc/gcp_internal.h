@@ -256,6 +256,11 @@ hipError_t launch_adam_prepare(int* step, int reset, float lr_alpha, float lr_mu
 hipError_t launch_adam_table(float* tab, int iters, float lr_alpha, float lr_mult, float decay, float b1, float b2,
                              hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+// dst[dst_row[i]][j] = src[src_row[i]][j] for i < n (n <= 65535), j < L; where
+// zero_col is given, column zero_col[i] of row i is written as 0 instead.
+// Row indices are device arrays.
+hipError_t launch_copy_rows(float* dst, int64_t ld_dst, const int32_t* dst_row, const float* src, int64_t ld_src,
+                            const int32_t* src_row, int n, int L, const int32_t* zero_col, hipStream_t st);
 hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* flags,
                            hipStream_t st);
 hipError_t launch_fill_bf16_from_f32(const float* src, bf16* dst, int64_t n, hipStream_t st);
@@ -297,6 +302,18 @@ struct ChainArgs {
 };
 // lds_bytes: 2 kChainRows P esz + kChainRows sign_ld
 hipError_t launch_chain_opt(int bf16, const ChainArgs& a, int n_tiles, size_t lds_bytes, hipStream_t st);
+
+}  // namespace gcp
+struct gcp_net;
+struct gcp_splits;
+namespace gcp {
+// A split handle of `net` holding B domains of K slots (host arrays as
+// gcp_splits_create takes them): *s is refilled in place, asynchronously on
+// st, when its buffers are large enough (the host arrays are staged in the
+// handle, which must not be refilled again before the copies are done),
+// else replaced by a new handle.  Returns a GCP_* code.
+int splits_assign(const gcp_net* net, gcp_splits** s, int32_t B, int32_t K, const int32_t* node,
+                  const int32_t* neuron, const int8_t* sign, hipStream_t st);
 
 // Static workspace (scratch.hip): the device address and size of the calling
 // thread's current device's copy, looked up on its first use on that device.

@@ -842,6 +842,25 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dst[dst_row[i]][j] = src[src_row[i]][j] (0 where j == zero_col[i]), j < L
+__global__ void __launch_bounds__(256) copy_rows_kernel(float* dst, int64_t ld_dst, const int32_t* dst_row,
+                                                        const float* src, int64_t ld_src, const int32_t* src_row,
+                                                        int L, const int32_t* zero_col) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  const float v = src[(int64_t)src_row[i] * ld_src + j];
+  dst[(int64_t)dst_row[i] * ld_dst + j] = (zero_col && zero_col[i] == j) ? 0.f : v;
+}
+hipError_t launch_copy_rows(float* dst, int64_t ld_dst, const int32_t* dst_row, const float* src, int64_t ld_src,
+                            const int32_t* src_row, int n, int L, const int32_t* zero_col, hipStream_t st) {
+  if (n <= 0 || L <= 0) return hipSuccess;
+  if (n > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3((L + 255) / 256, n), dim3(256), 0, st, dst, ld_dst, dst_row, src, ld_src,
+                     src_row, L, zero_col);
+  return hipGetLastError();
+}
+
 // flags[0] |= 1 if any value is not finite, |= 2 if outside [lo, hi]
 __global__ void validate_kernel(const float* p, int64_t n, float lo, float hi, int* flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
