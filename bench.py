@@ -52,6 +52,9 @@ def parse():
                     help="root pre-activation bounds of the workload: the stored fp64 CROWN bounds or interval bounds")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every GEMM/conv tile afresh instead of starting from the shipped MI355X choices")
+    ap.add_argument("--persist", action="store_true",
+                    help="run the Adam iterations as one persistent dataflow launch (GCP_FLAG_PERSIST; dense nets; "
+                         "with --workload batch every instance shares that launch)")
     ap.add_argument("--explicit-pi", action="store_true",
                     help="optimise pi of every unstable neuron too (gcp_optimize_pi) instead of Lemma A.1's pi*")
     a = ap.parse_args()
@@ -133,7 +136,8 @@ def main():
         gamma.copy_(gamma0)
         state.zero_()
         kw = dict(iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
-                  b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode, use_graph=use_graph[0])
+                  b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode | (B.GCP_FLAG_PERSIST if args.persist else 0),
+                  use_graph=use_graph[0])
         if explicit:
             rho.copy_(rho0)
             b, v = B.optimize_pi(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, alpha, beta, gamma, rho, state, **kw)
@@ -584,8 +588,8 @@ def bench_batch(args):
     def step_batched():
         reset()
         B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
-                         b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode,
-                         use_graph=use_graph[0])
+                         b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"],
+                         mode=mode | (B.GCP_FLAG_PERSIST if args.persist else 0), use_graph=use_graph[0])
 
     def step_single():
         reset()
@@ -636,8 +640,10 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
         "config": {
             "workload": f"GCP-CROWN batch: {len(probs)} MLP instances (depth 3-9, width 64-1024, input 784/3072, "
-                        f"16-4096 domains log-uniform, 50-1000 cuts, 9 spec rows), grouped launches, 20 Adam "
+                        f"16-4096 domains log-uniform, 50-1000 cuts, 9 spec rows), "
+                        f"{'one persistent launch' if args.persist else 'grouped launches'}, 20 Adam "
                         f"iterations + certifying pass",
+            "persistent_launch": bool(args.persist),
             "instances": len(probs), "domains": dom, "rows": sum(P.M for P in Ps), "graph_replay": args.graph,
             "per_instance_launches": {"value": dom * args.steps / dts, "ms_per_step": dts * 1000.0 / args.steps},
             "speedup_vs_per_instance": dts / dt,

@@ -189,6 +189,20 @@ int gcp_splits_destroy(gcp_splits* splits);
  * bounds of gcp_crown_bounds / gcp_crown_bounds_domain; gradients are those
  * of the bound without the slack.  Costs one extra read of every Lambda. */
 #define GCP_FLAG_OUTWARD     0x800
+/* Persistent dataflow iterations (gcp_optimize, gcp_optimize_batch): every
+ * (domain, spec row) of Theorem 3.1 is an independent problem, so a layer's
+ * step over a panel of rows needs only the earlier steps over the same rows.
+ * With GCP_FLAG_PERSIST the Adam iterations run as one launch whose
+ * workgroups claim (iteration, step, column tile, row panel) items in
+ * schedule order and wait per panel for the steps before, instead of one
+ * launch per layer (and, in gcp_optimize_batch, every instance shares that
+ * one launch).  Results are bit-identical to the per-layer launches.  Used
+ * for networks whose edges are all dense, whose output takes the c-hat form
+ * and whose a_hat is stored (Lemma A.1's pi*); otherwise the flag is
+ * ignored.  The first call of an argument set runs one iteration per layer
+ * (tile tuning, buffer sizing) and records the schedule; later calls with
+ * the same arguments run every iteration in the one launch. */
+#define GCP_FLAG_PERSIST     0x1000
 /* In every mode the row reductions (concretisation v.x0 - eps*|v|_1, bias,
  * h and cut-offset sums, gamma.d) accumulate in fp64; the bound is fp64. */
 

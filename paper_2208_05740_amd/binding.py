@@ -22,6 +22,7 @@ GCP_FLAG_VALIDATE = 0x100
 GCP_FLAG_RECOMPUTE = 0x200     # recompute a_hat in the adjoint wherever possible
 GCP_FLAG_STORE_AHAT = 0x400    # store a_hat of every layer
 GCP_FLAG_OUTWARD = 0x800       # subtract the pass's rounding slack from every bound
+GCP_FLAG_PERSIST = 0x1000      # iterations as one persistent dataflow launch (dense nets)
 EDGE_KIND = {"dense": 0, "conv": 1, "identity": 2}
 ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE", -6: "EUNSUPPORTED"}
 

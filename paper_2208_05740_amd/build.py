@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgcp.so")
 ARCH = os.environ.get("GCP_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["kernels.hip", "conv_kernels.hip", "chain_kernels.hip", "scratch.hip", "gcp_api.cpp", "bab.cpp"]
+SOURCES = ["kernels.hip", "conv_kernels.hip", "chain_kernels.hip", "persist_kernels.hip", "scratch.hip", "gcp_api.cpp", "bab.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 instructions are left to ordinary float code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -186,6 +187,19 @@ struct DBuf {
   template <class T> T* as() const { return (T*)p; }
 };
 
+// A recorded iteration schedule laid out for the persistent dataflow kernel
+// (tables in one device buffer) and its synchronisation words.
+struct PersistPlan {
+  std::vector<uintptr_t> key;
+  DBuf buf;          // steps, per-queue first items, GEMM arguments, epilogue blobs, elementwise and gamma jobs
+  DBuf sync;         // claim heads, abort flag, panel counters (zeroed before every launch)
+  size_t n_sync = 0;
+  PersistArgs args{};
+  int grid = 0;
+  int max_items = 0;   // most items one queue has in one iteration
+  double bytes = 0.0, alg = 0.0, flops = 0.0;   // per iteration, both byte models and the GEMM FLOPs
+};
+
 struct EdgeH {
   int src, dst, kind;
   int kh = 0, kw = 0, stride = 1, pad = 0;
@@ -253,6 +267,8 @@ struct gcp_net {
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<uintptr_t> gkey;
+    // persistent dataflow launch of gcp_optimize's iterations (one argument set)
+    std::unique_ptr<PersistPlan> pplan;
     uint64_t gen = 0;   // new process-unique value whenever a workspace buffer is reallocated
     std::vector<int> chat_off;   // offset (floats) of each node's c-hat block
     int n_slots = 0;
@@ -978,6 +994,196 @@ struct Recorder {
   bool in_adj = false;
   void push(const Rec& r) { (in_adj ? adj : bound).push_back(r); }
 };
+
+// ---------------------------------------------------------------- persistent dataflow plans
+// How the persistent launches order their workgroups: with one claim queue
+// per XCD (the probe found the XCDs), a producer's stores need only reach
+// the L2 its consumers share; otherwise agent-scope release fences write
+// the L2 back.  GCP_PERSIST_SYNC=agent forces the latter.
+int persist_xcd_sync(int queues) {
+  const char* e = std::getenv("GCP_PERSIST_SYNC");
+  if (e && std::strcmp(e, "agent") == 0) return 0;
+  return queues > 1 ? 1 : 0;
+}
+
+// Claim queues of the current device: the number of XCDs its workgroups
+// report (the hardware XCC_ID register of a probe launch), when the ids are
+// exactly 0 .. n-1 with n <= 8; else 1 (one queue, no XCD locality).
+int persist_queues() {
+  static std::mutex mu;
+  static std::map<int, int> by_dev;
+  int dev;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = by_dev.find(dev);
+  if (it != by_dev.end()) return it->second;
+  int cus = 0;
+  hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  const int n = std::max(64, cus * 4);
+  DBuf out;
+  out.alloc((size_t)n * sizeof(int));
+  hip_check(launch_xcc_probe(out.as<int>(), n, nullptr), "xcc probe");
+  std::vector<int> ids(n);
+  hip_check(hipMemcpy(ids.data(), out.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+  std::set<int> seen(ids.begin(), ids.end());
+  int q = (int)seen.size();
+  if (q > 8 || *seen.begin() != 0 || *seen.rbegin() != q - 1) q = 1;
+  by_dev[dev] = q;
+  return q;
+}
+
+// One instance's recorded iteration: its bound-pass and adjoint launches in
+// order, and its multiplier update.
+struct PersistInst {
+  const Recorder* rec;
+  bool has_gamma;
+  GammaJob gj;
+  int M;
+};
+
+// Lays the instances' schedules out as persistent steps: the w-th bound
+// launch of every instance, then the w-th adjoint launch of every instance,
+// then every multiplier update (dependent steps of one instance as far apart
+// in the queue as the schedule allows).  Returns false when the schedule
+// does not fit the kernel's step table.
+bool build_persist(PersistPlan& plan, const std::vector<PersistInst>& in, int bf16) {
+  const int n = (int)in.size();
+  const int Q = persist_queues();
+  const int xcd = persist_xcd_sync(Q);
+  struct Ord { int inst; const Rec* r; };
+  std::vector<Ord> order;
+  size_t maxb = 0, maxa = 0;
+  for (const auto& x : in) { maxb = std::max(maxb, x.rec->bound.size()); maxa = std::max(maxa, x.rec->adj.size()); }
+  for (size_t w = 0; w < maxb; ++w)
+    for (int i = 0; i < n; ++i) if (w < in[i].rec->bound.size()) order.push_back({i, &in[i].rec->bound[w]});
+  for (size_t w = 0; w < maxa; ++w)
+    for (int i = 0; i < n; ++i) if (w < in[i].rec->adj.size()) order.push_back({i, &in[i].rec->adj[w]});
+  for (int i = 0; i < n; ++i) if (in[i].has_gamma) order.push_back({i, nullptr});
+  const int ns = (int)order.size();
+  if (ns == 0 || ns > kPersistMaxSteps) return false;
+  std::vector<int> panels(n), base(n), acc(n, 0);
+  int tot = 0;
+  for (int i = 0; i < n; ++i) {
+    panels[i] = (in[i].M + kPersistRows - 1) / kPersistRows;
+    base[i] = tot;
+    tot += panels[i];
+  }
+  std::vector<PersistStep> steps;
+  std::vector<int> step_inst;
+  std::vector<GemmArgs> gemm;
+  std::vector<unsigned char> epi;
+  std::vector<ElemBoundJob> elem;
+  std::vector<GammaJob> gam;
+  plan.bytes = plan.alg = plan.flops = 0.0;
+  for (const Ord& o : order) {
+    PersistStep st{};
+    st.cnt0 = base[o.inst];
+    st.panels = panels[o.inst];
+    st.base = base[o.inst];
+    if (!o.r) {
+      const GammaJob& gj = in[o.inst].gj;
+      st.kind = PK_GAMMA;
+      st.job = (int)gam.size();
+      gam.push_back(gj);
+      st.ipp = (gj.N + 31) / 32;
+      plan.bytes += (double)gj.M * (gj.N * 24.0);
+      plan.alg += (double)gj.M * gj.N * 28.0;
+    } else if (o.r->type == 1) {
+      st.kind = PK_ELEM;
+      st.job = (int)elem.size();
+      elem.push_back(o.r->ej);
+      st.ipp = (o.r->ej.a.nd.size + 255) / 256 * (kPersistRows / kElemRows);   // one item per kElemRows rows
+      plan.bytes += o.r->bytes;
+      plan.alg += o.r->alg;
+    } else {
+      if (o.r->kind == EPI_AHAT) return false;
+      st.kind = o.r->kind;
+      st.sign = o.r->sign;
+      st.job = (int)gemm.size();
+      gemm.push_back(o.r->g);
+      const size_t off = epi.size();
+      epi.resize(off + kEpiBlob, 0);
+      std::memcpy(epi.data() + off, o.r->epi, sizeof(o.r->epi));
+      st.ipp = (o.r->g.N + 31) / 32;
+      plan.bytes += o.r->bytes;
+      plan.alg += o.r->alg;
+      plan.flops += o.r->flops;
+    }
+    if (st.ipp <= 0) continue;
+    st.wait = acc[o.inst];
+    acc[o.inst] += st.ipp;
+    steps.push_back(st);
+    step_inst.push_back(o.inst);
+  }
+  for (size_t k = 0; k < steps.size(); ++k) steps[k].per_iter = acc[step_inst[k]];
+  const int nst = (int)steps.size();
+  // per queue: first item of every step within an iteration
+  std::vector<int> qfirst((size_t)Q * (nst + 1));
+  for (int q = 0; q < Q; ++q) {
+    int a = 0;
+    for (int k = 0; k < nst; ++k) {
+      qfirst[(size_t)q * (nst + 1) + k] = a;
+      const PersistStep& st = steps[k];
+      const int r = ((q - st.base) % Q + Q) % Q;
+      const int owned = r < st.panels ? (st.panels - 1 - r) / Q + 1 : 0;
+      a += owned * st.ipp;
+    }
+    qfirst[(size_t)q * (nst + 1) + nst] = a;
+    plan.max_items = std::max(plan.max_items, a);
+  }
+  // one device buffer: [steps][qfirst][gemm][epi][elem][gam], 256-byte aligned parts
+  std::vector<unsigned char> host;
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + std::max<size_t>(bytes, 1), 0);
+    if (bytes) std::memcpy(host.data() + off, src, bytes);
+    return off;
+  };
+  const size_t o_steps = put(steps.data(), steps.size() * sizeof(PersistStep));
+  const size_t o_q = put(qfirst.data(), qfirst.size() * sizeof(int));
+  const size_t o_g = put(gemm.data(), gemm.size() * sizeof(GemmArgs));
+  const size_t o_e = put(epi.data(), epi.size());
+  const size_t o_el = put(elem.data(), elem.size() * sizeof(ElemBoundJob));
+  const size_t o_gm = put(gam.data(), gam.size() * sizeof(GammaJob));
+  plan.buf.upload(host);
+  unsigned char* b = (unsigned char*)plan.buf.p;
+  plan.n_sync = (size_t)Q + 1 + tot;
+  plan.sync.alloc(plan.n_sync * sizeof(int));
+  PersistArgs& a = plan.args;
+  a = PersistArgs{};
+  a.steps = (const PersistStep*)(b + o_steps);
+  a.n_steps = nst;
+  a.qfirst = (const int*)(b + o_q);
+  a.Q = Q;
+  a.gemm = (const GemmArgs*)(b + o_g);
+  a.epi = b + o_e;
+  a.elem = (const ElemBoundJob*)(b + o_el);
+  a.gam = (const GammaJob*)(b + o_gm);
+  a.sync = plan.sync.as<int>();
+  a.xcd_sync = xcd;
+  plan.grid = persist_grid(bf16, xcd);
+  if (plan.grid <= 0) fail(GCP_EDEVICE, "persistent launch: occupancy query failed");
+  return true;
+}
+
+// `iters` iterations of the plan in one launch, iteration t with the Adam
+// constants of iteration iter0 + t from the table `tab`.
+void run_persist(PersistPlan& plan, int bf16, int iters, int iter0, const AdamArgs& adam_tab, hipStream_t st) {
+  // iterations per launch: a queue's items stay below the abort offset
+  const int per_launch = std::max(1, (kPersistAbort / 2) / std::max(plan.max_items, 1));
+  for (int done = 0; done < iters; done += per_launch) {
+    const int n = std::min(per_launch, iters - done);
+    hip_check(launch_fill_f32((float*)plan.sync.p, (int64_t)plan.n_sync, 0.f, st), "persist sync reset");
+    PersistArgs a = plan.args;
+    a.iters = n;
+    a.iter0 = iter0 + done;
+    a.adam = adam_tab;
+    hip_check(timed(st, bf16 ? "persist.bf16" : "persist.fp32",
+                    Bytes{plan.bytes * n, plan.alg * n}, plan.flops * n,
+                    [&] { return launch_persist(bf16, a, plan.grid, st); }),
+              "persistent launch");
+  }
+}
 
 struct Call {
   Recorder* rec = nullptr;
@@ -2033,6 +2239,33 @@ void run_chain(Call& c, int bf16, const ChainPlan& pl, float* alpha, float* beta
             "fused chain");
 }
 
+// constants of the output layer for one call (c-hat = C W, C b_out)
+void launch_constants(Call& c) {
+  gcp_net* net = c.net;
+  auto& ws = *c.ws;
+  if (net->out_general) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
+  const NodeH& on = net->nodes[net->out];
+  hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");
+  for (int eid : on.in_edges) {
+    const EdgeH& E = *net->edges[eid];
+    hip_check(launch_chat(c.C, c.S, on.size, E.Wraw.as<float>(), E.d_src, E.kind == GCP_EDGE_IDENTITY ? 2 : 0,
+                          ws.chat.as<float>() + ws.chat_off[E.src], net->nodes[E.src].ld, c.st),
+              "c-hat");
+  }
+}
+
+// Whether a call's iterations can run as one persistent launch: every edge
+// dense (the recorded schedule is GEMM, elementwise and multiplier steps over
+// rows), the output in the c-hat form, Lemma A.1's pi*, a_hat stored.
+bool persist_eligible(const Call& c) {
+  if (c.net->out_general || c.rp.rho || c.M <= 0) return false;
+  for (const auto& e : c.net->edges)
+    if (e->kind != GCP_EDGE_DENSE) return false;
+  for (uint8_t r : c.recompute)
+    if (r) return false;
+  return true;
+}
+
 // gcp_optimize and gcp_optimize_pi (rho non-null: explicit pi, its Adam
 // moments after gamma's in adam_state)
 void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const double* C, int32_t S,
@@ -2094,17 +2327,8 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
                 }),
                 "gamma update");
   };
-  int done = 0;
-  if (chain.ok && opt->iters > 0) {   // every iteration in one launch
-    run_chain(c, bf16, chain, alpha, beta, ma, va, mb, vb, mg, vg, opt);
-    done = opt->iters;
-  }
-  if (done == 0 && opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
-    iteration(c, 0);
-    done = 1;
-    c.consts_done = !net->out_general || !bf16;
-  }
-  if (opt->use_graph && opt->iters > 1 && done < opt->iters) {
+  // the argument set a captured graph or a persistent plan was made for
+  auto plan_key = [&]() {
     std::vector<uintptr_t> key = {(uintptr_t)x0, (uintptr_t)C, (uintptr_t)splits->id, (uintptr_t)(c.cuts ? c.cuts->id : 0),
                                   (uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)gamma, (uintptr_t)rho,
                                   (uintptr_t)adam_state,
@@ -2116,6 +2340,59 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
       std::memcpy(&b, &v, 4);
       key.push_back(b);
     }
+    return key;
+  };
+  int done = 0;
+  if (chain.ok && opt->iters > 0) {   // every iteration in one launch
+    run_chain(c, bf16, chain, alpha, beta, ma, va, mb, vb, mg, vg, opt);
+    done = opt->iters;
+  }
+  // GCP_FLAG_PERSIST: the iterations as one persistent dataflow launch over
+  // the recorded schedule of one iteration (dense networks in the c-hat
+  // form, Lemma A.1's pi*, a_hat stored); bit-identical to the eager loop
+  if (done == 0 && opt->iters > 0 && (mode & GCP_FLAG_PERSIST) && persist_eligible(c)) {
+    const AdamArgs tab{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws.adam_tab.as<float>()};
+    std::vector<uintptr_t> key = plan_key();
+    key.push_back((uintptr_t)persist_xcd_sync(persist_queues()));
+    if (ws.pplan && ws.pplan->key == key) {
+      launch_constants(c);
+      run_persist(*ws.pplan, bf16, opt->iters, 0, tab, c.st);
+      done = opt->iters;
+    } else {
+      iteration(c, 0);   // tunes the per-layer tiles the schedule records, sizes buffers
+      done = 1;
+      c.consts_done = true;
+      key = plan_key();
+      key.push_back((uintptr_t)persist_xcd_sync(persist_queues()));
+      Recorder rec;
+      Call cr = c;
+      cr.rec = &rec;
+      BoundPass bp(cr, bf16, true, cr.nnz > 0, false);
+      bp.run();
+      rec.in_adj = true;
+      AdjPass ap{cr, bf16, adam, nullptr, nullptr, alpha, beta, ma, va, mb, vb};
+      ap.run();
+      std::vector<PersistInst> in{PersistInst{&rec, N > 0,
+                                              GammaJob{c.M, c.rp.mp, (int)N, N > 0 ? c.cuts->row_ptr.as<int32_t>() : nullptr,
+                                                       ws.contrib.as<float>(), N > 0 ? c.cuts->d.as<double>() : nullptr,
+                                                       ws.gammaT.as<float>(), mg, vg},
+                                              c.M}};
+      auto plan = std::make_unique<PersistPlan>();
+      plan->key = key;
+      if (build_persist(*plan, in, bf16)) {
+        ws.pplan = std::move(plan);
+        run_persist(*ws.pplan, bf16, opt->iters - done, done, tab, c.st);
+        done = opt->iters;
+      }
+    }
+  }
+  if (done == 0 && opt->iters > 0) {   // the first iteration runs eagerly (tunes tiles, sizes buffers)
+    iteration(c, 0);
+    done = 1;
+    c.consts_done = !net->out_general || !bf16;
+  }
+  if (opt->use_graph && opt->iters > 1 && done < opt->iters) {
+    std::vector<uintptr_t> key = plan_key();
     if (!ws.gstream) hip_check(hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking), "hipStreamCreate");
     // the replays continue the count from the eager iterations done so far
     hip_check(launch_adam_prepare(ws.step.as<int>(), done + 1, 0, 0, 0, 0, 0, nullptr, c.st), "adam step");
@@ -2297,20 +2574,6 @@ extern "C" int gcp_profile_read(int32_t idx, char* name, int32_t name_len, int64
 
 namespace {
 
-// constants of the output layer for one call (c-hat = C W, C b_out)
-void launch_constants(Call& c) {
-  gcp_net* net = c.net;
-  auto& ws = *c.ws;
-  if (net->out_general) fail(GCP_EUNSUPPORTED, "grouped launches need the c-hat form of the output");
-  const NodeH& on = net->nodes[net->out];
-  hip_check(launch_out_const(c.C, c.S, on.size, on.bias.as<float>(), ws.cb.as<double>(), c.st), "out const");
-  for (int eid : on.in_edges) {
-    const EdgeH& E = *net->edges[eid];
-    hip_check(launch_chat(c.C, c.S, on.size, E.Wraw.as<float>(), E.d_src, E.kind == GCP_EDGE_IDENTITY ? 2 : 0,
-                          ws.chat.as<float>() + ws.chat_off[E.src], net->nodes[E.src].ld, c.st),
-              "c-hat");
-  }
-}
 
 // Grouped launches of one iteration, tables in one device buffer.
 struct Group {
@@ -2328,7 +2591,13 @@ struct BatchPlan {
   double g_bytes = 0.0, g_alg = 0.0;      // bytes (both models) of the grouped gamma update
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
+  // GCP_FLAG_PERSIST: every instance's iterations in one persistent launch
+  std::unique_ptr<PersistPlan> persist;
+  DBuf adam_tab;                          // Adam constants of every iteration, [iters][4]
+  hipGraphExec_t pexec = nullptr;         // the captured persistent launch (use_graph)
+  int pexec_iters = -1;
   ~BatchPlan() {
+    if (pexec) (void)hipGraphExecDestroy(pexec);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gstream) (void)hipStreamDestroy(gstream);
   }
@@ -2495,7 +2764,11 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
       if (items_all[k].net == items_all[i].net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
   // large instances: their own launches (the same kernels and tiles as
   // gcp_optimize), spread over a few streams by longest-first assignment
-  const long alone = batch_alone_work();
+  // with GCP_FLAG_PERSIST every instance shares the one persistent launch
+  // (measured: keeping the large instances on their own launches beside it
+  // is slower still, since the persistent grid holds every compute unit
+  // until its queues drain)
+  const long alone = (mode & GCP_FLAG_PERSIST) ? std::numeric_limits<long>::max() : batch_alone_work();
   std::vector<gcp_batch_item> grouped;
   std::vector<std::pair<long, int>> big;
   for (int i = 0; i < n_all; ++i) {
@@ -2558,7 +2831,8 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   AdamArgs adam{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, ws0.consts.as<float>()};
   struct Moments { float *ma, *va, *mb, *vb, *mg, *vg; };
   std::vector<Moments> mom(n);
-  std::vector<uintptr_t> key = {(uintptr_t)n, (uintptr_t)bf16};
+  const bool persist = (mode & GCP_FLAG_PERSIST) != 0;
+  std::vector<uintptr_t> key = {(uintptr_t)n, (uintptr_t)bf16, (uintptr_t)persist};
   // the captured graph and the recorded epilogue arguments hold these
   for (float v : {opt->lr_alpha, opt->lr_mult, opt->decay, opt->adam_b1, opt->adam_b2, opt->adam_eps}) {
     uint32_t b;
@@ -2613,6 +2887,7 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     plan->key = key;
     std::vector<Recorder> recs(n);
     std::vector<GammaJob> gj;
+    std::vector<PersistInst> pin;
     for (int i = 0; i < n; ++i) {
       Call c = calls[i];
       c.rec = &recs[i];
@@ -2622,18 +2897,69 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
       AdjPass ap{c, bf16, adam, nullptr, nullptr, items[i].alpha, items[i].beta, mom[i].ma, mom[i].va, mom[i].mb,
                  mom[i].vb};
       ap.run();
+      GammaJob g1{c.M, c.rp.mp, c.rp.N, c.rp.N > 0 ? c.cuts->row_ptr.as<int32_t>() : nullptr,
+                  c.net->ws.contrib.as<float>(), c.rp.N > 0 ? c.cuts->d.as<double>() : nullptr,
+                  c.net->ws.gammaT.as<float>(), mom[i].mg, mom[i].vg};
       if (c.rp.N > 0) {
         plan->g_bytes += (double)c.M * (c.nnz * 4.0 + c.rp.N * 24.0);
         plan->g_alg += alg_mult(c);
-        gj.push_back(GammaJob{c.M, c.rp.mp, c.rp.N, c.cuts->row_ptr.as<int32_t>(), c.net->ws.contrib.as<float>(),
-                              c.cuts->d.as<double>(), c.net->ws.gammaT.as<float>(), mom[i].mg, mom[i].vg});
+        gj.push_back(g1);
       }
+      pin.push_back(PersistInst{&recs[i], c.rp.N > 0, g1, c.M});
     }
     build_plan(*plan, recs, gj);
+    if (persist) {
+      auto pp = std::make_unique<PersistPlan>();
+      if (build_persist(*pp, pin, bf16)) plan->persist = std::move(pp);
+    }
     delete g_batch;
     g_batch = plan.release();
   }
   BatchPlan& plan = *g_batch;
+  if (plan.persist && done < opt->iters) {
+    // the remaining iterations of every instance in one persistent launch
+    // (with use_graph: captured once per iteration count, replayed)
+    plan.adam_tab.ensure((size_t)std::max(opt->iters, 1) * 16);
+    const AdamArgs tab{1, opt->adam_b1, opt->adam_b2, opt->adam_eps, plan.adam_tab.as<float>()};
+    const int todo = opt->iters - done, first = done;
+    if (opt->use_graph) {
+      if (!plan.gstream) hip_check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "hipStreamCreate");
+      if (!plan.pexec || plan.pexec_iters != opt->iters * 1000 + first) {
+        if (plan.pexec) { (void)hipGraphExecDestroy(plan.pexec); plan.pexec = nullptr; }
+        hipGraph_t graph;
+        hip_check(hipStreamBeginCapture(plan.gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+          hip_check(launch_adam_table(plan.adam_tab.as<float>(), opt->iters, opt->lr_alpha, opt->lr_mult, opt->decay,
+                                      opt->adam_b1, opt->adam_b2, plan.gstream),
+                    "adam table");
+          run_persist(*plan.persist, bf16, todo, first, tab, plan.gstream);
+        } catch (...) {
+          hipGraph_t g2;
+          (void)hipStreamEndCapture(plan.gstream, &g2);
+          throw;
+        }
+        hip_check(hipStreamEndCapture(plan.gstream, &graph), "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&plan.pexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(ie, "hipGraphInstantiate");
+        plan.pexec_iters = opt->iters * 1000 + first;
+      }
+      hipEvent_t ev;
+      hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+      hip_check(hipEventRecord(ev, st), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(plan.gstream, ev, 0), "hipStreamWaitEvent");
+      hip_check(hipGraphLaunch(plan.pexec, plan.gstream), "hipGraphLaunch");
+      hip_check(hipEventRecord(ev, plan.gstream), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(st, ev, 0), "hipStreamWaitEvent");
+      (void)hipEventDestroy(ev);
+    } else {
+      hip_check(launch_adam_table(plan.adam_tab.as<float>(), opt->iters, opt->lr_alpha, opt->lr_mult, opt->decay,
+                                  opt->adam_b1, opt->adam_b2, st),
+                "adam table");
+      run_persist(*plan.persist, bf16, todo, first, tab, st);
+    }
+    done = opt->iters;
+  }
   if (opt->use_graph && opt->iters > 1 && done < opt->iters) {
     if (!plan.gstream) hip_check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "hipStreamCreate");
     hipEvent_t ev;

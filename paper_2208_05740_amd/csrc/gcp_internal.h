@@ -265,6 +265,47 @@ hipError_t launch_validate(const float* p, int64_t n, float lo, float hi, int* f
                            hipStream_t st);
 hipError_t launch_fill_bf16_from_f32(const float* src, bf16* dst, int64_t n, hipStream_t st);
 
+// ---------------------------------------------------------------- persistent dataflow
+// A recorded iteration schedule (the launches of one bound pass, adjoint and
+// multiplier update of one or more instances) executed for several
+// iterations in one launch (persist_kernels.hip).  Rows are independent
+// problems, so a step over a panel of kPersistRows rows depends only on the
+// earlier steps over the same panel (its GEMM operand spans the previous
+// layer's columns of those rows).  Items are (iteration, step, column tile,
+// panel); every GEMM tile is kPersistRows x 32, so each step has the same
+// number of items (`ipp`) on every panel of its instance.  Panels are dealt
+// to Q claim queues (panel p of an instance whose first global panel is
+// `base` belongs to queue (base + p) mod Q); a workgroup serves the queue of
+// the XCD it runs on, so all items of a panel meet in one L2.
+constexpr int kPersistRows = 32;
+constexpr int kPersistMaxSteps = 2048;   // steps of one iteration (all instances)
+constexpr int kPersistAbort = 1 << 29;   // added to every claim head when a wait runs out; items per queue stay below
+enum PersistKind { PK_STORE = EPI_STORE, PK_BOUND = EPI_BOUND, PK_CONC = EPI_CONC, PK_ADJ = EPI_ADJ, PK_ELEM = 5,
+                   PK_GAMMA = 6 };
+struct PersistStep {
+  int kind, sign, job;     // PersistKind; GEMM A operand is int8 signs; index into the kind's job table
+  int cnt0, panels, base;  // the instance's first completion counter (one per panel), panel count, first global panel
+  int ipp;                 // items per panel (column tiles / column blocks / cut groups)
+  int wait;                // items per panel in the instance's earlier steps of an iteration
+  int per_iter;            // items per panel in a whole iteration of the instance
+};
+constexpr size_t kEpiBlob = 16 * ((sizeof(AdjEpiArgs) > sizeof(BoundEpiArgs) ? sizeof(AdjEpiArgs) : sizeof(BoundEpiArgs)) / 16 + 1);
+struct PersistArgs {
+  const PersistStep* steps; int n_steps;
+  const int* qfirst;       // [Q][n_steps + 1]: first item of each step within an iteration, per queue
+  int Q, iters, iter0;     // iteration t of the launch uses the Adam constants of iteration iter0 + t
+  const GemmArgs* gemm; const unsigned char* epi;   // GEMM jobs: arguments, epilogue blobs of kEpiBlob bytes
+  const ElemBoundJob* elem; const GammaJob* gam;
+  AdamArgs adam;           // consts: table of every iteration's constants, [4 * t ..]
+  int* sync;               // [Q] claim heads, [Q] abort flag, [Q + 1 ..] panel completion counters (zeroed per launch)
+  int xcd_sync;            // 1: every queue is served by one XCD, so a producer's stores need only reach its L2
+};
+// Workgroups one launch runs (as many as are resident at once).
+int persist_grid(int bf16, int xcd_sync);
+// out[b] = the XCC_ID hardware register of workgroup b < n
+hipError_t launch_xcc_probe(int* out, int n, hipStream_t st);
+hipError_t launch_persist(int bf16, const PersistArgs& a, int grid, hipStream_t st);
+
 // ---------------------------------------------------------------- fused dense chains
 // A network whose ReLU nodes 0..L-1 form a chain of dense layers (node i's
 // only input is node i-1, node 0's the network input; the output's only
