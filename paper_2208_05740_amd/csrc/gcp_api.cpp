@@ -194,6 +194,7 @@ struct PersistPlan {
   DBuf buf;          // steps, per-queue first items, GEMM arguments, epilogue blobs, elementwise and gamma jobs
   DBuf sync;         // claim heads, abort flag, panel counters (zeroed before every launch)
   size_t n_sync = 0;
+  DBuf latch;        // set by a launch that aborted (zeroed once per call)
   PersistArgs args{};
   int grid = 0;
   int max_items = 0;   // most items one queue has in one iteration
@@ -1149,6 +1150,7 @@ bool build_persist(PersistPlan& plan, const std::vector<PersistInst>& in, int bf
   unsigned char* b = (unsigned char*)plan.buf.p;
   plan.n_sync = (size_t)Q + 1 + tot;
   plan.sync.alloc(plan.n_sync * sizeof(int));
+  plan.latch.alloc(16);
   PersistArgs& a = plan.args;
   a = PersistArgs{};
   a.steps = (const PersistStep*)(b + o_steps);
@@ -1161,6 +1163,7 @@ bool build_persist(PersistPlan& plan, const std::vector<PersistInst>& in, int bf
   a.gam = (const GammaJob*)(b + o_gm);
   a.sync = plan.sync.as<int>();
   a.xcd_sync = xcd;
+  a.latch = plan.latch.as<int>();
   plan.grid = persist_grid(bf16, xcd);
   if (plan.grid <= 0) fail(GCP_EDEVICE, "persistent launch: occupancy query failed");
   return true;
@@ -1168,9 +1171,18 @@ bool build_persist(PersistPlan& plan, const std::vector<PersistInst>& in, int bf
 
 // `iters` iterations of the plan in one launch, iteration t with the Adam
 // constants of iteration iter0 + t from the table `tab`.
+// The longest wait of a persistent launch before it aborts, in ticks of
+// the 100 MHz wall clock: 1 s, or GCP_PERSIST_SPIN_TICKS (tests force the
+// abort path with a tiny value).
+unsigned long long persist_spin_ticks() {
+  const char* e = std::getenv("GCP_PERSIST_SPIN_TICKS");
+  return e && *e ? std::strtoull(e, nullptr, 10) : 100000000ull;
+}
+
 void run_persist(PersistPlan& plan, int bf16, int iters, int iter0, const AdamArgs& adam_tab, hipStream_t st) {
   // iterations per launch: a queue's items stay below the abort offset
   const int per_launch = std::max(1, (kPersistAbort / 2) / std::max(plan.max_items, 1));
+  hip_check(launch_fill_f32((float*)plan.latch.p, 1, 0.f, st), "persist latch reset");
   for (int done = 0; done < iters; done += per_launch) {
     const int n = std::min(per_launch, iters - done);
     hip_check(launch_fill_f32((float*)plan.sync.p, (int64_t)plan.n_sync, 0.f, st), "persist sync reset");
@@ -1178,6 +1190,7 @@ void run_persist(PersistPlan& plan, int bf16, int iters, int iter0, const AdamAr
     a.iters = n;
     a.iter0 = iter0 + done;
     a.adam = adam_tab;
+    a.spin_ticks = persist_spin_ticks();
     hip_check(timed(st, bf16 ? "persist.bf16" : "persist.fp32",
                     Bytes{plan.bytes * n, plan.alg * n}, plan.flops * n,
                     [&] { return launch_persist(bf16, a, plan.grid, st); }),
@@ -2343,6 +2356,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
     return key;
   };
   int done = 0;
+  const int* persist_latch = nullptr;   // set when the iterations ran as persistent launches
   if (chain.ok && opt->iters > 0) {   // every iteration in one launch
     run_chain(c, bf16, chain, alpha, beta, ma, va, mb, vb, mg, vg, opt);
     done = opt->iters;
@@ -2358,6 +2372,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
       launch_constants(c);
       run_persist(*ws.pplan, bf16, opt->iters, 0, tab, c.st);
       done = opt->iters;
+      persist_latch = ws.pplan->latch.as<int>();
     } else {
       iteration(c, 0);   // tunes the per-layer tiles the schedule records, sizes buffers
       done = 1;
@@ -2383,6 +2398,7 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
         ws.pplan = std::move(plan);
         run_persist(*ws.pplan, bf16, opt->iters - done, done, tab, c.st);
         done = opt->iters;
+        persist_latch = ws.pplan->latch.as<int>();
       }
     }
   }
@@ -2429,6 +2445,8 @@ void optimize_impl(const gcp_net* net_c, const double* x0, double eps, const dou
   // certifying pass: fp32 GEMMs, fp64 reductions, margin check
   c.outward = (mode & GCP_FLAG_OUTWARD) != 0;
   bound_pass(c, 0, false, false, bound, verified);
+  if (persist_latch)   // a persistent launch that aborted leaves -inf bounds
+    hip_check(launch_persist_guard(persist_latch, bound, verified, c.M, c.st), "persist guard");
 }
 
 }  // namespace
@@ -2916,7 +2934,8 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     g_batch = plan.release();
   }
   BatchPlan& plan = *g_batch;
-  if (plan.persist && done < opt->iters) {
+  const bool ran_persist = plan.persist && done < opt->iters;
+  if (ran_persist) {
     // the remaining iterations of every instance in one persistent launch
     // (with use_graph: captured once per iteration count, replayed)
     plan.adam_tab.ensure((size_t)std::max(opt->iters, 1) * 16);
@@ -2993,6 +3012,9 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     Call& c = calls[i];
     c.outward = (mode & GCP_FLAG_OUTWARD) != 0;
     bound_pass(c, 0, false, false, items[i].bound, items[i].verified);
+    if (ran_persist)   // a persistent launch that aborted leaves -inf bounds
+      hip_check(launch_persist_guard(plan.persist->latch.as<int>(), items[i].bound, items[i].verified, c.M, st),
+                "persist guard");
     if (c.rp.N > 0)
       hip_check(launch_transpose(c.net->ws.gammaT.as<float>(), c.rp.N, c.M, c.rp.mp, items[i].gamma, c.rp.N, st),
                 "transpose");

@@ -299,12 +299,18 @@ struct PersistArgs {
   AdamArgs adam;           // consts: table of every iteration's constants, [4 * t ..]
   int* sync;               // [Q] claim heads, [Q] abort flag, [Q + 1 ..] panel completion counters (zeroed per launch)
   int xcd_sync;            // 1: every queue is served by one XCD, so a producer's stores need only reach its L2
+  unsigned long long spin_ticks;   // longest wait (100 MHz wall clock) before the launch aborts
+  int* latch;              // set to 1 when the launch aborts (kept across the launches of one call)
 };
 // Workgroups one launch runs (as many as are resident at once).
 int persist_grid(int bf16, int xcd_sync);
 // out[b] = the XCC_ID hardware register of workgroup b < n
 hipError_t launch_xcc_probe(int* out, int n, hipStream_t st);
 hipError_t launch_persist(int bf16, const PersistArgs& a, int grid, hipStream_t st);
+// After the certifying pass of a call that ran persistent launches: if one
+// of them aborted (*latch set), every row's bound becomes -inf (a valid lower
+// bound) and no row counts as verified.
+hipError_t launch_persist_guard(const int* latch, double* bound, uint8_t* verified, int M, hipStream_t st);
 
 // ---------------------------------------------------------------- fused dense chains
 // A network whose ReLU nodes 0..L-1 form a chain of dense layers (node i's

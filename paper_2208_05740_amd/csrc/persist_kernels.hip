@@ -18,10 +18,11 @@
 // queue, and a workgroup claims a few consecutive items at a time and runs
 // them in order, so the earliest unfinished item of a queue always has its
 // dependencies met and its workgroup resident.  Every wait is bounded
-// (kSpinTicks of the 100 MHz wall clock); a wait that runs out raises an
-// abort flag and moves every claim head past the end, at which every
-// workgroup stops, so a broken schedule ends the launch instead of hanging
-// it.
+// (spin_ticks of the 100 MHz wall clock, 1 s by default); a wait that runs
+// out raises an abort flag, and the first workgroup to raise it latches it
+// for the host side and moves every claim head past the end (once, so the
+// heads stay within the int range), at which every workgroup stops: a
+// stalled launch ends instead of hanging (and the call's bounds become -inf).
 //
 // Ordering between workgroups: the producer of an item makes its stores
 // complete, then bumps the panel counter; the consumer reads the counter,
@@ -46,7 +47,6 @@ namespace gcp {
 
 namespace {
 
-constexpr uint64_t kSpinTicks = 100000000ull;   // 1 s of the 100 MHz wall clock
 constexpr int kPersistClaim = 4;                // consecutive items per claim
 
 template <typename T>
@@ -134,7 +134,7 @@ persist_kernel(PersistArgs a, const PersistStep* __restrict__ steps, const int* 
       }
       __syncthreads();
       c = __builtin_amdgcn_readfirstlane(s_claim);
-      if (c >= total) break;
+      if (c >= total || c < 0) break;
       c_end = min(c + kPersistClaim, total);
     }
     // wave-uniform values in scalar registers, so the step's tables are read
@@ -175,10 +175,16 @@ persist_kernel(PersistArgs a, const PersistStep* __restrict__ steps, const int* 
           break;
         }
         __builtin_amdgcn_s_sleep(2);
-        if (wall_clock64() - t0 > kSpinTicks) {
-          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int k = 0; k < a.Q; ++k)
-            __hip_atomic_fetch_add(a.sync + k, one * kPersistAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wall_clock64() - t0 > a.spin_ticks) {
+          // only the first workgroup to abort moves the heads (once per
+          // launch, so they stay far below the int range)
+          const int was = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_fetch_add(abort_flag, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (was == 0) {
+            __hip_atomic_store(a.latch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < a.Q; ++k)
+              __hip_atomic_fetch_add(a.sync + k, one * kPersistAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
           bad = 1;
           break;
         }
@@ -265,6 +271,19 @@ const void* persist_fn(int bf16_mode, int xcd_sync, int wpe) {
   return xcd_sync ? persist_fn<float, true>(wpe) : persist_fn<float, false>(wpe);
 }
 }  // namespace
+
+__global__ void __launch_bounds__(256) persist_guard_kernel(const int* latch, double* bound, uint8_t* verified, int M) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < M && *latch != 0) {
+    bound[r] = -__builtin_inf();
+    if (verified) verified[r] = 0;
+  }
+}
+hipError_t launch_persist_guard(const int* latch, double* bound, uint8_t* verified, int M, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(persist_guard_kernel, dim3((M + 255) / 256), dim3(256), 0, st, latch, bound, verified, M);
+  return hipGetLastError();
+}
 
 // The XCD each of n workgroups ran on (plan set-up: how many claim queues
 // the launches can use).

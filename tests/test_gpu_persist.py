@@ -180,3 +180,32 @@ def test_batch_in_one_persistent_launch_equals_per_instance(mode):
             assert np.array_equal(it["alpha"].cpu().numpy(), a)
             assert np.array_equal(it["beta"].cpu().numpy(), b)
             assert np.array_equal(it["gamma"].cpu().numpy(), c)
+
+
+def test_persistent_wait_limit_ends_the_launch_with_sound_bounds(monkeypatch):
+    """The bounded wait's exit path, forced from the host: with a spin limit
+    of one wall-clock tick every wait that is not met at once aborts the
+    launch (every workgroup stops; nothing hangs), and the certifying pass's
+    bounds are then replaced by -inf, a valid lower bound, with no row
+    verified.  If no item had to wait, the results are the ordinary ones."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print("persistent launch abort path (spin limit 1 tick)", flush=True)
+    prob = gen.make_workload("mlp784", 0, B=64)
+    P = B.Problem(prob, device=_dev())
+    run = _Run(prob, P)
+    ref, _ = run(0, persist=False)
+    run(0, persist=True)                      # builds the plan with the ordinary limit
+    monkeypatch.setenv("GCP_PERSIST_SPIN_TICKS", "1")
+    got, ran = run(0, persist=True)           # every iteration in the persistent launch
+    torch.cuda.synchronize()
+    assert "persist.fp32" in ran
+    aborted = bool(np.all(np.isneginf(got["bound"])))
+    print(f"  aborted: {aborted}", flush=True)
+    if aborted:
+        assert not got["ver"].any()
+    else:
+        _same(got, ref)
+    monkeypatch.delenv("GCP_PERSIST_SPIN_TICKS")
+    again, _ = run(0, persist=True)           # the next call starts from a clear latch
+    _same(again, ref)
