@@ -121,13 +121,15 @@ def unstable_pi_h(a_hat, s, l, u):
       l n < s < u n      : pi* = (u n - s) / (u - l),    h = l pi*
     i.e. pi* = clip((u n - s)/(u - l), 0, n) and h = l pi* - [u(n - pi*) + l pi* - s]_+.
     The case is chosen on detached values so the derivative follows the
-    selected branch."""
+    selected branch.  The middle case needs l n < s < u n with n > 0, so
+    u > l there; elsewhere the quotient is not used and its denominator is
+    set to 1, so that a neuron with u = l adds no 0/0 to the derivative."""
     n = torch.relu(-a_hat)
     with torch.no_grad():
         case_zero = s >= u * n
         case_full = (~case_zero) & (s <= l * n)
         case_mid = (~case_zero) & (~case_full)
-    pi_mid = (u * n - s) / (u - l)
+    pi_mid = (u * n - s) / torch.where(case_mid, u - l, torch.ones_like(u - l))
     pi = torch.where(case_mid, pi_mid, torch.where(case_full, n, torch.zeros_like(n)))
     h = torch.where(case_mid, l * pi_mid, torch.where(case_full, s, torch.zeros_like(s)))
     return pi, h

@@ -235,6 +235,29 @@ def test_gradient_matches_finite_differences(kind, seed):
     assert checked > 20
 
 
+def test_gradient_finite_where_a_neuron_has_equal_bounds():
+    """Lemma A.1's middle case needs l < u; a neuron with l = u (24 of them
+    in the second node here) must add nothing undefined to the derivative:
+    the gradient is finite and equals central finite differences."""
+    p = gen.make_tiny("res16", 4, B=3, splits=(0, 0), n_cuts=0)
+    assert any(np.any(l == u) for l, u in p.lu)
+    a = np.asarray(O.full_alpha(p), np.float64)
+    b, c = np.asarray(p.beta, np.float64), np.asarray(p.gamma, np.float64)
+    _, ga, _, _ = O.bound_and_grad(p, a, b, c)
+    assert np.all(np.isfinite(ga))
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for idx in rng.choice(a.size, size=25, replace=False):
+        x = a.copy().reshape(-1)
+        x[idx] += h
+        gp = O.bound(p, x.reshape(a.shape), b, c)
+        x[idx] -= 2 * h
+        gm = O.bound(p, x.reshape(a.shape), b, c)
+        fd = (gp - gm).sum() / (2 * h)
+        an = ga.reshape(-1)[idx]
+        assert abs(fd - an) <= 1e-3 * max(1.0, abs(an)) + 1e-6, (idx, fd, an)
+
+
 # ------------------------------------------------- conv adjoint pin
 
 @pytest.mark.parametrize("shape", [((2, 5, 5), 3, 4, 2, 1), ((3, 6, 6), 2, 3, 1, 1),
