@@ -36,6 +36,9 @@ constexpr int kSlabBudget = 48 * 1024;   // bytes of fp32 slab + result bands a 
 constexpr int kRows = 4;                 // batch rows per workgroup
 constexpr int kEpiN = 1;                 // neurons per lane in one epilogue step
 constexpr int kLdsLimit = 64 * 1024;
+constexpr int kDirNW = 8;               // waves per workgroup of the direct transposed conv
+constexpr int kDirPF = 4;               // its staging vectors per thread held across a row's taps
+constexpr int kDirCh = 2;               // its 64-position chunks per wave
 __host__ __device__ inline int align16(int b) { return (b + 15) & ~15; }
 }  // namespace
 
@@ -142,6 +145,11 @@ static int conv_lds_bytes(const ConvPlan& P, int esz, int nw) {
          align16(P.Kch * P.CHS * esz) + kRows * align16(P.Nch * P.OS * 4);
 }
 
+// direct transposed-conv kernel: reduction slots, fp32 slab, four result bands
+static int conv_direct_lds_bytes(const ConvPlan& P) {
+  return align16(kDirNW * 8 * kRows) + align16(P.Kch * P.CHS * 4) + kRows * align16(P.Nch * P.OS * 4);
+}
+
 // ---------------------------------------------------------------- slab fill
 template <typename T, bool SIGN> struct SlabLoad;
 template <> struct SlabLoad<bf16, false> {
@@ -198,6 +206,66 @@ template <> struct Gather<float> {
     return uint4{S[base + ko[0]], S[base + ko[1]], S[base + ko[2]], S[base + ko[3]]};
   }
 };
+
+// Fused epilogue of one workgroup's band, over the results of its kRows batch
+// rows in LDS (row q at outs + q * OQ, channel n at n * OS, position
+// (y - yb0) * We + x): walk the band's neurons in memory order, then sum the
+// row constant of each batch row into its partial slot slot0 + band.
+template <int NW, class Epi>
+__device__ __forceinline__ void band_epilogue(const ConvArgs& c, const ConvPlan& P, const Epi& epi, const float* outs,
+                                              int OQ, double* red, int r0, int band, int yb0, int yb1) {
+  constexpr int NT = NW * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int HWe = P.He * P.We;
+  const int node_size = P.Nch * HWe;
+  // fused epilogue over the band's neurons in memory order: per step a lane
+  // takes kEpiN neurons (NT apart) of the four batch rows, so that the
+  // dependent load chains of several neurons are in flight together
+  double rs[kRows];
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) rs[q] = 0.0;
+  {
+    const int per_ch = (yb1 - yb0) * P.We;
+    const int nel = P.Nch * per_ch;
+    const int j0 = yb0 * P.We;
+    const float inv_pc = 1.f / (float)per_ch;
+    LaneCoords<kRows, kEpiN, false> lc;
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) lc.r[q] = r0 + q;
+    for (int e0 = tid; e0 < nel; e0 += kEpiN * NT) {
+      float val[kEpiN][kRows];
+#pragma unroll
+      for (int k = 0; k < kEpiN; ++k) {
+        const int e = e0 + k * NT;
+        // e = n * per_ch + off; the float quotient is within one of n
+        int n = (int)((float)e * inv_pc), off = e - n * per_ch;
+        if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
+        const bool ok = e < nel;
+        lc.j[k][0] = ok ? n * HWe + j0 + off : node_size;   // node_size marks no neuron
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) val[k][q] = ok && r0 + q < c.M ? outs[q * OQ + n * P.OS + off] : 0.f;
+      }
+      typename Epi::template Frag<kRows, kEpiN, false> fr;
+      epi.template load<kRows, kEpiN, false>(fr, lc, c.M, node_size);
+      epi.template apply<kRows, kEpiN, false>(fr, lc, val, rs, c.M, node_size);
+    }
+  }
+
+  if (c.partial) {
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      double tsum = rs[q];
+      for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+      if (lane == 0) red[wave * kRows + q] = tsum;
+    }
+    __syncthreads();
+    if (tid < kRows && r0 + tid < c.M) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[w * kRows + tid];
+      c.partial[(size_t)(c.slot0 + band) * c.mp + r0 + tid] = sum;
+    }
+  }
+}
 
 template <typename T, int NW, int TN, bool TRANS, bool SIGN, class Epi>
 __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan P, Epi epi) {
@@ -336,53 +404,177 @@ __global__ void __launch_bounds__(NW * 64) conv_slab_kernel(ConvArgs c, ConvPlan
   }
   __syncthreads();
 
-  // fused epilogue over the band's neurons in memory order: per step a lane
-  // takes kEpiN neurons (NT apart) of the four batch rows, so that the
-  // dependent load chains of several neurons are in flight together
-  double rs[kRows];
+  band_epilogue<NW>(c, P, epi, outs, OQ, red, r0, band, yb0, yb1);
+}
+
+// One 16-byte vector of a slab row as fp32 values.
+template <typename T> struct SlabCvt;
+template <> struct SlabCvt<float> {
+  __device__ static inline void get(const uint4& v, float* f) {
+    f[0] = __uint_as_float(v.x); f[1] = __uint_as_float(v.y); f[2] = __uint_as_float(v.z); f[3] = __uint_as_float(v.w);
+  }
+};
+template <> struct SlabCvt<bf16> {
+  __device__ static inline void get(const uint4& v, float* f) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-  for (int q = 0; q < kRows; ++q) rs[q] = 0.0;
-  {
-    const int per_ch = (yb1 - yb0) * P.We;
-    const int nel = P.Nch * per_ch;
-    const int j0 = yb0 * P.We;
-    const float inv_pc = 1.f / (float)per_ch;
-    LaneCoords<kRows, kEpiN, false> lc;
-#pragma unroll
-    for (int q = 0; q < kRows; ++q) lc.r[q] = r0 + q;
-    for (int e0 = tid; e0 < nel; e0 += kEpiN * NT) {
-      float val[kEpiN][kRows];
-#pragma unroll
-      for (int k = 0; k < kEpiN; ++k) {
-        const int e = e0 + k * NT;
-        // e = n * per_ch + off; the float quotient is within one of n
-        int n = (int)((float)e * inv_pc), off = e - n * per_ch;
-        if (off < 0) { --n; off += per_ch; } else if (off >= per_ch) { ++n; off -= per_ch; }
-        const bool ok = e < nel;
-        lc.j[k][0] = ok ? n * HWe + j0 + off : node_size;   // node_size marks no neuron
-#pragma unroll
-        for (int q = 0; q < kRows; ++q) val[k][q] = ok && r0 + q < c.M ? outs[q * OQ + n * P.OS + off] : 0.f;
-      }
-      typename Epi::template Frag<kRows, kEpiN, false> fr;
-      epi.template load<kRows, kEpiN, false>(fr, lc, c.M, node_size);
-      epi.template apply<kRows, kEpiN, false>(fr, lc, val, rs, c.M, node_size);
+    for (int q = 0; q < 4; ++q) {
+      f[2 * q] = __uint_as_float(w[q] << 16);
+      f[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
     }
   }
+};
 
-  if (c.partial) {
+// Transposed convolution into a source of at most four channels (the
+// network's input image) on the vector ALUs.  An MFMA tile's 16 columns
+// would carry NC real channels and padding, so here each lane computes all NC
+// channels of one source position: per tap, one LDS read of Lambda feeds NC
+// FMAs.  A wave takes 64 positions of one stride phase at a time, so the
+// phase's weights (taps TA x TB per phase, fp32 in the operand precision) are
+// wave-uniform scalar loads; the stride ST is a template parameter.  Band split, slab layout, per-row result buffers,
+// fused epilogue and partial slots are those of conv_slab_kernel; the slab is
+// held in fp32 for either operand type.  What does not depend on the batch
+// row -- each wave's (at most kDirCh) position chunks with their phase, slab
+// base and result offset, and each thread's (at most kDirPF) staging vectors
+// with their source and slab offsets -- is worked out once per workgroup and
+// kept in registers; the next row's staging loads are issued before this
+// row's taps, so their latency is hidden behind the FMAs.
+template <typename T, int NC, int TA, int TB, int ST, class Epi>
+__global__ void __launch_bounds__(kDirNW * 64) convT_direct_kernel(ConvArgs c, ConvPlan Pr, Epi epi) {
+  ConvPlan P = Pr;
+  P.s = ST;              // the stride as a constant: phase arithmetic without divisions
+  constexpr int NT = kDirNW * 64;
+  constexpr int VEC = Op<T>::VEC;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* sp = smem;
+  double* red = (double*)sp;  sp += align16(kDirNW * 8 * kRows);
+  float* slab = (float*)sp;   sp += align16(P.Kch * P.CHS * 4);
+  float* outs = (float*)sp;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = (blockIdx.x / P.n_bands) * kRows, band = blockIdx.x % P.n_bands;
+  const int OQ = align16(P.Nch * P.OS * 4) / 4;
+  const int s = P.s, p = P.p;
+  const int yb0 = band * P.BH, yb1 = min(P.He, yb0 + P.BH);
+  const int sy0 = (yb0 + p) / s - (TA - 1);
+  {
+    float4* z = (float4*)slab;
+    const int n16 = align16(P.Kch * P.CHS * 4) / 16;
+    for (int v = tid; v < n16; v += NT) z[v] = float4{0.f, 0.f, 0.f, 0.f};
+  }
+  // position chunks of this wave: chunk t = wave + k kDirNW of the band's
+  // 64-position chunks, phase by phase
+  int cph[kDirCh], cbase[kDirCh], coff[kDirCh];
+  bool clive[kDirCh];
 #pragma unroll
-    for (int q = 0; q < kRows; ++q) {
-      double tsum = rs[q];
-      for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
-      if (lane == 0) red[wave * kRows + q] = tsum;
+  for (int k = 0; k < kDirCh; ++k) {
+    int tl = wave + k * kDirNW, ph = 0, yf = 0, ny = 0, xf = 0, nx = 0;
+    for (; ph < P.n_phase; ++ph) {
+      phase_rows(P, ph, yb0, yb1, true, &yf, &ny, &xf, &nx);
+      const int nt = (ny * nx + 63) / 64;
+      if (tl < nt) break;
+      tl -= nt;
+    }
+    cph[k] = __builtin_amdgcn_readfirstlane(ph);      // n_phase: no chunk
+    const int i = tl * 64 + lane;
+    clive[k] = ph < P.n_phase && i < ny * nx;
+    const int iy = clive[k] ? i / nx : 0, ix = clive[k] ? i - iy * nx : 0;
+    const int ry = ph / s, rx = ph % s;
+    cbase[k] = clive[k] ? ((yf + p - ry) / s - sy0 + iy) * P.Wp + (xf + p - rx) / s + ix + P.xl
+                        : (TA - 1) * P.Wp + TB - 1;     // in-slab for every tap
+    coff[k] = (yf - yb0 + iy * s) * P.We + xf + ix * s;
+  }
+  // staging: item v of a batch row is VEC consecutive source elements (one
+  // where the rows are not whole vectors) of slab row rho, channel ch
+  const bool vec = P.ws % VEC == 0;
+  const int cw = vec ? VEC : 1;
+  const int nck = P.ws / cw;
+  const int total = P.Kch * P.rows_max * nck;
+  auto item = [&](int v, int* src, int* dst) -> bool {
+    const int xc = v % nck, rest = v / nck;
+    const int rho = rest % P.rows_max, ch = rest / P.rows_max;
+    const int sy = sy0 + rho;
+    if (v >= total || sy < 0 || sy >= P.hs) return false;
+    *src = (ch * P.hs + sy) * P.ws + xc * cw;
+    *dst = ch * P.CHS + rho * P.Wp + P.xl + xc * cw;
+    return true;
+  };
+  const bool pf = vec && total <= kDirPF * NT;
+  int ssrc[kDirPF], sdst[kDirPF];                     // sdst < 0: nothing to stage
+  uint4 nxt[kDirPF];
+  if (pf) {
+#pragma unroll
+    for (int u = 0; u < kDirPF; ++u)
+      if (!item(tid + u * NT, &ssrc[u], &sdst[u])) sdst[u] = -1;
+  }
+  auto fetch = [&](int r) {
+    const T* xr = (const T*)c.X + (size_t)r * c.ldx;
+#pragma unroll
+    for (int u = 0; u < kDirPF; ++u)
+      if (sdst[u] >= 0) nxt[u] = *(const uint4*)(xr + ssrc[u]);
+  };
+  if (pf) fetch(r0);
+  for (int q = 0; q < kRows && r0 + q < c.M; ++q) {
+    float* outq = outs + q * OQ;
+    __syncthreads();      // zeros written; the previous row's taps read
+    if (pf) {
+#pragma unroll
+      for (int u = 0; u < kDirPF; ++u) {
+        if (sdst[u] < 0) continue;
+        float f[VEC];
+        SlabCvt<T>::get(nxt[u], f);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) slab[sdst[u] + e] = f[e];
+      }
+    } else {
+      const size_t xrow = (size_t)(r0 + q) * c.ldx;
+      for (int v = tid; v < total; v += NT) {
+        int src, dst;
+        if (!item(v, &src, &dst)) continue;
+        if (vec) {
+          T tmp[VEC];
+          SlabLoad<T, false>::vec(c.X, xrow + src, tmp);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) slab[dst + e] = (float)tmp[e];
+        } else {
+          slab[dst] = (float)SlabLoad<T, false>::one(c.X, xrow + src);
+        }
+      }
     }
     __syncthreads();
-    if (tid < kRows && r0 + tid < c.M) {
-      double sum = 0.0;
-      for (int w = 0; w < NW; ++w) sum += red[w * kRows + tid];
-      c.partial[(size_t)(c.slot0 + band) * c.mp + r0 + tid] = sum;
+    if (pf && q + 1 < kRows && r0 + q + 1 < c.M) fetch(r0 + q + 1);
+#pragma unroll
+    for (int k = 0; k < kDirCh; ++k) {
+      if (cph[k] >= P.n_phase) continue;
+      const GCP_CONSTANT_AS float* W = cst(c.Btf) + (size_t)cph[k] * P.Nch * c.ldb;
+      float acc[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.f;
+#pragma unroll 2
+      for (int o = 0; o < P.Kch; ++o) {
+        const float* so = slab + o * P.CHS + cbase[k];
+        float v[TA][TB];
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) v[a][b] = so[-a * P.Wp - b];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+          const GCP_CONSTANT_AS float* w = W + (size_t)ch * c.ldb + o * (TA * TB);
+#pragma unroll
+          for (int a = 0; a < TA; ++a)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) acc[ch] = fmaf(v[a][b], w[a * TB + b], acc[ch]);
+        }
+      }
+      if (clive[k]) {
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) outq[ch * P.OS + coff[k]] = acc[ch];
+      }
     }
   }
+  __syncthreads();
+  band_epilogue<kDirNW>(c, P, epi, outs, OQ, red, r0, band, yb0, yb1);
 }
 
 // launch configurations: waves per workgroup x column tiles per wave
@@ -458,8 +650,59 @@ static hipError_t conv_typed_pi(int cfg, EpiKind kind, const ConvArgs& c, const 
   return conv_pi_any<T, false, false>(cfg, c, AdjEpi<T, true>{*(const AdjEpiArgs*)epi}, st);
 }
 
+bool conv_direct_ok(const ConvGeom& g, EpiKind kind) {
+  if (kind != EPI_CONC || g.ci < 1 || g.ci > 4) return false;
+  const ConvPlan P = conv_plan(g, 1);
+  if (!((P.A == 2 && P.Bn == 2 && P.s == 2) || (P.A == 3 && P.Bn == 3 && P.s == 1))) return false;
+  for (int b = 0; b < P.n_bands; ++b) {      // every band's positions in kDirCh chunks per wave
+    const int yb0 = b * P.BH, yb1 = std::min(P.He, yb0 + P.BH);
+    int nchunk = 0;
+    for (int ph = 0; ph < P.n_phase; ++ph) {
+      int yf, ny, xf, nx;
+      phase_rows(P, ph, yb0, yb1, true, &yf, &ny, &xf, &nx);
+      nchunk += (ny * nx + 63) / 64;
+    }
+    if (nchunk > kDirNW * kDirCh) return false;
+  }
+  return conv_direct_lds_bytes(P) <= kLdsLimit;
+}
+
+template <typename T, int NC, int TA, int TB, int ST, class Epi>
+static hipError_t direct_go(const ConvArgs& c, const ConvPlan& P, const Epi& epi, hipStream_t st) {
+  const long grid = (long)((c.M + kRows - 1) / kRows) * P.n_bands;
+  if (grid <= 0 || grid > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((convT_direct_kernel<T, NC, TA, TB, ST, Epi>), dim3((unsigned)grid), dim3(kDirNW * 64),
+                     (unsigned)conv_direct_lds_bytes(P), st, c, P, epi);
+  return hipGetLastError();
+}
+
+template <typename T, int NC, class Epi>
+static hipError_t direct_taps(const ConvArgs& c, const ConvPlan& P, const Epi& epi, hipStream_t st) {
+  if (P.A == 2 && P.Bn == 2 && P.s == 2) return direct_go<T, NC, 2, 2, 2>(c, P, epi, st);
+  if (P.A == 3 && P.Bn == 3 && P.s == 1) return direct_go<T, NC, 3, 3, 1>(c, P, epi, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t conv_direct(const ConvArgs& c, const ConcEpi& epi, hipStream_t st) {
+  const ConvPlan P = conv_plan(c.cg, 1);
+  if (!c.Btf || c.ldb < P.KP || c.ldb % 32 != 0 || conv_direct_lds_bytes(P) > kLdsLimit) return hipErrorInvalidValue;
+  switch (P.Nch) {
+    case 1: return direct_taps<T, 1>(c, P, epi, st);
+    case 2: return direct_taps<T, 2>(c, P, epi, st);
+    case 3: return direct_taps<T, 3>(c, P, epi, st);
+    case 4: return direct_taps<T, 4>(c, P, epi, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_conv(int bf16_mode, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st) {
   if (c.M <= 0) return hipSuccess;
+  if (cfg == kConvDirectCfg) {
+    if (!c.trans || !conv_direct_ok(c.cg, kind)) return hipErrorInvalidValue;
+    const ConcEpi e{*(const ConcEpiArgs*)epi};
+    return bf16_mode ? conv_direct<bf16>(c, e, st) : conv_direct<float>(c, e, st);
+  }
   if (cfg < 0 || cfg >= conv_num_configs()) return hipErrorInvalidValue;
   if (fused_explicit_pi(kind, epi))
     return bf16_mode ? conv_typed_pi<bf16>(cfg, kind, c, epi, st) : conv_typed_pi<float>(cfg, kind, c, epi, st);

@@ -24,6 +24,20 @@ namespace gcp {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Memory that no thread writes while a kernel runs, read through the
+// constant address space: a wave-uniform address then becomes a scalar load,
+// and pointers read from it are known to address global memory.
+// (The host pass only type-checks this code and has no address spaces.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GCP_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define GCP_CONSTANT_AS
+#endif
+template <typename T>
+__device__ inline const GCP_CONSTANT_AS T* cst(const T* p) {
+  return (const GCP_CONSTANT_AS T*)p;
+}
+
 // ------------------------------------------------------------------ MFMA
 template <typename T> struct Op;
 template <> struct Op<float> {

@@ -210,6 +210,7 @@ struct EdgeH {
   DBuf W16;
   DBuf WT32;     // bound Bt: dense [d_src][ld_dst]; conv [ci][ldk_t]
   DBuf WT16;
+  DBuf WT16f;    // conv: WT16's values as fp32 (read by the direct transposed conv in bf16 mode)
   DBuf Wraw;     // dense [d_dst][d_src] unpadded fp32 (for c-hat and W x0); conv: [co][ci][kh][kw]
   int ldk_f = 0, ldk_t = 0;   // conv: padded K of W32/W16 (adjoint) and WT32/WT16 (bound)
 };
@@ -342,6 +343,15 @@ std::vector<uint16_t> to_bf16(const std::vector<float>& v) {
     uint32_t lsb = (b >> 16) & 1u;
     b += 0x7fffu + lsb;
     o[i] = (uint16_t)(b >> 16);
+  }
+  return o;
+}
+
+std::vector<float> bf16_as_f32(const std::vector<uint16_t>& v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    const uint32_t b = (uint32_t)v[i] << 16;
+    std::memcpy(&o[i], &b, 4);
   }
   return o;
 }
@@ -525,6 +535,7 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
         E->ldk_t = kt;
         E->W32.upload(fw); E->W16.upload(to_bf16(fw));
         E->WT32.upload(ft); E->WT16.upload(to_bf16(ft));
+        E->WT16f.upload(bf16_as_f32(to_bf16(ft)));
         std::vector<double> wy(E->d_dst, 0.0);
         for (int o = 0; o < n.c; ++o)
           for (int y = 0; y < ho; ++y)
@@ -651,6 +662,21 @@ Cands dense_cands(int M, int N) {
 Cands conv_cands() {
   Cands c{{}, 0};
   for (int i = 0; i < conv_num_configs(); ++i) c.list.push_back(i);
+  return c;
+}
+// The concretisation over the input: the direct transposed conv joins the
+// candidates where it applies, and is the fallback there (GCP_CONV_DIRECT=0
+// leaves it out).
+bool conv_direct_enabled() {
+  const char* e = std::getenv("GCP_CONV_DIRECT");
+  return !(e && e[0] == '0');
+}
+Cands conc_conv_cands(const ConvGeom& g) {
+  Cands c = conv_cands();
+  if (conv_direct_enabled() && conv_direct_ok(g, EPI_CONC)) {
+    c.list.push_back(kConvDirectCfg);
+    c.fallback = kConvDirectCfg;
+  }
   return c;
 }
 // Explicit-pi launches: the shapes their epilogues are instantiated for, and
@@ -1532,6 +1558,7 @@ struct BoundPass {
       ca.M = c.M; ca.cg = cg; ca.trans = 1;
       ca.X = ws.lam[E.dst]->p; ca.ldx = dn.ld; ca.x_is_sign = 0;
       ca.Bt = bf16 ? E.WT16.p : E.WT32.p; ca.ldb = E.ldk_t;
+      ca.Btf = (const float*)(bf16 ? E.WT16f.p : E.WT32.p);
       ca.mp = c.rp.mp; ca.partial = nullptr;
       const double M = c.M, esz = bf16 ? 2 : 4;
       // every multiply-add of the forward conv appears once in its transpose
@@ -1577,13 +1604,14 @@ struct BoundPass {
         a.contrib = want_contrib ? ws.contrib.as<float>() : nullptr;
         a.nnz_e = c.nnz;
         if (!dry) {
-          int cfg = choose_cfg("convT", EPI_CONC, bf16, 0, c.M, d_src, dn.size, c.st, conv_cands(),
+          int cfg = choose_cfg("convT", EPI_CONC, bf16, 0, c.M, d_src, dn.size, c.st, conc_conv_cands(cg),
                                [&](int cf) { return launch_conv(bf16, cf, EPI_CONC, ca, &a, c.st); });
           ConvArgs cr = ca;
           cr.partial = ws.partial.as<double>(); cr.slot0 = slot;
           const double bytes = M * dn.size * esz + wbytes + (keep_ahat ? M * d_src : 0) +
                                M * nnz_of(c, -1) * 4 * (want_contrib ? 2 : 1) + M * nslot * 8;
-          check(timed(c.st, cls_name("convT_conc", bf16, 0, -1), Bytes{bytes, 0.0}, flops,
+          check(timed(c.st, cls_name("convT_conc", bf16, 0, -1) + (cfg == kConvDirectCfg ? ".direct" : ""),
+                      Bytes{bytes, 0.0}, flops,
                       [&] { return launch_conv(bf16, cfg, EPI_CONC, cr, &a, c.st); }));
         }
       }
@@ -1689,6 +1717,7 @@ struct AdjPass {
       ca.M = c.M; ca.cg = E.cg; ca.trans = 1;
       ca.X = ws.lam[E.dst]->p; ca.ldx = dn.ld; ca.x_is_sign = 0;
       ca.Bt = bf16 ? E.WT16.p : E.WT32.p; ca.ldb = E.ldk_t;
+      ca.Btf = (const float*)(bf16 ? E.WT16f.p : E.WT32.p);
       ca.mp = c.rp.mp; ca.partial = nullptr;
       const ConvGeom& cg = E.cg;
       const int cfg = choose_cfg("convT", EPI_BOUND, bf16, 0, c.M, E.d_src, dn.size, c.st, conv_cands(),

@@ -169,6 +169,7 @@ struct ConvArgs {
   int trans;              // 1: transposed (bound direction)
   const void* X; int ldx; int x_is_sign;
   const void* Bt; int ldb;
+  const float* Btf;       // transposed direction: Bt's values as fp32 (bf16-rounded in bf16 mode), for the direct kernel
   double* partial; int mp; int slot0;
 };
 // Work split of one conv launch: the epilogue-side rows form bands of BH
@@ -190,6 +191,11 @@ int conv_ldb(const ConvGeom& g, int trans);
 void conv_pack_weights(const ConvGeom& g, int trans, const float* raw, float* out);
 hipError_t launch_conv(int bf16, int cfg, EpiKind kind, const ConvArgs& c, const void* epi, hipStream_t st);
 int conv_num_configs();
+// launch_conv's cfg for the direct (VALU) transposed convolution, and whether
+// it applies: concretisation over a source of at most four channels, taps
+// per phase 2x2 at stride 2 or 3x3 at stride 1
+constexpr int kConvDirectCfg = 6;
+bool conv_direct_ok(const ConvGeom& g, EpiKind kind);
 // row-partial slots a conv launch owns: one per band
 inline int conv_slots(const ConvGeom& g, int trans) { return conv_plan(g, trans).n_bands; }
 

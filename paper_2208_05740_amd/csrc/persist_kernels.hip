@@ -71,16 +71,7 @@ __device__ inline int xcc_id() {
 // global instructions (read as generic pointers they would be flat ones,
 // which also count against the LDS counter, so every LDS wait of the tile
 // loop would wait for them too).
-// (The host pass only type-checks this code and has no address spaces.)
-#if defined(__HIP_DEVICE_COMPILE__)
-#define GCP_CONSTANT_AS __attribute__((address_space(4)))
-#else
-#define GCP_CONSTANT_AS
-#endif
-template <typename T>
-__device__ inline const GCP_CONSTANT_AS T* cst(const T* p) {
-  return (const GCP_CONSTANT_AS T*)p;
-}
+// (cst() in epilogues.h.)
 
 template <typename T, class Epi>
 __device__ inline void run_gemm(const GemmArgs& g, const Epi& e, int vt, bool sign, typename PersistCfg<T>::Lds& sm) {

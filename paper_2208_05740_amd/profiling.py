@@ -60,12 +60,28 @@ def conv_class_of(symbol):
     return name + (".sign" if sg == "1" else "") + f".w{nw}x{tn}"
 
 
+def direct_class_of(symbol):
+    """Kernel-class name ('convT_conc.fp32.direct.c3k2x2': source channels,
+    taps per phase) of a direct transposed-conv instantiation, or None."""
+    m = (re.search(r"convT_direct_kernelI(DF16b|f)Li(\d+)ELi(\d+)ELi(\d+)ELi\d+ENS_\d+(\w+?Epi)", symbol) or
+         re.search(r"convT_direct_kernel<(float|__bf16), (\d+), (\d+), (\d+), \d+, gcp::(\w+Epi)", symbol))
+    if not m:
+        return None
+    dt, nc, ta, tb, epi = m.groups()
+    kind = CONV_EPI.get(epi)
+    if kind is None:
+        return None
+    return f"convT_{kind}.{'bf16' if dt in ('DF16b', '__bf16') else 'fp32'}.direct.c{nc}k{ta}x{tb}"
+
+
 def class_of(symbol):
     """Library kernel-class name ('adj.bf16.t32x32', 'convT_bound.bf16.w4x1',
-    ...) of a gemm_epi or conv_slab instantiation, from its mangled or
-    demangled symbol; None otherwise."""
+    ...) of a gemm_epi, conv_slab or direct transposed-conv instantiation,
+    from its mangled or demangled symbol; None otherwise."""
     if "conv_slab_kernel" in symbol:
         return conv_class_of(symbol)
+    if "convT_direct_kernel" in symbol:
+        return direct_class_of(symbol)
     m = re.search(r"gemm_epi_kernelI(DF16b|f)Li(\d+)ELi(\d+)ELi\d+ELi\d+ELi\d+ELb([01])ENS_\d+(\w+?Epi)", symbol)
     if m:
         dt, bm, bn, sg, epi = m.groups()

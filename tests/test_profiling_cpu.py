@@ -30,6 +30,9 @@ CASES = [
      "convT_bound_pi.fp32.w8x1"),
     ("_ZN3gcp16conv_slab_kernelIDF16bLi8ELi1ELb1ELb0ENS_7AhatEpiIDF16bEEEEvNS_8ConvArgsENS_8ConvPlanET4_",
      "convT_ahat.bf16.w8x1"),
+    ("_ZN3gcp19convT_direct_kernelIfLi3ELi2ELi2ELi2ENS_7ConcEpiEEEvNS_8ConvArgsENS_8ConvPlanET4_",
+     "convT_conc.fp32.direct.c3k2x2"),
+    ("void gcp::convT_direct_kernel<__bf16, 1, 3, 3, 1, gcp::ConcEpi>", "convT_conc.bf16.direct.c1k3x3"),
     ("gcp::gamma_kernel", None),
     ("__amd_rocclr_copyBuffer", None),
 ]
