@@ -1910,7 +1910,9 @@ void prepare_call(Call& c, gcp_net* net, const double* x0, double eps, const dou
 // more GEMM, so only one layer's a_hat is live at a time instead of all of
 // them.  GCP_FLAG_RECOMPUTE forces it, GCP_FLAG_STORE_AHAT disables it;
 // otherwise it is used when the stored a_hat of all layers would exceed
-// GCP_AHAT_BUDGET_MB (default 8192 MiB).  Sizes the buffers either way.
+// GCP_AHAT_BUDGET_MB, by default half of the device memory that is free
+// or already held by a_hat buffers when the call is planned (storing is
+// the faster form wherever it fits).  Sizes the buffers either way.
 bool ahat_recomputable(const gcp_net* net, int i) {
   const NodeH& n = net->nodes[i];
   if (!n.relu || n.consumers.size() != 1) return false;
@@ -1925,7 +1927,17 @@ void plan_ahat(Call& c, int32_t mode) {
   for (int i = 0; i < nn; ++i)
     if (net->nodes[i].relu) stored += (size_t)c.M * net->nodes[i].ld * 4;
   const char* e = std::getenv("GCP_AHAT_BUDGET_MB");
-  const double budget = (e && *e ? std::atof(e) : 8192.0) * 1048576.0;
+  double budget = 8192.0 * 1048576.0;
+  if (e && *e) {
+    budget = std::atof(e) * 1048576.0;
+  } else {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      size_t held = ws.ahat_tmp.bytes;
+      for (int i = 0; i < nn; ++i) held += ws.ahat[i]->bytes;
+      budget = 0.5 * (double)(fr + held);
+    }
+  }
   const bool want = (mode & GCP_FLAG_RECOMPUTE) || (!(mode & GCP_FLAG_STORE_AHAT) && (double)stored > budget);
   c.recompute.assign(nn, 0);
   size_t tmp = 0;

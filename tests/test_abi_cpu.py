@@ -54,7 +54,8 @@ def test_null_arguments_are_rejected_without_a_device():
 def test_shipped_tile_choices_are_well_formed():
     # bench.py starts from these autotuner choices; each line is
     # "<family>.k<epilogue>.b<bf16>.s<sign>.M<m>.N<n>.K<k> <config>" with a
-    # config index the family's launcher accepts (8 dense tiles, 6 conv shapes)
+    # config index the family's launcher accepts (8 dense tiles, 6 conv shapes,
+    # and 6 = the direct kernel for the concretisation's transposed conv, k2)
     import re
     path = os.path.join(os.path.dirname(LIB), "tuned_tiles_gfx950.txt")
     pat = re.compile(r"^(gemm|conv|convT)\.k([0-4])\.b([01])\.s([01])\.M(\d+)\.N(\d+)\.K(\d+) (\d+)$")
@@ -64,6 +65,7 @@ def test_shipped_tile_choices_are_well_formed():
             m = pat.match(line.strip())
             assert m, line
             cfg = int(m.group(8))
-            assert 0 <= cfg < (8 if m.group(1) == "gemm" else 6), line
+            direct = m.group(1) == "convT" and m.group(2) == "2" and cfg == 6
+            assert direct or 0 <= cfg < (8 if m.group(1) == "gemm" else 6), line
             n += 1
     assert n > 0
