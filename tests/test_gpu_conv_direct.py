@@ -12,9 +12,11 @@ event profiler names the launch that ran.
 
 Cases: single-channel tiny networks (3x3 stride 2, 4x4 stride 2 and 3x3
 stride 1 stems; input cuts, so the epilogue's cut terms and gamma-gradient
-pieces are live), the 3x32x32 CNN stem (4x4 stride 2, two row bands) and the
-ResNet stem (3x3 stride 1, three bands), with batch rows that leave a ragged
-last group of four.  Tolerances are those of the other parity tests: FP32
+pieces are live), 2- and 4-channel tiny networks (every channel count the
+kernel is built for; rows of whole and of partial staging vectors), the
+3x32x32 CNN stem (4x4 stride 2, two row bands) and the ResNet stem (3x3
+stride 1, three bands), with batch rows that leave a ragged last group of
+four.  Tolerances are those of the other parity tests: FP32
 bound within 1e-5 of max(|g|, T) of the oracle (T the sum of the magnitudes
 of the terms added), gradients within 1e-4 of the row's largest, bf16
 within 2e-2 of T.  Direct and slab results differ only in the order of the
@@ -78,6 +80,16 @@ def _bound(prob, mode, which, tmp_path):
     return dict(bound=n(out), ver=n(ver), grads=[n(x) for x in g], a=a, b=b, c=c), ran
 
 
+def _multichannel(seed, in_shape, stem):
+    """A small conv net on a multi-channel input: the stem conv (c_out, k,
+    stride, pad), a 3x3 conv, dense 5, out 3; splits, cuts and input cuts."""
+    r_w, r_x, r_cut, r_split, r_par = gen._streams([seed, 98])
+    net = gen.cnn_net(r_w, in_shape, (stem, (3, 3, 1, 1)), (5, 3))
+    x0 = r_x.random(net.in_size)
+    return gen.make_problem(f"tiny-c{in_shape[0]}", net, x0, 0.1, None, 3, 1, 2, 5, 2, 4, (r_cut, r_split, r_par),
+                            alpha_init="given", gamma_dist="uniform", input_terms=1)
+
+
 CASES = [
     ("tiny", "cnn", 1, dict(B=5, splits=(1, 3), n_cuts=6, input_terms=1)),     # 1x6x6, 3x3 s2
     ("tiny", "cnn16", 2, dict(B=3, splits=(1, 2), n_cuts=6, input_terms=1)),   # 1x8x8, 4x4 s2
@@ -85,12 +97,17 @@ CASES = [
     ("tiny", "res16", 4, dict(B=3, splits=(0, 0), n_cuts=0)),                  # no cuts, no splits
     ("cnn", None, 0, dict(B=3)),       # 3x32x32, 4x4 s2: 27 rows, a ragged group of four
     ("resnet", None, 0, dict(B=1)),    # 3x32x32, 3x3 s1
+    ("multi", (2, 7, 7), 5, (3, 4, 2, 1)),   # 2 channels, 4x4 s2, rows of 3 (element-wise staging)
+    ("multi", (2, 8, 8), 6, (3, 4, 2, 1)),   # 2 channels, 4x4 s2, rows of 4
+    ("multi", (4, 6, 6), 7, (2, 3, 1, 1)),   # 4 channels, 3x3 s1
 ]
 
 
 def _problem(which, kind, seed, kw):
     if which == "tiny":
         return gen.make_tiny(kind, seed, **kw)
+    if which == "multi":
+        return _multichannel(seed, kind, kw)
     return gen.make_workload(which, seed, **kw)
 
 
@@ -125,7 +142,7 @@ def test_direct_conc_matches_oracle_and_slab(case, tmp_path):
     assert err.max() <= 1e-5, err.max()
 
 
-@pytest.mark.parametrize("case", [0, 4])
+@pytest.mark.parametrize("case", [0, 4, 7])
 def test_direct_conc_bf16_close_to_oracle(case, tmp_path):
     which, kind, seed, kw = CASES[case]
     print(f"direct transposed conv, bf16: {which} {kind} seed={seed} {kw}", flush=True)
