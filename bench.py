@@ -213,6 +213,21 @@ def main():
             "verified_rows": int((bound_main >= 0).sum()),
         },
     }
+    if kprof:
+        # the adjoint's a_hat: stored by the bound pass, or rebuilt per layer
+        # (the library recomputes only where the stored copies would not fit)
+        out["config"]["a_hat"] = ("recomputed" if any(k.split(".")[0] in ("ahat", "convT_ahat") for k in kprof)
+                                  else "stored")
+    if args.workload == "resnet" and not args.no_compare:
+        # the ResNet configuration's own form: a_hat recomputed in the adjoint
+        # (bitwise equal results: the recomputing GEMM sums in the same order)
+        dtr = timed(mode | B.GCP_FLAG_RECOMPUTE, max(1, args.steps // 2), 1)
+        torch.cuda.synchronize()
+        out["config"]["recompute_form"] = {
+            "value": args.domains * max(1, args.steps // 2) / dtr,
+            "ms_per_step": dtr * 1000.0 / max(1, args.steps // 2),
+            "final_bound_equals_stored": bool(np.array_equal(bound.cpu().numpy(), bound_main)),
+        }
     if pi:
         # the same optimisation with Lemma A.1's pi*, for the bound it reaches
         step(mode, explicit=False)
