@@ -162,8 +162,10 @@ int gcp_splits_destroy(gcp_splits* splits);
                                     (synchronises the stream)               */
 /* Pre-activation coefficients a_hat of every ReLU layer (Theorem 3.1) are
  * needed again by the adjoint.  By default they are stored by the bound pass
- * unless the stored copies of all layers would exceed GCP_AHAT_BUDGET_MB
- * (environment, default 8192 MiB); then a layer whose a_hat comes from a
+ * unless the stored copies of all layers would exceed half of the device
+ * memory that is free (or already held by a_hat buffers) when the call is
+ * planned, or GCP_AHAT_BUDGET_MB (environment, MiB) where that is set; then
+ * a layer whose a_hat comes from a
  * single dense or conv consumer recomputes it in the adjoint from that
  * consumer's Lambda (one more GEMM, one layer's a_hat live at a time).
  * Results are identical either way.  The flags force one policy. */
