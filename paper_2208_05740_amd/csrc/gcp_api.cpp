@@ -1376,6 +1376,10 @@ struct BoundPass {
   bool dry;           // count partial slots only
   int slot = 0;
   std::vector<int> pushes_left;   // per node (index n_nodes: input)
+  // Per node: the fp32 Lambda that stands in for its accumulation buffer when
+  // an identity edge is the first of exactly two pushes (the copy into the
+  // buffer would be exact), or null.
+  std::vector<const float*> acc_alias;
 
   BoundPass(Call& cc, int b, bool k, bool wc, bool d) : c(cc), bf16(b), keep_ahat(k), want_contrib(wc), dry(d) {}
 
@@ -1387,7 +1391,7 @@ struct BoundPass {
     a.nd = c.net->nodes[p].dev();
     a.cc = cut_col(c, p);
     a.rp = c.rp;
-    a.acc_in = has_acc ? ws.acc[p]->as<float>() : nullptr;
+    a.acc_in = has_acc ? (acc_alias[p] ? acc_alias[p] : ws.acc[p]->as<float>()) : nullptr;
     a.lam_out = ws.lam[p]->p;
     const bool rec = !c.recompute.empty() && c.recompute[p];
     a.ahat_out = (keep_ahat && !rec) ? ws.ahat[p]->p : nullptr;
@@ -1401,6 +1405,7 @@ struct BoundPass {
     const int nn = (int)net->nodes.size();
     auto& ws = *c.ws;
     pushes_left.assign(nn + 1, 0);
+    acc_alias.assign(nn + 1, nullptr);
     for (int i = 0; i < nn; ++i) pushes_left[i] = (int)net->nodes[i].consumers.size();
     pushes_left[nn] = (int)net->in_consumers.size();
     // output node: c-hat = C W (per spec row), constant C b_out
@@ -1622,6 +1627,10 @@ struct BoundPass {
       no_record(c, "identity");
       if (p < 0) fail(GCP_EUNSUPPORTED, "identity edge from the network input");
       if (!last) {
+        if (!bf16 && first && total == 2 && dn.ld == ld_src) {
+          acc_alias[p] = ws.lam[E.dst]->as<float>();   // the last push reads it in place of the buffer
+          return;
+        }
         if (!dry)
           check(launch_identity_acc(bf16, c.M, d_src, ws.lam[E.dst]->p, dn.ld, 0, 1.f, first ? nullptr : accbuf,
                                     accbuf, ld_src, c.st));
@@ -1741,6 +1750,10 @@ struct AdjPass {
     for (int eid : n.in_edges)
       if (net->edges[eid]->kind != GCP_EDGE_IDENTITY) order.push_back(eid);
     float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
+    // what the fused epilogue reads as the accumulated dLambda: the buffer, or,
+    // when an identity edge from an fp32 d a_hat is the first of exactly two
+    // edges (its copy into the buffer would be exact), that d a_hat itself
+    const float* acc_rd = accbuf;
     // the node's adjoint epilogue runs fused with its last GEMM, or
     // elementwise after all edges when the last edge is an identity
     const bool pi = c.rp.rho != nullptr;
@@ -1781,7 +1794,7 @@ struct AdjPass {
             check(timed(c.st, cls_name("store", bf16, sign, cfg), Bytes{bytes, 0.0}, 2.0 * g.M * g.N * g.K,
                         [&] { return launch_gemm(bf16, cfg, EPI_STORE, g, &s, c.st); }));
         } else {
-          AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
+          AdjEpiArgs a = epi(i, use_acc ? acc_rd : nullptr, scale);
           int cfg = choose_cfg("gemm", pi ? EPI_ADJ + kPiKey : EPI_ADJ, bf16, sign, g.M, g.N, g.K, c.st,
                                pi ? pi_dense_cands(g.M, g.N) : dense_cands(g.M, g.N), [&](int cf) {
             AdjEpiArgs t = a;     // gradient-only trial into scratch: no parameter moves
@@ -1818,7 +1831,7 @@ struct AdjPass {
           check(timed(c.st, cls_name("conv_store", bf16, sign, -1), Bytes{a_bytes + wbytes + M * di * 4 * (first ? 1 : 2), 0.0},
                       flops, [&] { return launch_conv(bf16, cfg, EPI_STORE, ca, &s, c.st); }));
         } else {
-          AdjEpiArgs a = epi(i, use_acc ? accbuf : nullptr, scale);
+          AdjEpiArgs a = epi(i, use_acc ? acc_rd : nullptr, scale);
           int cfg = choose_cfg("conv", pi ? EPI_ADJ + kPiKey : EPI_ADJ, bf16, sign, c.M, n.size, E.d_src, c.st,
                                pi ? pi_conv_cands() : conv_cands(), [&](int cf) {
             AdjEpiArgs t = a;
@@ -1834,6 +1847,10 @@ struct AdjPass {
         }
       } else {   // identity: accumulate; the node's relaxation runs after the last edge
         no_record(c, "identity");
+        if (!bf16 && !sign && first && !last && order.size() == 2 && lda == n.ld) {
+          acc_rd = (const float*)A;
+          continue;
+        }
         check(launch_identity_acc(bf16, c.M, n.size, A, lda, sign, scale, first ? nullptr : accbuf, accbuf, n.ld,
                                   c.st));
       }
@@ -1845,7 +1862,7 @@ struct AdjPass {
     }
   }
 
-  AdjEpiArgs epi(int i, float* acc_in, float scale) {
+  AdjEpiArgs epi(int i, const float* acc_in, float scale) {
     gcp_net* net = c.net;
     auto& ws = *c.ws;
     const NodeH& n = net->nodes[i];
