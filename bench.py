@@ -29,6 +29,9 @@ PEAKS = {  # MI355X published dense peaks
     "bf16_TFLOPs": 2500.0,
     "fp32_TFLOPs": 157.3,
     "fp64_TFLOPs": 78.6,
+    # fp32 FMAs on the vector ALUs without packed math (the build leaves it
+    # off): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz
+    "fp32_valu_TFLOPs": 78.6,
 }
 
 
@@ -415,7 +418,12 @@ def roofline(kprof, dtype):
          "algorithmic_bytes_per_launch": alg / n, "flops_per_launch": k["flops"] / n,
          "operand_bytes_per_launch": k["bytes"] / n, "operand_GBps": k["bytes"] / secs / 1e9,
          "arith_intensity": ai, "ridge": ridge}
-    if ai < ridge:
+    if ".direct" in name:
+        # the direct transposed conv does its FMAs on the vector ALUs
+        ach = k["flops"] / secs / 1e12
+        peak = PEAKS["fp32_valu_TFLOPs"]
+        r.update(bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
+    elif ai < ridge:
         ach = alg / secs / 1e9
         r.update(bound="hbm", achieved=ach, peak=PEAKS["hbm_GBps"], unit="GB/s", frac=ach / PEAKS["hbm_GBps"])
     else:
