@@ -1752,7 +1752,8 @@ struct AdjPass {
     float* accbuf = ws.acc[i]->p ? ws.acc[i]->as<float>() : nullptr;
     // what the fused epilogue reads as the accumulated dLambda: the buffer, or,
     // when an identity edge from an fp32 d a_hat is the first of exactly two
-    // edges (its copy into the buffer would be exact), that d a_hat itself
+    // edges and the other is a GEMM edge (its copy into the buffer would be
+    // exact), that d a_hat itself
     const float* acc_rd = accbuf;
     // the node's adjoint epilogue runs fused with its last GEMM, or
     // elementwise after all edges when the last edge is an identity
@@ -1847,7 +1848,7 @@ struct AdjPass {
         }
       } else {   // identity: accumulate; the node's relaxation runs after the last edge
         no_record(c, "identity");
-        if (!bf16 && !sign && first && !last && order.size() == 2 && lda == n.ld) {
+        if (!bf16 && !sign && first && !last && fused_last && order.size() == 2 && lda == n.ld) {
           acc_rd = (const float*)A;
           continue;
         }
