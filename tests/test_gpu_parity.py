@@ -316,13 +316,30 @@ def test_optimize_conv_matches_oracle():
     assert rel_err(g, go.reshape(-1), To).max() <= 1e-3
 
 
-def test_graph_replayed_optimisation_equals_eager():
+GRAPH_CASES = [
+    ("mlp784", dict(seed=1, B=3, roots="ibp"), 0),
+    ("tiny", dict(kind="cnn", seed=2, B=3, splits=(1, 2), n_cuts=6, input_terms=1), 0),
+    ("tiny", dict(kind="res16", seed=4, B=2, splits=(1, 2), n_cuts=5, input_terms=1), 1),
+    ("cnn", dict(seed=0, B=2, roots="ibp"), 0),       # 3x32x32 stem: the direct transposed conv
+    ("cnn", dict(seed=0, B=2, roots="ibp"), 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(GRAPH_CASES)))
+def test_graph_replayed_optimisation_equals_eager(case):
     # One Adam iteration captured in a hipGraph and replayed must give the
     # same final parameters and bound as the eager loop, on every call, with
-    # eager work in between.
+    # eager work in between: dense nets, conv nets (the input term through
+    # the transposed conv) and a residual DAG, in both precisions.
     import torch
     from paper_2208_05740_amd import binding as B
-    p = gen.make_workload("mlp784", 1, B=3, roots="ibp")
+    which, kw, mode = GRAPH_CASES[case]
+    kw = dict(kw)
+    print(f"graph replay: {which} {kw} mode={mode}", flush=True)
+    if which == "tiny":
+        p = gen.make_tiny(kw.pop("kind"), kw.pop("seed"), **kw)
+    else:
+        p = gen.make_workload(which, kw.pop("seed"), **kw)
     P = upload(p)
     a0, b0, c0, *_ = params(p, P)
     o = p.opt
@@ -331,9 +348,10 @@ def test_graph_replayed_optimisation_equals_eager():
         a, b, c = a0.clone(), b0.clone(), c0.clone()
         st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
         out, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=o["iters"],
-                            lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], use_graph=graph)
+                            lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], mode=mode,
+                            use_graph=graph)
         torch.cuda.synchronize()
-        return out.cpu().numpy(), a.cpu().numpy(), c.cpu().numpy()
+        return out.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
 
     ref = run(False)
     for rep in range(3):
