@@ -444,8 +444,11 @@ typedef struct {
  * them.  With opt->use_graph the grouped iteration is captured once and
  * replayed.  Results equal per-instance gcp_optimize calls with the same
  * tiles.  Every item needs its own net handle; grouped instances must be
- * dense networks (EUNSUPPORTED for conv or identity edges).  Calls from
- * several threads are serialised. */
+ * dense networks with the output in the c-hat form: a batch whose grouped
+ * part holds conv or identity edges (or a materialised output Lambda) is
+ * rejected with EUNSUPPORTED, and null handles, state or bound pointers with
+ * EINVAL, before anything is launched.  Calls from several threads are
+ * serialised. */
 int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode, void* stream);
 
 /* ------------------------------------------------------------ profiling */

@@ -2826,6 +2826,16 @@ long instance_work(const gcp_batch_item& it) {
   for (const NodeH& nd : it.net->nodes) width = std::max(width, nd.ld);
   return (long)it.splits->B * it.S * width;
 }
+// Grouped launches replay a recorded schedule of dense GEMMs with fused
+// epilogues: conv and identity edges and a materialised output Lambda have no
+// recorded form.  Returns what stands in the way, or null.
+const char* grouped_unsupported(const gcp_net* net) {
+  for (const auto& e : net->edges) {
+    if (e->kind == GCP_EDGE_CONV) return "conv";
+    if (e->kind == GCP_EDGE_IDENTITY) return "identity";
+  }
+  return net->out_general ? "output Lambda not in the c-hat form" : nullptr;
+}
 }  // namespace
 
 extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all, const gcp_opt* opt, int32_t mode,
@@ -2836,9 +2846,12 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   const int bf16 = (mode & 0xff) == GCP_MODE_BF16;
   if ((mode & 0xff) != GCP_MODE_FP32 && !bf16) fail(GCP_EINVAL, "unknown mode");
   hipStream_t st = (hipStream_t)stream;
-  for (int i = 0; i < n_all; ++i)
+  for (int i = 0; i < n_all; ++i) {
+    if (!items_all[i].net || !items_all[i].splits) fail(GCP_EINVAL, "null net or splits handle in a batch item");
+    if (!items_all[i].adam_state || !items_all[i].bound) fail(GCP_EINVAL, "null adam_state or bound");
     for (int k = 0; k < i; ++k)
       if (items_all[k].net == items_all[i].net) fail(GCP_EINVAL, "each batch item needs its own net handle (workspace)");
+  }
   // large instances: their own launches (the same kernels and tiles as
   // gcp_optimize), spread over a few streams by longest-first assignment
   // with GCP_FLAG_PERSIST every instance shares the one persistent launch
@@ -2852,6 +2865,11 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     const long w = instance_work(items_all[i]);
     if (w < alone) grouped.push_back(items_all[i]);
     else big.push_back({w, i});
+  }
+  // what would stop the grouped part is reported before anything runs
+  for (const gcp_batch_item& it : grouped) {
+    if (const char* why = grouped_unsupported(it.net))
+      fail(GCP_EUNSUPPORTED, std::string("batched optimisation supports dense edges only (") + why + ")");
   }
   if (!big.empty()) {
     const int ns = std::min<int>(batch_streams(), (int)big.size());

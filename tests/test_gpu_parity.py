@@ -459,6 +459,55 @@ def test_batched_optimisation_mixed_alone_and_grouped(monkeypatch):
             assert np.array_equal(it["gamma"].cpu().numpy(), c)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batched_optimisation_conv_and_residual_instances(mode, monkeypatch):
+    # conv and residual instances above the work threshold run alone (their
+    # own gcp_optimize launches) beside grouped dense instances, with results
+    # equal to per-instance gcp_optimize; below it they would be grouped, and
+    # the call is rejected with EUNSUPPORTED before anything runs
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print(f"batch with conv and residual instances, mode={mode}", flush=True)
+    probs = [gen.make_tiny("cnn", 2, B=4, splits=(1, 2), n_cuts=6, input_terms=1),
+             gen.make_tiny("mlp", 3, B=5, splits=(1, 3), n_cuts=6),
+             gen.make_tiny("res16", 4, B=3, splits=(1, 2), n_cuts=5),
+             gen.make_tiny("mlp", 5, B=2, splits=(0, 0), n_cuts=0)]
+    work = [p.B * p.S * max((n.size + 15) // 16 * 16 for n in p.net.nodes) for p in probs]
+    dense = [1, 3]
+    lo, hi = max(work[i] for i in dense), min(w for i, w in enumerate(work) if i not in dense)
+    assert lo < hi
+    Ps = [upload(p) for p in probs]
+    o = probs[0].opt
+    ref = []
+    for p, P in zip(probs, Ps):
+        g, a, b, c = _optimize(p, P, mode)
+        ref.append((g, a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()))
+    monkeypatch.setenv("GCP_BATCH_ALONE_WORK", str((lo + hi) // 2))
+    for graph in (False, True):
+        items = _batch_items(probs, Ps)
+        B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                         mode=mode, use_graph=graph)
+        torch.cuda.synchronize()
+        for it, (g, a, b, c) in zip(items, ref):
+            assert np.array_equal(it["bound"].cpu().numpy(), g)
+            assert np.array_equal(it["alpha"].cpu().numpy(), a)
+            assert np.array_equal(it["beta"].cpu().numpy(), b)
+            assert np.array_equal(it["gamma"].cpu().numpy(), c)
+    monkeypatch.delenv("GCP_BATCH_ALONE_WORK")
+    items = _batch_items(probs, Ps)
+    for it in items:
+        it["bound"].fill_(float("nan"))
+    before = [{k: it[k].clone() for k in ("alpha", "beta", "gamma", "state")} for it in items]
+    with pytest.raises(B.GcpError) as e:
+        B.optimize_batch(items, iters=o["iters"], mode=mode)
+    torch.cuda.synchronize()
+    assert e.value.code == -6 and "conv" in str(e.value), str(e.value)
+    for it, b0 in zip(items, before):
+        assert torch.isnan(it["bound"]).all()
+        for k, v in b0.items():
+            assert torch.equal(it[k], v), k
+
+
 def test_batched_optimisation_certified_bound_matches_oracle():
     import torch
     from paper_2208_05740_amd import binding as B
