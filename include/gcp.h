@@ -90,7 +90,9 @@ typedef struct gcp_net gcp_net;
 
 /* Copies weights, biases and root bounds to the current device (fp32 and
  * bf16 copies of every weight).  Errors: EINVAL (shapes, edge sources not
- * earlier, conv geometry), ENONFINITE (weights/bounds), ENOMEM, EDEVICE. */
+ * earlier, conv geometry, an unused input), EUNSUPPORTED (a ReLU node without
+ * consumers; the input feeding more than one edge, or an identity edge),
+ * ENONFINITE (weights/bounds), ENOMEM, EDEVICE. */
 int gcp_net_create(const gcp_net_desc* desc, gcp_net** out);
 int gcp_net_destroy(gcp_net* net);
 

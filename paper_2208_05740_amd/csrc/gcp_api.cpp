@@ -574,6 +574,10 @@ void build_net(const gcp_net_desc* d, gcp_net* net) {
     if (net->nodes[i].consumers.empty()) fail(GCP_EUNSUPPORTED, "ReLU node without consumers");
   build_slack_weights(net, e_wy, e_terms);
   if (net->in_consumers.empty()) fail(GCP_EINVAL, "network input is unused");
+  // the concretisation takes one pushed Lambda, through a dense or conv edge
+  if (net->in_consumers.size() > 1) fail(GCP_EUNSUPPORTED, "several consumers of the network input");
+  if (net->edges[net->in_consumers[0]]->kind == GCP_EDGE_IDENTITY)
+    fail(GCP_EUNSUPPORTED, "identity edge from the network input");
   const char* og = std::getenv("GCP_OUT_GENERAL");
   net->out_general = og && *og && std::atoi(og) != 0;
   for (int eid : net->nodes[net->out].in_edges) {

@@ -197,6 +197,36 @@ def test_bad_splits_cuts_and_call_arguments_are_rejected_before_any_launch():
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
 
 
+def test_unsupported_net_structures_are_rejected_at_creation():
+    """Structures the bound pass has no form for fail when the net is created
+    (GCP_EUNSUPPORTED), not in a later call: the input feeding two edges, an
+    identity edge from the input, a ReLU node nothing consumes."""
+    from paper_2208_05740_amd import binding as B
+    from workloads.gen import Edge, Net, Node
+    r = np.random.default_rng(0)
+    W = lambda o, i: gen._f32(r.normal(0.0, 0.4, (o, i)))  # noqa: E731
+    b = lambda n: gen._f32(r.normal(0.0, 0.3, n))  # noqa: E731
+    nets = [
+        ("several consumers", Net((6,), [Node((8,), b(8), [Edge(-1, "dense", W(8, 6))]),
+                                         Node((8,), b(8), [Edge(0, "dense", W(8, 8)), Edge(-1, "dense", W(8, 6))]),
+                                         Node((3,), b(3), [Edge(1, "dense", W(3, 8))], relu=False)])),
+        ("identity edge", Net((6,), [Node((6,), b(6), [Edge(-1, "identity")]),
+                                     Node((3,), b(3), [Edge(0, "dense", W(3, 6))], relu=False)])),
+        ("without consumers", Net((6,), [Node((8,), b(8), [Edge(-1, "dense", W(8, 6))]),
+                                         Node((8,), b(8), [Edge(0, "dense", W(8, 8))]),
+                                         Node((3,), b(3), [Edge(0, "dense", W(3, 8))], relu=False)])),
+    ]
+    x0 = r.random(6)
+    for why, net in nets:
+        lu = gen.ibp_bounds(net, x0, 0.1)
+        with pytest.raises(B.GcpError) as ei:
+            B.Net(net, lu)
+        assert ei.value.code == -6 and why in str(ei.value), (why, str(ei.value))
+    ok = Net((6,), [Node((8,), b(8), [Edge(-1, "dense", W(8, 6))]),
+                    Node((3,), b(3), [Edge(0, "dense", W(3, 8))], relu=False)])
+    B.Net(ok, gen.ibp_bounds(ok, x0, 0.1))      # the device is usable afterwards
+
+
 def test_autograd_function_matches_adjoint():
     import torch
     from paper_2208_05740_amd import binding as B
