@@ -24,6 +24,9 @@
   max(|g|, T), T the sum of the magnitudes of every term of the fp32 run's
   bound (the oracle's error scale at its final parameters): near g = 0 the
   plain |d| / |g| measures nothing (reported beside it).
+* The batch of 64 uneven MLP instances, optimised by gcp_optimize_batch as
+  the benchmark launches it: sampled rows of every instance's certified
+  bound against the oracle at the final parameters, in both modes.
 """
 import numpy as np
 import pytest
@@ -34,6 +37,7 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 FULL = {"mlp784": 1024, "cnn": 2048, "resnet": 4096}
+_CACHE = {}
 
 
 def _dev():
@@ -158,3 +162,49 @@ def test_full_size_bf16_optimised_bound_equals_fp32_within_1e3(name):
     print(f"  max |d|/max(|g|,T) {rel_T.max():.2e}; max |d|/|g| {rel.max():.2e}, median {np.median(rel):.2e}; "
           f"bf16 tighter on {np.mean(res[1] > res[0]):.2f} of the rows", flush=True)
     assert rel_T.max() <= 1e-3, (rel_T.max(), int(rel_T.argmax()))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_full_size_batch_certified_bounds_match_oracle(mode):
+    """The 64 uneven MLP instances (42,144 domains) optimised by
+    gcp_optimize_batch as the benchmark launches them (small instances
+    grouped, large ones alone on side streams; bf16 or fp32 iterations, the
+    fp32 certifying pass with fp64 reductions): on every instance, sampled rows
+    (first, random, last) of the certified bound against the oracle at the
+    final parameters, within 1e-5 of max(|g|, T)."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print(f"full-size batch, mode={mode}", flush=True)
+    if "batch" not in _CACHE:
+        _CACHE["batch"] = gen.make_batch(seed=0)
+    probs = _CACHE["batch"]
+    Ps = [B.Problem(p, device=_dev()) for p in probs]
+    o = probs[0].opt
+    items = []
+    for p, P in zip(probs, Ps):
+        a0 = torch.tensor(gen.crown_alpha_init(p.lu), dtype=torch.float32, device=_dev())
+        items.append(dict(P=P, alpha=a0.expand(P.M, -1).contiguous(),
+                          beta=torch.tensor(p.beta.reshape(P.M, -1), dtype=torch.float32, device=_dev()),
+                          gamma=torch.zeros(P.M, P.N, dtype=torch.float32, device=_dev()),
+                          state=torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32,
+                                            device=_dev()),
+                          bound=torch.empty(P.M, dtype=torch.float64, device=_dev()),
+                          verified=torch.empty(P.M, dtype=torch.uint8, device=_dev())))
+    B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                     b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (p, it) in enumerate(zip(probs, items)):
+        M = p.B * p.S
+        rows = _rows(M, 5, 100 + i)
+        idx = torch.as_tensor(rows, device=_dev())
+        f64 = lambda t: t[idx].cpu().numpy().astype(np.float64)  # noqa: E731
+        a64, b64, c64 = f64(it["alpha"]), f64(it["beta"]), f64(it["gamma"])
+        ref = O.bound(p, a64, b64, c64, rows=rows, flat=True)
+        T = O.error_scale(p, a64, b64, c64, rows=rows, flat=True)
+        g = it["bound"].cpu().numpy()[rows]
+        err = np.abs(g - ref) / np.maximum(np.abs(ref), T)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-5, (i, p.name, err.max())
+        assert np.array_equal(it["verified"].cpu().numpy()[rows], (g >= 0).astype(np.uint8))
+    print(f"  {len(probs)} instances, max |d|/max(|g|,T) {worst:.2e}", flush=True)
