@@ -28,6 +28,10 @@
  *    device copies and are released by the matching *_destroy.
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
  *    default stream); results are ready when the stream is synchronised.
+ *    `stream` may be a non-blocking stream: device memory the library
+ *    allocates (handles, workspace growth on a first call) is cleared and
+ *    filled on the null stream and waited for before the call goes on, and
+ *    a buffer is freed only after the device is idle.
  *  - Calls that share a gcp_net use its workspace: do not run two calls on
  *    the same net concurrently on different streams.
  *  - Row r of every per-row array is domain b = r / S, spec row s = r % S.

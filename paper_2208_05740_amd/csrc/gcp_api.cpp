@@ -140,7 +140,11 @@ std::string cls_name(const char* kind, int bf16, int sign, int cfg) {
 int pi_cfg(int cfg) { return (cfg == 6 || cfg == 7) ? cfg : 5; }
 
 // Owned device allocation (zero-filled at allocation), or a borrowed view of
-// memory owned elsewhere (never freed here).
+// memory owned elsewhere (never freed here).  The fill and uploads run on the
+// null stream and are waited for before returning: callers' streams may be
+// non-blocking (no implicit order with the null stream), and their work on a
+// new buffer must not race its clear.  A free first waits for the device, as
+// work in flight on any stream may still use the buffer.
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -159,7 +163,10 @@ struct DBuf {
   }
   ~DBuf() { release(); }
   void release() {
-    if (p && owned) (void)hipFree(p);
+    if (p && owned) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
     owned = true;
@@ -176,13 +183,16 @@ struct DBuf {
     hip_check(hipMalloc(&p, n), "hipMalloc");
     bytes = n;
     hip_check(hipMemset(p, 0, n), "hipMemset");
+    hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
   }
   void ensure(size_t n) {
     if (n > bytes) alloc(n);
   }
   template <class T> void upload(const std::vector<T>& v) {
     alloc(v.size() * sizeof(T));
-    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+    if (v.empty()) return;
+    hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+    hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
   }
   template <class T> T* as() const { return (T*)p; }
 };
@@ -2757,6 +2767,7 @@ void build_plan(BatchPlan& plan, std::vector<Recorder>& recs, std::vector<GammaJ
   }
   plan.buf.alloc(std::max<size_t>(host.size(), 16));
   hip_check(hipMemcpy(plan.buf.p, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");   // ordered before any stream's launches
 }
 
 void run_grouped_iteration(BatchPlan& plan, int* step, float* consts, const gcp_opt* opt, AdamArgs adam,

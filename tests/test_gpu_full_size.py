@@ -171,7 +171,12 @@ def test_full_size_batch_certified_bounds_match_oracle(mode):
     grouped, large ones alone on side streams; bf16 or fp32 iterations, the
     fp32 certifying pass with fp64 reductions): on every instance, sampled rows
     (first, random, last) of the certified bound against the oracle at the
-    final parameters, within 1e-5 of max(|g|, T)."""
+    final parameters, within 1e-5 of max(|g|, T); and on three of them the
+    final bound against the oracle's own 20-iteration ascent from the same
+    start (Appendix C.1), within 1e-3 of max(|g|, T) in fp32 as for the other
+    optimisation parity tests, 2e-3 in bf16 (that bar plus the 1e-3 the bf16
+    iterations may add).  The first call runs every instance's iterations,
+    the large instances concurrently on the library's side streams."""
     import torch
     from paper_2208_05740_amd import binding as B
     print(f"full-size batch, mode={mode}", flush=True)
@@ -190,10 +195,12 @@ def test_full_size_batch_certified_bounds_match_oracle(mode):
                                             device=_dev()),
                           bound=torch.empty(P.M, dtype=torch.float64, device=_dev()),
                           verified=torch.empty(P.M, dtype=torch.uint8, device=_dev())))
+    start = [(gen.crown_alpha_init(p.lu).astype(np.float64), p.beta.reshape(p.B * p.S, -1).astype(np.float64))
+             for p in probs]
     B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
                      b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode)
     torch.cuda.synchronize()
-    worst = 0.0
+    worst, worst_traj = 0.0, 0.0
     for i, (p, it) in enumerate(zip(probs, items)):
         M = p.B * p.S
         rows = _rows(M, 5, 100 + i)
@@ -207,4 +214,14 @@ def test_full_size_batch_certified_bounds_match_oracle(mode):
         worst = max(worst, float(err.max()))
         assert err.max() <= 1e-5, (i, p.name, err.max())
         assert np.array_equal(it["verified"].cpu().numpy()[rows], (g >= 0).astype(np.uint8))
-    print(f"  {len(probs)} instances, max |d|/max(|g|,T) {worst:.2e}", flush=True)
+        tr = rows[[0, 1, -1]]
+        a_s = np.broadcast_to(start[i][0], (len(tr), start[i][0].size)).copy()
+        b_s, c_s = start[i][1][tr], np.zeros((len(tr), p.cuts.n))
+        go, *_ = O.optimize(p, alpha=a_s, beta=b_s, gamma=c_s, rows=tr, flat=True)
+        To = O.error_scale(p, a_s, b_s, c_s, rows=tr, flat=True)
+        gt = it["bound"].cpu().numpy()[tr]
+        e = np.abs(gt - go) / np.maximum(np.abs(go), To)
+        worst_traj = max(worst_traj, float(e.max()))
+        assert e.max() <= (1e-3 if mode == 0 else 2e-3), (i, p.name, e.max(), gt, go)
+    print(f"  {len(probs)} instances, max |d|/max(|g|,T) {worst:.2e} at the final parameters, "
+          f"{worst_traj:.2e} against the oracle's ascent", flush=True)

@@ -393,6 +393,32 @@ def test_graph_replayed_optimisation_equals_eager(case):
             assert np.array_equal(x, y), rep
 
 
+def test_first_call_on_a_side_stream_while_the_null_stream_is_busy():
+    # A fresh net's first gcp_optimize allocates and clears its workspace;
+    # on a caller's stream that does not wait for the null stream, the
+    # iterations must still see the cleared buffers and their own tables
+    # (the null stream is kept busy, so a clear left queued there would land
+    # after them).  The result must equal the same call on the default stream.
+    import torch
+    from paper_2208_05740_amd import binding as B
+    if torch.cuda.default_stream().cuda_stream != 0:
+        pytest.skip("the default stream is not the null stream")
+    p = gen.make_tiny("mlp", 2, B=6, splits=(1, 3), n_cuts=6, input_terms=1)
+    g_ref, a_ref, b_ref, c_ref = _optimize(p, upload(p), 0)
+    P = upload(p)                                       # fresh net: no workspace yet
+    s = torch.cuda.Stream()
+    x = torch.rand(4096, 4096, device=_dev())
+    for _ in range(30):                                 # tens of ms of work on the null stream
+        x = torch.tanh(x @ x)
+    with torch.cuda.stream(s):
+        g, a, b, c = _optimize(p, P, 0)
+    torch.cuda.synchronize()
+    assert np.isfinite(x.sum().item())
+    assert np.array_equal(g, g_ref)
+    for got, want in ((a, a_ref), (b, b_ref), (c, c_ref)):
+        assert torch.equal(got, want)
+
+
 # ------------------------------------------------------------------ batched instances
 
 def _batch_items(probs, Ps):

@@ -209,3 +209,40 @@ def test_persistent_wait_limit_ends_the_launch_with_sound_bounds(monkeypatch):
     monkeypatch.delenv("GCP_PERSIST_SPIN_TICKS")
     again, _ = run(0, persist=True)           # the next call starts from a clear latch
     _same(again, ref)
+
+
+def test_full_size_batch_in_one_persistent_launch_equals_grouped_launches():
+    """The 64 uneven MLP instances (42,144 domains) as the benchmark runs
+    them: in one persistent launch (GCP_FLAG_PERSIST) the final bounds and
+    parameters equal, bit for bit, those of the default launches (small
+    instances grouped, large ones alone on side streams)."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print("full-size batch: persistent launch vs grouped launches", flush=True)
+    probs = gen.make_batch(seed=0)
+    Ps = [B.Problem(p, device=_dev()) for p in probs]
+    o = probs[0].opt
+    a0 = [torch.tensor(gen.crown_alpha_init(p.lu), dtype=torch.float32, device=_dev()).expand(P.M, -1).contiguous()
+          for p, P in zip(probs, Ps)]
+    items = [dict(P=P, alpha=torch.empty_like(a), beta=torch.empty(P.M, P.K, dtype=torch.float32, device=_dev()),
+                  gamma=torch.empty(P.M, P.N, dtype=torch.float32, device=_dev()),
+                  state=torch.empty(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev()),
+                  bound=torch.empty(P.M, dtype=torch.float64, device=_dev()),
+                  verified=torch.empty(P.M, dtype=torch.uint8, device=_dev())) for P, a in zip(Ps, a0)]
+
+    def run(flags):
+        for p, it, a in zip(probs, items, a0):
+            it["alpha"].copy_(a)
+            it["beta"].copy_(torch.tensor(p.beta.reshape(it["P"].M, -1), dtype=torch.float32))
+            it["gamma"].zero_()
+            it["state"].zero_()
+        B.optimize_batch(items, iters=o["iters"], lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"],
+                         b1=o["adam_b1"], b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=flags)
+        torch.cuda.synchronize()
+        return [{k: it[k].cpu().numpy() for k in ("bound", "alpha", "beta", "gamma")} for it in items]
+
+    ref = run(B.GCP_MODE_FP32)
+    got = run(B.GCP_MODE_FP32 | B.GCP_FLAG_PERSIST)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        for k in r:
+            assert np.array_equal(g[k], r[k]), (i, probs[i].name, k)
