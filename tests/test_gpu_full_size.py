@@ -27,6 +27,9 @@
 * The batch of 64 uneven MLP instances, optimised by gcp_optimize_batch as
   the benchmark launches it: sampled rows of every instance's certified
   bound against the oracle at the final parameters, in both modes.
+* The whole optimisation (20 Adam iterations and the certifying pass) of
+  each full workload and of the batch against the oracle's own ascent from
+  the same start, on sampled rows.
 """
 import numpy as np
 import pytest
@@ -225,3 +228,39 @@ def test_full_size_batch_certified_bounds_match_oracle(mode):
         assert e.max() <= (1e-3 if mode == 0 else 2e-3), (i, p.name, e.max(), gt, go)
     print(f"  {len(probs)} instances, max |d|/max(|g|,T) {worst:.2e} at the final parameters, "
           f"{worst_traj:.2e} against the oracle's ascent", flush=True)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["mlp784", "cnn", "resnet"])
+def test_full_size_optimisation_follows_the_oracle_ascent(name, mode):
+    """gcp_optimize on the full workloads from the benchmark's start
+    (CROWN-adaptive alpha, the domains' beta, gamma = 0; 20 Adam iterations,
+    then the fp32 certifying pass): on sampled rows the final bound against
+    the oracle's own 20-iteration ascent from the same start (Appendix C.1),
+    within 1e-3 of max(|g|, T) in fp32 as for the other optimisation parity
+    tests, 2e-3 with bf16 iterations (that bar plus the 1e-3 they may add)."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print(f"full-size ascent vs oracle: {name} mode={mode}", flush=True)
+    prob = gen.make_workload(name, 0, B=FULL[name])
+    P = B.Problem(prob, device=_dev())
+    o = prob.opt
+    a0 = gen.crown_alpha_init(prob.lu).astype(np.float32)
+    a = torch.tensor(a0, device=_dev()).expand(P.M, -1).contiguous()
+    b = torch.tensor(prob.beta.reshape(P.M, -1), dtype=torch.float32, device=_dev())
+    c = torch.zeros(P.M, P.N, dtype=torch.float32, device=_dev())
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N), dtype=torch.float32, device=_dev())
+    b_start = b.cpu().numpy().astype(np.float64)
+    out, _ = B.optimize(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, st, iters=o["iters"],
+                        lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
+                        b2=o["adam_b2"], adam_eps=o["adam_eps"], mode=mode)
+    torch.cuda.synchronize()
+    rows = _rows(P.M, 3, 11)
+    a_s = np.broadcast_to(a0.astype(np.float64), (len(rows), a0.size)).copy()
+    b_s, c_s = b_start[rows], np.zeros((len(rows), P.N))
+    go, *_ = O.optimize(prob, alpha=a_s, beta=b_s, gamma=c_s, rows=rows, flat=True)
+    T = O.error_scale(prob, a_s, b_s, c_s, rows=rows, flat=True)
+    g = out.cpu().numpy()[rows]
+    e = np.abs(g - go) / np.maximum(np.abs(go), T)
+    print(f"  {len(rows)} rows: max |d|/max(|g|,T) {e.max():.2e}", flush=True)
+    assert e.max() <= (1e-3 if mode == 0 else 2e-3), (e.max(), g, go)
