@@ -393,7 +393,8 @@ def test_graph_replayed_optimisation_equals_eager(case):
             assert np.array_equal(x, y), rep
 
 
-def test_first_call_on_a_side_stream_while_the_null_stream_is_busy():
+@pytest.mark.parametrize("kind", ["mlp", "cnn16", "res16"])
+def test_first_call_on_a_side_stream_while_the_null_stream_is_busy(kind):
     # A fresh net's first gcp_optimize allocates and clears its workspace;
     # on a caller's stream that does not wait for the null stream, the
     # iterations must still see the cleared buffers and their own tables
@@ -403,7 +404,8 @@ def test_first_call_on_a_side_stream_while_the_null_stream_is_busy():
     from paper_2208_05740_amd import binding as B
     if torch.cuda.default_stream().cuda_stream != 0:
         pytest.skip("the default stream is not the null stream")
-    p = gen.make_tiny("mlp", 2, B=6, splits=(1, 3), n_cuts=6, input_terms=1)
+    print(f"first call on a side stream: {kind}", flush=True)
+    p = gen.make_tiny(kind, 2, B=6, splits=(1, 3), n_cuts=6, input_terms=1)
     g_ref, a_ref, b_ref, c_ref = _optimize(p, upload(p), 0)
     P = upload(p)                                       # fresh net: no workspace yet
     s = torch.cuda.Stream()
