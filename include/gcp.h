@@ -452,9 +452,11 @@ typedef struct {
  * tiles.  Every item needs its own net handle; grouped instances must be
  * dense networks with the output in the c-hat form: a batch whose grouped
  * part holds conv or identity edges (or a materialised output Lambda) is
- * rejected with EUNSUPPORTED, and null handles, state or bound pointers with
- * EINVAL, before anything is launched.  Calls from several threads are
- * serialised. */
+ * rejected with EUNSUPPORTED, and a batch with an item whose arguments
+ * gcp_optimize would reject (null or foreign handles, null pointers, S, eps)
+ * with that error, before anything is launched; only the value checks of
+ * GCP_FLAG_VALIDATE on a large instance run with its own launches.  Calls
+ * from several threads are serialised. */
 int gcp_optimize_batch(int32_t n, const gcp_batch_item* items, const gcp_opt* opt, int32_t mode, void* stream);
 
 /* ------------------------------------------------------------ profiling */

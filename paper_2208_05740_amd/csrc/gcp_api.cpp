@@ -2881,10 +2881,27 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
     if (w < alone) grouped.push_back(items_all[i]);
     else big.push_back({w, i});
   }
-  // what would stop the grouped part is reported before anything runs
+  // every item's arguments are checked (and its workspace sized) before
+  // anything is launched
   for (const gcp_batch_item& it : grouped) {
     if (const char* why = grouped_unsupported(it.net))
       fail(GCP_EUNSUPPORTED, std::string("batched optimisation supports dense edges only (") + why + ")");
+  }
+  for (const auto& b : big) {
+    const gcp_batch_item& it = items_all[b.second];
+    Call chk{};
+    prepare_call(chk, const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
+                 it.beta, it.gamma, stream);
+  }
+  const int n = (int)grouped.size();
+  const gcp_batch_item* items = grouped.data();
+  std::vector<Call> calls(n);
+  for (int i = 0; i < n; ++i) {
+    const gcp_batch_item& it = items[i];
+    prepare_call(calls[i], const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
+                 it.beta, it.gamma, stream);
+    if (mode & GCP_FLAG_VALIDATE) validate_params(calls[i], it.alpha, it.beta, it.gamma);
+    plan_ahat(calls[i], GCP_FLAG_STORE_AHAT);   // grouped launches replay a stored schedule
   }
   if (!big.empty()) {
     const int ns = std::min<int>(batch_streams(), (int)big.size());
@@ -2923,17 +2940,6 @@ extern "C" int gcp_optimize_batch(int32_t n_all, const gcp_batch_item* items_all
   if (grouped.empty()) {
     g_err.clear();
     return GCP_OK;
-  }
-  const int n = (int)grouped.size();
-  const gcp_batch_item* items = grouped.data();
-  std::vector<Call> calls(n);
-  for (int i = 0; i < n; ++i) {
-    const gcp_batch_item& it = items[i];
-    if (!it.adam_state || !it.bound) fail(GCP_EINVAL, "null adam_state or bound");
-    prepare_call(calls[i], const_cast<gcp_net*>(it.net), it.x0, it.eps, it.C, it.S, it.splits, it.cuts, it.alpha,
-                 it.beta, it.gamma, stream);
-    if (mode & GCP_FLAG_VALIDATE) validate_params(calls[i], it.alpha, it.beta, it.gamma);
-    plan_ahat(calls[i], GCP_FLAG_STORE_AHAT);   // grouped launches replay a stored schedule
   }
   std::lock_guard<std::mutex> lk(g_batch_mu);
   // shared Adam counter and constants: the first instance's workspace

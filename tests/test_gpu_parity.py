@@ -9,6 +9,8 @@ Tolerances:
   * BF16 path: bf16 operands carry 8 mantissa bits (unit 4e-3); the bound
     error is checked at 2e-2 of T.
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -560,6 +562,19 @@ def test_batched_optimisation_conv_and_residual_instances(mode, monkeypatch):
         B.optimize_batch(items, iters=o["iters"], mode=mode)
     torch.cuda.synchronize()
     assert e.value.code == -6 and "conv" in str(e.value), str(e.value)
+    for it, b0 in zip(items, before):
+        assert torch.isnan(it["bound"]).all()
+        for k, v in b0.items():
+            assert torch.equal(it[k], v), k
+    # an alone instance with another net's splits: EINVAL, again before anything runs
+    monkeypatch.setenv("GCP_BATCH_ALONE_WORK", str((lo + hi) // 2))
+    bad = copy.copy(Ps[2])
+    bad.splits = Ps[0].splits
+    items[2]["P"] = bad
+    with pytest.raises(B.GcpError) as e:
+        B.optimize_batch(items, iters=o["iters"], mode=mode)
+    torch.cuda.synchronize()
+    assert e.value.code == -1 and "another net" in str(e.value), str(e.value)
     for it, b0 in zip(items, before):
         assert torch.isnan(it["bound"]).all()
         for k, v in b0.items():
