@@ -29,7 +29,7 @@
   bound against the oracle at the final parameters, in both modes.
 * The whole optimisation (20 Adam iterations and the certifying pass) of
   each full workload and of the batch against the oracle's own ascent from
-  the same start, on sampled rows.
+  the same start, on sampled rows; likewise the explicit-pi optimisation.
 """
 import numpy as np
 import pytest
@@ -264,3 +264,50 @@ def test_full_size_optimisation_follows_the_oracle_ascent(name, mode):
     e = np.abs(g - go) / np.maximum(np.abs(go), T)
     print(f"  {len(rows)} rows: max |d|/max(|g|,T) {e.max():.2e}", flush=True)
     assert e.max() <= (1e-3 if mode == 0 else 2e-3), (e.max(), g, go)
+
+
+@pytest.mark.parametrize("name", ["mlp784", "cnn", "resnet"])
+def test_full_size_explicit_pi_optimisation_follows_the_oracle_ascent(name):
+    """gcp_optimize_pi (rho as a fourth parameter) on the full workloads,
+    fp32, from CROWN-adaptive alpha, the domains' beta, gamma = 0 and a
+    seeded rho in [0.1, 0.9] (away from the kink of h at u / (u - l), where
+    several trajectories are correct): on sampled rows the certified bound
+    against the oracle's bound at the final parameters (1e-5) and against the
+    oracle's own 20-iteration ascent from the same start (1e-3), both of
+    max(|g|, T)."""
+    import torch
+    from paper_2208_05740_amd import binding as B
+    print(f"full-size explicit-pi ascent vs oracle: {name}", flush=True)
+    prob = gen.make_workload(name, 0, B=FULL[name])
+    P = B.Problem(prob, device=_dev())
+    o = prob.opt
+    a0 = gen.crown_alpha_init(prob.lu).astype(np.float32)
+    gen_r = torch.Generator(device=_dev())
+    gen_r.manual_seed(5)
+    r = 0.1 + 0.8 * torch.rand(P.M, P.n_I, generator=gen_r, device=_dev(), dtype=torch.float32)
+    a = torch.tensor(a0, device=_dev()).expand(P.M, -1).contiguous()
+    b = torch.tensor(prob.beta.reshape(P.M, -1), dtype=torch.float32, device=_dev())
+    c = torch.zeros(P.M, P.N, dtype=torch.float32, device=_dev())
+    st = torch.zeros(B.adam_state_size(P.M, P.n_I, P.K, P.N, explicit_pi=True), dtype=torch.float32, device=_dev())
+    b_start = b.cpu().numpy().astype(np.float64)
+    rows = _rows(P.M, 3, 13)
+    idx = torch.as_tensor(rows, device=_dev())
+    r_s = r[idx].cpu().numpy().astype(np.float64)
+    out, _ = B.optimize_pi(P.net, P.x0, P.eps, P.C, P.splits, P.cuts, a, b, c, r, st, iters=o["iters"],
+                           lr_alpha=o["lr_alpha"], lr_mult=o["lr_mult"], decay=o["decay"], b1=o["adam_b1"],
+                           b2=o["adam_b2"], adam_eps=o["adam_eps"])
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()[rows]
+    fin = [t[idx].cpu().numpy().astype(np.float64) for t in (a, b, c, r)]
+    ref = O.bound_pi(prob, *fin[:3], rho=fin[3], rows=rows, flat=True)
+    T = O.error_scale(prob, *fin[:3], rho=fin[3], rows=rows, flat=True)
+    e_fin = np.abs(g - ref) / np.maximum(np.abs(ref), T)
+    a_s = np.broadcast_to(a0.astype(np.float64), (len(rows), a0.size)).copy()
+    b_s, c_s = b_start[rows], np.zeros((len(rows), P.N))
+    go, *_ = O.optimize_pi(prob, alpha=a_s, beta=b_s, gamma=c_s, rho=r_s, rows=rows, flat=True)
+    To = O.error_scale(prob, a_s, b_s, c_s, rho=r_s, rows=rows, flat=True)
+    e = np.abs(g - go) / np.maximum(np.abs(go), To)
+    print(f"  {len(rows)} rows: at the final parameters {e_fin.max():.2e}, against the ascent {e.max():.2e}",
+          flush=True)
+    assert e_fin.max() <= 1e-5, e_fin.max()
+    assert e.max() <= 1e-3, (e.max(), g, go)
